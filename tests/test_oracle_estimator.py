@@ -1,0 +1,291 @@
+"""Statistical pins of the oracle's whole estimator against what the paper's
+mathematics fixes (section 3.2-3.4).
+
+With a constant monitor the generator (Gen) is the heat equation
+x_t = lap x, the SDE is dPhi = sqrt(2) dW, and the Euler-Maruyama step is
+exact in law.  With the Brownian-bridge boundary test the survival event of
+each substep is exact too (up to the two-sided-crossing term, negligible
+here), so the estimator is unbiased for the closed forms below even at a
+coarse K.  Every check is "within 4 sigma" of the reported standard error
+plus any bias bound stated beside it; each is paired with a check that a
+plausible mistake (no bridge, wrong time direction, no winding, wrong drift
+sign, transposed axes) would be caught."""
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.integrate
+
+from paper_1504_00084_amd import workloads as W
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+THREADS = min(8, os.cpu_count() or 1)
+
+
+def golden():
+    vals = {}
+    for ln in open(os.path.join(HERE, "golden", "closed_forms.txt")):
+        if ln.strip() and not ln.startswith("#"):
+            k, v = ln.split()
+            vals[k] = float(v)
+    return vals
+
+
+def S(a, t, terms=4001):
+    k = np.arange(1, terms, 2)
+    return float(np.sum(4.0 / (k * np.pi) * np.sin(k * np.pi * a) * np.exp(-k * k * np.pi ** 2 * t)))
+
+
+def P0(a, t, terms=4001):
+    k = np.arange(1, terms)
+    return float((1.0 - a) - np.sum(2.0 / (k * np.pi) * np.sin(k * np.pi * a) * np.exp(-k * k * np.pi ** 2 * t)))
+
+
+def test_series_match_golden():
+    g = golden()
+    assert abs(S(0.5, 0.05) ** 2 - g["S(0.5,0.05)^2"]) < 1e-11
+    assert abs(S(0.5, 0.05) * S(0.25, 0.05) - g["S(0.5,0.05)*S(0.25,0.05)"]) < 1e-11
+    assert abs(P0(0.5, 0.05) - g["P0(0.5,0.05)"]) < 1e-11
+    assert abs(P0(0.1, 0.05) - g["P0(0.1,0.05)"]) < 1e-11
+    assert abs(P0(0.1, 0.01) - g["P0(0.1,0.01)"]) < 1e-11
+    assert abs(math.exp(-2 * math.pi ** 2 * 0.05) - g["D(0.05)"]) < 1e-11
+
+
+def problem(oracle_lib, inst, **over):
+    kw = inst.problem_kwargs()
+    kw.update(over)
+    return oracle_lib.Problem(**kw)
+
+
+def rank_of(oracle_lib, P, i, j):
+    ii, jj = oracle_lib.interface_nodes(P)
+    hit = np.nonzero((ii == i) & (jj == j))[0]
+    assert len(hit) == 1, (i, j)
+    return int(hit[0])
+
+
+def solve(oracle_lib, inst, nodes=None, **over):
+    P = problem(oracle_lib, inst, **over)
+    return oracle_lib.solve(P, inst.rho, inst.x, inst.y, inst.bnd_t0, inst.bnd_t1, inst.n_paths,
+                            nodes=nodes, threads=THREADS)
+
+
+# --------------------------------------------------------------------------
+def test_uniform_mesh_is_steady_dirichlet(oracle_lib):
+    """rho const: the uniform mesh x = Lx xi, y = Ly eta solves (Gen)."""
+    inst = W.constant_problem(17, 2, 0, 0, tau=0.05, K=40, n_paths=20_000, Lx=2.0, Ly=3.0)
+    r = solve(oracle_lib, inst)
+    i, j = oracle_lib.interface_nodes(problem(oracle_lib, inst))
+    xi, eta = i / 16.0, j / 16.0
+    assert np.all(r["se_x"] > 0) and np.all(r["se_y"] > 0)
+    assert np.all(np.abs(r["mean_x"] - 2.0 * xi) <= 4 * r["se_x"])
+    assert np.all(np.abs(r["mean_y"] - 3.0 * eta) <= 4 * r["se_y"])
+
+
+@pytest.mark.parametrize("px,pe", [(1, 0), (0, 1), (1, 1)])
+def test_uniform_mesh_is_steady_periodic(oracle_lib, px, pe):
+    """Periodic axes wrap the path and add w*L at evaluation (reading R8)."""
+    inst = W.constant_problem(17, 2, px, pe, tau=0.05, K=40, n_paths=20_000, Lx=2.0, Ly=3.0)
+    r = solve(oracle_lib, inst)
+    i, j = oracle_lib.interface_nodes(problem(oracle_lib, inst))
+    assert np.all(np.abs(r["mean_x"] - 2.0 * i / 16.0) <= 4 * r["se_x"])
+    assert np.all(np.abs(r["mean_y"] - 3.0 * j / 16.0) <= 4 * r["se_y"])
+    if px and pe:
+        # paths never exit on a doubly periodic domain
+        assert np.all(r["exit_frac"] == 0.0)
+
+
+def _survival_instance(n_paths, K=10, bridge=1):
+    inst = W.constant_problem(33, 2, 0, 0, tau=0.05, K=K, n_paths=n_paths)
+    inst.sub_eta = 4
+    inst.x[:] = 1.0
+    inst.y[:] = 1.0
+    inst.bnd_t0[:] = 0.0
+    inst.bnd_t1[:] = 0.0
+    inst.bridge = bridge
+    return inst
+
+
+def test_survival_closed_form_with_bridge(oracle_lib):
+    """x0 = 1, f = 0: the estimate is P(no exit before tau) =
+    S(xi,tau) S(eta,tau); the bridge test makes it exact at K = 10."""
+    g = golden()
+    inst = _survival_instance(200_000)
+    P = problem(oracle_lib, inst)
+    nodes = [rank_of(oracle_lib, P, 16, 16), rank_of(oracle_lib, P, 16, 8)]
+    r = solve(oracle_lib, inst, nodes=nodes)
+    want = [g["S(0.5,0.05)^2"], g["S(0.5,0.05)*S(0.25,0.05)"]]
+    for q in range(2):
+        assert abs(r["mean_x"][q] - want[q]) <= 4 * r["se_x"][q], (q, r["mean_x"][q], want[q])
+        assert abs(r["exit_frac"][q] - (1 - want[q])) <= 4 * r["se_x"][q]
+    # without the bridge the endpoint-only test misses crossings: biased high
+    r0 = solve(oracle_lib, inst, nodes=nodes, bridge=0)
+    assert r0["mean_x"][0] - want[0] > 8 * r0["se_x"][0]
+
+
+def test_killing_mode_decay(oracle_lib):
+    """x0 = sin(pi xi) sin(pi eta), f = 0: exp(-2 pi^2 tau) x0 (the factor
+    2 pi^2 fixes the diffusion sqrt(2) dW); terminal value via bicubic."""
+    g = golden()
+    n = 65
+    for tau, key in [(0.05, "D(0.05)"), (0.01, "D(0.01)")]:
+        inst = W.constant_problem(n, 2, 0, 0, tau=tau, K=20, n_paths=100_000)
+        XI, ETA = np.meshgrid(np.arange(n) / (n - 1), np.arange(n) / (n - 1))
+        inst.x[:] = np.sin(np.pi * XI) * np.sin(np.pi * ETA)
+        inst.bnd_t0[:] = 0.0
+        inst.bnd_t1[:] = 0.0
+        P = problem(oracle_lib, inst)
+        nodes = [rank_of(oracle_lib, P, 32, 32), rank_of(oracle_lib, P, 32, 16)]
+        r = solve(oracle_lib, inst, nodes=nodes)
+        # interpolation error bound of the bicubic on this mesh, measured
+        rng = np.random.default_rng(0)
+        interp = max(abs(oracle_lib.keys_bicubic(inst.x, a, b) - math.sin(math.pi * a) * math.sin(math.pi * b))
+                     for a, b in rng.random((400, 2)))
+        for q, (a, b) in enumerate([(0.5, 0.5), (0.5, 0.25)]):
+            want = g[key] * math.sin(math.pi * a) * math.sin(math.pi * b)
+            assert abs(r["mean_x"][q] - want) <= 4 * r["se_x"][q] + interp, (tau, q, r["mean_x"][q], want)
+
+
+@pytest.mark.parametrize("a,tau,key", [(20, 0.05, "P0(0.5,0.05)"), (4, 0.05, "P0(0.1,0.05)"), (4, 0.01, "P0(0.1,0.01)")])
+def test_exit_distribution_closed_form(oracle_lib, a, tau, key):
+    """xi Dirichlet, eta periodic, f = 1 on xi = 0 only, x0 = 0: the
+    estimate is the probability of leaving through xi = 0 before tau."""
+    g = golden()
+    n = 41
+    inst = W.constant_problem(n, 10, 0, 1, tau=tau, K=10, n_paths=200_000)
+    inst.sub_eta = 1
+    inst.x[:] = 0.0
+    for b in (inst.bnd_t0, inst.bnd_t1):
+        b[:] = 0.0
+        b[0:n] = 1.0            # side 0 (xi = 0), x component
+    P = problem(oracle_lib, inst)
+    node = rank_of(oracle_lib, P, a, 5)
+    r = solve(oracle_lib, inst, nodes=[node])
+    assert abs(r["mean_x"][0] - g[key]) <= 4 * r["se_x"][0], (r["mean_x"][0], g[key])
+    # the side choice matters: putting f = 1 on xi = 1 instead gives P1(a) = P0(1 - a)
+    for b in (inst.bnd_t0, inst.bnd_t1):
+        b[:] = 0.0
+        b[2 * n:3 * n] = 1.0    # side 1 (xi = 1), x component
+    r1 = solve(oracle_lib, inst, nodes=[node])
+    # (rule of three for the case where no path exits through xi = 1)
+    assert abs(r1["mean_x"][0] - P0(1.0 - a / 40.0, tau)) <= 4 * r1["se_x"][0] + 3.0 / inst.n_paths
+
+
+def test_exit_time_moment_time_direction(oracle_lib):
+    """x0 = 0, boundary 1 at t^n and 0 at t^{n+1}: an exit after elapsed s
+    reads s/tau (the path runs backward from t^{n+1}), so the estimate is
+    E[(T/tau) 1{T < tau}] = (1/tau) int_0^tau S^2 du - S^2(tau), plus at
+    most (1/K) P(exit) because the exit is dated at the end of its substep."""
+    K = 200
+    inst = _survival_instance(100_000, K=K)
+    inst.x[:] = 0.0
+    inst.bnd_t0[:] = 1.0
+    inst.bnd_t1[:] = 0.0
+    P = problem(oracle_lib, inst)
+    node = rank_of(oracle_lib, P, 16, 16)
+    r = solve(oracle_lib, inst, nodes=[node])
+    tau = 0.05
+    integral = scipy.integrate.quad(lambda u: S(0.5, u) ** 2 if u > 0 else 1.0, 0.0, tau, limit=200)[0]
+    want = integral / tau - S(0.5, tau) ** 2
+    p_exit = 1.0 - S(0.5, tau) ** 2
+    est, se = r["mean_x"][0], r["se_x"][0]
+    assert want - 4 * se <= est <= want + p_exit / K + 4 * se, (est, want, se)
+    # reversed time weighting would give P(exit) - want, far away
+    assert abs(est - (p_exit - want)) > 10 * se
+
+
+@pytest.mark.parametrize("axis", ["xi", "eta"])
+def test_drift_sign_and_winding(oracle_lib, axis):
+    """rho = exp(c a) along one Dirichlet axis a, the other axis periodic.
+    Drift grad rho / rho = c, so x_a = a + c t solves (Gen) with boundary
+    data a + c t (linear in time), and the periodic coordinate stays
+    uniform only if wrapped paths add w*L."""
+    n, c, tau, K = 33, 2.0, 0.05, 50
+    Lx, Ly = 1.5, 2.0
+    if axis == "xi":
+        inst = W.constant_problem(n, 4, 0, 1, tau=tau, K=K, n_paths=40_000, Lx=Lx, Ly=Ly)
+    else:
+        inst = W.constant_problem(n, 4, 1, 0, tau=tau, K=K, n_paths=40_000, Lx=Lx, Ly=Ly)
+    XI, ETA = np.meshgrid(np.arange(n) / (n - 1), np.arange(n) / (n - 1))
+    A = XI if axis == "xi" else ETA
+    inst.rho = np.exp(c * A)
+    L = Lx if axis == "xi" else Ly
+    comp_x = (axis == "xi")
+    # boundary at t^{n+1} shifted by c tau (in computational units) on the drifting component
+    shifted = W.boundary_from_mesh(inst.x + (L * c * tau if comp_x else 0.0),
+                                   inst.y + (0.0 if comp_x else L * c * tau))
+    inst.bnd_t1 = shifted
+    r = solve(oracle_lib, inst)
+    P = problem(oracle_lib, inst)
+    i, j = oracle_lib.interface_nodes(P)
+    h = 1.0 / (n - 1)
+    kappa = math.sinh(c * h) / h          # the central-difference drift
+    # FD drift error inside (kappa - c) and in the one-sided edge cells (c^3 h^2 / 3),
+    # plus the end-of-substep dating of exits on time-dependent boundary data
+    bias = L * ((abs(kappa - c) + c ** 3 * h * h / 3.0) * tau + c * tau / K)
+    if comp_x:
+        want_drift, got, se = Lx * (i * h + kappa * tau), r["mean_x"], r["se_x"]
+        want_flat, got_flat, se_flat = Ly * j * h, r["mean_y"], r["se_y"]
+    else:
+        want_drift, got, se = Ly * (j * h + kappa * tau), r["mean_y"], r["se_y"]
+        want_flat, got_flat, se_flat = Lx * i * h, r["mean_x"], r["se_x"]
+    z = np.abs(got - want_drift) / (4 * se + bias)
+    assert np.all(z <= 1.0), (np.max(z), np.argmax(z))
+    assert np.all(np.abs(got_flat - want_flat) <= 4 * se_flat)
+    # a flipped drift sign would land 2 c tau L away
+    assert np.all(np.abs(got - (want_drift - 2 * L * kappa * tau)) > 8 * se)
+
+
+def test_fd_single_domain_reference(oracle_lib):
+    """Non-constant monitor: the estimate agrees with a deterministic
+    finite-difference solve of (Gen) with the same coefficient field
+    (centred differences, forward Euler, refined grid), within the MC
+    standard error plus the FD discretisation error."""
+    from oracle import fd_reference
+    n = 17
+    x, y = W.uniform_mesh(n, n)
+    ux, uy = W.gaussian_bump_grad(x, y, 0.45, 0.55, 0.05)
+    rho = W.arc_length_monitor(ux, uy, 5.0)
+    b = W.boundary_from_mesh(x, y)
+    tau = 0.02
+    inst = W.Instance("fdref", n, n, 2, 2, 0, 0, 1.0, 1.0, tau, 400, 20_000, rho, x, y, b, b.copy())
+    r = solve(oracle_lib, inst)
+    P = problem(oracle_lib, inst)
+    i, j = oracle_lib.interface_nodes(P)
+    x4, y4 = fd_reference.solve(rho, x, y, b, b, tau, refine=4)
+    x8, y8 = fd_reference.solve(rho, x, y, b, b, tau, refine=8)
+    fx, fy = x8[j, i], y8[j, i]
+    ex, ey = np.abs(x8 - x4)[j, i], np.abs(y8 - y4)[j, i]
+    # the drift moves the mesh noticeably, so this is not the trivial steady case
+    assert np.max(np.abs(fx - i / (n - 1.0))) > 10 * np.max(r["se_x"])
+    zx = (r["mean_x"] - fx) / np.sqrt(r["se_x"] ** 2 + ex ** 2)
+    zy = (r["mean_y"] - fy) / np.sqrt(r["se_y"] ** 2 + ey ** 2)
+    z = np.concatenate([zx, zy])
+    assert np.max(np.abs(z)) < 4.0, np.max(np.abs(z))
+    assert np.mean(z ** 2) < 1.6, np.mean(z ** 2)
+
+
+def test_standard_error_is_calibrated(oracle_lib):
+    """Spread of independent estimates (different seeds) matches the
+    reported standard error: unbiased variance over N - 1, divided by N."""
+    inst = W.config1(400)
+    inst.K = 50
+    means, ses = [], []
+    for seed in range(40):
+        r = solve(oracle_lib, inst, nodes=[15], seed=seed)
+        means.append(r["mean_x"][0])
+        ses.append(r["se_x"][0])
+    ratio = np.std(means, ddof=1) / np.mean(ses)
+    assert 0.6 < ratio < 1.45, ratio
+
+
+def test_single_path_and_determinism(oracle_lib):
+    inst = W.config1(1)
+    inst.K = 20
+    r = solve(oracle_lib, inst, nodes=[0, 5])
+    assert np.all(np.isnan(r["se_x"]))
+    r2 = solve(oracle_lib, inst, nodes=[5])
+    assert r2["mean_x"][0] == r["mean_x"][1]        # per-node result does not depend on the node set
+    p = oracle_lib.paths(problem(oracle_lib, inst), inst.rho, inst.x, inst.y, inst.bnd_t0, inst.bnd_t1, 5, 0, 1)
+    assert p["vx"][0] == r["mean_x"][1]
