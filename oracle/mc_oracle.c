@@ -44,18 +44,16 @@
  *      mesh is quasi-periodic, x(xi+1) = x(xi) + Lx, y(eta+1) = y(eta) + Ly;
  *   R7 the periodic seam is an interface;
  *   R8 paths that wrap carry a winding number that adds w*L at evaluation;
- *   R13 random numbers: Philox4x32-10 (Salmon et al., SC'11), counter
+ *   R13 random numbers: Philox4x32-10 (Salmon et al., SC'11), stream
  *      layout below, uniforms ((r >> 9) + 1/2) 2^-23, Box-Muller normals;
  *   R14 unbiased variance from shifted sums.
  *
- * Counter layout (R13).  For path p of interface node `node` (its rank in
- * the row-major interface enumeration), instance id I and mesh step S:
- *   normals of substeps 2m and 2m+1: ctr = (m, p, node, I<<16 | S&0xffff),
- *     words (r0,r1) -> Box-Muller -> the pair for substep 2m,
- *     words (r2,r3) -> the pair for substep 2m+1;
- *   bridge uniform of substep k:    ctr = (0x80000000 | k, p, node, same),
- *     word r0;
- *   key = (seed & 0xffffffff, seed >> 32).
+ * Stream layout (R13).  Path p of interface node `node` (its rank in the
+ * row-major interface enumeration), instance id I and mesh step S owns the
+ * word sequence w_0, w_1, ... where w_q is word (q mod 4) of the Philox
+ * block with counter (q div 4, p, node, I<<16 | S&0xffff) and key
+ * (seed & 0xffffffff, seed >> 32).  Substep k uses w_{3k}, w_{3k+1}
+ * (Box-Muller -> the two normals) and w_{3k+2} (the bridge uniform).
  */
 #include <math.h>
 #include <pthread.h>
@@ -126,37 +124,33 @@ void oracle_box_muller(uint32_t r0, uint32_t r1, double *n1, double *n2)
     *n2 = radius * sin(two_pi * u1);
 }
 
-static void make_counter(const oracle_problem *P, uint32_t word0, int64_t path, int32_t node,
-                         uint32_t ctr[4], uint32_t key[2])
+/* Word q of the stream of one path (stream layout R13). */
+uint32_t oracle_stream_word(const oracle_problem *P, int32_t node, int64_t path, int64_t q)
 {
-    ctr[0] = word0;
+    uint32_t ctr[4], key[2], r[4];
+    ctr[0] = (uint32_t)(q / 4);
     ctr[1] = (uint32_t)path;
     ctr[2] = (uint32_t)node;
     ctr[3] = (P->instance_id << 16) | (P->mesh_step & 0xFFFFu);
     key[0] = (uint32_t)(P->seed & 0xFFFFFFFFu);
     key[1] = (uint32_t)(P->seed >> 32);
+    oracle_philox4x32_10(ctr, key, r);
+    return r[q % 4];
 }
 
 /* The two standard normals that drive substep k of path `path` at `node`. */
 void oracle_normals(const oracle_problem *P, int32_t node, int64_t path, int32_t k,
                     double *n1, double *n2)
 {
-    uint32_t ctr[4], key[2], r[4];
-    make_counter(P, (uint32_t)(k / 2), path, node, ctr, key);
-    oracle_philox4x32_10(ctr, key, r);
-    if (k % 2 == 0)
-        oracle_box_muller(r[0], r[1], n1, n2);
-    else
-        oracle_box_muller(r[2], r[3], n1, n2);
+    uint32_t a = oracle_stream_word(P, node, path, 3 * (int64_t)k);
+    uint32_t b = oracle_stream_word(P, node, path, 3 * (int64_t)k + 1);
+    oracle_box_muller(a, b, n1, n2);
 }
 
 /* The uniform that drives the bridge test of substep k. */
 double oracle_bridge_uniform(const oracle_problem *P, int32_t node, int64_t path, int32_t k)
 {
-    uint32_t ctr[4], key[2], r[4];
-    make_counter(P, 0x80000000u | (uint32_t)k, path, node, ctr, key);
-    oracle_philox4x32_10(ctr, key, r);
-    return oracle_uniform(r[0]);
+    return oracle_uniform(oracle_stream_word(P, node, path, 3 * (int64_t)k + 2));
 }
 
 /* ------------------------------------------------------------------------ */

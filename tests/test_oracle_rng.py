@@ -41,8 +41,8 @@ def test_philox_matches_rocrand(oracle_lib, rocrand_ref):
         c[1] %= 2 ** 29        # keeps 4*(c0 + 2^32 c1) inside rocRAND's 64-bit offset
         k = rng.integers(0, 2 ** 32, size=2, dtype=np.uint64)
         rows.append([int(v) for v in c] + [int(v) for v in k])
-    # the layouts the estimator uses: (m, p, node, I<<16|S) and the bridge tag
-    for (m, p, node, inst, step) in [(0, 0, 0, 0, 0), (249, 99_999, 752, 3, 7), (0x80000000 | 499, 5, 31, 65535, 65535)]:
+    # counters of the form the estimator uses: (block, path, node, I<<16|S)
+    for (m, p, node, inst, step) in [(0, 0, 0, 0, 0), (374, 99_999, 752, 3, 7), (0x7FFFFFFF, 5, 31, 65535, 65535)]:
         rows.append([m, p, node, (inst << 16) | step, 0, 0])
         rows.append([m, p, node, (inst << 16) | step, 0xDEADBEEF, 0x12345678])
     ref = rocrand_ref(rows)
@@ -86,18 +86,26 @@ def test_box_muller_identities(oracle_lib):
         assert abs(ang - 2 * math.pi * u1) < 1e-9 or abs(abs(ang - 2 * math.pi * u1) - 2 * math.pi) < 1e-9
 
 
-def test_counter_layout(oracle_lib):
-    """Substeps 2m and 2m+1 share one block: words (0,1) and (2,3); the
-    bridge uniform uses the tagged counter word 0x80000000|k, word 0."""
+def test_stream_layout(oracle_lib):
+    """Stream word q of a path is word q mod 4 of the Philox block with
+    counter (q div 4, path, node, I<<16 | S); substep k takes words 3k,
+    3k+1 for Box-Muller and word 3k+2 for the bridge uniform."""
     P = oracle_lib.Problem(n_xi=33, n_eta=33, sub_xi=2, sub_eta=1, seed=0x0123456789ABCDEF,
                            instance_id=9, mesh_step=4)
     key = [0x89ABCDEF, 0x01234567]
-    for (node, path, k) in [(0, 0, 0), (3, 17, 1), (30, 9999, 498), (30, 9999, 499)]:
-        r = oracle_lib.philox4x32_10([k // 2, path, node, (9 << 16) | 4], key)
-        want = oracle_lib.box_muller(r[0], r[1]) if k % 2 == 0 else oracle_lib.box_muller(r[2], r[3])
+
+    def word(node, path, q):
+        return oracle_lib.philox4x32_10([q // 4, path, node, (9 << 16) | 4], key)[q % 4]
+    for (node, path, k) in [(0, 0, 0), (3, 17, 1), (3, 17, 2), (3, 17, 3), (30, 9999, 498), (30, 9999, 499)]:
+        for q in (3 * k, 3 * k + 1, 3 * k + 2):
+            assert oracle_lib.stream_word(P, node, path, q) == word(node, path, q)
+        want = oracle_lib.box_muller(word(node, path, 3 * k), word(node, path, 3 * k + 1))
         assert oracle_lib.normals(P, node, path, k) == want
-        rb = oracle_lib.philox4x32_10([0x80000000 | k, path, node, (9 << 16) | 4], key)
-        assert oracle_lib.bridge_uniform(P, node, path, k) == oracle_lib.uniform(rb[0])
+        assert oracle_lib.bridge_uniform(P, node, path, k) == oracle_lib.uniform(word(node, path, 3 * k + 2))
+    # mesh step uses only its low 16 bits; instance id sits above it
+    P2 = oracle_lib.Problem(n_xi=33, n_eta=33, sub_xi=2, sub_eta=1, seed=0x0123456789ABCDEF,
+                            instance_id=9, mesh_step=4 + 65536)
+    assert oracle_lib.stream_word(P2, 1, 2, 3) == oracle_lib.stream_word(P, 1, 2, 3)
 
 
 def test_normals_distribution(oracle_lib):
