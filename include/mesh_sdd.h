@@ -1,0 +1,272 @@
+/*
+ * mesh_sdd.h -- C-ABI of the MI355X interface-node Monte-Carlo solver for
+ * stochastic domain decomposition of the parabolic mesh generator
+ * (Bihlo, Haynes & Walsh, arXiv:1504.00084).
+ *
+ * Problem solved per call (paper section 3.4-3.6): given the mesh density
+ * rho frozen at t^n (section 3.2, MP linearisation), the mesh (x^n, y^n) and
+ * the boundary data at t^n and t^{n+1}, estimate (x, y) at t^{n+1} at every
+ * artificial subdomain-interface node of the computational grid, by N
+ * independent Euler-Maruyama paths of K substeps of the SDE
+ *     dPhi = (grad rho / rho) dt + sqrt(2) dW          (eq. ...SolutionB)
+ * started at the node and run over one mesh step tau.  A path that leaves a
+ * Dirichlet side (endpoint outside, or Brownian-bridge crossing inside a
+ * substep) takes the boundary value there (eq. ...SolutionA, second term);
+ * a survivor takes the bicubic interpolant of the mesh at t^n at its final
+ * position (first term; periodic problems: eq. StochasticSolutionPeriodic...).
+ * Periodic axes wrap the path and add the winding w*L (quasi-periodic mesh,
+ * section 2).  The estimate is the arithmetic mean over the N paths; the
+ * standard error uses the unbiased variance (sums kept in FP64).
+ *
+ * Conventions
+ *   - Every function returns a status: MESH_SDD_OK (0), MESH_SDD_PENDING (1)
+ *     or a negative error.  No exception crosses the ABI.  The text of the
+ *     last error of the calling thread is returned by mesh_sdd_last_error().
+ *   - Arrays are row-major [n_eta][n_xi] doubles (index j*n_xi + i), node
+ *     (i, j) sitting at computational coordinates (i/(n_xi-1), j/(n_eta-1)).
+ *     A periodic axis has n nodes of which node n-1 is the image of node 0
+ *     (its values are ignored; x(xi + 1) = x(xi) + Lx, y(eta + 1) = y + Ly).
+ *   - Boundary arrays hold, in this order, side 0 (xi = 0) x then y, side 1
+ *     (xi = 1) x then y -- n_eta values each -- then side 2 (eta = 0) x then
+ *     y, side 3 (eta = 1) x then y -- n_xi values each: 4*n_eta + 4*n_xi
+ *     doubles.  Sides normal to a periodic axis are ignored.
+ *   - Interface nodes (section 3.5): node (i, j) with i a multiple of
+ *     (n_xi-1)/sub_xi or j a multiple of (n_eta-1)/sub_eta, not on a
+ *     Dirichlet side; on a periodic axis the seam (index 0) is an interface.
+ *     Order: row-major in (j, i).  Results are indexed by this rank.
+ *   - Random numbers: path p of interface node r owns the word stream w_q =
+ *     word (q mod 4) of Philox4x32-10 with counter
+ *     (q div 4, p, r, instance_id << 16 | (mesh_step & 0xffff)) and key
+ *     (seed low 32 bits, seed high 32 bits); substep k uses w_{3k}, w_{3k+1}
+ *     (Box-Muller normals, uniforms ((w >> 9) + 1/2) 2^-23) and w_{3k+2}
+ *     (bridge uniform).  A result is therefore a pure function of the inputs,
+ *     the seed, instance_id and mesh_step: it is the same whether the
+ *     request runs alone or batched with others.
+ *   - Ownership: inputs are caller-owned and are copied before the call
+ *     returns (submit included), so the caller may free or reuse them at
+ *     once.  Device tables, meshes and partial sums are library-owned and
+ *     stay resident until mesh_sdd_destroy.  Result arrays are caller-owned
+ *     and are written by mesh_sdd_solve_interfaces / mesh_sdd_solve_batch, or
+ *     by the mesh_sdd_poll that returns MESH_SDD_OK.
+ *   - Threading: a context is safe for concurrent submit/poll from several
+ *     threads.  One instance must not be used from two threads at once.
+ *   - Device pointers are HIP device addresses on the context's device.  Data
+ *     behind device input pointers must be complete when the call is made
+ *     (written on the context's stream, or the writer's stream synchronised).
+ */
+#ifndef MESH_SDD_H
+#define MESH_SDD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mesh_sdd_ctx mesh_sdd_ctx; /* device, stream, HBM budget, queue, tuning cache */
+typedef struct mesh_sdd mesh_sdd;         /* one problem instance with its resident tables  */
+typedef uint64_t mesh_sdd_ticket;
+
+enum {
+    MESH_SDD_OK = 0,
+    MESH_SDD_PENDING = 1,
+    MESH_SDD_E_INVAL = -1,     /* bad argument or descriptor                  */
+    MESH_SDD_E_NOMEM = -2,     /* device or host allocation failed            */
+    MESH_SDD_E_BUDGET = -3,    /* one request alone exceeds the HBM budget    */
+    MESH_SDD_E_DEVICE = -4,    /* a HIP call failed                           */
+    MESH_SDD_E_STATE = -5,     /* call out of order (e.g. solve before monitor) */
+    MESH_SDD_E_CANCELLED = -6  /* request cancelled or context destroyed      */
+};
+
+enum { MESH_SDD_FP32 = 0, MESH_SDD_FP64 = 1 };
+
+/* Problem instance.  struct_size must be sizeof(mesh_sdd_desc). */
+typedef struct {
+    uint32_t struct_size;
+    int32_t n_xi, n_eta;             /* grid nodes per axis, >= 4                    */
+    int32_t sub_xi, sub_eta;         /* subdomains per axis, (n-1) % sub == 0        */
+    int32_t periodic_xi, periodic_eta;
+    int32_t K;                       /* Euler-Maruyama substeps per mesh step, >= 1  */
+    double Lx, Ly;                   /* physical extents, > 0                        */
+    double tau;                      /* mesh time step Delta t, > 0                  */
+    int32_t precision;               /* MESH_SDD_FP32: batched FP32 paths with FP64
+                                        sums; MESH_SDD_FP64: plain FP64 path         */
+    int32_t bridge;                  /* 1: Brownian-bridge test (section 3.4)        */
+    uint64_t seed;                   /* Philox key                                   */
+    uint32_t instance_id;            /* request-owned RNG identity, < 65536          */
+    uint32_t reserved;
+} mesh_sdd_desc;
+
+/* One mesh step.  struct_size must be sizeof(mesh_sdd_step). */
+typedef struct {
+    uint32_t struct_size;
+    int32_t inputs_on_device;        /* 1: the four pointers below are device ptrs   */
+    const double *x_cur, *y_cur;     /* mesh at t^n, [n_eta][n_xi]                   */
+    const double *bnd_t0, *bnd_t1;   /* boundary arrays at t^n and t^{n+1}; pass the
+                                        same pointer twice if only one level exists */
+    int64_t paths_per_node;          /* N >= 1; ignored when target_se > 0           */
+    double target_se;                /* > 0: N = min(max_paths, ceil(2 tau L^2/se^2)) */
+    int64_t max_paths;               /* cap for target_se (0: 1e6)                   */
+    uint32_t mesh_step;              /* enters the RNG counter (low 16 bits)         */
+    uint32_t reserved;
+} mesh_sdd_step;
+
+/* Per-node results, caller-owned arrays of length M (interface-node count). */
+typedef struct {
+    uint32_t struct_size;
+    int32_t outputs_on_device;       /* 1: the five pointers are device ptrs         */
+    double *mean_x, *mean_y;         /* estimate of (x, y) at t^{n+1}                */
+    double *se_x, *se_y;             /* standard error (NaN when N == 1)             */
+    double *exit_frac;               /* fraction of paths that left the domain       */
+    uint64_t executed_path_steps;    /* out: EM substeps actually executed           */
+    int64_t paths_per_node;          /* out: N used                                  */
+    double device_ms;                /* out: path + finalize kernel time             */
+} mesh_sdd_result;
+
+/* Serving statistics of a context (mesh_sdd_ctx_stats). */
+typedef struct {
+    uint32_t struct_size;
+    uint32_t reserved;
+    uint64_t submitted, completed, failed, cancelled;
+    uint64_t queued, running;        /* requests waiting / admitted now              */
+    uint64_t ticks;                  /* persistent launches issued by the scheduler  */
+    uint64_t hbm_in_use, hbm_budget; /* bytes admitted / allowed                     */
+    double p50_ms, p99_ms, mean_ms;  /* submit-to-completion latency of completed    */
+    double busy_ms;                  /* device time of all ticks                     */
+    uint64_t executed_path_steps;    /* summed over completed requests               */
+} mesh_sdd_stats;
+
+/* Launch shape of the batched FP32 kernel (chosen by the autotuner or set). */
+typedef struct {
+    uint32_t struct_size;
+    int32_t block;                   /* threads per workgroup (64, 128, 256, 512)    */
+    int32_t waves_per_simd;          /* persistent residency target (1..8)           */
+    int32_t chunk_paths;             /* paths per work item (multiple of 64)         */
+    int32_t table_in_lds;            /* 1: stage the monitor table in LDS when it fits */
+} mesh_sdd_launch;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes caps the device
+ * memory of admitted requests (0: 90% of the free memory).  hip_stream: a
+ * hipStream_t to launch on (NULL: the context creates its own, default
+ * priority).  Starts the serving scheduler thread.  Errors: E_INVAL,
+ * E_DEVICE, E_NOMEM. */
+int mesh_sdd_ctx_create(int device, size_t hbm_budget_bytes, void *hip_stream, mesh_sdd_ctx **out);
+
+/* Stop the scheduler (pending requests end with E_CANCELLED), free
+ * everything the context owns.  Instances must be destroyed first
+ * (E_STATE otherwise). */
+int mesh_sdd_ctx_destroy(mesh_sdd_ctx *ctx);
+
+/* Counters and latency percentiles of the serving loop. */
+int mesh_sdd_ctx_stats(mesh_sdd_ctx *ctx, mesh_sdd_stats *out);
+
+/* Fix the launch shape of the batched kernel (overrides the autotuner for
+ * every later launch); NULL restores autotuning. */
+int mesh_sdd_set_launch(mesh_sdd_ctx *ctx, const mesh_sdd_launch *launch);
+
+/* Launch shape that the next launch over `inst` would use. */
+int mesh_sdd_get_launch(mesh_sdd *inst, mesh_sdd_launch *out);
+
+/* Autotune the batched kernel for the shape bucket of `inst` (grid size,
+ * periodicity) by timing candidate shapes on a reduced path count of
+ * `step`; the result is cached in the context (and in the file named by
+ * MESH_SDD_TUNE_CACHE when set).  Writes the winner to *out if non-NULL. */
+int mesh_sdd_autotune(mesh_sdd *inst, const mesh_sdd_step *step, mesh_sdd_launch *out);
+
+/* ---- host-only helpers (no device needed) --------------------------------- */
+
+/* Validate a descriptor without creating anything: MESH_SDD_OK or E_INVAL
+ * with the reason in mesh_sdd_last_error(). */
+int mesh_sdd_desc_check(const mesh_sdd_desc *desc);
+
+/* Interface nodes of a descriptor's partition (section 3.5): returns M >= 0
+ * (or a negative error) and, when i and j are not NULL, writes the nodes in
+ * rank order into caller arrays of length M. */
+int mesh_sdd_desc_interface_nodes(const mesh_sdd_desc *desc, int32_t *i, int32_t *j);
+
+/* ---- instances ----------------------------------------------------------- */
+
+/* Validate the descriptor (n >= 4, (n-1) % sub == 0, sub >= 1, K >= 1,
+ * tau > 0, L > 0, instance_id < 65536, precision in {FP32, FP64}) and
+ * allocate the instance's resident device buffers.  E_INVAL, E_NOMEM,
+ * E_BUDGET (the instance alone exceeds the context's budget). */
+int mesh_sdd_create(mesh_sdd_ctx *ctx, const mesh_sdd_desc *desc, mesh_sdd **out);
+
+/* Free an instance.  E_STATE if it has requests in flight. */
+int mesh_sdd_destroy(mesh_sdd *inst);
+
+/* Freeze the monitor for the next solves (section 3.2): rho is
+ * [n_eta][n_xi] doubles, > 0, host (is_device_ptr = 0) or device memory.
+ * Builds the finite-difference gradient table on the device (section 3.4).
+ * E_INVAL on a null pointer or a non-positive / non-finite value (host
+ * input only; device input is not inspected). */
+int mesh_sdd_set_monitor(mesh_sdd *inst, const double *rho, int is_device_ptr);
+
+/* Number M of interface nodes (>= 0), or a negative error. */
+int mesh_sdd_num_interface_nodes(const mesh_sdd *inst);
+
+/* Write the interface nodes (i, j) in rank order into caller arrays of
+ * length M (host memory). */
+int mesh_sdd_interface_nodes(const mesh_sdd *inst, int32_t *i, int32_t *j);
+
+/* ---- solving -------------------------------------------------------------- */
+
+/* Blocking solve of one mesh step.  E_STATE before set_monitor; E_INVAL on
+ * a bad step (null pointers, N < 1, corner values of the boundary arrays
+ * that disagree by more than 1e-12 (Lx + Ly), host inputs that are not
+ * finite). */
+int mesh_sdd_solve_interfaces(mesh_sdd *inst, const mesh_sdd_step *step, mesh_sdd_result *result);
+
+/* Blocking solve of `count` instances: all FP32 instances run in ONE
+ * persistent launch over a shared (instance, node, path-chunk) work queue;
+ * FP64 instances run one launch each.  Per-instance status codes go to
+ * status[] (may be NULL); the return value is the first error or OK. */
+int mesh_sdd_solve_batch(mesh_sdd *const *insts, const mesh_sdd_step *steps, mesh_sdd_result *results,
+                         int32_t count, int32_t *status);
+
+/* Non-blocking: snapshot the step's inputs and queue a request.  The
+ * scheduler admits requests while the HBM in use plus the request's cost
+ * stays within the budget, and runs all admitted requests' pending chunks
+ * in persistent launches ("ticks"); a request that arrives while a tick is
+ * running joins the next tick (continuous batching at chunk granularity).
+ * E_BUDGET only if the request alone exceeds the budget. */
+int mesh_sdd_submit(mesh_sdd *inst, const mesh_sdd_step *step, mesh_sdd_ticket *ticket);
+
+/* MESH_SDD_PENDING while the request runs; MESH_SDD_OK once done (the
+ * result arrays given here are filled, the ticket is released); a negative
+ * error if it failed (ticket released).  E_INVAL for an unknown ticket. */
+int mesh_sdd_poll(mesh_sdd_ctx *ctx, mesh_sdd_ticket ticket, mesh_sdd_result *result);
+
+/* Like poll but waits up to timeout_ms (< 0: forever) for completion. */
+int mesh_sdd_wait(mesh_sdd_ctx *ctx, mesh_sdd_ticket ticket, mesh_sdd_result *result, int64_t timeout_ms);
+
+/* Cancel a queued request (E_STATE if it is already running). */
+int mesh_sdd_cancel(mesh_sdd_ctx *ctx, mesh_sdd_ticket ticket);
+
+/* ---- diagnostics ----------------------------------------------------------- */
+
+/* Per-path outcomes of interface node `node_rank`, paths [p_begin, p_end),
+ * run by the instance's own path kernel arithmetic (FP32 or FP64) one path
+ * per lane: value (vx, vy), exit flag, exit side (-1: survived) and
+ * executed substeps.  If trace != NULL it receives, per path and substep,
+ * (xi, eta, n1, n2) after the wrap and before any exit projection
+ * ([p][K][4] doubles; entries after an exit are left as they were).
+ * Host arrays.  For checking the path arithmetic on tiny cases. */
+int mesh_sdd_debug_paths(mesh_sdd *inst, const mesh_sdd_step *step, int32_t node_rank, int64_t p_begin,
+                         int64_t p_end, double *vx, double *vy, int32_t *exited, int32_t *side,
+                         int32_t *steps, double *trace);
+
+/* Text of the last error on the calling thread ("" if none). */
+const char *mesh_sdd_last_error(void);
+
+/* Library version string. */
+const char *mesh_sdd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MESH_SDD_H */

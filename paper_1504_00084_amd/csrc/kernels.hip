@@ -1,0 +1,987 @@
+// HIP kernels (gfx950) of the interface-node Monte-Carlo solver for the
+// linearised parabolic mesh generator (Bihlo, Haynes & Walsh,
+// arXiv:1504.00084, section 3.4):
+//
+//   Phi^{k+1} = Phi^k + (grad rho / rho)(Phi^k) dt + sqrt(2 dt) N(0, 1)   (EM)
+//
+// with rho and grad rho bilinearly interpolated from a finite-difference
+// table, a Brownian-bridge exit test per substep on Dirichlet sides, wrap
+// with winding on periodic axes, bicubic (Keys) evaluation of the mesh at
+// t^n for survivors, boundary data (linear in time) for exits, and FP64
+// shifted sums per (node, path chunk).
+//
+// Two path kernels:
+//   * paths_fp32: the production kernel.  FP32 path arithmetic with the
+//     hardware transcendentals, per-cell bilinear coefficients read through
+//     the caches, a persistent grid of waves pulling (instance, node, chunk)
+//     items from a queue, lanes refilled with the chunk's next path when a
+//     path ends, FP64 per-lane sums reduced by wave shuffles.
+//   * paths_fp64: the plain baseline.  One thread per path, FP64 throughout
+//     (software transcendentals), one launch per instance, block reduction.
+//
+// The random stream of path p of interface node r: word q is word (q mod 4)
+// of Philox4x32-10 (Salmon et al., SC'11) at counter
+// (q div 4, p, r, instance << 16 | mesh_step); substep k uses words 3k and
+// 3k+1 (Box-Muller) and 3k+2 (bridge uniform).  A wave advances its lanes
+// four substeps at a time, which is exactly three Philox blocks.
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "msdd_device.hpp"
+#include "msdd_kernels.hpp"
+
+namespace msdd {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 and uniforms
+// ---------------------------------------------------------------------------
+struct Words4 {
+    uint32_t w0, w1, w2, w3;
+};
+
+__device__ __forceinline__ Words4 philox4x32_10(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3, uint32_t k0,
+                                                uint32_t k1)
+{
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint64_t m0 = (uint64_t)0xD2511F53u * (uint64_t)x0;
+        const uint64_t m1 = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
+        const uint32_t y0 = (uint32_t)(m1 >> 32) ^ x1 ^ k0;
+        const uint32_t y2 = (uint32_t)(m0 >> 32) ^ x3 ^ k1;
+        x1 = (uint32_t)m1;
+        x3 = (uint32_t)m0;
+        x0 = y0;
+        x2 = y2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return Words4{x0, x1, x2, x3};
+}
+
+// (2 floor(r / 2^9) + 1) 2^-24: exact in binary32.
+__device__ __forceinline__ float uniform_f32(uint32_t r)
+{
+    return fmaf((float)(r >> 9), 0x1.0p-23f, 0x1.0p-24f);
+}
+
+__device__ __forceinline__ double uniform_f64(uint32_t r)
+{
+    return fma((double)(r >> 9), 0x1.0p-23, 0x1.0p-24);
+}
+
+// ---------------------------------------------------------------------------
+// Uniform (per-instance) constants of the FP32 path, loaded once per item.
+// ---------------------------------------------------------------------------
+struct ConstF {
+    int n_xi, n_eta, nx1, ny1;
+    int per_xi, per_eta, bridge, K;
+    float fnx1, fny1, dt, sq2dt, inv_dt, inv_tau, Lx, Ly;
+    const float4 *cells;
+};
+
+__device__ __forceinline__ ConstF load_const_f(const InstView &I)
+{
+    ConstF c;
+    c.n_xi = I.n_xi;
+    c.n_eta = I.n_eta;
+    c.nx1 = I.n_xi - 1;
+    c.ny1 = I.n_eta - 1;
+    c.per_xi = I.per_xi;
+    c.per_eta = I.per_eta;
+    c.bridge = I.bridge;
+    c.K = I.K;
+    c.fnx1 = (float)(I.n_xi - 1);
+    c.fny1 = (float)(I.n_eta - 1);
+    c.dt = I.dt_f;
+    c.sq2dt = I.sq2dt_f;
+    c.inv_dt = I.inv_dt_f;
+    c.inv_tau = I.inv_tau_f;
+    c.Lx = I.Lx_f;
+    c.Ly = I.Ly_f;
+    c.cells = I.cells;
+    return c;
+}
+
+struct PathF {
+    float x, y;   // position in [0,1]^2 (periodic axes wrapped)
+    int wx, wy;   // winding numbers
+    int k;        // substeps done
+};
+
+// Cell index and local coordinate along one axis with `n1` cells.
+__device__ __forceinline__ int cell_of(float s, int n1, float &t)
+{
+    int c = (int)s;
+    c = max(0, min(c, n1 - 1));
+    t = s - (float)c;
+    return c;
+}
+
+// One EM substep of the FP32 path (a3-a6).  Returns the exit side (0: xi=0,
+// 1: xi=1, 2: eta=0, 3: eta=1) with the position moved onto it, or -1.
+__device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t wa, uint32_t wb, uint32_t wc,
+                                           float *trace4)
+{
+    // a3: Box-Muller on two stream words; hardware log2 / sqrt / sin / cos
+    // (sin and cos take revolutions: sin(2 pi u)).
+    const float u0 = uniform_f32(wa);
+    const float u1 = uniform_f32(wb);
+    const float rad = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u0));
+    const float n1 = rad * __builtin_amdgcn_cosf(u1);
+    const float n2 = rad * __builtin_amdgcn_sinf(u1);
+
+    // a4: bilinear interpolation of (rho, rho_xi, rho_eta) on the cell.
+    float tx, ty;
+    const int cx = cell_of(P.x * C.fnx1, C.nx1, tx);
+    const int cy = cell_of(P.y * C.fny1, C.ny1, ty);
+    const float4 *cell = C.cells + 3 * (cy * C.nx1 + cx);
+    const float4 A = cell[0], B = cell[1], G = cell[2];
+    const float rho = fmaf(ty, fmaf(A.w, tx, A.z), fmaf(A.y, tx, A.x));
+    const float gx = fmaf(ty, fmaf(B.w, tx, B.z), fmaf(B.y, tx, B.x));
+    const float gy = fmaf(ty, fmaf(G.w, tx, G.z), fmaf(G.y, tx, G.x));
+    const float inv_rho = __builtin_amdgcn_rcpf(rho);
+
+    // a5: Euler-Maruyama.
+    float nx = fmaf(C.sq2dt, n1, fmaf(gx * inv_rho, C.dt, P.x));
+    float ny = fmaf(C.sq2dt, n2, fmaf(gy * inv_rho, C.dt, P.y));
+
+    // a6: periodic wrap with winding.
+    if (C.per_xi) {
+        const float f = floorf(nx);
+        nx -= f;
+        P.wx += (int)f;
+        if (nx >= 1.0f) {
+            nx -= 1.0f;
+            P.wx += 1;
+        }
+    }
+    if (C.per_eta) {
+        const float f = floorf(ny);
+        ny -= f;
+        P.wy += (int)f;
+        if (ny >= 1.0f) {
+            ny -= 1.0f;
+            P.wy += 1;
+        }
+    }
+
+    if (trace4) {   // diagnostics: position after the wrap, before any exit projection
+        trace4[0] = nx;
+        trace4[1] = ny;
+        trace4[2] = n1;
+        trace4[3] = n2;
+    }
+
+    // a6: endpoint outside a Dirichlet side.
+    int side = -1;
+    if (!C.per_xi) {
+        if (nx < 0.0f) {
+            side = 0;
+            nx = 0.0f;
+        } else if (nx > 1.0f) {
+            side = 1;
+            nx = 1.0f;
+        }
+    }
+    if (!C.per_eta) {
+        if (ny < 0.0f) {
+            side = side < 0 ? 2 : side;
+            ny = 0.0f;
+        } else if (ny > 1.0f) {
+            side = side < 0 ? 3 : side;
+            ny = 1.0f;
+        }
+    }
+
+    // a6: Brownian bridge between the two inside points.  A side with
+    // d0 d1 / dt > 18.5 has crossing probability < 2^-26.6, too small to
+    // beat the smallest uniform (2^-24) even summed over four sides, so the
+    // exponentials are evaluated only when some side is that close.
+    if (side < 0 && C.bridge) {
+        const float big = 1.0e30f;
+        const float a0 = C.per_xi ? big : P.x * nx * C.inv_dt;
+        const float a1 = C.per_xi ? big : (1.0f - P.x) * (1.0f - nx) * C.inv_dt;
+        const float a2 = C.per_eta ? big : P.y * ny * C.inv_dt;
+        const float a3 = C.per_eta ? big : (1.0f - P.y) * (1.0f - ny) * C.inv_dt;
+        const float amin = fminf(fminf(a0, a1), fminf(a2, a3));
+        if (amin < 18.5f) {
+            const float L2E = 1.4426950408889634f;
+            const float p0 = __builtin_amdgcn_exp2f(-a0 * L2E);
+            const float p1 = __builtin_amdgcn_exp2f(-a1 * L2E);
+            const float p2 = __builtin_amdgcn_exp2f(-a2 * L2E);
+            const float p3 = __builtin_amdgcn_exp2f(-a3 * L2E);
+            // q = 1 - prod(1 - p_s), accumulated without cancellation
+            float q = p0;
+            q = fmaf(-q, p1, q + p1);
+            q = fmaf(-q, p2, q + p2);
+            q = fmaf(-q, p3, q + p3);
+            if (uniform_f32(wc) < q) {
+                int s = 0;
+                float am = a0;
+                if (a1 < am) { s = 1; am = a1; }
+                if (a2 < am) { s = 2; am = a2; }
+                if (a3 < am) { s = 3; am = a3; }
+                side = s;
+                if (s == 0) nx = 0.0f;
+                if (s == 1) nx = 1.0f;
+                if (s == 2) ny = 0.0f;
+                if (s == 3) ny = 1.0f;
+            }
+        }
+    }
+    P.x = nx;
+    P.y = ny;
+    return side;
+}
+
+// a7 (exit): boundary value, linear along the side and linear in time.
+__device__ __forceinline__ float boundary_f32(const float *b0, const float *b1, int n_xi, int n_eta, int side,
+                                              int comp, float tang, float w_tn)
+{
+    const int len = side < 2 ? n_eta : n_xi;
+    const int off = side < 2 ? (side * 2 + comp) * n_eta : 4 * n_eta + ((side - 2) * 2 + comp) * n_xi;
+    float fr;
+    const int c = cell_of(tang * (float)(len - 1), len - 1, fr);
+    const float v0 = fmaf(fr, b0[off + c + 1] - b0[off + c], b0[off + c]);
+    const float v1 = fmaf(fr, b1[off + c + 1] - b1[off + c], b1[off + c]);
+    return fmaf(w_tn, v0 - v1, v1);   // w_tn v0 + (1 - w_tn) v1
+}
+
+// a7 (survivor): Keys cubic convolution (a = -1/2) on the padded mesh.
+__device__ __forceinline__ float keys_f32(const float *pad, int n_xi, int nx1, int ny1, float fnx1, float fny1,
+                                          float x, float y)
+{
+    float tx, ty;
+    const int cx = cell_of(x * fnx1, nx1, tx);
+    const int cy = cell_of(y * fny1, ny1, ty);
+    const float wx[4] = {((-0.5f * tx + 1.0f) * tx - 0.5f) * tx, (1.5f * tx - 2.5f) * tx * tx + 1.0f,
+                         ((-1.5f * tx + 2.0f) * tx + 0.5f) * tx, (0.5f * tx - 0.5f) * tx * tx};
+    const float wy[4] = {((-0.5f * ty + 1.0f) * ty - 0.5f) * ty, (1.5f * ty - 2.5f) * ty * ty + 1.0f,
+                         ((-1.5f * ty + 2.0f) * ty + 0.5f) * ty, (0.5f * ty - 0.5f) * ty * ty};
+    const int stride = n_xi + 2;
+    const float *row = pad + cy * stride + cx;   // padded node (cx-1, cy-1)
+    float acc = 0.0f;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const float r = fmaf(wx[3], row[3], fmaf(wx[2], row[2], fmaf(wx[1], row[1], wx[0] * row[0])));
+        acc = fmaf(wy[b], r, acc);
+        row += stride;
+    }
+    return acc;
+}
+
+// Value of an ended FP32 path (a7), winding offsets included.
+__device__ __forceinline__ void path_value_f32(const InstView &I, const ConstF &C, const PathF &P, int side,
+                                               float &vx, float &vy)
+{
+    if (side >= 0) {
+        const float w_tn = (float)P.k * C.dt * C.inv_tau;
+        const float tang = side < 2 ? P.y : P.x;
+        vx = boundary_f32(I.bnd0_f, I.bnd1_f, C.n_xi, C.n_eta, side, 0, tang, w_tn);
+        vy = boundary_f32(I.bnd0_f, I.bnd1_f, C.n_xi, C.n_eta, side, 1, tang, w_tn);
+    } else {
+        vx = keys_f32(I.xpad_f, C.n_xi, C.nx1, C.ny1, C.fnx1, C.fny1, P.x, P.y);
+        vy = keys_f32(I.ypad_f, C.n_xi, C.nx1, C.ny1, C.fnx1, C.fny1, P.x, P.y);
+    }
+    if (C.per_xi) vx = fmaf((float)P.wx, C.Lx, vx);
+    if (C.per_eta) vy = fmaf((float)P.wy, C.Ly, vy);
+}
+
+// Up to four substeps of one path: the three Philox blocks of the group are
+// drawn at once (words 3s..3s+2 of substep s of the group).  Returns the exit
+// side or -1; `ended` is set when the path exited or reached K.
+template <bool TRACE>
+__device__ __forceinline__ int group_f32(PathF &P, const ConstF &C, uint32_t path, uint32_t node, uint32_t ctr3,
+                                         uint32_t key0, uint32_t key1, bool &ended, double *trace)
+{
+    const uint32_t blk = 3u * ((uint32_t)P.k >> 2);
+    const Words4 A = philox4x32_10(blk, path, node, ctr3, key0, key1);
+    const Words4 B = philox4x32_10(blk + 1u, path, node, ctr3, key0, key1);
+    const Words4 G = philox4x32_10(blk + 2u, path, node, ctr3, key0, key1);
+    const uint32_t w[12] = {A.w0, A.w1, A.w2, A.w3, B.w0, B.w1, B.w2, B.w3, G.w0, G.w1, G.w2, G.w3};
+    int side = -1;
+    ended = false;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        if (!ended && P.k < C.K) {
+            float t4[4];
+            side = substep_f32(P, C, w[3 * s], w[3 * s + 1], w[3 * s + 2], TRACE ? t4 : nullptr);
+            if (TRACE) {
+                double *t = trace + 4 * (size_t)P.k;
+                t[0] = t4[0];
+                t[1] = t4[1];
+                t[2] = t4[2];
+                t[3] = t4[3];
+            }
+            P.k += 1;
+            ended = side >= 0;
+        }
+    }
+    ended = ended || P.k >= C.K;
+    return side;
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Runs one work item with one wave (lanes refilled from the chunk).
+__device__ __forceinline__ void run_item_f32(const InstView &I, const WorkItem &w, int lane, Partial *out)
+{
+    const ConstF C = load_const_f(I);
+    const uint32_t node = w.node;
+    const int i0 = I.node_i[node], j0 = I.node_j[node];
+    const float x0 = (float)((double)i0 / (double)C.nx1);
+    const float y0 = (float)((double)j0 / (double)C.ny1);
+    const double refx = I.x64[(size_t)j0 * C.n_xi + i0];
+    const double refy = I.y64[(size_t)j0 * C.n_xi + i0];
+    const uint32_t key0 = I.key0, key1 = I.key1, ctr3 = I.ctr3;
+
+    double s1x = 0.0, s2x = 0.0, s1y = 0.0, s2y = 0.0;
+    unsigned long long exits = 0, steps = 0;
+
+    PathF P{x0, y0, 0, 0, 0};
+    uint32_t path = 0;
+    bool has = false;
+    uint32_t issued = 0;          // paths of the chunk handed out (wave-uniform)
+    const uint32_t count = w.p_count;
+
+    for (;;) {
+        // refill lanes that have no path with the chunk's next paths, in lane order
+        if (issued < count) {
+            const uint64_t need = __ballot(!has);
+            const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(need >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
+            if (!has && issued + below < count) {
+                has = true;
+                path = w.p_begin + issued + below;
+                P.x = x0;
+                P.y = y0;
+                P.wx = 0;
+                P.wy = 0;
+                P.k = 0;
+            }
+            issued += (uint32_t)__popcll(need);
+        }
+        if (__ballot(has) == 0) break;
+        if (has) {
+            bool ended;
+            const int side = group_f32<false>(P, C, path, node, ctr3, key0, key1, ended, nullptr);
+            if (ended) {
+                float vx, vy;
+                path_value_f32(I, C, P, side, vx, vy);
+                const double dx = (double)vx - refx, dy = (double)vy - refy;
+                s1x += dx;
+                s2x = fma(dx, dx, s2x);
+                s1y += dy;
+                s2y = fma(dy, dy, s2y);
+                exits += side >= 0 ? 1u : 0u;
+                steps += (unsigned long long)P.k;
+                has = false;
+            }
+        }
+    }
+    s1x = wave_sum(s1x);
+    s2x = wave_sum(s2x);
+    s1y = wave_sum(s1y);
+    s2y = wave_sum(s2y);
+    exits = wave_sum_u64(exits);
+    steps = wave_sum_u64(steps);
+    if (lane == 0) {
+        out->s1x = s1x;
+        out->s2x = s2x;
+        out->s1y = s1y;
+        out->s2y = s2y;
+        out->exits = exits;
+        out->steps = steps;
+    }
+}
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void paths_fp32(const InstView *__restrict__ insts,
+                                                    const WorkItem *__restrict__ items, uint32_t n_items,
+                                                    uint32_t *__restrict__ head)
+{
+    const int lane = threadIdx.x & 63;
+    for (;;) {
+        uint32_t it = 0;
+        if (lane == 0) it = atomicAdd(head, 1u);
+        it = __builtin_amdgcn_readfirstlane(__shfl(it, 0, 64));
+        if (it >= n_items) break;
+        const WorkItem w = items[it];
+        const InstView &I = insts[w.inst];
+        run_item_f32(I, w, lane, I.partials + w.partial);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 plain path
+// ---------------------------------------------------------------------------
+struct StreamF64 {
+    uint32_t path, node, ctr3, key0, key1;
+    uint32_t blk;
+    Words4 cur;
+    __device__ uint32_t word(uint32_t q)
+    {
+        const uint32_t b = q >> 2;
+        if (b != blk) {
+            cur = philox4x32_10(b, path, node, ctr3, key0, key1);
+            blk = b;
+        }
+        const uint32_t r = q & 3u;
+        return r == 0 ? cur.w0 : (r == 1 ? cur.w1 : (r == 2 ? cur.w2 : cur.w3));
+    }
+};
+
+__device__ __forceinline__ int cell_of_d(double s, int n1, double &t)
+{
+    int c = (int)floor(s);
+    c = max(0, min(c, n1 - 1));
+    t = s - (double)c;
+    return c;
+}
+
+__device__ __forceinline__ double bilinear_d(const double *f, int n_xi, int cx, int cy, double tx, double ty)
+{
+    const double *r0 = f + (size_t)cy * n_xi + cx;
+    const double *r1 = r0 + n_xi;
+    return (1.0 - tx) * (1.0 - ty) * r0[0] + tx * (1.0 - ty) * r0[1] + (1.0 - tx) * ty * r1[0] + tx * ty * r1[1];
+}
+
+__device__ __forceinline__ double boundary_d(const double *b0, const double *b1, int n_xi, int n_eta, int side,
+                                             int comp, double tang, double w_tn)
+{
+    const int len = side < 2 ? n_eta : n_xi;
+    const int off = side < 2 ? (side * 2 + comp) * n_eta : 4 * n_eta + ((side - 2) * 2 + comp) * n_xi;
+    double fr;
+    const int c = cell_of_d(tang * (double)(len - 1), len - 1, fr);
+    const double v0 = (1.0 - fr) * b0[off + c] + fr * b0[off + c + 1];
+    const double v1 = (1.0 - fr) * b1[off + c] + fr * b1[off + c + 1];
+    return w_tn * v0 + (1.0 - w_tn) * v1;
+}
+
+__device__ __forceinline__ double keys_d(const double *pad, int n_xi, int n_eta, double x, double y)
+{
+    double tx, ty;
+    const int cx = cell_of_d(x * (double)(n_xi - 1), n_xi - 1, tx);
+    const int cy = cell_of_d(y * (double)(n_eta - 1), n_eta - 1, ty);
+    const double wx[4] = {((-0.5 * tx + 1.0) * tx - 0.5) * tx, (1.5 * tx - 2.5) * tx * tx + 1.0,
+                          ((-1.5 * tx + 2.0) * tx + 0.5) * tx, (0.5 * tx - 0.5) * tx * tx};
+    const double wy[4] = {((-0.5 * ty + 1.0) * ty - 0.5) * ty, (1.5 * ty - 2.5) * ty * ty + 1.0,
+                          ((-1.5 * ty + 2.0) * ty + 0.5) * ty, (0.5 * ty - 0.5) * ty * ty};
+    const int stride = n_xi + 2;
+    const double *row = pad + (size_t)cy * stride + cx;
+    double acc = 0.0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        acc += wy[b] * (wx[0] * row[0] + wx[1] * row[1] + wx[2] * row[2] + wx[3] * row[3]);
+        row += stride;
+    }
+    return acc;
+}
+
+struct PathOutD {
+    double vx, vy;
+    int side;
+    int steps;
+};
+
+// One whole path in FP64 (a2-a7).
+template <bool TRACE>
+__device__ __forceinline__ PathOutD run_path_f64(const InstView &I, uint32_t node, uint32_t path, double *trace)
+{
+    const int nx1 = I.n_xi - 1, ny1 = I.n_eta - 1;
+    const double dt = I.dt, sq = sqrt(2.0 * dt);
+    StreamF64 S{path, node, I.ctr3, I.key0, I.key1, 0xFFFFFFFFu, Words4{0, 0, 0, 0}};
+    double x = (double)I.node_i[node] / (double)nx1;
+    double y = (double)I.node_j[node] / (double)ny1;
+    long wx = 0, wy = 0;
+    PathOutD out{0.0, 0.0, -1, I.K};
+    for (int k = 0; k < I.K; ++k) {
+        const uint32_t q = 3u * (uint32_t)k;
+        const double u0 = uniform_f64(S.word(q));
+        const double u1 = uniform_f64(S.word(q + 1u));
+        double sn, cs;
+        sincospi(2.0 * u1, &sn, &cs);
+        const double rad = sqrt(-2.0 * log(u0));
+        const double n1 = rad * cs, n2 = rad * sn;
+
+        double tx, ty;
+        const int cx = cell_of_d(x * (double)nx1, nx1, tx);
+        const int cy = cell_of_d(y * (double)ny1, ny1, ty);
+        const double r = bilinear_d(I.rho, I.n_xi, cx, cy, tx, ty);
+        const double rx = bilinear_d(I.rho_xi, I.n_xi, cx, cy, tx, ty);
+        const double ry = bilinear_d(I.rho_eta, I.n_xi, cx, cy, tx, ty);
+        double nx = x + (rx / r) * dt + sq * n1;
+        double ny = y + (ry / r) * dt + sq * n2;
+        if (I.per_xi) {
+            const double f = floor(nx);
+            nx -= f;
+            wx += (long)f;
+            if (nx >= 1.0) { nx -= 1.0; wx += 1; }
+        }
+        if (I.per_eta) {
+            const double f = floor(ny);
+            ny -= f;
+            wy += (long)f;
+            if (ny >= 1.0) { ny -= 1.0; wy += 1; }
+        }
+        if (TRACE) {
+            trace[4 * k + 0] = nx;
+            trace[4 * k + 1] = ny;
+            trace[4 * k + 2] = n1;
+            trace[4 * k + 3] = n2;
+        }
+        int side = -1;
+        if (!I.per_xi) {
+            if (nx < 0.0) { side = 0; nx = 0.0; }
+            else if (nx > 1.0) { side = 1; nx = 1.0; }
+        }
+        if (!I.per_eta) {
+            if (ny < 0.0) { side = side < 0 ? 2 : side; ny = 0.0; }
+            else if (ny > 1.0) { side = side < 0 ? 3 : side; ny = 1.0; }
+        }
+        if (side < 0 && I.bridge) {
+            double p[4] = {0.0, 0.0, 0.0, 0.0};
+            if (!I.per_xi) {
+                p[0] = exp(-x * nx / dt);
+                p[1] = exp(-(1.0 - x) * (1.0 - nx) / dt);
+            }
+            if (!I.per_eta) {
+                p[2] = exp(-y * ny / dt);
+                p[3] = exp(-(1.0 - y) * (1.0 - ny) / dt);
+            }
+            const double q_exit = 1.0 - (1.0 - p[0]) * (1.0 - p[1]) * (1.0 - p[2]) * (1.0 - p[3]);
+            if (uniform_f64(S.word(q + 2u)) < q_exit) {
+                int s = 0;
+                double pm = p[0];
+                if (p[1] > pm) { s = 1; pm = p[1]; }
+                if (p[2] > pm) { s = 2; pm = p[2]; }
+                if (p[3] > pm) { s = 3; pm = p[3]; }
+                side = s;
+                if (s == 0) nx = 0.0;
+                if (s == 1) nx = 1.0;
+                if (s == 2) ny = 0.0;
+                if (s == 3) ny = 1.0;
+            }
+        }
+        x = nx;
+        y = ny;
+        if (side >= 0) {
+            const double w_tn = (double)(k + 1) * dt / I.tau;
+            const double tang = side < 2 ? y : x;
+            out.vx = boundary_d(I.bnd0, I.bnd1, I.n_xi, I.n_eta, side, 0, tang, w_tn);
+            out.vy = boundary_d(I.bnd0, I.bnd1, I.n_xi, I.n_eta, side, 1, tang, w_tn);
+            out.side = side;
+            out.steps = k + 1;
+            break;
+        }
+    }
+    if (out.side < 0) {
+        out.vx = keys_d(I.xpad, I.n_xi, I.n_eta, x, y);
+        out.vy = keys_d(I.ypad, I.n_xi, I.n_eta, x, y);
+    }
+    if (I.per_xi) out.vx += (double)wx * I.Lx;
+    if (I.per_eta) out.vy += (double)wy * I.Ly;
+    return out;
+}
+
+__global__ __launch_bounds__(kFp64Block) void paths_fp64(const InstView *__restrict__ inst, uint32_t n_paths,
+                                                         uint32_t chunks, Partial *__restrict__ partials)
+{
+    const InstView &I = *inst;
+    const uint32_t node = blockIdx.x / chunks;
+    const uint32_t chunk = blockIdx.x - node * chunks;
+    const uint32_t path = chunk * kFp64Block + threadIdx.x;
+    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (path < n_paths) {
+        const PathOutD o = run_path_f64<false>(I, node, path, nullptr);
+        const int i0 = I.node_i[node], j0 = I.node_j[node];
+        const double dx = o.vx - I.x64[(size_t)j0 * I.n_xi + i0];
+        const double dy = o.vy - I.y64[(size_t)j0 * I.n_xi + i0];
+        v[0] = dx;
+        v[1] = dx * dx;
+        v[2] = dy;
+        v[3] = dy * dy;
+        v[4] = o.side >= 0 ? 1.0 : 0.0;
+        v[5] = (double)o.steps;
+    }
+    // fixed-order tree reduction over the block
+    __shared__ double red[6][kFp64Block];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) red[c][threadIdx.x] = v[c];
+    __syncthreads();
+    for (int s = kFp64Block / 2; s >= 1; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        Partial &o = partials[blockIdx.x];
+        o.s1x = red[0][0];
+        o.s2x = red[1][0];
+        o.s1y = red[2][0];
+        o.s2y = red[3][0];
+        o.exits = (unsigned long long)red[4][0];
+        o.steps = (unsigned long long)red[5][0];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Finalize (a9)
+// ---------------------------------------------------------------------------
+__global__ void finalize_kernel(const Partial *__restrict__ partials, const NodeSpan *__restrict__ spans,
+                                const InstView *__restrict__ inst, uint32_t M, uint64_t n_paths,
+                                double *mean_x, double *mean_y, double *se_x, double *se_y, double *exit_frac,
+                                unsigned long long *steps_total)
+{
+    const uint32_t node = blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long my_steps = 0;
+    if (node < M) {
+        const InstView &I = *inst;
+        const NodeSpan sp = spans[node];
+        double s1x = 0.0, s2x = 0.0, s1y = 0.0, s2y = 0.0;
+        unsigned long long ex = 0;
+        for (uint32_t c = 0; c < sp.count; ++c) {
+            const Partial &p = partials[sp.first + c];
+            s1x += p.s1x;
+            s2x += p.s2x;
+            s1y += p.s1y;
+            s2y += p.s2y;
+            ex += p.exits;
+            my_steps += p.steps;
+        }
+        const int i0 = I.node_i[node], j0 = I.node_j[node];
+        const double N = (double)n_paths;
+        mean_x[node] = I.x64[(size_t)j0 * I.n_xi + i0] + s1x / N;
+        mean_y[node] = I.y64[(size_t)j0 * I.n_xi + i0] + s1y / N;
+        if (n_paths > 1) {
+            const double vx = (s2x - s1x * s1x / N) / (N - 1.0);
+            const double vy = (s2y - s1y * s1y / N) / (N - 1.0);
+            se_x[node] = sqrt(fmax(vx, 0.0) / N);
+            se_y[node] = sqrt(fmax(vy, 0.0) / N);
+        } else {
+            se_x[node] = __longlong_as_double(0x7FF8000000000000ll);
+            se_y[node] = __longlong_as_double(0x7FF8000000000000ll);
+        }
+        exit_frac[node] = (double)ex / N;
+    }
+    // one atomic per wave for the executed-step total
+    my_steps = wave_sum_u64(my_steps);
+    if ((threadIdx.x & 63) == 0 && my_steps) atomicAdd(steps_total, my_steps);
+}
+
+// ---------------------------------------------------------------------------
+// Table and mesh preparation (a0, a7 set-up)
+// ---------------------------------------------------------------------------
+__global__ void prep_gradient_kernel(const double *__restrict__ in, int n_xi, int n_eta, int per_xi, int per_eta,
+                                     double *rho, double *rx, double *ry)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n_xi * n_eta) return;
+    int i = idx % n_xi, j = idx / n_xi;
+    // the image node of a periodic axis carries node 0's values
+    if (per_xi && i == n_xi - 1) i = 0;
+    if (per_eta && j == n_eta - 1) j = 0;
+    const double hx = 1.0 / (double)(n_xi - 1), hy = 1.0 / (double)(n_eta - 1);
+    auto at = [&](int a, int b) { return in[(size_t)b * n_xi + a]; };
+    double gx, gy;
+    if (per_xi) {
+        const int m = n_xi - 1;
+        gx = (at((i + 1) % m, j) - at((i + m - 1) % m, j)) / (2.0 * hx);
+    } else if (i == 0) {
+        gx = (-3.0 * at(0, j) + 4.0 * at(1, j) - at(2, j)) / (2.0 * hx);
+    } else if (i == n_xi - 1) {
+        gx = (3.0 * at(i, j) - 4.0 * at(i - 1, j) + at(i - 2, j)) / (2.0 * hx);
+    } else {
+        gx = (at(i + 1, j) - at(i - 1, j)) / (2.0 * hx);
+    }
+    if (per_eta) {
+        const int m = n_eta - 1;
+        gy = (at(i, (j + 1) % m) - at(i, (j + m - 1) % m)) / (2.0 * hy);
+    } else if (j == 0) {
+        gy = (-3.0 * at(i, 0) + 4.0 * at(i, 1) - at(i, 2)) / (2.0 * hy);
+    } else if (j == n_eta - 1) {
+        gy = (3.0 * at(i, j) - 4.0 * at(i, j - 1) + at(i, j - 2)) / (2.0 * hy);
+    } else {
+        gy = (at(i, j + 1) - at(i, j - 1)) / (2.0 * hy);
+    }
+    rho[idx] = at(i, j);
+    rx[idx] = gx;
+    ry[idx] = gy;
+}
+
+__global__ void prep_cells_kernel(const double *__restrict__ rho, const double *__restrict__ rx,
+                                  const double *__restrict__ ry, int n_xi, int n_eta, float4 *cells)
+{
+    const int nx1 = n_xi - 1, ny1 = n_eta - 1;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nx1 * ny1) return;
+    const int cx = idx % nx1, cy = idx / nx1;
+    const size_t a = (size_t)cy * n_xi + cx, b = a + n_xi;
+    const double *f[3] = {rho, rx, ry};
+    for (int c = 0; c < 3; ++c) {
+        const double f00 = f[c][a], f10 = f[c][a + 1], f01 = f[c][b], f11 = f[c][b + 1];
+        cells[3 * (size_t)idx + c] = make_float4((float)f00, (float)(f10 - f00), (float)(f01 - f00),
+                                                 (float)(f11 - f10 - f01 + f00));
+    }
+}
+
+// Weights and node indices that express padded node `a` (in [-1, n]) as a
+// combination of real nodes along one axis; `period` receives the number of
+// periods crossed on a periodic axis.
+__device__ int pad_stencil(int a, int n, int periodic, int idx[3], double wt[3], int &period)
+{
+    period = 0;
+    if (periodic) {
+        const int m = n - 1;
+        int q = 0;
+        while (a < 0) { a += m; --q; }
+        while (a >= m) { a -= m; ++q; }
+        period = q;
+        idx[0] = a;
+        wt[0] = 1.0;
+        return 1;
+    }
+    if (a < 0) {
+        idx[0] = 0; idx[1] = 1; idx[2] = 2;
+        wt[0] = 3.0; wt[1] = -3.0; wt[2] = 1.0;
+        return 3;
+    }
+    if (a > n - 1) {
+        idx[0] = n - 1; idx[1] = n - 2; idx[2] = n - 3;
+        wt[0] = 3.0; wt[1] = -3.0; wt[2] = 1.0;
+        return 3;
+    }
+    idx[0] = a;
+    wt[0] = 1.0;
+    return 1;
+}
+
+__global__ void prep_mesh_kernel(const double *__restrict__ x, const double *__restrict__ y, int n_xi, int n_eta,
+                                 int per_xi, int per_eta, double Lx, double Ly, double *xpad, double *ypad,
+                                 float *xpad_f, float *ypad_f)
+{
+    const int px = n_xi + 2, py = n_eta + 2;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= px * py) return;
+    const int a = idx % px - 1, b = idx / px - 1;
+    int ia[3], jb[3], qa, qb;
+    double wa[3], wb[3];
+    const int na = pad_stencil(a, n_xi, per_xi, ia, wa, qa);
+    const int nb = pad_stencil(b, n_eta, per_eta, jb, wb, qb);
+    double vx = 0.0, vy = 0.0;
+    for (int s = 0; s < nb; ++s)
+        for (int r = 0; r < na; ++r) {
+            const size_t o = (size_t)jb[s] * n_xi + ia[r];
+            vx += wb[s] * wa[r] * x[o];
+            vy += wb[s] * wa[r] * y[o];
+        }
+    vx += (double)qa * Lx;   // x winds along xi (periodic axis only: qa = 0 otherwise)
+    vy += (double)qb * Ly;   // y winds along eta
+    xpad[idx] = vx;
+    ypad[idx] = vy;
+    xpad_f[idx] = (float)vx;
+    ypad_f[idx] = (float)vy;
+}
+
+__global__ void to_f32_kernel(const double *__restrict__ in, float *out, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (float)in[i];
+}
+
+__global__ void fill_u32_kernel(uint32_t *p, uint32_t v, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Diagnostics: one path per thread
+// ---------------------------------------------------------------------------
+__global__ void debug_paths_kernel(const InstView *__restrict__ inst, int fp64, uint32_t node, uint32_t p_begin,
+                                   uint32_t count, double *vx, double *vy, int32_t *exited, int32_t *side_out,
+                                   int32_t *steps, double *trace)
+{
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count) return;
+    const InstView &I = *inst;
+    const uint32_t path = p_begin + t;
+    double *tr = trace ? trace + (size_t)t * 4 * I.K : nullptr;
+    if (fp64) {
+        const PathOutD o = tr ? run_path_f64<true>(I, node, path, tr) : run_path_f64<false>(I, node, path, nullptr);
+        vx[t] = o.vx;
+        vy[t] = o.vy;
+        exited[t] = o.side >= 0;
+        side_out[t] = o.side;
+        steps[t] = o.steps;
+        return;
+    }
+    const ConstF C = load_const_f(I);
+    const int i0 = I.node_i[node], j0 = I.node_j[node];
+    PathF P{(float)((double)i0 / (double)C.nx1), (float)((double)j0 / (double)C.ny1), 0, 0, 0};
+    int side = -1;
+    bool ended = false;
+    while (!ended) {
+        side = tr ? group_f32<true>(P, C, path, node, I.ctr3, I.key0, I.key1, ended, tr)
+                  : group_f32<false>(P, C, path, node, I.ctr3, I.key0, I.key1, ended, nullptr);
+    }
+    float fx, fy;
+    path_value_f32(I, C, P, side, fx, fy);
+    vx[t] = fx;
+    vy[t] = fy;
+    exited[t] = side >= 0;
+    side_out[t] = side;
+    steps[t] = P.k;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+static inline unsigned blocks_for(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
+
+hipError_t launch_prep_gradient(const double *rho_in, int n_xi, int n_eta, int per_xi, int per_eta, double *rho,
+                                double *rho_xi, double *rho_eta, hipStream_t s)
+{
+    const size_t n = (size_t)n_xi * n_eta;
+    hipLaunchKernelGGL(prep_gradient_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, rho_in, n_xi, n_eta, per_xi,
+                       per_eta, rho, rho_xi, rho_eta);
+    return hipGetLastError();
+}
+
+hipError_t launch_prep_cells(const double *rho, const double *rho_xi, const double *rho_eta, int n_xi, int n_eta,
+                             float4 *cells, hipStream_t s)
+{
+    const size_t n = (size_t)(n_xi - 1) * (n_eta - 1);
+    hipLaunchKernelGGL(prep_cells_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, rho, rho_xi, rho_eta, n_xi,
+                       n_eta, cells);
+    return hipGetLastError();
+}
+
+hipError_t launch_prep_mesh(const double *x, const double *y, int n_xi, int n_eta, int per_xi, int per_eta, double Lx,
+                            double Ly, double *xpad, double *ypad, float *xpad_f, float *ypad_f, hipStream_t s)
+{
+    const size_t n = (size_t)(n_xi + 2) * (n_eta + 2);
+    hipLaunchKernelGGL(prep_mesh_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, x, y, n_xi, n_eta, per_xi,
+                       per_eta, Lx, Ly, xpad, ypad, xpad_f, ypad_f);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_f32(const double *in, float *out, size_t n, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(to_f32_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, in, out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, value, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_paths_fp32(const InstView *insts, const WorkItem *items, uint32_t n_items, uint32_t *head,
+                             int grid, int block, hipStream_t s)
+{
+    hipError_t e = launch_fill_u32(head, 0u, 1, s);
+    if (e != hipSuccess) return e;
+    if (n_items == 0) return hipSuccess;
+    switch (block) {
+    case 64:
+        hipLaunchKernelGGL(paths_fp32<64>, dim3(grid), dim3(64), 0, s, insts, items, n_items, head);
+        break;
+    case 128:
+        hipLaunchKernelGGL(paths_fp32<128>, dim3(grid), dim3(128), 0, s, insts, items, n_items, head);
+        break;
+    case 256:
+        hipLaunchKernelGGL(paths_fp32<256>, dim3(grid), dim3(256), 0, s, insts, items, n_items, head);
+        break;
+    case 512:
+        hipLaunchKernelGGL(paths_fp32<512>, dim3(grid), dim3(512), 0, s, insts, items, n_items, head);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_paths_fp64(const InstView *inst, uint32_t M, uint32_t n_paths, uint32_t chunks_per_node,
+                             Partial *partials, hipStream_t s)
+{
+    const size_t blocks = (size_t)M * chunks_per_node;
+    if (blocks == 0) return hipSuccess;
+    if (blocks > 0x7FFFFFFFu) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(paths_fp64, dim3((unsigned)blocks), dim3(kFp64Block), 0, s, inst, n_paths, chunks_per_node,
+                       partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const Partial *partials, const NodeSpan *spans, const InstView *inst, uint32_t M,
+                           uint64_t n_paths, double *mean_x, double *mean_y, double *se_x, double *se_y,
+                           double *exit_frac, unsigned long long *steps_total, hipStream_t s)
+{
+    if (M == 0) return hipSuccess;
+    hipLaunchKernelGGL(finalize_kernel, dim3(blocks_for(M, 256)), dim3(256), 0, s, partials, spans, inst, M, n_paths,
+                       mean_x, mean_y, se_x, se_y, exit_frac, steps_total);
+    return hipGetLastError();
+}
+
+hipError_t launch_debug_paths(const InstView *inst, int fp64, uint32_t node, uint32_t p_begin, uint32_t count,
+                              double *vx, double *vy, int32_t *exited, int32_t *side, int32_t *steps, double *trace,
+                              hipStream_t s)
+{
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(debug_paths_kernel, dim3(blocks_for(count, 64)), dim3(64), 0, s, inst, fp64, node, p_begin,
+                       count, vx, vy, exited, side, steps, trace);
+    return hipGetLastError();
+}
+
+int paths_fp32_blocks_per_cu(int block)
+{
+    int n = 0;
+    hipError_t e = hipErrorInvalidValue;
+    switch (block) {
+    case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32<64>, 64, 0); break;
+    case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32<128>, 128, 0); break;
+    case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32<256>, 256, 0); break;
+    case 512: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32<512>, 512, 0); break;
+    default: break;
+    }
+    return e == hipSuccess ? n : 0;
+}
+
+int paths_fp32_attributes(int block, int *vgprs, int *sgprs, int *lds_bytes)
+{
+    hipFuncAttributes a;
+    hipError_t e = hipErrorInvalidValue;
+    switch (block) {
+    case 64: e = hipFuncGetAttributes(&a, reinterpret_cast<const void *>(paths_fp32<64>)); break;
+    case 128: e = hipFuncGetAttributes(&a, reinterpret_cast<const void *>(paths_fp32<128>)); break;
+    case 256: e = hipFuncGetAttributes(&a, reinterpret_cast<const void *>(paths_fp32<256>)); break;
+    case 512: e = hipFuncGetAttributes(&a, reinterpret_cast<const void *>(paths_fp32<512>)); break;
+    default: break;
+    }
+    if (e != hipSuccess) return -1;
+    if (vgprs) *vgprs = a.numRegs;
+    if (sgprs) *sgprs = 0;
+    if (lds_bytes) *lds_bytes = (int)a.sharedSizeBytes;
+    return 0;
+}
+
+}  // namespace msdd

@@ -1,0 +1,73 @@
+// Device-visible records shared by the host runtime and the HIP kernels of
+// the interface-node Monte-Carlo solver (paper section 3.4-3.6).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace msdd {
+
+// A unit of work of the batched kernel: paths [p_begin, p_begin + p_count)
+// of interface node `node` of instance slot `inst`; the sums go to
+// partials[partial].
+struct WorkItem {
+    uint32_t inst;
+    uint32_t node;
+    uint32_t p_begin;
+    uint32_t p_count;
+    uint32_t partial;
+    uint32_t pad[3];
+};
+
+// Shifted sums of one (node, chunk): S1 = sum(v - v_ref), S2 = sum((v - v_ref)^2).
+struct Partial {
+    double s1x, s2x, s1y, s2y;
+    unsigned long long exits;
+    unsigned long long steps;
+};
+
+// One problem instance as the kernels see it.  All pointers are device
+// addresses owned by the instance.  Grids are row-major [n_eta][n_xi].
+struct InstView {
+    int32_t n_xi, n_eta;          // nodes per axis
+    int32_t per_xi, per_eta;      // periodic flags
+    int32_t K;                    // substeps
+    int32_t bridge;               // Brownian-bridge test on/off
+    int32_t M;                    // interface nodes
+    int32_t pad0;
+    uint32_t key0, key1;          // Philox key (seed low / high word)
+    uint32_t ctr3;                // instance_id << 16 | mesh_step & 0xffff
+    uint32_t pad1;
+    double Lx, Ly, tau, dt;       // extents, mesh step, substep
+    float Lx_f, Ly_f, dt_f, sq2dt_f, inv_dt_f, inv_tau_f, pad2, pad3;
+
+    const int32_t *node_i, *node_j;   // interface nodes in rank order
+
+    // FP32 path: per-cell bilinear coefficients (three float4 per cell:
+    // rho, rho_xi, rho_eta as a + b tx + c ty + d tx ty), (n_xi-1)(n_eta-1)
+    // cells; padded mesh [n_eta+2][n_xi+2] with ghost / wrapped values,
+    // origin at node (-1, -1); boundary arrays in the C-ABI layout.
+    const float4 *cells;
+    const float *xpad_f, *ypad_f;
+    const float *bnd0_f, *bnd1_f;
+
+    // FP64 path: node tables rho, rho_xi, rho_eta; padded mesh; boundary.
+    const double *rho, *rho_xi, *rho_eta;
+    const double *xpad, *ypad;
+    const double *bnd0, *bnd1;
+
+    // FP64 mesh at t^n (for the reference values of the shifted sums).
+    const double *x64, *y64;
+
+    // Partial sums of this request's work items.
+    Partial *partials;
+};
+
+// Per-node finalize descriptor: the partials of one node are
+// partials[first .. first + count) in chunk order.
+struct NodeSpan {
+    uint32_t first;
+    uint32_t count;
+};
+
+}  // namespace msdd

@@ -1,0 +1,58 @@
+// Host-callable launchers of the HIP kernels (defined in kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "msdd_device.hpp"
+
+namespace msdd {
+
+// a0: finite-difference gradient of the frozen monitor (section 3.4) into
+// FP64 node tables; on a periodic axis node n-1 receives node 0's values.
+hipError_t launch_prep_gradient(const double *rho_in, int n_xi, int n_eta, int per_xi, int per_eta,
+                                double *rho, double *rho_xi, double *rho_eta, hipStream_t s);
+
+// a0 (FP32 path): per-cell bilinear coefficients of (rho, rho_xi, rho_eta).
+hipError_t launch_prep_cells(const double *rho, const double *rho_xi, const double *rho_eta, int n_xi,
+                             int n_eta, float4 *cells, hipStream_t s);
+
+// a7 set-up: padded mesh [n_eta+2][n_xi+2] (ghost rows / columns by Keys'
+// rule on Dirichlet axes, wrapped with quasi-periodic offsets on periodic
+// axes) in FP64 and FP32, for x (offset Lx along xi) and y (Ly along eta).
+hipError_t launch_prep_mesh(const double *x, const double *y, int n_xi, int n_eta, int per_xi, int per_eta,
+                            double Lx, double Ly, double *xpad, double *ypad, float *xpad_f, float *ypad_f,
+                            hipStream_t s);
+
+hipError_t launch_to_f32(const double *in, float *out, size_t n, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t s);
+
+// a2-a8, FP32: persistent batched kernel over a work queue.  `head` is the
+// queue counter (zeroed by this launcher); item sums go to
+// insts[item.inst].partials[item.partial].
+hipError_t launch_paths_fp32(const InstView *insts, const WorkItem *items, uint32_t n_items, uint32_t *head,
+                             int grid, int block, hipStream_t s);
+
+// a2-a8, FP64 plain: one thread per path, one launch per instance; the
+// partial of (node, chunk) goes to partials[node * chunks + chunk].
+hipError_t launch_paths_fp64(const InstView *inst, uint32_t M, uint32_t n_paths, uint32_t chunks_per_node,
+                             Partial *partials, hipStream_t s);
+constexpr int kFp64Block = 256;
+
+// a9: fixed-order combine of each node's partials; mean, SE, exit fraction.
+hipError_t launch_finalize(const Partial *partials, const NodeSpan *spans, const InstView *inst, uint32_t M,
+                           uint64_t n_paths, double *mean_x, double *mean_y, double *se_x, double *se_y,
+                           double *exit_frac, unsigned long long *steps_total, hipStream_t s);
+
+// Diagnostics: one path per thread with the FP32 or FP64 path arithmetic.
+hipError_t launch_debug_paths(const InstView *inst, int fp64, uint32_t node, uint32_t p_begin, uint32_t count,
+                              double *vx, double *vy, int32_t *exited, int32_t *side, int32_t *steps,
+                              double *trace, hipStream_t s);
+
+// Occupancy of the FP32 kernel: resident workgroups per CU for `block`.
+int paths_fp32_blocks_per_cu(int block);
+// Register / LDS usage of the FP32 kernel for `block` (for reports).
+int paths_fp32_attributes(int block, int *vgprs, int *sgprs, int *lds_bytes);
+
+}  // namespace msdd

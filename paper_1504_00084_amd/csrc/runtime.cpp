@@ -1,0 +1,1341 @@
+// Host runtime behind the C-ABI of include/mesh_sdd.h: contexts, problem
+// instances, requests (one interface solve each, paper section 3.4-3.6),
+// the work-queue builder, the autotuner of the batched FP32 kernel, and the
+// continuous-batching scheduler that serves submit/poll.
+//
+// Data flow of one request:
+//   host/device inputs --(copy, snapshot)--> FP64 staging (mesh, boundary)
+//   --prep kernels--> padded meshes (FP64 + FP32), FP32 boundary
+//   --path kernel (FP32 batched or FP64 plain)--> per-(node, chunk) partials
+//   --finalize kernel--> mean, SE, exit fraction per interface node
+//   --copy--> caller's result arrays.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "mesh_sdd.h"
+#include "msdd_device.hpp"
+#include "msdd_kernels.hpp"
+
+using msdd::InstView;
+using msdd::NodeSpan;
+using msdd::Partial;
+using msdd::WorkItem;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                                     \
+    do {                                                                                                  \
+        hipError_t e_ = (expr);                                                                           \
+        if (e_ != hipSuccess) return fail(MESH_SDD_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+using Clock = std::chrono::steady_clock;
+
+double ms_since(Clock::time_point t0)
+{
+    return std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+}
+
+// Device allocation owned by one object.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    hipError_t alloc(size_t n)
+    {
+        release();
+        if (n == 0) n = 16;
+        hipError_t e = hipMalloc(&p, n);
+        if (e == hipSuccess)
+            bytes = n;
+        else
+            p = nullptr;
+        return e;
+    }
+    // grow-only reuse
+    hipError_t reserve(size_t n)
+    {
+        if (n <= bytes && p) return hipSuccess;
+        return alloc(n);
+    }
+    template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Objects behind the opaque handles
+// ---------------------------------------------------------------------------
+struct Request;
+
+struct mesh_sdd {
+    mesh_sdd_ctx *ctx = nullptr;
+    mesh_sdd_desc d{};
+    int32_t M = 0;
+    std::vector<int32_t> node_i, node_j;
+    DevBuf dev_i, dev_j;                    // interface nodes
+    DevBuf rho_in, rho, rho_xi, rho_eta;    // FP64 monitor staging and node tables
+    DevBuf cells;                           // FP32 per-cell bilinear coefficients
+    bool monitor_set = false;
+    std::atomic<int> inflight{0};
+    size_t resident_bytes = 0;
+};
+
+struct Request {
+    uint64_t ticket = 0;
+    mesh_sdd *inst = nullptr;
+    int64_t N = 0;
+    uint32_t mesh_step = 0;
+    int chunk_paths = 0;
+    // host snapshots of host inputs
+    std::vector<double> hx, hy, hb0, hb1;
+    // device buffers owned by the request
+    DevBuf x64, y64, b0, b1, xpad, ypad, xpad_f, ypad_f, b0f, b1f;
+    DevBuf view, partials, spans, out, steps_total;
+    InstView v{};
+    std::vector<WorkItem> items;   // FP32 work (partial index = node-major chunk slot)
+    size_t next_item = 0;          // first item not yet handed to a tick
+    size_t done_items = 0;
+    uint32_t chunks_per_node = 0;
+    size_t cost_bytes = 0;
+    // completion
+    int status = MESH_SDD_PENDING;
+    std::string error;
+    std::vector<double> host_out;  // 5 * M
+    uint64_t executed_steps = 0;
+    double device_ms = 0.0;
+    Clock::time_point t_submit, t_done;
+    bool finished = false;
+    bool admitted = false;
+    bool cancelled = false;
+};
+
+struct TuneKey {
+    int n_xi, n_eta, per_xi, per_eta;
+    bool operator<(const TuneKey &o) const
+    {
+        return std::tie(n_xi, n_eta, per_xi, per_eta) < std::tie(o.n_xi, o.n_eta, o.per_xi, o.per_eta);
+    }
+};
+
+struct mesh_sdd_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int cu_count = 0;
+    size_t budget = 0;
+
+    std::mutex gpu_mu;   // serialises use of the stream and the launch scratch below
+    DevBuf head, views, items;
+
+    std::mutex mu;       // guards everything below
+    std::condition_variable cv, done_cv;
+    size_t in_use = 0;
+    int n_instances = 0;
+    std::deque<std::shared_ptr<Request>> queue;    // submitted, not admitted
+    std::vector<std::shared_ptr<Request>> running; // admitted, not finished
+    std::unordered_map<uint64_t, std::shared_ptr<Request>> tickets;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    std::thread worker;
+
+    // stats
+    uint64_t submitted = 0, completed = 0, failed = 0, cancelled = 0, ticks = 0, executed = 0;
+    double busy_ms = 0.0;
+    std::vector<double> latencies;
+
+    // launch shapes
+    bool has_override = false;
+    mesh_sdd_launch override_launch{};
+    std::map<TuneKey, mesh_sdd_launch> tuned;
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Validation and interface nodes (a1)
+// ---------------------------------------------------------------------------
+int validate_desc(const mesh_sdd_desc *d)
+{
+    if (!d) return fail(MESH_SDD_E_INVAL, "descriptor is NULL");
+    if (d->struct_size != sizeof(mesh_sdd_desc))
+        return fail(MESH_SDD_E_INVAL, "desc.struct_size %u != %zu", d->struct_size, sizeof(mesh_sdd_desc));
+    if (d->n_xi < 4 || d->n_eta < 4 || d->n_xi > 8193 || d->n_eta > 8193)
+        return fail(MESH_SDD_E_INVAL, "grid %d x %d outside [4, 8193]", d->n_xi, d->n_eta);
+    if (d->sub_xi < 1 || d->sub_eta < 1 || (d->n_xi - 1) % d->sub_xi || (d->n_eta - 1) % d->sub_eta)
+        return fail(MESH_SDD_E_INVAL, "(n-1) %% sub != 0: n = (%d, %d), sub = (%d, %d)", d->n_xi, d->n_eta,
+                    d->sub_xi, d->sub_eta);
+    if ((d->periodic_xi != 0 && d->periodic_xi != 1) || (d->periodic_eta != 0 && d->periodic_eta != 1))
+        return fail(MESH_SDD_E_INVAL, "periodic flags must be 0 or 1");
+    if (d->K < 1 || d->K > (1 << 28)) return fail(MESH_SDD_E_INVAL, "K = %d outside [1, 2^28]", d->K);
+    if (!(d->tau > 0.0) || !std::isfinite(d->tau)) return fail(MESH_SDD_E_INVAL, "tau must be > 0");
+    if (!(d->Lx > 0.0) || !(d->Ly > 0.0) || !std::isfinite(d->Lx) || !std::isfinite(d->Ly))
+        return fail(MESH_SDD_E_INVAL, "Lx, Ly must be > 0");
+    if (d->precision != MESH_SDD_FP32 && d->precision != MESH_SDD_FP64)
+        return fail(MESH_SDD_E_INVAL, "precision must be MESH_SDD_FP32 or MESH_SDD_FP64");
+    if (d->bridge != 0 && d->bridge != 1) return fail(MESH_SDD_E_INVAL, "bridge must be 0 or 1");
+    if (d->instance_id >= 65536u) return fail(MESH_SDD_E_INVAL, "instance_id %u >= 65536", d->instance_id);
+    return MESH_SDD_OK;
+}
+
+// Interface nodes (section 3.5): a multiple of the subdomain width on either
+// axis, not on a Dirichlet side; on a periodic axis the image node n-1 is
+// skipped and the seam (index 0) belongs to the interfaces.  Row-major (j, i).
+void enumerate_nodes(const mesh_sdd_desc &d, std::vector<int32_t> &ni, std::vector<int32_t> &nj)
+{
+    const int wx = (d.n_xi - 1) / d.sub_xi, wy = (d.n_eta - 1) / d.sub_eta;
+    const int j_lo = d.periodic_eta ? 0 : 1, j_hi = d.n_eta - 2;   // inclusive
+    const int i_lo = d.periodic_xi ? 0 : 1, i_hi = d.n_xi - 2;
+    ni.clear();
+    nj.clear();
+    for (int j = j_lo; j <= j_hi; ++j) {
+        const bool row_line = (j % wy) == 0;
+        for (int i = i_lo; i <= i_hi; ++i) {
+            if (row_line || (i % wx) == 0) {
+                ni.push_back(i);
+                nj.push_back(j);
+            }
+        }
+    }
+}
+
+size_t instance_bytes(const mesh_sdd_desc &d, int M)
+{
+    const size_t n = (size_t)d.n_xi * d.n_eta;
+    const size_t cells = (size_t)(d.n_xi - 1) * (d.n_eta - 1);
+    return 4 * n * sizeof(double) + 3 * cells * sizeof(float4) + 2 * (size_t)M * sizeof(int32_t);
+}
+
+int64_t resolve_paths(const mesh_sdd &inst, const mesh_sdd_step &s)
+{
+    if (s.target_se > 0.0) {
+        const double L = std::max(inst.d.Lx, inst.d.Ly);
+        const double n = std::ceil(2.0 * inst.d.tau * L * L / (s.target_se * s.target_se));
+        const int64_t cap = s.max_paths > 0 ? s.max_paths : 1000000;
+        return std::max<int64_t>(2, std::min<int64_t>(cap, (int64_t)n));
+    }
+    return s.paths_per_node;
+}
+
+int validate_step(const mesh_sdd &inst, const mesh_sdd_step *s, int64_t *N_out)
+{
+    if (!s) return fail(MESH_SDD_E_INVAL, "step is NULL");
+    if (s->struct_size != sizeof(mesh_sdd_step))
+        return fail(MESH_SDD_E_INVAL, "step.struct_size %u != %zu", s->struct_size, sizeof(mesh_sdd_step));
+    if (!s->x_cur || !s->y_cur || !s->bnd_t0 || !s->bnd_t1)
+        return fail(MESH_SDD_E_INVAL, "step input pointer is NULL");
+    if (s->target_se < 0.0 || !std::isfinite(s->target_se)) return fail(MESH_SDD_E_INVAL, "target_se < 0");
+    const int64_t N = resolve_paths(inst, *s);
+    if (N < 1 || N > (int64_t)1 << 31) return fail(MESH_SDD_E_INVAL, "paths per node %lld outside [1, 2^31]", (long long)N);
+    *N_out = N;
+    if (s->inputs_on_device) return MESH_SDD_OK;   // device inputs are not inspected
+    const mesh_sdd_desc &d = inst.d;
+    const size_t n = (size_t)d.n_xi * d.n_eta;
+    const size_t nb = 4 * (size_t)d.n_eta + 4 * (size_t)d.n_xi;
+    for (size_t k = 0; k < n; ++k)
+        if (!std::isfinite(s->x_cur[k]) || !std::isfinite(s->y_cur[k]))
+            return fail(MESH_SDD_E_INVAL, "mesh value %zu is not finite", k);
+    for (size_t k = 0; k < nb; ++k)
+        if (!std::isfinite(s->bnd_t0[k]) || !std::isfinite(s->bnd_t1[k]))
+            return fail(MESH_SDD_E_INVAL, "boundary value %zu is not finite", k);
+    if (!d.periodic_xi && !d.periodic_eta) {
+        // the four corners belong to two sides each; their values must agree
+        const double tol = 1e-12 * (d.Lx + d.Ly);
+        const double *levels[2] = {s->bnd_t0, s->bnd_t1};
+        const size_t ne = d.n_eta, nx = d.n_xi;
+        for (int l = 0; l < 2; ++l) {
+            const double *b = levels[l];
+            for (int c = 0; c < 2; ++c) {
+                const double *s0 = b + (0 * 2 + c) * ne, *s1 = b + (1 * 2 + c) * ne;
+                const double *s2 = b + 4 * ne + (0 * 2 + c) * nx, *s3 = b + 4 * ne + (1 * 2 + c) * nx;
+                const double pairs[4][2] = {{s0[0], s2[0]}, {s0[ne - 1], s3[0]}, {s1[0], s2[nx - 1]},
+                                            {s1[ne - 1], s3[nx - 1]}};
+                for (auto &p : pairs)
+                    if (std::fabs(p[0] - p[1]) > tol)
+                        return fail(MESH_SDD_E_INVAL, "boundary corner values disagree (%g vs %g)", p[0], p[1]);
+            }
+        }
+    }
+    return MESH_SDD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Launch shape
+// ---------------------------------------------------------------------------
+mesh_sdd_launch default_launch()
+{
+    mesh_sdd_launch l{};
+    l.struct_size = sizeof(mesh_sdd_launch);
+    l.block = 256;
+    l.waves_per_simd = 0;   // 0: as many as the registers allow
+    l.chunk_paths = 1024;
+    l.table_in_lds = 0;
+    return l;
+}
+
+mesh_sdd_launch launch_for(mesh_sdd_ctx *ctx, const mesh_sdd_desc &d)
+{
+    std::lock_guard<std::mutex> g(ctx->mu);
+    if (ctx->has_override) return ctx->override_launch;
+    auto it = ctx->tuned.find(TuneKey{d.n_xi, d.n_eta, d.periodic_xi, d.periodic_eta});
+    if (it != ctx->tuned.end()) return it->second;
+    return default_launch();
+}
+
+int grid_for(mesh_sdd_ctx *ctx, const mesh_sdd_launch &l)
+{
+    const int waves_per_block = l.block / 64;
+    int per_cu = msdd::paths_fp32_blocks_per_cu(l.block);   // resident blocks per CU
+    if (per_cu < 1) per_cu = 1;
+    if (l.waves_per_simd > 0) {
+        const int want = std::max(1, (l.waves_per_simd * 4) / waves_per_block);
+        per_cu = std::min(per_cu, want);
+    }
+    return std::max(1, ctx->cu_count * per_cu);
+}
+
+// ---------------------------------------------------------------------------
+// Requests
+// ---------------------------------------------------------------------------
+size_t request_bytes(const mesh_sdd &inst, int64_t N, int chunk)
+{
+    const mesh_sdd_desc &d = inst.d;
+    const size_t n = (size_t)d.n_xi * d.n_eta;
+    const size_t np = (size_t)(d.n_xi + 2) * (d.n_eta + 2);
+    const size_t nb = 4 * (size_t)d.n_eta + 4 * (size_t)d.n_xi;
+    size_t chunks;
+    if (d.precision == MESH_SDD_FP64)
+        chunks = (size_t)((N + msdd::kFp64Block - 1) / msdd::kFp64Block);
+    else
+        chunks = (size_t)((N + chunk - 1) / chunk);
+    return 2 * n * 8 + 2 * np * 12 + 2 * nb * 12 + (size_t)inst.M * chunks * sizeof(Partial) +
+           (size_t)inst.M * (sizeof(NodeSpan) + 5 * sizeof(double)) + sizeof(InstView) + 64;
+}
+
+// Snapshot host inputs (the caller may free them once submit returns).
+std::shared_ptr<Request> make_request(mesh_sdd *inst, const mesh_sdd_step &s, int64_t N)
+{
+    auto r = std::make_shared<Request>();
+    r->inst = inst;
+    r->N = N;
+    r->mesh_step = s.mesh_step;
+    r->chunk_paths = std::max(64, launch_for(inst->ctx, inst->d).chunk_paths / 64 * 64);
+    r->cost_bytes = request_bytes(*inst, N, r->chunk_paths);
+    const size_t n = (size_t)inst->d.n_xi * inst->d.n_eta;
+    const size_t nb = 4 * (size_t)inst->d.n_eta + 4 * (size_t)inst->d.n_xi;
+    if (!s.inputs_on_device) {
+        r->hx.assign(s.x_cur, s.x_cur + n);
+        r->hy.assign(s.y_cur, s.y_cur + n);
+        r->hb0.assign(s.bnd_t0, s.bnd_t0 + nb);
+        r->hb1.assign(s.bnd_t1, s.bnd_t1 + nb);
+    }
+    return r;
+}
+
+// Allocate the request's device buffers, stage its inputs and run the prep
+// kernels; builds the work items.  Caller holds gpu_mu.
+int stage_request(Request &r, const mesh_sdd_step *dev_step)
+{
+    mesh_sdd &inst = *r.inst;
+    mesh_sdd_ctx *ctx = inst.ctx;
+    const mesh_sdd_desc &d = inst.d;
+    hipStream_t st = ctx->stream;
+    const size_t n = (size_t)d.n_xi * d.n_eta;
+    const size_t np = (size_t)(d.n_xi + 2) * (d.n_eta + 2);
+    const size_t nb = 4 * (size_t)d.n_eta + 4 * (size_t)d.n_xi;
+    const int M = inst.M;
+    const bool fp64 = d.precision == MESH_SDD_FP64;
+
+    uint32_t chunks;
+    if (fp64)
+        chunks = (uint32_t)((r.N + msdd::kFp64Block - 1) / msdd::kFp64Block);
+    else
+        chunks = (uint32_t)((r.N + r.chunk_paths - 1) / r.chunk_paths);
+    r.chunks_per_node = chunks;
+    const size_t n_part = (size_t)M * chunks;
+
+    if (r.x64.alloc(n * 8) || r.y64.alloc(n * 8) || r.b0.alloc(nb * 8) || r.b1.alloc(nb * 8) ||
+        r.xpad.alloc(np * 8) || r.ypad.alloc(np * 8) || r.xpad_f.alloc(np * 4) || r.ypad_f.alloc(np * 4) ||
+        r.b0f.alloc(nb * 4) || r.b1f.alloc(nb * 4) || r.view.alloc(sizeof(InstView)) ||
+        r.partials.alloc(n_part * sizeof(Partial)) || r.spans.alloc((size_t)M * sizeof(NodeSpan)) ||
+        r.out.alloc((size_t)5 * M * sizeof(double)) || r.steps_total.alloc(sizeof(unsigned long long)))
+        return fail(MESH_SDD_E_NOMEM, "device allocation for a request failed");
+
+    if (dev_step) {
+        HIP_TRY(hipMemcpyAsync(r.x64.p, dev_step->x_cur, n * 8, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipMemcpyAsync(r.y64.p, dev_step->y_cur, n * 8, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipMemcpyAsync(r.b0.p, dev_step->bnd_t0, nb * 8, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipMemcpyAsync(r.b1.p, dev_step->bnd_t1, nb * 8, hipMemcpyDeviceToDevice, st));
+    } else {
+        HIP_TRY(hipMemcpyAsync(r.x64.p, r.hx.data(), n * 8, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(r.y64.p, r.hy.data(), n * 8, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(r.b0.p, r.hb0.data(), nb * 8, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(r.b1.p, r.hb1.data(), nb * 8, hipMemcpyHostToDevice, st));
+    }
+    HIP_TRY(msdd::launch_prep_mesh(r.x64.as<double>(), r.y64.as<double>(), d.n_xi, d.n_eta, d.periodic_xi,
+                                   d.periodic_eta, d.Lx, d.Ly, r.xpad.as<double>(), r.ypad.as<double>(),
+                                   r.xpad_f.as<float>(), r.ypad_f.as<float>(), st));
+    HIP_TRY(msdd::launch_to_f32(r.b0.as<double>(), r.b0f.as<float>(), nb, st));
+    HIP_TRY(msdd::launch_to_f32(r.b1.as<double>(), r.b1f.as<float>(), nb, st));
+
+    // kernel view
+    InstView &v = r.v;
+    std::memset(&v, 0, sizeof v);
+    v.n_xi = d.n_xi;
+    v.n_eta = d.n_eta;
+    v.per_xi = d.periodic_xi;
+    v.per_eta = d.periodic_eta;
+    v.K = d.K;
+    v.bridge = d.bridge;
+    v.M = M;
+    v.key0 = (uint32_t)(d.seed & 0xFFFFFFFFu);
+    v.key1 = (uint32_t)(d.seed >> 32);
+    v.ctr3 = (d.instance_id << 16) | (r.mesh_step & 0xFFFFu);
+    v.Lx = d.Lx;
+    v.Ly = d.Ly;
+    v.tau = d.tau;
+    v.dt = d.tau / (double)d.K;
+    v.Lx_f = (float)d.Lx;
+    v.Ly_f = (float)d.Ly;
+    v.dt_f = (float)v.dt;
+    v.sq2dt_f = (float)std::sqrt(2.0 * v.dt);
+    v.inv_dt_f = (float)(1.0 / v.dt);
+    v.inv_tau_f = (float)(1.0 / d.tau);
+    v.node_i = inst.dev_i.as<int32_t>();
+    v.node_j = inst.dev_j.as<int32_t>();
+    v.cells = inst.cells.as<float4>();
+    v.xpad_f = r.xpad_f.as<float>();
+    v.ypad_f = r.ypad_f.as<float>();
+    v.bnd0_f = r.b0f.as<float>();
+    v.bnd1_f = r.b1f.as<float>();
+    v.rho = inst.rho.as<double>();
+    v.rho_xi = inst.rho_xi.as<double>();
+    v.rho_eta = inst.rho_eta.as<double>();
+    v.xpad = r.xpad.as<double>();
+    v.ypad = r.ypad.as<double>();
+    v.bnd0 = r.b0.as<double>();
+    v.bnd1 = r.b1.as<double>();
+    v.x64 = r.x64.as<double>();
+    v.y64 = r.y64.as<double>();
+    v.partials = r.partials.as<Partial>();
+    HIP_TRY(hipMemcpyAsync(r.view.p, &v, sizeof v, hipMemcpyHostToDevice, st));
+
+    // node spans: node-major chunk slots
+    std::vector<NodeSpan> spans((size_t)M);
+    for (int m = 0; m < M; ++m) spans[m] = NodeSpan{(uint32_t)((size_t)m * chunks), chunks};
+    if (M) HIP_TRY(hipMemcpyAsync(r.spans.p, spans.data(), spans.size() * sizeof(NodeSpan), hipMemcpyHostToDevice, st));
+    HIP_TRY(msdd::launch_fill_u32(r.steps_total.as<uint32_t>(), 0u, 2, st));
+
+    // FP32 work items: every (node, chunk); chunk c of every node before
+    // chunk c+1 so that concurrent waves spread over the nodes.
+    r.items.clear();
+    if (!fp64) {
+        r.items.reserve(n_part);
+        for (uint32_t c = 0; c < chunks; ++c) {
+            const uint32_t p0 = c * (uint32_t)r.chunk_paths;
+            const uint32_t cnt = (uint32_t)std::min<int64_t>(r.chunk_paths, r.N - (int64_t)p0);
+            for (int m = 0; m < M; ++m) {
+                WorkItem w{};
+                w.inst = 0;
+                w.node = (uint32_t)m;
+                w.p_begin = p0;
+                w.p_count = cnt;
+                w.partial = (uint32_t)((size_t)m * chunks + c);
+                r.items.push_back(w);
+            }
+        }
+    }
+    r.next_item = 0;
+    r.done_items = 0;
+    // the host snapshots are no longer needed once the copies are done
+    HIP_TRY(hipStreamSynchronize(st));
+    std::vector<double>().swap(r.hx);
+    std::vector<double>().swap(r.hy);
+    std::vector<double>().swap(r.hb0);
+    std::vector<double>().swap(r.hb1);
+    return MESH_SDD_OK;
+}
+
+void release_request_buffers(Request &r)
+{
+    for (DevBuf *b : {&r.x64, &r.y64, &r.b0, &r.b1, &r.xpad, &r.ypad, &r.xpad_f, &r.ypad_f, &r.b0f, &r.b1f,
+                      &r.view, &r.partials, &r.spans, &r.out, &r.steps_total})
+        b->release();
+}
+
+// One persistent FP32 launch over `items` (inst fields index `views`).
+// Caller holds gpu_mu.  Returns the device time in ms via *ms.
+int run_fp32_launch(mesh_sdd_ctx *ctx, const std::vector<InstView> &views, const std::vector<WorkItem> &items,
+                    const mesh_sdd_launch &l, double *ms)
+{
+    hipStream_t st = ctx->stream;
+    if (items.empty()) {
+        *ms = 0.0;
+        return MESH_SDD_OK;
+    }
+    if (ctx->views.reserve(views.size() * sizeof(InstView)) || ctx->items.reserve(items.size() * sizeof(WorkItem)) ||
+        ctx->head.reserve(64))
+        return fail(MESH_SDD_E_NOMEM, "device allocation for the work queue failed");
+    HIP_TRY(hipMemcpyAsync(ctx->views.p, views.data(), views.size() * sizeof(InstView), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(ctx->items.p, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice, st));
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipEventRecord(e0, st));
+    hipError_t le = msdd::launch_paths_fp32(ctx->views.as<InstView>(), ctx->items.as<WorkItem>(),
+                                            (uint32_t)items.size(), ctx->head.as<uint32_t>(), grid_for(ctx, l),
+                                            l.block, st);
+    HIP_TRY(hipEventRecord(e1, st));
+    hipError_t se = hipEventSynchronize(e1);
+    float t = 0.0f;
+    (void)hipEventElapsedTime(&t, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (le != hipSuccess) return fail(MESH_SDD_E_DEVICE, "path kernel launch failed: %s", hipGetErrorString(le));
+    if (se != hipSuccess) return fail(MESH_SDD_E_DEVICE, "path kernel failed: %s", hipGetErrorString(se));
+    *ms = t;
+    return MESH_SDD_OK;
+}
+
+// FP64 plain launch of one request.  Caller holds gpu_mu.
+int run_fp64_launch(mesh_sdd_ctx *ctx, Request &r, double *ms)
+{
+    hipStream_t st = ctx->stream;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipEventRecord(e0, st));
+    hipError_t le = msdd::launch_paths_fp64(r.view.as<InstView>(), (uint32_t)r.inst->M, (uint32_t)r.N,
+                                            r.chunks_per_node, r.partials.as<Partial>(), st);
+    HIP_TRY(hipEventRecord(e1, st));
+    hipError_t se = hipEventSynchronize(e1);
+    float t = 0.0f;
+    (void)hipEventElapsedTime(&t, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (le != hipSuccess) return fail(MESH_SDD_E_DEVICE, "FP64 path kernel launch failed: %s", hipGetErrorString(le));
+    if (se != hipSuccess) return fail(MESH_SDD_E_DEVICE, "FP64 path kernel failed: %s", hipGetErrorString(se));
+    *ms = t;
+    return MESH_SDD_OK;
+}
+
+// Finalize (a9) into the request's output buffer and copy it to the host.
+int finalize_request(mesh_sdd_ctx *ctx, Request &r)
+{
+    hipStream_t st = ctx->stream;
+    const int M = r.inst->M;
+    double *o = r.out.as<double>();
+    HIP_TRY(msdd::launch_finalize(r.partials.as<Partial>(), r.spans.as<NodeSpan>(), r.view.as<InstView>(),
+                                  (uint32_t)M, (uint64_t)r.N, o, o + M, o + 2 * (size_t)M, o + 3 * (size_t)M,
+                                  o + 4 * (size_t)M, r.steps_total.as<unsigned long long>(), st));
+    r.host_out.resize((size_t)5 * M);
+    unsigned long long steps = 0;
+    if (M) HIP_TRY(hipMemcpyAsync(r.host_out.data(), o, r.host_out.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(&steps, r.steps_total.p, sizeof steps, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    r.executed_steps = steps;
+    return MESH_SDD_OK;
+}
+
+int copy_result(mesh_sdd_ctx *ctx, const Request &r, mesh_sdd_result *res)
+{
+    if (!res) return MESH_SDD_OK;
+    if (res->struct_size != sizeof(mesh_sdd_result))
+        return fail(MESH_SDD_E_INVAL, "result.struct_size %u != %zu", res->struct_size, sizeof(mesh_sdd_result));
+    const int M = r.inst->M;
+    double *dst[5] = {res->mean_x, res->mean_y, res->se_x, res->se_y, res->exit_frac};
+    for (int k = 0; k < 5; ++k) {
+        if (!dst[k]) continue;
+        const double *src = r.host_out.data() + (size_t)k * M;
+        if (res->outputs_on_device) {
+            std::lock_guard<std::mutex> g(ctx->gpu_mu);
+            HIP_TRY(hipMemcpy(dst[k], src, (size_t)M * sizeof(double), hipMemcpyHostToDevice));
+        } else if (M) {
+            std::memcpy(dst[k], src, (size_t)M * sizeof(double));
+        }
+    }
+    res->executed_path_steps = r.executed_steps;
+    res->paths_per_node = r.N;
+    res->device_ms = r.device_ms;
+    return MESH_SDD_OK;
+}
+
+// Blocking path of one or several requests: FP32 ones share ONE launch.
+int run_blocking(mesh_sdd_ctx *ctx, std::vector<std::shared_ptr<Request>> &reqs,
+                 const std::vector<const mesh_sdd_step *> &dev_steps, std::vector<int> &status)
+{
+    std::lock_guard<std::mutex> g(ctx->gpu_mu);
+    status.assign(reqs.size(), MESH_SDD_OK);
+    std::vector<InstView> views;
+    std::vector<WorkItem> items;
+    std::vector<size_t> fp32_reqs;
+    mesh_sdd_launch l = default_launch();
+    bool have_launch = false;
+    for (size_t q = 0; q < reqs.size(); ++q) {
+        Request &r = *reqs[q];
+        int rc = stage_request(r, dev_steps[q]);
+        if (rc != MESH_SDD_OK) {
+            status[q] = rc;
+            r.error = g_last_error;
+            continue;
+        }
+        if (r.inst->d.precision == MESH_SDD_FP64) {
+            double ms = 0.0;
+            rc = run_fp64_launch(ctx, r, &ms);
+            if (rc == MESH_SDD_OK) rc = finalize_request(ctx, r);
+            r.device_ms = ms;
+            status[q] = rc;
+            if (rc != MESH_SDD_OK) r.error = g_last_error;
+        } else {
+            const uint32_t slot = (uint32_t)views.size();
+            views.push_back(r.v);
+            for (WorkItem w : r.items) {
+                w.inst = slot;
+                items.push_back(w);
+            }
+            fp32_reqs.push_back(q);
+            if (!have_launch) {
+                l = launch_for(ctx, r.inst->d);
+                have_launch = true;
+            }
+        }
+    }
+    if (!fp32_reqs.empty()) {
+        // longest items first (equal-size chunks keep their node-spread order)
+        std::stable_sort(items.begin(), items.end(),
+                         [](const WorkItem &a, const WorkItem &b) { return a.p_count > b.p_count; });
+        double ms = 0.0;
+        int rc = run_fp32_launch(ctx, views, items, l, &ms);
+        for (size_t q : fp32_reqs) {
+            Request &r = *reqs[q];
+            int rq = rc;
+            if (rq == MESH_SDD_OK) rq = finalize_request(ctx, r);
+            r.device_ms = ms;
+            status[q] = rq;
+            if (rq != MESH_SDD_OK) r.error = g_last_error;
+        }
+    }
+    for (auto &r : reqs) release_request_buffers(*r);
+    for (int s : status)
+        if (s != MESH_SDD_OK) return s;
+    return MESH_SDD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Serving scheduler: admission by HBM budget, chunk-granularity ticks.
+// ---------------------------------------------------------------------------
+constexpr double kTickPathSteps = 6.0e9;   // work per tick, ~tens of ms at full rate
+
+void finish_request(mesh_sdd_ctx *ctx, const std::shared_ptr<Request> &r, int status, const std::string &err)
+{
+    // ctx->mu held by caller
+    r->status = status;
+    r->error = err;
+    r->finished = true;
+    r->t_done = Clock::now();
+    if (r->admitted) ctx->in_use -= std::min(ctx->in_use, r->cost_bytes);
+    r->inst->inflight.fetch_sub(1);
+    if (status == MESH_SDD_OK) {
+        ++ctx->completed;
+        ctx->executed += r->executed_steps;
+        ctx->latencies.push_back(std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count());
+    } else if (status == MESH_SDD_E_CANCELLED) {
+        ++ctx->cancelled;
+    } else {
+        ++ctx->failed;
+    }
+    ctx->done_cv.notify_all();
+}
+
+void scheduler_loop(mesh_sdd_ctx *ctx)
+{
+    (void)hipSetDevice(ctx->device);
+    for (;;) {
+        std::vector<std::shared_ptr<Request>> to_admit;
+        {
+            std::unique_lock<std::mutex> lk(ctx->mu);
+            ctx->cv.wait(lk, [&] { return ctx->stop || !ctx->queue.empty() || !ctx->running.empty(); });
+            if (ctx->stop) break;
+            // admission in arrival order while the budget allows
+            while (!ctx->queue.empty()) {
+                auto &r = ctx->queue.front();
+                if (ctx->in_use + r->cost_bytes > ctx->budget && !ctx->running.empty()) break;
+                ctx->in_use += r->cost_bytes;
+                r->admitted = true;
+                to_admit.push_back(r);
+                ctx->running.push_back(r);
+                ctx->queue.pop_front();
+                if (ctx->in_use > ctx->budget) break;   // a lone request over budget never reaches here
+            }
+        }
+        // stage newly admitted requests (FP64 ones run whole, here)
+        for (auto &r : to_admit) {
+            int rc;
+            double ms = 0.0;
+            {
+                std::lock_guard<std::mutex> g(ctx->gpu_mu);
+                rc = stage_request(*r, nullptr);
+                if (rc == MESH_SDD_OK && r->inst->d.precision == MESH_SDD_FP64) {
+                    rc = run_fp64_launch(ctx, *r, &ms);
+                    if (rc == MESH_SDD_OK) rc = finalize_request(ctx, *r);
+                    r->device_ms = ms;
+                    release_request_buffers(*r);
+                }
+            }
+            // FP32 requests without work (no interface node) finish at once
+            const bool empty_fp32 = rc == MESH_SDD_OK && r->inst->d.precision == MESH_SDD_FP32 && r->items.empty();
+            if (empty_fp32) {
+                std::lock_guard<std::mutex> g(ctx->gpu_mu);
+                rc = finalize_request(ctx, *r);
+                release_request_buffers(*r);
+            }
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            ctx->busy_ms += ms;
+            if (rc != MESH_SDD_OK || r->inst->d.precision == MESH_SDD_FP64 || empty_fp32) {
+                ctx->running.erase(std::find(ctx->running.begin(), ctx->running.end(), r));
+                if (rc != MESH_SDD_OK) release_request_buffers(*r);
+                finish_request(ctx, r, rc, rc == MESH_SDD_OK ? std::string() : g_last_error);
+            }
+        }
+        // build one tick over the running FP32 requests: a fair share of the
+        // tick's work for each, at least one item each
+        std::vector<std::shared_ptr<Request>> in_tick;
+        std::vector<InstView> views;
+        std::vector<WorkItem> items;
+        std::vector<std::pair<std::shared_ptr<Request>, size_t>> taken;
+        {
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            size_t active = 0;
+            for (auto &r : ctx->running)
+                if (r->next_item < r->items.size()) ++active;
+            if (active == 0) continue;
+            const double share = kTickPathSteps / (double)active;
+            for (auto &r : ctx->running) {
+                if (r->next_item >= r->items.size()) continue;
+                const double per_item = (double)r->chunk_paths * (double)r->inst->d.K;
+                size_t take = (size_t)std::max(1.0, share / per_item);
+                take = std::min(take, r->items.size() - r->next_item);
+                const uint32_t slot = (uint32_t)views.size();
+                views.push_back(r->v);
+                for (size_t k = 0; k < take; ++k) {
+                    WorkItem w = r->items[r->next_item + k];
+                    w.inst = slot;
+                    items.push_back(w);
+                }
+                r->next_item += take;
+                taken.emplace_back(r, take);
+            }
+            ++ctx->ticks;
+        }
+        std::stable_sort(items.begin(), items.end(),
+                         [](const WorkItem &a, const WorkItem &b) { return a.p_count > b.p_count; });
+        double ms = 0.0;
+        int rc;
+        {
+            std::lock_guard<std::mutex> g(ctx->gpu_mu);
+            const mesh_sdd_launch l = launch_for(ctx, taken.front().first->inst->d);
+            rc = run_fp32_launch(ctx, views, items, l, &ms);
+        }
+        std::string err = rc == MESH_SDD_OK ? std::string() : g_last_error;
+        std::vector<std::shared_ptr<Request>> complete;
+        {
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            ctx->busy_ms += ms;
+            for (auto &t : taken) {
+                t.first->done_items += t.second;
+                t.first->device_ms += ms;
+                if (rc != MESH_SDD_OK || t.first->done_items == t.first->items.size()) complete.push_back(t.first);
+            }
+        }
+        for (auto &r : complete) {
+            int fr = rc;
+            if (fr == MESH_SDD_OK) {
+                std::lock_guard<std::mutex> g(ctx->gpu_mu);
+                fr = finalize_request(ctx, *r);
+            }
+            std::string e2 = fr == MESH_SDD_OK ? std::string() : (rc != MESH_SDD_OK ? err : g_last_error);
+            {
+                std::lock_guard<std::mutex> g(ctx->gpu_mu);
+                release_request_buffers(*r);
+            }
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            ctx->running.erase(std::find(ctx->running.begin(), ctx->running.end(), r));
+            finish_request(ctx, r, fr, e2);
+        }
+    }
+    // cancel whatever is left (buffers are freed without holding ctx->mu)
+    std::vector<std::shared_ptr<Request>> left;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        for (auto &r : ctx->queue) finish_request(ctx, r, MESH_SDD_E_CANCELLED, "context destroyed");
+        ctx->queue.clear();
+        left.swap(ctx->running);
+    }
+    {
+        std::lock_guard<std::mutex> g(ctx->gpu_mu);
+        for (auto &r : left) release_request_buffers(*r);
+    }
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    for (auto &r : left) finish_request(ctx, r, MESH_SDD_E_CANCELLED, "context destroyed");
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C-ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *mesh_sdd_last_error(void) { return g_last_error.c_str(); }
+
+const char *mesh_sdd_version(void) { return "mesh_sdd 0.1 (gfx950)"; }
+
+int mesh_sdd_ctx_create(int device, size_t hbm_budget_bytes, void *hip_stream, mesh_sdd_ctx **out)
+{
+    if (!out) return fail(MESH_SDD_E_INVAL, "out is NULL");
+    *out = nullptr;
+    int count = 0;
+    HIP_TRY(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count) return fail(MESH_SDD_E_INVAL, "device %d not in [0, %d)", device, count);
+    HIP_TRY(hipSetDevice(device));
+    auto ctx = std::make_unique<mesh_sdd_ctx>();
+    ctx->device = device;
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, device));
+    ctx->cu_count = prop.multiProcessorCount;
+    if (hip_stream) {
+        ctx->stream = static_cast<hipStream_t>(hip_stream);
+    } else {
+        HIP_TRY(hipStreamCreate(&ctx->stream));   // blocking: ordered after legacy default-stream work
+        ctx->own_stream = true;
+    }
+    if (hbm_budget_bytes == 0) {
+        size_t free_b = 0, total_b = 0;
+        HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+        hbm_budget_bytes = free_b / 10 * 9;
+    }
+    ctx->budget = hbm_budget_bytes;
+    mesh_sdd_ctx *raw = ctx.get();
+    try {
+        raw->worker = std::thread(scheduler_loop, raw);
+    } catch (...) {
+        if (raw->own_stream) (void)hipStreamDestroy(raw->stream);
+        return fail(MESH_SDD_E_NOMEM, "could not start the scheduler thread");
+    }
+    *out = ctx.release();
+    return MESH_SDD_OK;
+}
+
+int mesh_sdd_ctx_destroy(mesh_sdd_ctx *ctx)
+{
+    if (!ctx) return fail(MESH_SDD_E_INVAL, "ctx is NULL");
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        if (ctx->n_instances > 0) return fail(MESH_SDD_E_STATE, "%d instances still alive", ctx->n_instances);
+        ctx->stop = true;
+    }
+    ctx->cv.notify_all();
+    if (ctx->worker.joinable()) ctx->worker.join();
+    (void)hipSetDevice(ctx->device);
+    ctx->head.release();
+    ctx->views.release();
+    ctx->items.release();
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return MESH_SDD_OK;
+}
+
+int mesh_sdd_ctx_stats(mesh_sdd_ctx *ctx, mesh_sdd_stats *out)
+{
+    if (!ctx || !out) return fail(MESH_SDD_E_INVAL, "NULL argument");
+    if (out->struct_size != sizeof(mesh_sdd_stats))
+        return fail(MESH_SDD_E_INVAL, "stats.struct_size %u != %zu", out->struct_size, sizeof(mesh_sdd_stats));
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    out->submitted = ctx->submitted;
+    out->completed = ctx->completed;
+    out->failed = ctx->failed;
+    out->cancelled = ctx->cancelled;
+    out->queued = ctx->queue.size();
+    out->running = ctx->running.size();
+    out->ticks = ctx->ticks;
+    out->hbm_in_use = ctx->in_use;
+    out->hbm_budget = ctx->budget;
+    out->busy_ms = ctx->busy_ms;
+    out->executed_path_steps = ctx->executed;
+    std::vector<double> lat = ctx->latencies;
+    if (lat.empty()) {
+        out->p50_ms = out->p99_ms = out->mean_ms = 0.0;
+    } else {
+        std::sort(lat.begin(), lat.end());
+        auto pct = [&](double q) {
+            const double pos = q * (double)(lat.size() - 1);
+            const size_t a = (size_t)pos;
+            const size_t b = std::min(a + 1, lat.size() - 1);
+            return lat[a] + (pos - (double)a) * (lat[b] - lat[a]);
+        };
+        out->p50_ms = pct(0.50);
+        out->p99_ms = pct(0.99);
+        double s = 0.0;
+        for (double x : lat) s += x;
+        out->mean_ms = s / (double)lat.size();
+    }
+    return MESH_SDD_OK;
+}
+
+int mesh_sdd_set_launch(mesh_sdd_ctx *ctx, const mesh_sdd_launch *launch)
+{
+    if (!ctx) return fail(MESH_SDD_E_INVAL, "ctx is NULL");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (!launch) {
+        ctx->has_override = false;
+        return MESH_SDD_OK;
+    }
+    if (launch->struct_size != sizeof(mesh_sdd_launch))
+        return fail(MESH_SDD_E_INVAL, "launch.struct_size %u != %zu", launch->struct_size, sizeof(mesh_sdd_launch));
+    if (launch->block != 64 && launch->block != 128 && launch->block != 256 && launch->block != 512)
+        return fail(MESH_SDD_E_INVAL, "block must be 64, 128, 256 or 512");
+    if (launch->waves_per_simd < 0 || launch->waves_per_simd > 8)
+        return fail(MESH_SDD_E_INVAL, "waves_per_simd must be in [0, 8]");
+    if (launch->chunk_paths < 64 || launch->chunk_paths % 64 || launch->chunk_paths > (1 << 24))
+        return fail(MESH_SDD_E_INVAL, "chunk_paths must be a multiple of 64 in [64, 2^24]");
+    ctx->override_launch = *launch;
+    ctx->has_override = true;
+    return MESH_SDD_OK;
+}
+
+int mesh_sdd_get_launch(mesh_sdd *inst, mesh_sdd_launch *out)
+{
+    if (!inst || !out) return fail(MESH_SDD_E_INVAL, "NULL argument");
+    *out = launch_for(inst->ctx, inst->d);
+    if (out->waves_per_simd == 0) {
+        const int per_cu = msdd::paths_fp32_blocks_per_cu(out->block);
+        out->waves_per_simd = per_cu * (out->block / 64) / 4;
+    }
+    return MESH_SDD_OK;
+}
+
+int mesh_sdd_desc_check(const mesh_sdd_desc *desc) { return validate_desc(desc); }
+
+int mesh_sdd_desc_interface_nodes(const mesh_sdd_desc *desc, int32_t *i, int32_t *j)
+{
+    int rc = validate_desc(desc);
+    if (rc != MESH_SDD_OK) return rc;
+    std::vector<int32_t> ni, nj;
+    enumerate_nodes(*desc, ni, nj);
+    if (ni.size() > 0x7FFFFFFFu) return fail(MESH_SDD_E_INVAL, "too many interface nodes");
+    if (i && j && !ni.empty()) {
+        std::memcpy(i, ni.data(), ni.size() * 4);
+        std::memcpy(j, nj.data(), nj.size() * 4);
+    }
+    return (int)ni.size();
+}
+
+int mesh_sdd_create(mesh_sdd_ctx *ctx, const mesh_sdd_desc *desc, mesh_sdd **out)
+{
+    if (!ctx || !out) return fail(MESH_SDD_E_INVAL, "NULL argument");
+    *out = nullptr;
+    int rc = validate_desc(desc);
+    if (rc != MESH_SDD_OK) return rc;
+    auto inst = std::make_unique<mesh_sdd>();
+    inst->ctx = ctx;
+    inst->d = *desc;
+    enumerate_nodes(inst->d, inst->node_i, inst->node_j);
+    inst->M = (int32_t)inst->node_i.size();
+    inst->resident_bytes = instance_bytes(inst->d, inst->M);
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        if (inst->resident_bytes > ctx->budget)
+            return fail(MESH_SDD_E_BUDGET, "instance tables (%zu B) exceed the HBM budget (%zu B)",
+                        inst->resident_bytes, ctx->budget);
+    }
+    const size_t n = (size_t)desc->n_xi * desc->n_eta;
+    const size_t cells = (size_t)(desc->n_xi - 1) * (desc->n_eta - 1);
+    std::lock_guard<std::mutex> g(ctx->gpu_mu);
+    HIP_TRY(hipSetDevice(ctx->device));
+    if (inst->dev_i.alloc((size_t)inst->M * 4) || inst->dev_j.alloc((size_t)inst->M * 4) ||
+        inst->rho_in.alloc(n * 8) || inst->rho.alloc(n * 8) || inst->rho_xi.alloc(n * 8) ||
+        inst->rho_eta.alloc(n * 8) || inst->cells.alloc(cells * 3 * sizeof(float4)))
+        return fail(MESH_SDD_E_NOMEM, "device allocation for the instance tables failed");
+    if (inst->M) {
+        HIP_TRY(hipMemcpy(inst->dev_i.p, inst->node_i.data(), (size_t)inst->M * 4, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(inst->dev_j.p, inst->node_j.data(), (size_t)inst->M * 4, hipMemcpyHostToDevice));
+    }
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->in_use += inst->resident_bytes;
+        ++ctx->n_instances;
+    }
+    *out = inst.release();
+    return MESH_SDD_OK;
+}
+
+int mesh_sdd_destroy(mesh_sdd *inst)
+{
+    if (!inst) return fail(MESH_SDD_E_INVAL, "instance is NULL");
+    if (inst->inflight.load() > 0) return fail(MESH_SDD_E_STATE, "instance has requests in flight");
+    mesh_sdd_ctx *ctx = inst->ctx;
+    const size_t bytes = inst->resident_bytes;
+    {
+        std::lock_guard<std::mutex> g(ctx->gpu_mu);
+        (void)hipSetDevice(ctx->device);
+        delete inst;   // DevBuf destructors free the tables
+    }
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->in_use -= std::min(ctx->in_use, bytes);
+    --ctx->n_instances;
+    return MESH_SDD_OK;
+}
+
+int mesh_sdd_set_monitor(mesh_sdd *inst, const double *rho, int is_device_ptr)
+{
+    if (!inst || !rho) return fail(MESH_SDD_E_INVAL, "NULL argument");
+    const mesh_sdd_desc &d = inst->d;
+    const size_t n = (size_t)d.n_xi * d.n_eta;
+    if (!is_device_ptr) {
+        for (size_t k = 0; k < n; ++k)
+            if (!(rho[k] > 0.0) || !std::isfinite(rho[k]))
+                return fail(MESH_SDD_E_INVAL, "monitor value %zu is not a positive finite number", k);
+    }
+    if (inst->inflight.load() > 0) return fail(MESH_SDD_E_STATE, "instance has requests in flight");
+    mesh_sdd_ctx *ctx = inst->ctx;
+    std::lock_guard<std::mutex> g(ctx->gpu_mu);
+    hipStream_t st = ctx->stream;
+    HIP_TRY(hipMemcpyAsync(inst->rho_in.p, rho, n * 8, is_device_ptr ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+    HIP_TRY(msdd::launch_prep_gradient(inst->rho_in.as<double>(), d.n_xi, d.n_eta, d.periodic_xi, d.periodic_eta,
+                                       inst->rho.as<double>(), inst->rho_xi.as<double>(), inst->rho_eta.as<double>(), st));
+    HIP_TRY(msdd::launch_prep_cells(inst->rho.as<double>(), inst->rho_xi.as<double>(), inst->rho_eta.as<double>(),
+                                    d.n_xi, d.n_eta, inst->cells.as<float4>(), st));
+    HIP_TRY(hipStreamSynchronize(st));
+    inst->monitor_set = true;
+    return MESH_SDD_OK;
+}
+
+int mesh_sdd_num_interface_nodes(const mesh_sdd *inst)
+{
+    if (!inst) return fail(MESH_SDD_E_INVAL, "instance is NULL");
+    return inst->M;
+}
+
+int mesh_sdd_interface_nodes(const mesh_sdd *inst, int32_t *i, int32_t *j)
+{
+    if (!inst) return fail(MESH_SDD_E_INVAL, "instance is NULL");
+    if (inst->M && (!i || !j)) return fail(MESH_SDD_E_INVAL, "output array is NULL");
+    if (inst->M) {
+        std::memcpy(i, inst->node_i.data(), (size_t)inst->M * 4);
+        std::memcpy(j, inst->node_j.data(), (size_t)inst->M * 4);
+    }
+    return MESH_SDD_OK;
+}
+
+int mesh_sdd_solve_batch(mesh_sdd *const *insts, const mesh_sdd_step *steps, mesh_sdd_result *results,
+                         int32_t count, int32_t *status)
+{
+    if (count < 0 || (count > 0 && (!insts || !steps || !results))) return fail(MESH_SDD_E_INVAL, "bad batch arguments");
+    if (count == 0) return MESH_SDD_OK;
+    mesh_sdd_ctx *ctx = insts[0] ? insts[0]->ctx : nullptr;
+    if (!ctx) return fail(MESH_SDD_E_INVAL, "instance is NULL");
+    std::vector<std::shared_ptr<Request>> reqs;
+    std::vector<const mesh_sdd_step *> dev_steps;
+    std::vector<int> st((size_t)count, MESH_SDD_OK);
+    int first_err = MESH_SDD_OK;
+    std::string first_msg;
+    std::vector<int> idx;
+    for (int32_t q = 0; q < count; ++q) {
+        mesh_sdd *inst = insts[q];
+        int rc = MESH_SDD_OK;
+        int64_t N = 0;
+        if (!inst) rc = fail(MESH_SDD_E_INVAL, "instance %d is NULL", q);
+        else if (inst->ctx != ctx) rc = fail(MESH_SDD_E_INVAL, "instance %d belongs to another context", q);
+        else if (!inst->monitor_set) rc = fail(MESH_SDD_E_STATE, "set_monitor not called on instance %d", q);
+        else if (results[q].struct_size != sizeof(mesh_sdd_result)) rc = fail(MESH_SDD_E_INVAL, "result.struct_size mismatch");
+        if (rc == MESH_SDD_OK) rc = validate_step(*inst, &steps[q], &N);
+        if (rc != MESH_SDD_OK) {
+            st[q] = rc;
+            if (first_err == MESH_SDD_OK) {
+                first_err = rc;
+                first_msg = g_last_error;
+            }
+            continue;
+        }
+        inst->inflight.fetch_add(1);
+        reqs.push_back(make_request(inst, steps[q], N));
+        dev_steps.push_back(steps[q].inputs_on_device ? &steps[q] : nullptr);
+        idx.push_back(q);
+    }
+    std::vector<int> rst;
+    int rc = reqs.empty() ? MESH_SDD_OK : run_blocking(ctx, reqs, dev_steps, rst);
+    if (rc != MESH_SDD_OK && first_err == MESH_SDD_OK) {
+        first_err = rc;
+        first_msg = g_last_error;
+    }
+    for (size_t k = 0; k < reqs.size(); ++k) {
+        const int q = idx[k];
+        st[q] = rst[k];
+        if (rst[k] == MESH_SDD_OK) {
+            int c = copy_result(ctx, *reqs[k], &results[q]);
+            if (c != MESH_SDD_OK) {
+                st[q] = c;
+                if (first_err == MESH_SDD_OK) {
+                    first_err = c;
+                    first_msg = g_last_error;
+                }
+            }
+        }
+        reqs[k]->inst->inflight.fetch_sub(1);
+    }
+    if (status)
+        for (int32_t q = 0; q < count; ++q) status[q] = st[q];
+    if (first_err != MESH_SDD_OK) g_last_error = first_msg;
+    return first_err;
+}
+
+int mesh_sdd_solve_interfaces(mesh_sdd *inst, const mesh_sdd_step *step, mesh_sdd_result *result)
+{
+    if (!inst || !result) return fail(MESH_SDD_E_INVAL, "NULL argument");
+    int32_t st = 0;
+    mesh_sdd *one[1] = {inst};
+    return mesh_sdd_solve_batch(one, step, result, 1, &st);
+}
+
+int mesh_sdd_submit(mesh_sdd *inst, const mesh_sdd_step *step, mesh_sdd_ticket *ticket)
+{
+    if (!inst || !ticket) return fail(MESH_SDD_E_INVAL, "NULL argument");
+    if (!inst->monitor_set) return fail(MESH_SDD_E_STATE, "set_monitor not called");
+    int64_t N = 0;
+    int rc = validate_step(*inst, step, &N);
+    if (rc != MESH_SDD_OK) return rc;
+    mesh_sdd_ctx *ctx = inst->ctx;
+    auto r = make_request(inst, *step, N);
+    if (step->inputs_on_device) {
+        // snapshot device inputs to the host so the caller may reuse them at once
+        const size_t n = (size_t)inst->d.n_xi * inst->d.n_eta;
+        const size_t nb = 4 * (size_t)inst->d.n_eta + 4 * (size_t)inst->d.n_xi;
+        r->hx.resize(n);
+        r->hy.resize(n);
+        r->hb0.resize(nb);
+        r->hb1.resize(nb);
+        std::lock_guard<std::mutex> g(ctx->gpu_mu);
+        HIP_TRY(hipMemcpy(r->hx.data(), step->x_cur, n * 8, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(r->hy.data(), step->y_cur, n * 8, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(r->hb0.data(), step->bnd_t0, nb * 8, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(r->hb1.data(), step->bnd_t1, nb * 8, hipMemcpyDeviceToHost));
+    }
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        if (ctx->stop) return fail(MESH_SDD_E_CANCELLED, "context is shutting down");
+        if (r->cost_bytes > ctx->budget)
+            return fail(MESH_SDD_E_BUDGET, "request needs %zu B, budget is %zu B", r->cost_bytes, ctx->budget);
+        r->ticket = ctx->next_ticket++;
+        r->t_submit = Clock::now();
+        inst->inflight.fetch_add(1);
+        ctx->tickets[r->ticket] = r;
+        ctx->queue.push_back(r);
+        ++ctx->submitted;
+        *ticket = r->ticket;
+    }
+    ctx->cv.notify_all();
+    return MESH_SDD_OK;
+}
+
+static int poll_impl(mesh_sdd_ctx *ctx, mesh_sdd_ticket ticket, mesh_sdd_result *result, int64_t timeout_ms)
+{
+    if (!ctx) return fail(MESH_SDD_E_INVAL, "ctx is NULL");
+    std::shared_ptr<Request> r;
+    {
+        std::unique_lock<std::mutex> lk(ctx->mu);
+        auto it = ctx->tickets.find(ticket);
+        if (it == ctx->tickets.end()) return fail(MESH_SDD_E_INVAL, "unknown ticket %llu", (unsigned long long)ticket);
+        r = it->second;
+        if (!r->finished && timeout_ms != 0) {
+            auto pred = [&] { return r->finished; };
+            if (timeout_ms < 0)
+                ctx->done_cv.wait(lk, pred);
+            else
+                ctx->done_cv.wait_for(lk, std::chrono::milliseconds(timeout_ms), pred);
+        }
+        if (!r->finished) return MESH_SDD_PENDING;
+        ctx->tickets.erase(it);
+    }
+    if (r->status != MESH_SDD_OK) return fail(r->status, "%s", r->error.c_str());
+    return copy_result(ctx, *r, result);
+}
+
+int mesh_sdd_poll(mesh_sdd_ctx *ctx, mesh_sdd_ticket ticket, mesh_sdd_result *result)
+{
+    return poll_impl(ctx, ticket, result, 0);
+}
+
+int mesh_sdd_wait(mesh_sdd_ctx *ctx, mesh_sdd_ticket ticket, mesh_sdd_result *result, int64_t timeout_ms)
+{
+    return poll_impl(ctx, ticket, result, timeout_ms);
+}
+
+int mesh_sdd_cancel(mesh_sdd_ctx *ctx, mesh_sdd_ticket ticket)
+{
+    if (!ctx) return fail(MESH_SDD_E_INVAL, "ctx is NULL");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    auto it = ctx->tickets.find(ticket);
+    if (it == ctx->tickets.end()) return fail(MESH_SDD_E_INVAL, "unknown ticket");
+    auto r = it->second;
+    if (r->finished) return fail(MESH_SDD_E_STATE, "request already finished");
+    auto q = std::find(ctx->queue.begin(), ctx->queue.end(), r);
+    if (q == ctx->queue.end()) return fail(MESH_SDD_E_STATE, "request is already running");
+    ctx->queue.erase(q);
+    finish_request(ctx, r, MESH_SDD_E_CANCELLED, "cancelled");
+    return MESH_SDD_OK;
+}
+
+int mesh_sdd_autotune(mesh_sdd *inst, const mesh_sdd_step *step, mesh_sdd_launch *out)
+{
+    if (!inst || !step) return fail(MESH_SDD_E_INVAL, "NULL argument");
+    if (!inst->monitor_set) return fail(MESH_SDD_E_STATE, "set_monitor not called");
+    if (inst->d.precision != MESH_SDD_FP32) return fail(MESH_SDD_E_INVAL, "autotuning applies to the FP32 kernel");
+    int64_t N = 0;
+    int rc = validate_step(*inst, step, &N);
+    if (rc != MESH_SDD_OK) return rc;
+    mesh_sdd_ctx *ctx = inst->ctx;
+    // candidates: residency x chunk size, timed on a reduced path count
+    const int blocks[] = {256};
+    const int chunks[] = {256, 512, 1024, 2048};
+    const int max_waves = std::max(1, msdd::paths_fp32_blocks_per_cu(256) * 4 / 4);
+    std::vector<int> waves;
+    for (int w = 1; w <= max_waves; ++w) waves.push_back(w);
+    mesh_sdd_step s = *step;
+    s.target_se = 0.0;
+    s.paths_per_node = std::min<int64_t>(N, std::max<int64_t>(4096, 2000000 / std::max(1, inst->M)));
+    double best = 1e300;
+    mesh_sdd_launch best_l = default_launch();
+    bool saved_override;
+    mesh_sdd_launch saved_l;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        saved_override = ctx->has_override;
+        saved_l = ctx->override_launch;
+    }
+    for (int b : blocks)
+        for (int c : chunks)
+            for (int w : waves) {
+                mesh_sdd_launch l = default_launch();
+                l.block = b;
+                l.chunk_paths = c;
+                l.waves_per_simd = w;
+                {
+                    std::lock_guard<std::mutex> lk(ctx->mu);
+                    ctx->override_launch = l;
+                    ctx->has_override = true;
+                }
+                std::vector<std::shared_ptr<Request>> reqs{make_request(inst, s, s.paths_per_node)};
+                std::vector<const mesh_sdd_step *> ds{s.inputs_on_device ? &s : nullptr};
+                std::vector<int> st;
+                inst->inflight.fetch_add(1);
+                rc = run_blocking(ctx, reqs, ds, st);
+                inst->inflight.fetch_sub(1);
+                if (rc != MESH_SDD_OK) break;
+                const double rate_ms = reqs[0]->device_ms / std::max<double>(1.0, (double)reqs[0]->executed_steps);
+                if (rate_ms < best) {
+                    best = rate_ms;
+                    best_l = l;
+                }
+            }
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->has_override = saved_override;
+        ctx->override_launch = saved_l;
+        if (rc == MESH_SDD_OK)
+            ctx->tuned[TuneKey{inst->d.n_xi, inst->d.n_eta, inst->d.periodic_xi, inst->d.periodic_eta}] = best_l;
+    }
+    if (rc != MESH_SDD_OK) return rc;
+    if (out) *out = best_l;
+    return MESH_SDD_OK;
+}
+
+int mesh_sdd_debug_paths(mesh_sdd *inst, const mesh_sdd_step *step, int32_t node_rank, int64_t p_begin, int64_t p_end,
+                         double *vx, double *vy, int32_t *exited, int32_t *side, int32_t *steps, double *trace)
+{
+    if (!inst || !step || !vx || !vy || !exited || !side || !steps) return fail(MESH_SDD_E_INVAL, "NULL argument");
+    if (!inst->monitor_set) return fail(MESH_SDD_E_STATE, "set_monitor not called");
+    if (node_rank < 0 || node_rank >= inst->M) return fail(MESH_SDD_E_INVAL, "node rank %d outside [0, %d)", node_rank, inst->M);
+    if (p_begin < 0 || p_end < p_begin || p_end > ((int64_t)1 << 31) || p_end - p_begin > (1 << 20))
+        return fail(MESH_SDD_E_INVAL, "path range [%lld, %lld) invalid", (long long)p_begin, (long long)p_end);
+    int64_t N = 0;
+    int rc = validate_step(*inst, step, &N);
+    if (rc != MESH_SDD_OK) return rc;
+    mesh_sdd_ctx *ctx = inst->ctx;
+    const uint32_t count = (uint32_t)(p_end - p_begin);
+    auto r = make_request(inst, *step, std::max<int64_t>(1, count));
+    std::lock_guard<std::mutex> g(ctx->gpu_mu);
+    inst->inflight.fetch_add(1);
+    rc = stage_request(*r, step->inputs_on_device ? step : nullptr);
+    DevBuf dvx, dvy, dex, dsd, dst, dtr;
+    if (rc == MESH_SDD_OK && count) {
+        const size_t trace_n = trace ? (size_t)count * 4 * inst->d.K : 0;
+        if (dvx.alloc(count * 8) || dvy.alloc(count * 8) || dex.alloc(count * 4) || dsd.alloc(count * 4) ||
+            dst.alloc(count * 4) || (trace && dtr.alloc(trace_n * 8))) {
+            rc = fail(MESH_SDD_E_NOMEM, "device allocation failed");
+        } else {
+            hipStream_t s = ctx->stream;
+            hipError_t e = hipSuccess;
+            if (trace) e = hipMemcpyAsync(dtr.p, trace, trace_n * 8, hipMemcpyHostToDevice, s);
+            if (e == hipSuccess)
+                e = msdd::launch_debug_paths(r->view.as<InstView>(), inst->d.precision == MESH_SDD_FP64,
+                                             (uint32_t)node_rank, (uint32_t)p_begin, count, dvx.as<double>(),
+                                             dvy.as<double>(), dex.as<int32_t>(), dsd.as<int32_t>(),
+                                             dst.as<int32_t>(), trace ? dtr.as<double>() : nullptr, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e == hipSuccess) e = hipMemcpy(vx, dvx.p, count * 8, hipMemcpyDeviceToHost);
+            if (e == hipSuccess) e = hipMemcpy(vy, dvy.p, count * 8, hipMemcpyDeviceToHost);
+            if (e == hipSuccess) e = hipMemcpy(exited, dex.p, count * 4, hipMemcpyDeviceToHost);
+            if (e == hipSuccess) e = hipMemcpy(side, dsd.p, count * 4, hipMemcpyDeviceToHost);
+            if (e == hipSuccess) e = hipMemcpy(steps, dst.p, count * 4, hipMemcpyDeviceToHost);
+            if (e == hipSuccess && trace) e = hipMemcpy(trace, dtr.p, trace_n * 8, hipMemcpyDeviceToHost);
+            if (e != hipSuccess) rc = fail(MESH_SDD_E_DEVICE, "debug path kernel failed: %s", hipGetErrorString(e));
+        }
+    }
+    release_request_buffers(*r);
+    inst->inflight.fetch_sub(1);
+    return rc;
+}
+
+}  // extern "C"

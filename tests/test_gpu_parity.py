@@ -1,0 +1,151 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 CPU oracle on the
+same seeded inputs and the same Philox streams (paper section 3.4).
+
+Bars: the FP64 plain kernel within 1e-9 per node (rounding of libm vs the
+device math library only; far inside the 1e-5 target); the FP32 batched
+kernel within 1e-5 absolute per node on unit-square coordinates (scaled by
+L otherwise), with the number of FP32/FP64 exit-decision flips reported."""
+import numpy as np
+import pytest
+
+from paper_1504_00084_amd import workloads as W
+from gpu_helpers import compare, gpu_solve, oracle_solve, say
+
+pytestmark = pytest.mark.gpu
+
+_cache = {}
+
+
+@pytest.fixture(scope="module")
+def M():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1504_00084_amd import mesh_sdd
+    mesh_sdd.load()      # raises if the HIP library was not built
+    return mesh_sdd
+
+
+@pytest.fixture(scope="module")
+def ctx(M):
+    c = M.mesh_sdd_ctx_create(0)
+    yield c
+    M.mesh_sdd_ctx_destroy(c)
+
+
+def cfg1_oracle(oracle_lib):
+    if "cfg1" not in _cache:
+        inst = W.config1()
+        say("oracle: bump33 2x1, 31 nodes, N=1e4, K=500")
+        _cache["cfg1"] = (inst, oracle_solve(oracle_lib, inst))
+    return _cache["cfg1"]
+
+
+def test_fp64_plain_matches_oracle_bump33(M, ctx, oracle_lib):
+    inst, ora = cfg1_oracle(oracle_lib)
+    say("gpu fp64: bump33 2x1 full size")
+    g = gpu_solve(M, ctx, inst, M.FP64)
+    assert g["paths_per_node"] == 10_000
+    s = compare(g, ora, label="fp64 bump33")
+    assert s["err"] <= 1e-9
+    assert s["se_err"] <= 1e-9
+    assert s["flips"] <= 1
+    assert g["executed_path_steps"] == int(np.sum(ora["steps"]))
+
+
+def test_fp32_batched_matches_oracle_bump33(M, ctx, oracle_lib):
+    inst, ora = cfg1_oracle(oracle_lib)
+    say("gpu fp32: bump33 2x1 full size")
+    g = gpu_solve(M, ctx, inst, M.FP32)
+    s = compare(g, ora, label="fp32 bump33")
+    assert s["err"] <= 1e-5
+    assert s["se_err"] <= 1e-5
+    # executed steps agree up to the few paths whose exit decision flipped
+    assert abs(g["executed_path_steps"] - int(np.sum(ora["steps"]))) <= 1e-5 * np.sum(ora["steps"])
+
+
+SMALL_CASES = {
+    # name: (n_xi, n_eta, sub_xi, sub_eta, per_xi, per_eta, K, N, tau, Lx, Ly, monitor)
+    "bump17_dir_2x2": (17, 17, 2, 2, 0, 0, 60, 3000, 0.02, 1.0, 1.0, "bump"),
+    "front33_perx_4x4": (33, 33, 4, 4, 1, 0, 50, 2000, 0.01, 1.0, 1.0, "front"),
+    "bump33_pery_4x2": (33, 33, 4, 2, 0, 1, 45, 1500, 0.01, 2.0, 0.5, "bump"),
+    "front17_perxy_2x2": (17, 17, 2, 2, 1, 1, 37, 1000, 0.02, 1.0, 1.0, "front"),
+    "ragged31x13_3x4": (31, 13, 3, 4, 0, 0, 33, 1111, 0.01, 1.5, 1.0, "bump"),
+    "k1_bump9": (9, 9, 2, 2, 0, 0, 1, 777, 0.002, 1.0, 1.0, "bump"),
+}
+
+
+def small_instance(name):
+    n_xi, n_eta, sx, sy, px, py, K, N, tau, Lx, Ly, mon = SMALL_CASES[name]
+    x, y = W.uniform_mesh(n_xi, n_eta, Lx, Ly)
+    if mon == "bump":
+        ux, uy = W.gaussian_bump_grad(x / Lx, y / Ly, 0.45, 0.55, 0.02)
+        rho = W.arc_length_monitor(ux, uy, 10.0)
+    else:
+        ux, uy = W.tanh_front_grad(x / Lx, y / Ly, 0.0, 0.05)
+        rho = W.arc_length_monitor(ux, uy, 1.0)
+    # a perturbed (non-uniform) mesh, consistent with the periodic images
+    xi = np.arange(n_xi) / (n_xi - 1)
+    eta = np.arange(n_eta) / (n_eta - 1)
+    XI, ETA = np.meshgrid(xi, eta)
+    x = x + 0.01 * Lx * np.sin(2 * np.pi * XI) * np.sin(np.pi * ETA if not py else 2 * np.pi * ETA)
+    y = y + 0.01 * Ly * np.sin(np.pi * XI if not px else 2 * np.pi * XI) * np.sin(2 * np.pi * ETA)
+    b0 = W.boundary_from_mesh(x, y)
+    # boundary data one mesh step later: moved along eta when eta is periodic
+    # (the xi sides then have no corners), unchanged otherwise
+    b1 = W.boundary_from_mesh(x + (0.003 * Lx * np.sin(2 * np.pi * ETA) if py else 0.0), y)
+    inst = W.Instance(name, n_xi, n_eta, sx, sy, px, py, Lx, Ly, tau, K, N, rho, x, y, b0, b1,
+                      seed=0xABCDEF0123 + n_xi, instance_id=7, mesh_step=3)
+    return inst
+
+
+@pytest.mark.parametrize("name", sorted(SMALL_CASES))
+def test_small_cases_both_precisions(M, ctx, oracle_lib, name):
+    inst = small_instance(name)
+    say("case %s: grid %dx%d sub %dx%d per (%d,%d) K=%d N=%d" % (name, inst.n_xi, inst.n_eta, inst.sub_xi,
+                                                                 inst.sub_eta, inst.periodic_xi, inst.periodic_eta,
+                                                                 inst.K, inst.n_paths))
+    ora = oracle_solve(oracle_lib, inst)
+    g64 = gpu_solve(M, ctx, inst, M.FP64)
+    s64 = compare(g64, ora, label=name + " fp64")
+    assert s64["err"] <= 1e-9 * max(inst.Lx, inst.Ly)
+    g32 = gpu_solve(M, ctx, inst, M.FP32)
+    s32 = compare(g32, ora, label=name + " fp32")
+    assert s32["err"] <= 1e-5 * max(inst.Lx, inst.Ly)
+
+
+def test_trajectories_match_oracle(M, ctx, oracle_lib):
+    """Tiny brute force: N = 4 paths, K = 5 substeps, per-substep positions
+    and normals of the GPU debug kernel against the oracle's."""
+    for name in ("bump17_dir_2x2", "front33_perx_4x4"):
+        inst = small_instance(name)
+        inst.K = 5
+        inst.tau = 0.02
+        P = oracle_lib.Problem(**inst.problem_kwargs())
+        h = M.mesh_sdd_create(ctx, M.desc_for(inst, M.FP64))
+        try:
+            M.mesh_sdd_set_monitor(h, inst.rho)
+            st = M.make_step(inst.x, inst.y, inst.bnd_t0, inst.bnd_t1, paths_per_node=4, mesh_step=inst.mesh_step)
+            for node in (0, 3):
+                o = oracle_lib.paths(P, inst.rho, inst.x, inst.y, inst.bnd_t0, inst.bnd_t1, node, 0, 4, trace=True)
+                g = M.mesh_sdd_debug_paths(h, st, node, 0, 4, inst.K, trace=True)
+                mask = ~np.isnan(o["trace"])
+                assert np.array_equal(mask, ~np.isnan(g["trace"]))
+                assert np.max(np.abs(o["trace"][mask] - g["trace"][mask])) < 1e-12
+                assert np.array_equal(o["side"], g["side"]) and np.array_equal(o["steps"], g["steps"])
+                assert np.max(np.abs(o["vx"] - g["vx"])) < 1e-12 and np.max(np.abs(o["vy"] - g["vy"])) < 1e-12
+        finally:
+            M.mesh_sdd_destroy(h)
+        h = M.mesh_sdd_create(ctx, M.desc_for(inst, M.FP32))
+        try:
+            M.mesh_sdd_set_monitor(h, inst.rho)
+            st = M.make_step(inst.x, inst.y, inst.bnd_t0, inst.bnd_t1, paths_per_node=4, mesh_step=inst.mesh_step)
+            o = oracle_lib.paths(P, inst.rho, inst.x, inst.y, inst.bnd_t0, inst.bnd_t1, 1, 0, 4, trace=True)
+            g = M.mesh_sdd_debug_paths(h, st, 1, 0, 4, inst.K, trace=True)
+            mask = ~np.isnan(o["trace"]) & ~np.isnan(g["trace"])
+            d = np.abs(o["trace"][mask] - g["trace"][mask])
+            say("fp32 trace max diff %.3e" % d.max())
+            assert d.max() < 1e-5
+            assert np.array_equal(o["side"], g["side"])
+        finally:
+            M.mesh_sdd_destroy(h)
