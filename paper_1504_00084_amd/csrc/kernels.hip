@@ -399,14 +399,25 @@ __device__ __forceinline__ void run_item_f32(const InstView &I, const WorkItem &
     s2y = wave_sum(s2y);
     exits = wave_sum_u64(exits);
     steps = wave_sum_u64(steps);
-    if (lane == 0) {
-        out->s1x = s1x;
-        out->s2x = s2x;
-        out->s1y = s1y;
-        out->s2y = s2y;
-        out->exits = exits;
-        out->steps = steps;
-    }
+    // Every lane holds the same totals after the butterfly and stores them:
+    // no lane-conditional branch is left next to the item loop, which the
+    // compiler could otherwise merge with the pop of the next item into a
+    // path where lane 0 leaves the loop that the others keep shuffling in.
+    out->s1x = s1x;
+    out->s2x = s2x;
+    out->s1y = s1y;
+    out->s2y = s2y;
+    out->exits = exits;
+    out->steps = steps;
+}
+
+// Next item of the queue for the whole wave.  Every lane takes part in the
+// atomic (lane 0 adds 1, the others 0), so the pop has no lane-conditional
+// branch; lane 0's old value is the wave's item.
+__device__ __forceinline__ uint32_t pop_item(uint32_t *head, int lane)
+{
+    const uint32_t old = atomicAdd(head, lane == 0 ? 1u : 0u);
+    return __builtin_amdgcn_readfirstlane(old);
 }
 
 template <int BLOCK>
@@ -415,14 +426,12 @@ __global__ __launch_bounds__(BLOCK) void paths_fp32(const InstView *__restrict__
                                                     uint32_t *__restrict__ head)
 {
     const int lane = threadIdx.x & 63;
-    for (;;) {
-        uint32_t it = 0;
-        if (lane == 0) it = atomicAdd(head, 1u);
-        it = __builtin_amdgcn_readfirstlane(__shfl(it, 0, 64));
-        if (it >= n_items) break;
+    uint32_t it = pop_item(head, lane);
+    while (it < n_items) {
         const WorkItem w = items[it];
         const InstView &I = insts[w.inst];
         run_item_f32(I, w, lane, I.partials + w.partial);
+        it = pop_item(head, lane);
     }
 }
 
