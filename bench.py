@@ -44,7 +44,21 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 plain comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-tune", action="store_true", help="use the default launch shape")
+    ap.add_argument("--launch", default="", help="fixed launch shape BLOCK,WAVES_PER_SIMD,CHUNK (skips autotuning)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU work of the oracle sample")
+    ap.add_argument("--mode", default="step", choices=["step", "batch", "serve"],
+                    help="step: the metric line (rotating bump 129^2); batch: the 64-instance mix in one "
+                         "persistent launch; serve: Poisson request stream through submit/poll")
+    ap.add_argument("--batch-count", type=int, default=64)
+    ap.add_argument("--batch-scale", type=float, default=1.0, help="scale the mix's path counts (batch mode)")
+    ap.add_argument("--requests", type=int, default=40, help="requests in serve mode")
+    ap.add_argument("--rate", type=float, default=0.0,
+                    help="arrival rate in req/s for serve mode (0: 0.7 x the measured capacity)")
+    ap.add_argument("--serve-sizes", default="33,65,129,257,513", help="grid sizes of the serving mix")
+    ap.add_argument("--serve-precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--budget-mb", type=int, default=0, help="HBM budget of the serving context (0: 90%% free)")
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (HBM counter calibration)")
     return ap.parse_args()
 
 
@@ -54,6 +68,10 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.mode == "batch":
+        return run_batch(args)
+    if args.mode == "serve":
+        return run_serve(args)
     import numpy as np
     import torch
 
@@ -74,6 +92,13 @@ def main():
         b0 = torch.from_numpy(inst.bnd_t0).to(dev)
         b1 = torch.from_numpy(inst.bnd_t1).to(dev)
     stream.synchronize()
+    if args.copy_mb:
+        src = torch.ones(args.copy_mb << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("plain copy: %d MiB read, %d MiB written" % (args.copy_mb, args.copy_mb))
+        del src, dst
     ctx = M.mesh_sdd_ctx_create(0, 0, stream.cuda_stream)
     h32 = M.mesh_sdd_create(ctx, M.desc_for(inst, M.FP32))
     m = M.mesh_sdd_num_interface_nodes(h32)
@@ -82,7 +107,10 @@ def main():
     step = M.make_step(x, y, b0, b1, paths_per_node=inst.n_paths, mesh_step=0)
 
     M.mesh_sdd_set_monitor(h32, rho)
-    if not args.no_tune:
+    if args.launch:
+        b, w, c = (int(v) for v in args.launch.split(","))
+        M.mesh_sdd_set_launch(ctx, M.make_launch(b, w, c))
+    elif not args.no_tune:
         t = time.time()
         lo = M.mesh_sdd_autotune(h32, step)
         log("autotune: block %d, waves/SIMD %d, chunk %d (%.1f s)" % (lo.block, lo.waves_per_simd, lo.chunk_paths,
@@ -184,6 +212,129 @@ def main():
     }
     print(json.dumps(line), flush=True)
     M.mesh_sdd_destroy(h32)
+    M.mesh_sdd_ctx_destroy(ctx)
+
+
+def run_batch(args):
+    """The batched mix: independent instances (grids 33..513, 2x2..16x16
+    subdomains, bump or periodic front, 1e4..1e6 paths) in ONE persistent
+    FP32 launch through mesh_sdd_solve_batch."""
+    import numpy as np
+    import torch
+
+    from paper_1504_00084_amd import mesh_sdd as M
+    from paper_1504_00084_amd import workloads as W
+
+    M.load()
+    insts = W.config4(count=args.batch_count)
+    if args.batch_scale != 1.0:
+        for it in insts:
+            it.n_paths = max(64, int(it.n_paths * args.batch_scale) // 64 * 64)
+    ctx = M.mesh_sdd_ctx_create(0)
+    hs, ms, steps, results, arrs = [], [], [], [], []
+    for it in insts:
+        h = M.mesh_sdd_create(ctx, M.desc_for(it, M.FP32))
+        M.mesh_sdd_set_monitor(h, it.rho)
+        m = M.mesh_sdd_num_interface_nodes(h)
+        a, r = M.host_result(m)
+        hs.append(h)
+        ms.append(m)
+        arrs.append(a)
+        results.append(r)
+        steps.append(M.make_step(it.x, it.y, it.bnd_t0, it.bnd_t1, paths_per_node=it.n_paths))
+    if args.launch:
+        b, w, c = (int(v) for v in args.launch.split(","))
+        M.mesh_sdd_set_launch(ctx, M.make_launch(b, w, c))
+    nominal = sum(m * it.n_paths * it.K for m, it in zip(ms, insts))
+    log("batch: %d instances, %d interface nodes, nominal %.3e path-steps" % (len(insts), sum(ms), nominal))
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    M.mesh_sdd_solve_batch(hs, steps, results)
+    wall = time.perf_counter() - t
+    executed = sum(int(r.executed_path_steps) for r in results)
+    kernel_ms = results[0].device_ms
+    se = max(float(np.max(np.maximum(a[2][:m], a[3][:m]))) for a, m in zip(arrs, ms) if m)
+    line = {"metric": "batched mix path-steps/s (one persistent launch)", "value": executed / wall,
+            "unit": "path-steps/s", "kernel_ms": kernel_ms, "wall_s": wall, "executed_path_steps": executed,
+            "nominal_path_steps": nominal, "instances": len(insts), "interface_nodes": sum(ms), "max_se": se,
+            "path_scale": args.batch_scale, "dtype": "f32 (paths) / f64 (sums)", "data": "synthetic",
+            "roofline_frac": W_SLOTS_PER_STEP * executed / (kernel_ms / 1e3) / 1e12 / VALU_PEAK_TOPS}
+    print(json.dumps(line), flush=True)
+    for h in hs:
+        M.mesh_sdd_destroy(h)
+    M.mesh_sdd_ctx_destroy(ctx)
+
+
+def run_serve(args):
+    """Poisson stream of interface-solve requests from the batched mix, with
+    a per-request standard-error target setting N; requests are created,
+    frozen and submitted at their arrival times and served by the library's
+    continuous-batching scheduler.  p50 / p99 are the library's
+    submit-to-completion latencies."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    from paper_1504_00084_amd import mesh_sdd as M
+    from paper_1504_00084_amd import workloads as W
+
+    M.load()
+    sizes = tuple(int(v) for v in args.serve_sizes.split(","))
+    prec = M.FP32 if args.serve_precision == "fp32" else M.FP64
+    stream = W.serving_stream(args.requests, rate_hz=1.0, sizes=sizes)   # unit rate, rescaled below
+    work = []
+    for _, it, _ in stream:
+        m = len(M.mesh_sdd_desc_interface_nodes(M.desc_for(it))[0])
+        work.append(m * it.n_paths * it.K)
+    rate = args.rate
+    if rate <= 0.0:
+        # 0.7 x capacity: capacity from a short FP32 solve of the rotating bump
+        cap = 2.0e11 if prec == M.FP32 else 6.0e10
+        rate = 0.7 * cap * 0.85 / float(np.mean(work))
+    arrivals = [t / rate for t, _, _ in stream]
+    ctx = M.mesh_sdd_ctx_create(0, args.budget_mb << 20)
+    if args.launch:
+        b, w, c = (int(v) for v in args.launch.split(","))
+        M.mesh_sdd_set_launch(ctx, M.make_launch(b, w, c))
+    log("serve: %d requests at %.3f req/s (%s), mean nominal work %.3e path-steps"
+        % (len(stream), rate, args.serve_precision, float(np.mean(work))))
+    done, e2e = [], []
+    lock = threading.Lock()
+    t0 = time.perf_counter()
+
+    def client(k):
+        ta = arrivals[k]
+        now = time.perf_counter() - t0
+        if ta > now:
+            time.sleep(ta - now)
+        ts = time.perf_counter()
+        _, it, _ = stream[k]
+        h = M.mesh_sdd_create(ctx, M.desc_for(it, prec))
+        M.mesh_sdd_set_monitor(h, it.rho)
+        m = M.mesh_sdd_num_interface_nodes(h)
+        a, r = M.host_result(m)
+        tk = M.mesh_sdd_submit(h, M.make_step(it.x, it.y, it.bnd_t0, it.bnd_t1, paths_per_node=it.n_paths))
+        M.mesh_sdd_wait(ctx, tk, r, -1)
+        M.mesh_sdd_destroy(h)
+        with lock:
+            done.append(int(r.executed_path_steps))
+            e2e.append(time.perf_counter() - ts)
+
+    threads = [threading.Thread(target=client, args=(k,)) for k in range(len(stream))]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    wall = time.perf_counter() - t0
+    st = M.mesh_sdd_ctx_stats(ctx)
+    line = {"metric": "serving p50/p99 latency and throughput", "precision": args.serve_precision,
+            "requests": len(stream), "rate_req_s": rate, "completed": int(st.completed), "failed": int(st.failed),
+            "p50_ms": st.p50_ms, "p99_ms": st.p99_ms, "mean_ms": st.mean_ms,
+            "client_p50_ms": 1e3 * float(np.percentile(e2e, 50)), "client_p99_ms": 1e3 * float(np.percentile(e2e, 99)),
+            "throughput_path_steps_s": sum(done) / wall, "busy_ms": st.busy_ms, "wall_s": wall, "ticks": int(st.ticks),
+            "sizes": list(sizes), "data": "synthetic"}
+    print(json.dumps(line), flush=True)
     M.mesh_sdd_ctx_destroy(ctx)
 
 

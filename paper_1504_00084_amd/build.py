@@ -19,6 +19,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libmesh_sdd.so")
+PROBE = os.path.join(PKG, "valu_probe")
 
 ARCH = "gfx950"
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
@@ -54,8 +55,16 @@ def build(verbose: bool = False) -> str:
     if res.returncode != 0:
         raise RuntimeError("link failed: %s\n%s\n%s" % (" ".join(cmd), res.stdout, res.stderr))
     os.replace(tmp, LIB)
+    # stand-alone VALU issue-cost probe (roofline calibration)
+    tmp = PROBE + ".tmp%d" % os.getpid()
+    cmd = [hipcc(), "-O3", "-std=c++17", "--offload-arch=" + ARCH] + DEVICE_FLAGS + [
+        os.path.join(CSRC, "valu_probe.hip"), "-o", tmp]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError("probe build failed: %s\n%s\n%s" % (" ".join(cmd), res.stdout, res.stderr))
+    os.replace(tmp, PROBE)
     if verbose:
-        print("built", LIB)
+        print("built", LIB, "and", PROBE)
     return LIB
 
 

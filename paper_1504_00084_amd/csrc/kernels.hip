@@ -34,6 +34,13 @@
 
 namespace msdd {
 
+// Pointers into device global memory: loads through them compile to global
+// (not flat) instructions with a scalar base and 32-bit lane offsets.
+#define GLOBAL __attribute__((address_space(1)))
+template <class T> __device__ __forceinline__ const GLOBAL T *gptr(const T *p) { return (const GLOBAL T *)p; }
+template <class T> __device__ __forceinline__ GLOBAL T *gptr_rw(T *p) { return (GLOBAL T *)p; }
+typedef float f32x4 __attribute__((ext_vector_type(4)));   // plain 16-byte vector load
+
 // ---------------------------------------------------------------------------
 // Philox4x32-10 and uniforms
 // ---------------------------------------------------------------------------
@@ -48,8 +55,9 @@ __device__ __forceinline__ Words4 philox4x32_10(uint32_t x0, uint32_t x1, uint32
     for (int round = 0; round < 10; ++round) {
         const uint64_t m0 = (uint64_t)0xD2511F53u * (uint64_t)x0;
         const uint64_t m1 = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
-        const uint32_t y0 = (uint32_t)(m1 >> 32) ^ x1 ^ k0;
-        const uint32_t y2 = (uint32_t)(m0 >> 32) ^ x3 ^ k1;
+        // three-input XOR in one instruction (truth table 0x96)
+        const uint32_t y0 = __builtin_amdgcn_bitop3_b32((uint32_t)(m1 >> 32), x1, k0, 0x96);
+        const uint32_t y2 = __builtin_amdgcn_bitop3_b32((uint32_t)(m0 >> 32), x3, k1, 0x96);
         x1 = (uint32_t)m1;
         x3 = (uint32_t)m0;
         x0 = y0;
@@ -78,7 +86,7 @@ struct ConstF {
     int n_xi, n_eta, nx1, ny1;
     int per_xi, per_eta, bridge, K;
     float fnx1, fny1, dt, sq2dt, inv_dt, inv_tau, Lx, Ly;
-    const float4 *cells;
+    const GLOBAL f32x4 *cells;
 };
 
 __device__ __forceinline__ ConstF load_const_f(const InstView &I)
@@ -100,7 +108,7 @@ __device__ __forceinline__ ConstF load_const_f(const InstView &I)
     c.inv_tau = I.inv_tau_f;
     c.Lx = I.Lx_f;
     c.Ly = I.Ly_f;
-    c.cells = I.cells;
+    c.cells = (const GLOBAL f32x4 *)I.cells;
     return c;
 }
 
@@ -136,8 +144,8 @@ __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t w
     float tx, ty;
     const int cx = cell_of(P.x * C.fnx1, C.nx1, tx);
     const int cy = cell_of(P.y * C.fny1, C.ny1, ty);
-    const float4 *cell = C.cells + 3 * (cy * C.nx1 + cx);
-    const float4 A = cell[0], B = cell[1], G = cell[2];
+    const GLOBAL f32x4 *cell = C.cells + (uint32_t)(3 * (cy * C.nx1 + cx));
+    const f32x4 A = cell[0], B = cell[1], G = cell[2];
     const float rho = fmaf(ty, fmaf(A.w, tx, A.z), fmaf(A.y, tx, A.x));
     const float gx = fmaf(ty, fmaf(B.w, tx, B.z), fmaf(B.y, tx, B.x));
     const float gy = fmaf(ty, fmaf(G.w, tx, G.z), fmaf(G.y, tx, G.x));
@@ -237,20 +245,21 @@ __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t w
 }
 
 // a7 (exit): boundary value, linear along the side and linear in time.
-__device__ __forceinline__ float boundary_f32(const float *b0, const float *b1, int n_xi, int n_eta, int side,
-                                              int comp, float tang, float w_tn)
+__device__ __forceinline__ float boundary_f32(const GLOBAL float *b0, const GLOBAL float *b1, int n_xi, int n_eta,
+                                              int side, int comp, float tang, float w_tn)
 {
     const int len = side < 2 ? n_eta : n_xi;
     const int off = side < 2 ? (side * 2 + comp) * n_eta : 4 * n_eta + ((side - 2) * 2 + comp) * n_xi;
     float fr;
     const int c = cell_of(tang * (float)(len - 1), len - 1, fr);
-    const float v0 = fmaf(fr, b0[off + c + 1] - b0[off + c], b0[off + c]);
-    const float v1 = fmaf(fr, b1[off + c + 1] - b1[off + c], b1[off + c]);
+    const uint32_t o = (uint32_t)(off + c);
+    const float v0 = fmaf(fr, b0[o + 1] - b0[o], b0[o]);
+    const float v1 = fmaf(fr, b1[o + 1] - b1[o], b1[o]);
     return fmaf(w_tn, v0 - v1, v1);   // w_tn v0 + (1 - w_tn) v1
 }
 
 // a7 (survivor): Keys cubic convolution (a = -1/2) on the padded mesh.
-__device__ __forceinline__ float keys_f32(const float *pad, int n_xi, int nx1, int ny1, float fnx1, float fny1,
+__device__ __forceinline__ float keys_f32(const GLOBAL float *pad, int n_xi, int nx1, int ny1, float fnx1, float fny1,
                                           float x, float y)
 {
     float tx, ty;
@@ -261,7 +270,7 @@ __device__ __forceinline__ float keys_f32(const float *pad, int n_xi, int nx1, i
     const float wy[4] = {((-0.5f * ty + 1.0f) * ty - 0.5f) * ty, (1.5f * ty - 2.5f) * ty * ty + 1.0f,
                          ((-1.5f * ty + 2.0f) * ty + 0.5f) * ty, (0.5f * ty - 0.5f) * ty * ty};
     const int stride = n_xi + 2;
-    const float *row = pad + cy * stride + cx;   // padded node (cx-1, cy-1)
+    const GLOBAL float *row = pad + (uint32_t)(cy * stride + cx);   // padded node (cx-1, cy-1)
     float acc = 0.0f;
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
@@ -279,11 +288,11 @@ __device__ __forceinline__ void path_value_f32(const InstView &I, const ConstF &
     if (side >= 0) {
         const float w_tn = (float)P.k * C.dt * C.inv_tau;
         const float tang = side < 2 ? P.y : P.x;
-        vx = boundary_f32(I.bnd0_f, I.bnd1_f, C.n_xi, C.n_eta, side, 0, tang, w_tn);
-        vy = boundary_f32(I.bnd0_f, I.bnd1_f, C.n_xi, C.n_eta, side, 1, tang, w_tn);
+        vx = boundary_f32(gptr(I.bnd0_f), gptr(I.bnd1_f), C.n_xi, C.n_eta, side, 0, tang, w_tn);
+        vy = boundary_f32(gptr(I.bnd0_f), gptr(I.bnd1_f), C.n_xi, C.n_eta, side, 1, tang, w_tn);
     } else {
-        vx = keys_f32(I.xpad_f, C.n_xi, C.nx1, C.ny1, C.fnx1, C.fny1, P.x, P.y);
-        vy = keys_f32(I.ypad_f, C.n_xi, C.nx1, C.ny1, C.fnx1, C.fny1, P.x, P.y);
+        vx = keys_f32(gptr(I.xpad_f), C.n_xi, C.nx1, C.ny1, C.fnx1, C.fny1, P.x, P.y);
+        vy = keys_f32(gptr(I.ypad_f), C.n_xi, C.nx1, C.ny1, C.fnx1, C.fny1, P.x, P.y);
     }
     if (C.per_xi) vx = fmaf((float)P.wx, C.Lx, vx);
     if (C.per_eta) vy = fmaf((float)P.wy, C.Ly, vy);
@@ -338,15 +347,15 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 }
 
 // Runs one work item with one wave (lanes refilled from the chunk).
-__device__ __forceinline__ void run_item_f32(const InstView &I, const WorkItem &w, int lane, Partial *out)
+__device__ __forceinline__ void run_item_f32(const InstView &I, uint32_t node, uint32_t p_begin, uint32_t count,
+                                             GLOBAL Partial *out)
 {
     const ConstF C = load_const_f(I);
-    const uint32_t node = w.node;
-    const int i0 = I.node_i[node], j0 = I.node_j[node];
+    const int i0 = gptr(I.node_i)[node], j0 = gptr(I.node_j)[node];
     const float x0 = (float)((double)i0 / (double)C.nx1);
     const float y0 = (float)((double)j0 / (double)C.ny1);
-    const double refx = I.x64[(size_t)j0 * C.n_xi + i0];
-    const double refy = I.y64[(size_t)j0 * C.n_xi + i0];
+    const double refx = gptr(I.x64)[(uint32_t)(j0 * C.n_xi + i0)];
+    const double refy = gptr(I.y64)[(uint32_t)(j0 * C.n_xi + i0)];
     const uint32_t key0 = I.key0, key1 = I.key1, ctr3 = I.ctr3;
 
     double s1x = 0.0, s2x = 0.0, s1y = 0.0, s2y = 0.0;
@@ -356,7 +365,6 @@ __device__ __forceinline__ void run_item_f32(const InstView &I, const WorkItem &
     uint32_t path = 0;
     bool has = false;
     uint32_t issued = 0;          // paths of the chunk handed out (wave-uniform)
-    const uint32_t count = w.p_count;
 
     for (;;) {
         // refill lanes that have no path with the chunk's next paths, in lane order
@@ -366,7 +374,7 @@ __device__ __forceinline__ void run_item_f32(const InstView &I, const WorkItem &
                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
             if (!has && issued + below < count) {
                 has = true;
-                path = w.p_begin + issued + below;
+                path = p_begin + issued + below;
                 P.x = x0;
                 P.y = y0;
                 P.wx = 0;
@@ -422,15 +430,31 @@ __device__ __forceinline__ uint32_t pop_item(uint32_t *head, int lane)
 
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void paths_fp32(const InstView *__restrict__ insts,
-                                                    const WorkItem *__restrict__ items, uint32_t n_items,
-                                                    uint32_t *__restrict__ head)
+                                                    const WorkRange *__restrict__ ranges, uint32_t n_ranges,
+                                                    uint32_t n_items, uint32_t *__restrict__ head)
 {
     const int lane = threadIdx.x & 63;
+    const GLOBAL WorkRange *rg = gptr(ranges);
     uint32_t it = pop_item(head, lane);
     while (it < n_items) {
-        const WorkItem w = items[it];
-        const InstView &I = insts[w.inst];
-        run_item_f32(I, w, lane, I.partials + w.partial);
+        // range holding launch item `it` (ranges are sorted by base, base[0] = 0)
+        uint32_t lo = 0, hi = n_ranges;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (rg[mid].base <= it)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        const GLOBAL WorkRange &R = rg[lo];
+        const uint32_t M = R.M, chunk_paths = R.chunk_paths;
+        const uint32_t q = R.first + (it - R.base);    // request-wide item, chunk-major
+        const uint32_t c = q / M;
+        const uint32_t node = q - c * M;
+        const uint32_t p_begin = c * chunk_paths;
+        const uint32_t count = min(chunk_paths, R.N - p_begin);
+        const InstView &I = insts[R.inst];
+        run_item_f32(I, node, p_begin, count, gptr_rw(I.partials) + (node * R.chunks + c));
         it = pop_item(head, lane);
     }
 }
@@ -905,24 +929,24 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_paths_fp32(const InstView *insts, const WorkItem *items, uint32_t n_items, uint32_t *head,
-                             int grid, int block, hipStream_t s)
+hipError_t launch_paths_fp32(const InstView *insts, const WorkRange *ranges, uint32_t n_ranges, uint32_t n_items,
+                             uint32_t *head, int grid, int block, hipStream_t s)
 {
     hipError_t e = launch_fill_u32(head, 0u, 1, s);
     if (e != hipSuccess) return e;
     if (n_items == 0) return hipSuccess;
     switch (block) {
     case 64:
-        hipLaunchKernelGGL(paths_fp32<64>, dim3(grid), dim3(64), 0, s, insts, items, n_items, head);
+        hipLaunchKernelGGL(paths_fp32<64>, dim3(grid), dim3(64), 0, s, insts, ranges, n_ranges, n_items, head);
         break;
     case 128:
-        hipLaunchKernelGGL(paths_fp32<128>, dim3(grid), dim3(128), 0, s, insts, items, n_items, head);
+        hipLaunchKernelGGL(paths_fp32<128>, dim3(grid), dim3(128), 0, s, insts, ranges, n_ranges, n_items, head);
         break;
     case 256:
-        hipLaunchKernelGGL(paths_fp32<256>, dim3(grid), dim3(256), 0, s, insts, items, n_items, head);
+        hipLaunchKernelGGL(paths_fp32<256>, dim3(grid), dim3(256), 0, s, insts, ranges, n_ranges, n_items, head);
         break;
     case 512:
-        hipLaunchKernelGGL(paths_fp32<512>, dim3(grid), dim3(512), 0, s, insts, items, n_items, head);
+        hipLaunchKernelGGL(paths_fp32<512>, dim3(grid), dim3(512), 0, s, insts, ranges, n_ranges, n_items, head);
         break;
     default:
         return hipErrorInvalidValue;

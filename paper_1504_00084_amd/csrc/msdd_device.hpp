@@ -7,16 +7,21 @@
 
 namespace msdd {
 
-// A unit of work of the batched kernel: paths [p_begin, p_begin + p_count)
-// of interface node `node` of instance slot `inst`; the sums go to
-// partials[partial].
-struct WorkItem {
-    uint32_t inst;
-    uint32_t node;
-    uint32_t p_begin;
-    uint32_t p_count;
-    uint32_t partial;
-    uint32_t pad[3];
+// The work of one request inside one launch of the batched kernel.  A
+// request's work items are numbered chunk-major (item = chunk * M + node):
+// item q covers paths [c * chunk_paths, min(N, (c + 1) * chunk_paths)) of
+// node q mod M, with c = q div M, and its sums go to partial slot
+// node * chunks + c.  The range holds the request's items
+// [first, first + count), which are items [base, base + count) of the launch.
+struct WorkRange {
+    uint32_t inst;         // InstView slot in the launch
+    uint32_t base;         // first launch-wide item of the range
+    uint32_t count;        // items in the range
+    uint32_t first;        // first request-wide item
+    uint32_t M;            // interface nodes of the request
+    uint32_t chunks;       // chunks per node
+    uint32_t chunk_paths;  // paths per full chunk
+    uint32_t N;            // paths per node
 };
 
 // Shifted sums of one (node, chunk): S1 = sum(v - v_ref), S2 = sum((v - v_ref)^2).

@@ -28,11 +28,11 @@ hipError_t launch_prep_mesh(const double *x, const double *y, int n_xi, int n_et
 hipError_t launch_to_f32(const double *in, float *out, size_t n, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t s);
 
-// a2-a8, FP32: persistent batched kernel over a work queue.  `head` is the
-// queue counter (zeroed by this launcher); item sums go to
-// insts[item.inst].partials[item.partial].
-hipError_t launch_paths_fp32(const InstView *insts, const WorkItem *items, uint32_t n_items, uint32_t *head,
-                             int grid, int block, hipStream_t s);
+// a2-a8, FP32: persistent batched kernel over a work queue of n_items items
+// described by n_ranges ranges (sorted by base, contiguous from 0).  `head`
+// is the queue counter (zeroed by this launcher).
+hipError_t launch_paths_fp32(const InstView *insts, const WorkRange *ranges, uint32_t n_ranges, uint32_t n_items,
+                             uint32_t *head, int grid, int block, hipStream_t s);
 
 // a2-a8, FP64 plain: one thread per path, one launch per instance; the
 // partial of (node, chunk) goes to partials[node * chunks + chunk].

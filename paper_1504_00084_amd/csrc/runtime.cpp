@@ -37,7 +37,7 @@
 using msdd::InstView;
 using msdd::NodeSpan;
 using msdd::Partial;
-using msdd::WorkItem;
+using msdd::WorkRange;
 
 namespace {
 
@@ -67,24 +67,88 @@ double ms_since(Clock::time_point t0)
     return std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
 }
 
-// Device allocation owned by one object.
+// Free device blocks kept for reuse, keyed by their exact size (requests of
+// the same shape reuse the same blocks, so steady-state solves call neither
+// hipMalloc nor hipFree).  Bounded: blocks beyond `cap` bytes are freed.
+struct DevPool {
+    std::mutex mu;
+    std::multimap<size_t, void *> free_blocks;
+    size_t pooled = 0;
+    size_t cap = (size_t)1 << 30;
+    ~DevPool() { trim(0); }
+    void *get(size_t n)
+    {
+        {
+            std::lock_guard<std::mutex> g(mu);
+            auto it = free_blocks.find(n);
+            if (it != free_blocks.end()) {
+                void *p = it->second;
+                free_blocks.erase(it);
+                pooled -= n;
+                return p;
+            }
+        }
+        void *p = nullptr;
+        if (hipMalloc(&p, n) != hipSuccess) {
+            trim(0);   // give cached blocks back and try once more
+            if (hipMalloc(&p, n) != hipSuccess) return nullptr;
+        }
+        return p;
+    }
+    void put(void *p, size_t n)
+    {
+        std::lock_guard<std::mutex> g(mu);
+        free_blocks.emplace(n, p);
+        pooled += n;
+        while (pooled > cap && !free_blocks.empty()) {
+            auto it = free_blocks.begin();
+            pooled -= it->first;
+            (void)hipFree(it->second);
+            free_blocks.erase(it);
+        }
+    }
+    void trim(size_t keep)
+    {
+        std::lock_guard<std::mutex> g(mu);
+        while (pooled > keep && !free_blocks.empty()) {
+            auto it = free_blocks.begin();
+            pooled -= it->first;
+            (void)hipFree(it->second);
+            free_blocks.erase(it);
+        }
+    }
+};
+
+// Device allocation owned by one object (from a pool when one is given).
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    DevPool *pool = nullptr;
     DevBuf() = default;
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
     ~DevBuf() { release(); }
     void release()
     {
-        if (p) (void)hipFree(p);
+        if (p) {
+            if (pool)
+                pool->put(p, bytes);
+            else
+                (void)hipFree(p);
+        }
         p = nullptr;
         bytes = 0;
     }
     hipError_t alloc(size_t n)
     {
         release();
-        if (n == 0) n = 16;
+        n = n == 0 ? 256 : (n + 255) / 256 * 256;
+        if (pool) {
+            p = pool->get(n);
+            if (!p) return hipErrorOutOfMemory;
+            bytes = n;
+            return hipSuccess;
+        }
         hipError_t e = hipMalloc(&p, n);
         if (e == hipSuccess)
             bytes = n;
@@ -125,7 +189,8 @@ struct mesh_sdd {
 
 struct Request {
     uint64_t ticket = 0;
-    mesh_sdd *inst = nullptr;
+    mesh_sdd *inst = nullptr;      // valid until the request finishes
+    int32_t M = 0;                 // interface nodes (kept for poll after finish)
     int64_t N = 0;
     uint32_t mesh_step = 0;
     int chunk_paths = 0;
@@ -135,7 +200,7 @@ struct Request {
     DevBuf x64, y64, b0, b1, xpad, ypad, xpad_f, ypad_f, b0f, b1f;
     DevBuf view, partials, spans, out, steps_total;
     InstView v{};
-    std::vector<WorkItem> items;   // FP32 work (partial index = node-major chunk slot)
+    size_t n_items = 0;            // FP32 work items (chunk-major, see WorkRange)
     size_t next_item = 0;          // first item not yet handed to a tick
     size_t done_items = 0;
     uint32_t chunks_per_node = 0;
@@ -167,8 +232,9 @@ struct mesh_sdd_ctx {
     int cu_count = 0;
     size_t budget = 0;
 
+    DevPool pool;        // recycled request buffers (declared before users)
     std::mutex gpu_mu;   // serialises use of the stream and the launch scratch below
-    DevBuf head, views, items;
+    DevBuf head, views, ranges;
 
     std::mutex mu;       // guards everything below
     std::condition_variable cv, done_cv;
@@ -359,6 +425,7 @@ std::shared_ptr<Request> make_request(mesh_sdd *inst, const mesh_sdd_step &s, in
 {
     auto r = std::make_shared<Request>();
     r->inst = inst;
+    r->M = inst->M;
     r->N = N;
     r->mesh_step = s.mesh_step;
     r->chunk_paths = std::max(64, launch_for(inst->ctx, inst->d).chunk_paths / 64 * 64);
@@ -396,6 +463,9 @@ int stage_request(Request &r, const mesh_sdd_step *dev_step)
     r.chunks_per_node = chunks;
     const size_t n_part = (size_t)M * chunks;
 
+    for (DevBuf *b : {&r.x64, &r.y64, &r.b0, &r.b1, &r.xpad, &r.ypad, &r.xpad_f, &r.ypad_f, &r.b0f, &r.b1f,
+                      &r.view, &r.partials, &r.spans, &r.out, &r.steps_total})
+        b->pool = &ctx->pool;
     if (r.x64.alloc(n * 8) || r.y64.alloc(n * 8) || r.b0.alloc(nb * 8) || r.b1.alloc(nb * 8) ||
         r.xpad.alloc(np * 8) || r.ypad.alloc(np * 8) || r.xpad_f.alloc(np * 4) || r.ypad_f.alloc(np * 4) ||
         r.b0f.alloc(nb * 4) || r.b1f.alloc(nb * 4) || r.view.alloc(sizeof(InstView)) ||
@@ -468,25 +538,10 @@ int stage_request(Request &r, const mesh_sdd_step *dev_step)
     if (M) HIP_TRY(hipMemcpyAsync(r.spans.p, spans.data(), spans.size() * sizeof(NodeSpan), hipMemcpyHostToDevice, st));
     HIP_TRY(msdd::launch_fill_u32(r.steps_total.as<uint32_t>(), 0u, 2, st));
 
-    // FP32 work items: every (node, chunk); chunk c of every node before
-    // chunk c+1 so that concurrent waves spread over the nodes.
-    r.items.clear();
-    if (!fp64) {
-        r.items.reserve(n_part);
-        for (uint32_t c = 0; c < chunks; ++c) {
-            const uint32_t p0 = c * (uint32_t)r.chunk_paths;
-            const uint32_t cnt = (uint32_t)std::min<int64_t>(r.chunk_paths, r.N - (int64_t)p0);
-            for (int m = 0; m < M; ++m) {
-                WorkItem w{};
-                w.inst = 0;
-                w.node = (uint32_t)m;
-                w.p_begin = p0;
-                w.p_count = cnt;
-                w.partial = (uint32_t)((size_t)m * chunks + c);
-                r.items.push_back(w);
-            }
-        }
-    }
+    // FP32 work: every (node, chunk), numbered chunk-major so that chunk c of
+    // every node comes before chunk c+1 (concurrent waves spread over the
+    // nodes, and each node's short last chunk comes at the end)
+    r.n_items = fp64 ? 0 : n_part;
     r.next_item = 0;
     r.done_items = 0;
     // the host snapshots are no longer needed once the copies are done
@@ -505,28 +560,32 @@ void release_request_buffers(Request &r)
         b->release();
 }
 
-// One persistent FP32 launch over `items` (inst fields index `views`).
-// Caller holds gpu_mu.  Returns the device time in ms via *ms.
-int run_fp32_launch(mesh_sdd_ctx *ctx, const std::vector<InstView> &views, const std::vector<WorkItem> &items,
+// One persistent FP32 launch over the items described by `ranges` (their
+// inst fields index `views`).  Caller holds gpu_mu.  Returns the device time
+// in ms via *ms.
+int run_fp32_launch(mesh_sdd_ctx *ctx, const std::vector<InstView> &views, const std::vector<WorkRange> &ranges,
                     const mesh_sdd_launch &l, double *ms)
 {
     hipStream_t st = ctx->stream;
-    if (items.empty()) {
+    size_t n_items = 0;
+    for (const WorkRange &w : ranges) n_items += w.count;
+    if (n_items == 0) {
         *ms = 0.0;
         return MESH_SDD_OK;
     }
-    if (ctx->views.reserve(views.size() * sizeof(InstView)) || ctx->items.reserve(items.size() * sizeof(WorkItem)) ||
-        ctx->head.reserve(64))
+    if (n_items > 0xFFFFFFF0u) return fail(MESH_SDD_E_INVAL, "too many work items in one launch");
+    if (ctx->views.reserve(views.size() * sizeof(InstView)) ||
+        ctx->ranges.reserve(ranges.size() * sizeof(WorkRange)) || ctx->head.reserve(64))
         return fail(MESH_SDD_E_NOMEM, "device allocation for the work queue failed");
     HIP_TRY(hipMemcpyAsync(ctx->views.p, views.data(), views.size() * sizeof(InstView), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(ctx->items.p, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(ctx->ranges.p, ranges.data(), ranges.size() * sizeof(WorkRange), hipMemcpyHostToDevice, st));
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     HIP_TRY(hipEventRecord(e0, st));
-    hipError_t le = msdd::launch_paths_fp32(ctx->views.as<InstView>(), ctx->items.as<WorkItem>(),
-                                            (uint32_t)items.size(), ctx->head.as<uint32_t>(), grid_for(ctx, l),
-                                            l.block, st);
+    hipError_t le = msdd::launch_paths_fp32(ctx->views.as<InstView>(), ctx->ranges.as<WorkRange>(),
+                                            (uint32_t)ranges.size(), (uint32_t)n_items, ctx->head.as<uint32_t>(),
+                                            grid_for(ctx, l), l.block, st);
     HIP_TRY(hipEventRecord(e1, st));
     hipError_t se = hipEventSynchronize(e1);
     float t = 0.0f;
@@ -537,6 +596,21 @@ int run_fp32_launch(mesh_sdd_ctx *ctx, const std::vector<InstView> &views, const
     if (se != hipSuccess) return fail(MESH_SDD_E_DEVICE, "path kernel failed: %s", hipGetErrorString(se));
     *ms = t;
     return MESH_SDD_OK;
+}
+
+// Range of request `r`'s items [first, first + count) at launch offset base.
+WorkRange range_of(const Request &r, uint32_t slot, size_t base, size_t first, size_t count)
+{
+    WorkRange w{};
+    w.inst = slot;
+    w.base = (uint32_t)base;
+    w.count = (uint32_t)count;
+    w.first = (uint32_t)first;
+    w.M = (uint32_t)r.M;
+    w.chunks = r.chunks_per_node;
+    w.chunk_paths = (uint32_t)r.chunk_paths;
+    w.N = (uint32_t)r.N;
+    return w;
 }
 
 // FP64 plain launch of one request.  Caller holds gpu_mu.
@@ -584,7 +658,7 @@ int copy_result(mesh_sdd_ctx *ctx, const Request &r, mesh_sdd_result *res)
     if (!res) return MESH_SDD_OK;
     if (res->struct_size != sizeof(mesh_sdd_result))
         return fail(MESH_SDD_E_INVAL, "result.struct_size %u != %zu", res->struct_size, sizeof(mesh_sdd_result));
-    const int M = r.inst->M;
+    const int M = r.M;   // the instance may already be destroyed
     double *dst[5] = {res->mean_x, res->mean_y, res->se_x, res->se_y, res->exit_frac};
     for (int k = 0; k < 5; ++k) {
         if (!dst[k]) continue;
@@ -609,8 +683,9 @@ int run_blocking(mesh_sdd_ctx *ctx, std::vector<std::shared_ptr<Request>> &reqs,
     std::lock_guard<std::mutex> g(ctx->gpu_mu);
     status.assign(reqs.size(), MESH_SDD_OK);
     std::vector<InstView> views;
-    std::vector<WorkItem> items;
+    std::vector<WorkRange> ranges;
     std::vector<size_t> fp32_reqs;
+    size_t base = 0;
     mesh_sdd_launch l = default_launch();
     bool have_launch = false;
     for (size_t q = 0; q < reqs.size(); ++q) {
@@ -631,9 +706,9 @@ int run_blocking(mesh_sdd_ctx *ctx, std::vector<std::shared_ptr<Request>> &reqs,
         } else {
             const uint32_t slot = (uint32_t)views.size();
             views.push_back(r.v);
-            for (WorkItem w : r.items) {
-                w.inst = slot;
-                items.push_back(w);
+            if (r.n_items) {
+                ranges.push_back(range_of(r, slot, base, 0, r.n_items));
+                base += r.n_items;
             }
             fp32_reqs.push_back(q);
             if (!have_launch) {
@@ -643,11 +718,8 @@ int run_blocking(mesh_sdd_ctx *ctx, std::vector<std::shared_ptr<Request>> &reqs,
         }
     }
     if (!fp32_reqs.empty()) {
-        // longest items first (equal-size chunks keep their node-spread order)
-        std::stable_sort(items.begin(), items.end(),
-                         [](const WorkItem &a, const WorkItem &b) { return a.p_count > b.p_count; });
         double ms = 0.0;
-        int rc = run_fp32_launch(ctx, views, items, l, &ms);
+        int rc = run_fp32_launch(ctx, views, ranges, l, &ms);
         for (size_t q : fp32_reqs) {
             Request &r = *reqs[q];
             int rq = rc;
@@ -725,7 +797,7 @@ void scheduler_loop(mesh_sdd_ctx *ctx)
                 }
             }
             // FP32 requests without work (no interface node) finish at once
-            const bool empty_fp32 = rc == MESH_SDD_OK && r->inst->d.precision == MESH_SDD_FP32 && r->items.empty();
+            const bool empty_fp32 = rc == MESH_SDD_OK && r->inst->d.precision == MESH_SDD_FP32 && r->n_items == 0;
             if (empty_fp32) {
                 std::lock_guard<std::mutex> g(ctx->gpu_mu);
                 rc = finalize_request(ctx, *r);
@@ -741,42 +813,45 @@ void scheduler_loop(mesh_sdd_ctx *ctx)
         }
         // build one tick over the running FP32 requests: a fair share of the
         // tick's work for each, at least one item each
-        std::vector<std::shared_ptr<Request>> in_tick;
         std::vector<InstView> views;
-        std::vector<WorkItem> items;
+        std::vector<WorkRange> ranges;
         std::vector<std::pair<std::shared_ptr<Request>, size_t>> taken;
+        mesh_sdd_launch l = default_launch();
         {
             std::lock_guard<std::mutex> lk(ctx->mu);
             size_t active = 0;
             for (auto &r : ctx->running)
-                if (r->next_item < r->items.size()) ++active;
+                if (r->next_item < r->n_items) ++active;
             if (active == 0) continue;
             const double share = kTickPathSteps / (double)active;
+            size_t base = 0;
             for (auto &r : ctx->running) {
-                if (r->next_item >= r->items.size()) continue;
+                if (r->next_item >= r->n_items) continue;
                 const double per_item = (double)r->chunk_paths * (double)r->inst->d.K;
                 size_t take = (size_t)std::max(1.0, share / per_item);
-                take = std::min(take, r->items.size() - r->next_item);
+                take = std::min(take, r->n_items - r->next_item);
                 const uint32_t slot = (uint32_t)views.size();
                 views.push_back(r->v);
-                for (size_t k = 0; k < take; ++k) {
-                    WorkItem w = r->items[r->next_item + k];
-                    w.inst = slot;
-                    items.push_back(w);
-                }
+                ranges.push_back(range_of(*r, slot, base, r->next_item, take));
+                base += take;
                 r->next_item += take;
                 taken.emplace_back(r, take);
             }
             ++ctx->ticks;
+            if (ctx->has_override)
+                l = ctx->override_launch;
+            else {
+                auto it = ctx->tuned.find(TuneKey{taken.front().first->inst->d.n_xi, taken.front().first->inst->d.n_eta,
+                                                  taken.front().first->inst->d.periodic_xi,
+                                                  taken.front().first->inst->d.periodic_eta});
+                if (it != ctx->tuned.end()) l = it->second;
+            }
         }
-        std::stable_sort(items.begin(), items.end(),
-                         [](const WorkItem &a, const WorkItem &b) { return a.p_count > b.p_count; });
         double ms = 0.0;
         int rc;
         {
             std::lock_guard<std::mutex> g(ctx->gpu_mu);
-            const mesh_sdd_launch l = launch_for(ctx, taken.front().first->inst->d);
-            rc = run_fp32_launch(ctx, views, items, l, &ms);
+            rc = run_fp32_launch(ctx, views, ranges, l, &ms);
         }
         std::string err = rc == MESH_SDD_OK ? std::string() : g_last_error;
         std::vector<std::shared_ptr<Request>> complete;
@@ -786,7 +861,7 @@ void scheduler_loop(mesh_sdd_ctx *ctx)
             for (auto &t : taken) {
                 t.first->done_items += t.second;
                 t.first->device_ms += ms;
-                if (rc != MESH_SDD_OK || t.first->done_items == t.first->items.size()) complete.push_back(t.first);
+                if (rc != MESH_SDD_OK || t.first->done_items == t.first->n_items) complete.push_back(t.first);
             }
         }
         for (auto &r : complete) {
@@ -881,7 +956,7 @@ int mesh_sdd_ctx_destroy(mesh_sdd_ctx *ctx)
     (void)hipSetDevice(ctx->device);
     ctx->head.release();
     ctx->views.release();
-    ctx->items.release();
+    ctx->ranges.release();
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
     return MESH_SDD_OK;

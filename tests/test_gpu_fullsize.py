@@ -1,0 +1,92 @@
+"""Parity at the workloads' full sizes, in the launch configuration the
+benchmark times (autotuned shape, FP32 batched kernel, 1e5 paths per node,
+K = 500): every interface node is solved on the GPU; the oracle recomputes
+a sample of nodes one by one on the same streams.  Properties that hold at
+any size are checked on all nodes."""
+import numpy as np
+import pytest
+
+from paper_1504_00084_amd import workloads as W
+from gpu_helpers import compare, oracle_solve, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def M():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1504_00084_amd import mesh_sdd
+    mesh_sdd.load()
+    return mesh_sdd
+
+
+@pytest.fixture(scope="module")
+def ctx(M):
+    c = M.mesh_sdd_ctx_create(0)
+    yield c
+    M.mesh_sdd_ctx_destroy(c)
+
+
+def run_full(M, ctx, inst, precision, tune=True):
+    h = M.mesh_sdd_create(ctx, M.desc_for(inst, precision))
+    try:
+        M.mesh_sdd_set_monitor(h, inst.rho)
+        m = M.mesh_sdd_num_interface_nodes(h)
+        arrs, res = M.host_result(m)
+        st = M.make_step(inst.x, inst.y, inst.bnd_t0, inst.bnd_t1, paths_per_node=inst.n_paths,
+                         mesh_step=inst.mesh_step)
+        if tune and precision == M.FP32:
+            lo = M.mesh_sdd_autotune(h, st)
+            say("autotuned: block %d waves/SIMD %d chunk %d" % (lo.block, lo.waves_per_simd, lo.chunk_paths))
+        M.mesh_sdd_solve_interfaces(h, st, res)
+        return M.result_dict(arrs, res, m)
+    finally:
+        M.mesh_sdd_destroy(h)
+
+
+def sample_nodes(m, k=6):
+    return np.unique(np.linspace(0, m - 1, k).astype(np.int32))
+
+
+def check_all_nodes(g, inst, se_bound=1e-3):
+    for k in ("mean_x", "mean_y", "se_x", "se_y", "exit_frac"):
+        assert np.all(np.isfinite(g[k])), k
+    assert np.all((g["exit_frac"] >= 0) & (g["exit_frac"] <= 1))
+    # sigma <= 1e-3 at 1e5 paths per node
+    assert np.max(np.maximum(g["se_x"], g["se_y"])) <= se_bound
+    lo_x, hi_x = (-inst.Lx, 2 * inst.Lx) if inst.periodic_xi else (0.0, inst.Lx)
+    assert np.all((g["mean_x"] >= lo_x - 1e-9) & (g["mean_x"] <= hi_x + 1e-9))
+    assert np.all((g["mean_y"] >= -1e-9) & (g["mean_y"] <= inst.Ly + 1e-9))
+
+
+@pytest.mark.parametrize("which", ["rotbump129", "front257"])
+def test_fullsize_fp32_vs_oracle(M, ctx, oracle_lib, which):
+    inst = W.config2() if which == "rotbump129" else W.config3()
+    say("full size %s: %dx%d, sub %dx%d, N=%d, K=%d" % (inst.name, inst.n_xi, inst.n_eta, inst.sub_xi, inst.sub_eta,
+                                                        inst.n_paths, inst.K))
+    g = run_full(M, ctx, inst, M.FP32)
+    m = len(g["mean_x"])
+    say("gpu: %d nodes, %.3e path-steps in %.1f ms" % (m, g["executed_path_steps"], g["device_ms"]))
+    check_all_nodes(g, inst)
+    nodes = sample_nodes(m)
+    ora = oracle_solve(oracle_lib, inst, nodes=nodes)
+    sub = {k: np.asarray(v)[nodes] for k, v in g.items() if isinstance(v, np.ndarray)}
+    sub["paths_per_node"] = g["paths_per_node"]
+    s = compare(sub, ora, label=which + " fp32 sampled")
+    assert s["err"] <= 1e-5
+
+
+def test_fullsize_fp64_plain_vs_oracle(M, ctx, oracle_lib):
+    inst = W.config2()
+    g = run_full(M, ctx, inst, M.FP64)
+    m = len(g["mean_x"])
+    say("gpu fp64 plain: %d nodes, %.3e path-steps in %.1f ms" % (m, g["executed_path_steps"], g["device_ms"]))
+    check_all_nodes(g, inst)
+    nodes = sample_nodes(m, 3)
+    ora = oracle_solve(oracle_lib, inst, nodes=nodes)
+    sub = {k: np.asarray(v)[nodes] for k, v in g.items() if isinstance(v, np.ndarray)}
+    sub["paths_per_node"] = g["paths_per_node"]
+    s = compare(sub, ora, label="rotbump129 fp64 sampled")
+    assert s["err"] <= 1e-9

@@ -1,0 +1,261 @@
+"""Batching and serving through the C-ABI: one persistent launch over many
+instances, submit/poll with continuous batching and HBM admission, error
+paths, device pointers.  A request's result is a pure function of its
+inputs and RNG identity, so alone, batched and served results must agree
+exactly (same chunk plan, fixed-order FP64 sums)."""
+import ctypes
+import time
+
+import numpy as np
+import pytest
+
+from paper_1504_00084_amd import workloads as W
+from gpu_helpers import say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def M():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1504_00084_amd import mesh_sdd
+    mesh_sdd.load()
+    return mesh_sdd
+
+
+@pytest.fixture(scope="module")
+def ctx(M):
+    c = M.mesh_sdd_ctx_create(0)
+    yield c
+    M.mesh_sdd_ctx_destroy(c)
+
+
+def mix(count=8, n_paths=3000, seed=3):
+    insts = W.config4(count=count, seed=seed, n_paths=n_paths, sizes=(33, 65, 129))
+    for q, it in enumerate(insts):
+        it.K = 100 + 7 * q          # uneven K too (some not multiples of 4)
+        it.instance_id = 100 + q
+    return insts
+
+
+class Handles:
+    def __init__(self, M, ctx, insts, precision):
+        self.M, self.h, self.m = M, [], []
+        for it in insts:
+            h = M.mesh_sdd_create(ctx, M.desc_for(it, precision))
+            M.mesh_sdd_set_monitor(h, it.rho)
+            self.h.append(h)
+            self.m.append(M.mesh_sdd_num_interface_nodes(h))
+
+    def close(self):
+        for h in self.h:
+            self.M.mesh_sdd_destroy(h)
+
+
+def steps_for(M, insts):
+    return [M.make_step(it.x, it.y, it.bnd_t0, it.bnd_t1, paths_per_node=it.n_paths, mesh_step=it.mesh_step)
+            for it in insts]
+
+
+def solve_alone(M, H, insts):
+    out = []
+    for h, m, st in zip(H.h, H.m, steps_for(M, insts)):
+        arrs, res = M.host_result(m)
+        M.mesh_sdd_solve_interfaces(h, st, res)
+        out.append(M.result_dict(arrs, res, m))
+    return out
+
+
+def same(a, b):
+    for k in ("mean_x", "mean_y", "se_x", "se_y", "exit_frac"):
+        if not np.array_equal(a[k], b[k], equal_nan=True):
+            return False
+    return a["executed_path_steps"] == b["executed_path_steps"]
+
+
+def test_batch_equals_alone(M, ctx):
+    insts = mix()
+    H = Handles(M, ctx, insts, M.FP32)
+    try:
+        alone = solve_alone(M, H, insts)
+        pairs = [M.host_result(m) for m in H.m]
+        status = M.mesh_sdd_solve_batch(H.h, steps_for(M, insts), [p[1] for p in pairs])
+        assert status == [0] * len(insts)
+        for q, (arrs, res) in enumerate(pairs):
+            b = M.result_dict(arrs, res, H.m[q])
+            assert same(alone[q], b), q
+        say("batch of %d instances == alone (bitwise)" % len(insts))
+    finally:
+        H.close()
+
+
+def test_serving_equals_alone_and_pending(M, ctx):
+    insts = mix(count=10, seed=4)
+    H = Handles(M, ctx, insts, M.FP32)
+    try:
+        alone = solve_alone(M, H, insts)
+        st = steps_for(M, insts)
+        tickets = [M.mesh_sdd_submit(h, s) for h, s in zip(H.h, st)]
+        pend = [M.mesh_sdd_poll(ctx, tickets[-1], None)]    # most likely still pending
+        outs = []
+        for q, t in enumerate(tickets):
+            arrs, res = M.host_result(H.m[q])
+            assert M.mesh_sdd_wait(ctx, t, res, 120_000)
+            outs.append(M.result_dict(arrs, res, H.m[q]))
+        for q in range(len(insts)):
+            assert same(alone[q], outs[q]), q
+        s = M.mesh_sdd_ctx_stats(ctx)
+        say("served %d, ticks %d, p50 %.1f ms, p99 %.1f ms, first poll pending=%s"
+            % (s.completed, s.ticks, s.p50_ms, s.p99_ms, not pend[0]))
+        assert s.completed >= len(insts) and s.failed == 0
+        with pytest.raises(M.MeshSddError):      # tickets are released once done
+            M.mesh_sdd_poll(ctx, tickets[0], None)
+    finally:
+        H.close()
+
+
+def test_admission_with_small_budget(M):
+    insts = W.config4(count=6, seed=5, n_paths=3000, sizes=(33, 65))
+    for q, it in enumerate(insts):
+        it.K = 120
+        it.instance_id = 200 + q
+    # about two small requests fit next to the resident tables at a time
+    c = M.mesh_sdd_ctx_create(0, 3 << 20)
+    try:
+        H = Handles(M, c, insts, M.FP32)
+        try:
+            alone = solve_alone(M, H, insts)
+            st = steps_for(M, insts)
+            tickets = [M.mesh_sdd_submit(h, s) for h, s in zip(H.h, st)]
+            seen_queue = M.mesh_sdd_ctx_stats(c).queued
+            for q, t in enumerate(tickets):
+                arrs, res = M.host_result(H.m[q])
+                assert M.mesh_sdd_wait(c, t, res, 120_000)
+                assert same(alone[q], M.result_dict(arrs, res, H.m[q])), q
+            s = M.mesh_sdd_ctx_stats(c)
+            say("small budget: queued right after submit %d, in use %d of %d B, ticks %d"
+                % (seen_queue, s.hbm_in_use, s.hbm_budget, s.ticks))
+            assert s.hbm_in_use <= s.hbm_budget and s.completed == len(insts)
+        finally:
+            H.close()
+        # a request larger than the whole budget is refused at submit
+        big = W.config2(n_paths=1_000_000)
+        h = M.mesh_sdd_create(c, M.desc_for(big, M.FP32))
+        try:
+            M.mesh_sdd_set_monitor(h, big.rho)
+            with pytest.raises(M.MeshSddError) as e:
+                M.mesh_sdd_submit(h, M.make_step(big.x, big.y, big.bnd_t0, big.bnd_t1, paths_per_node=big.n_paths))
+            assert e.value.code == M.E_BUDGET
+        finally:
+            M.mesh_sdd_destroy(h)
+    finally:
+        M.mesh_sdd_ctx_destroy(c)
+
+
+def test_error_paths(M, ctx):
+    inst = W.config1(500)
+    inst.K = 20
+    h = M.mesh_sdd_create(ctx, M.desc_for(inst, M.FP32))
+    try:
+        m = M.mesh_sdd_num_interface_nodes(h)
+        arrs, res = M.host_result(m)
+        st = M.make_step(inst.x, inst.y, inst.bnd_t0, inst.bnd_t1, paths_per_node=500)
+        with pytest.raises(M.MeshSddError) as e:          # before set_monitor
+            M.mesh_sdd_solve_interfaces(h, st, res)
+        assert e.value.code == M.E_STATE
+        bad_rho = inst.rho.copy()
+        bad_rho[3, 3] = -1.0
+        with pytest.raises(M.MeshSddError) as e:
+            M.mesh_sdd_set_monitor(h, bad_rho)
+        assert e.value.code == M.E_INVAL
+        M.mesh_sdd_set_monitor(h, inst.rho)
+        b = inst.bnd_t1.copy()
+        b[0] += 1e-3                                      # corner (xi=0, eta=0) disagrees
+        with pytest.raises(M.MeshSddError) as e:
+            M.mesh_sdd_solve_interfaces(h, M.make_step(inst.x, inst.y, inst.bnd_t0, b, paths_per_node=500), res)
+        assert e.value.code == M.E_INVAL
+        with pytest.raises(M.MeshSddError) as e:
+            M.mesh_sdd_solve_interfaces(h, M.make_step(inst.x, inst.y, inst.bnd_t0, inst.bnd_t1, paths_per_node=0), res)
+        assert e.value.code == M.E_INVAL
+        # destroy with a request in flight is refused
+        t = M.mesh_sdd_submit(h, st)
+        try:
+            M.mesh_sdd_destroy(h)
+            destroyed = True
+        except M.MeshSddError as e2:
+            destroyed = False
+            assert e2.code == M.E_STATE
+        if not destroyed:
+            assert M.mesh_sdd_wait(ctx, t, res, 60_000)
+        else:   # the request finished before destroy: nothing left to wait for
+            h = None
+    finally:
+        if h is not None:
+            M.mesh_sdd_destroy(h)
+
+
+def test_degenerate_cases(M, ctx):
+    # no interface node at all
+    inst = W.constant_problem(9, 1, 0, 0, tau=0.01, K=10, n_paths=100)
+    h = M.mesh_sdd_create(ctx, M.desc_for(inst, M.FP32))
+    try:
+        M.mesh_sdd_set_monitor(h, inst.rho)
+        assert M.mesh_sdd_num_interface_nodes(h) == 0
+        arrs, res = M.host_result(0)
+        M.mesh_sdd_solve_interfaces(h, M.make_step(inst.x, inst.y, inst.bnd_t0, inst.bnd_t1, paths_per_node=100), res)
+        assert res.executed_path_steps == 0
+    finally:
+        M.mesh_sdd_destroy(h)
+    # one path per node: SE is NaN, the mean is the single path's value
+    inst = W.config1(1)
+    inst.K = 30
+    for prec in (M.FP32, M.FP64):
+        g = M.solve_instance(ctx, inst, prec)
+        assert np.all(np.isnan(g["se_x"])) and np.all(np.isfinite(g["mean_x"]))
+
+
+def test_device_pointers_match_host(M, ctx):
+    import torch
+    inst = W.config1(2000)
+    inst.K = 60
+    dev = torch.device("cuda:0")
+    h = M.mesh_sdd_create(ctx, M.desc_for(inst, M.FP32))
+    try:
+        m = M.mesh_sdd_num_interface_nodes(h)
+        M.mesh_sdd_set_monitor(h, torch.from_numpy(inst.rho).to(dev))
+        tx, ty = torch.from_numpy(inst.x).to(dev), torch.from_numpy(inst.y).to(dev)
+        t0, t1 = torch.from_numpy(inst.bnd_t0).to(dev), torch.from_numpy(inst.bnd_t1).to(dev)
+        outs = [torch.full((m,), float("nan"), dtype=torch.float64, device=dev) for _ in range(5)]
+        torch.cuda.synchronize()
+        res = M.make_result(*outs)
+        M.mesh_sdd_solve_interfaces(h, M.make_step(tx, ty, t0, t1, paths_per_node=2000), res)
+        torch.cuda.synchronize()
+        g_dev = {k: o.cpu().numpy() for k, o in zip(("mean_x", "mean_y", "se_x", "se_y", "exit_frac"), outs)}
+        g_dev["executed_path_steps"] = int(res.executed_path_steps)
+        M.mesh_sdd_set_monitor(h, inst.rho)
+        arrs, res2 = M.host_result(m)
+        M.mesh_sdd_solve_interfaces(h, M.make_step(inst.x, inst.y, inst.bnd_t0, inst.bnd_t1, paths_per_node=2000), res2)
+        assert same(g_dev, M.result_dict(arrs, res2, m))
+    finally:
+        M.mesh_sdd_destroy(h)
+
+
+def test_target_se_sets_path_count(M, ctx):
+    inst = W.config1(1)
+    inst.K = 40
+    h = M.mesh_sdd_create(ctx, M.desc_for(inst, M.FP32))
+    try:
+        M.mesh_sdd_set_monitor(h, inst.rho)
+        m = M.mesh_sdd_num_interface_nodes(h)
+        arrs, res = M.host_result(m)
+        se = 3e-3
+        st = M.make_step(inst.x, inst.y, inst.bnd_t0, inst.bnd_t1, target_se=se)
+        M.mesh_sdd_solve_interfaces(h, st, res)
+        want = int(np.ceil(2 * inst.tau * 1.0 / se ** 2))
+        assert res.paths_per_node == want
+        g = M.result_dict(arrs, res, m)
+        assert np.max(np.maximum(g["se_x"], g["se_y"])) <= se
+    finally:
+        M.mesh_sdd_destroy(h)
