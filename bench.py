@@ -28,7 +28,7 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # Algorithmic VALU issue slots per executed path-step (see the design notes:
 # Philox 0.75 blocks, Box-Muller, bilinear of three fields, drift, EM, exit
 # test), weighted by the measured issue cost of each instruction class.
-W_SLOTS_PER_STEP = 120.0
+W_SLOTS_PER_STEP = 99.5
 
 
 def log(*a):

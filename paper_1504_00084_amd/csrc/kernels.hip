@@ -80,13 +80,16 @@ __device__ __forceinline__ double uniform_f64(uint32_t r)
 }
 
 // ---------------------------------------------------------------------------
-// Uniform (per-instance) constants of the FP32 path, loaded once per item.
+// FP32 path: per-instance constants (wave-uniform)
 // ---------------------------------------------------------------------------
 struct ConstF {
     int n_xi, n_eta, nx1, ny1;
     int per_xi, per_eta, bridge, K;
-    float fnx1, fny1, dt, sq2dt, inv_dt, inv_tau, Lx, Ly;
-    const GLOBAL f32x4 *cells;
+    float fnx1, fny1, dt, inv_dt, inv_tau, Lx, Ly;
+    float c_rad;   // -4 ln2 dt, so that sqrt(c_rad log2 u) = sqrt(2 dt) sqrt(-2 ln u)
+    float sq2dt;   // sqrt(2 dt) (diagnostics only)
+    float delta;   // sqrt(18.5 dt): farther from every side, no bridge crossing can matter
+    const GLOBAL f32x4 *cells;   // per cell: rho, dt rho_xi, dt rho_eta in coefficient form
 };
 
 __device__ __forceinline__ ConstF load_const_f(const InstView &I)
@@ -103,17 +106,20 @@ __device__ __forceinline__ ConstF load_const_f(const InstView &I)
     c.fnx1 = (float)(I.n_xi - 1);
     c.fny1 = (float)(I.n_eta - 1);
     c.dt = I.dt_f;
-    c.sq2dt = I.sq2dt_f;
     c.inv_dt = I.inv_dt_f;
     c.inv_tau = I.inv_tau_f;
     c.Lx = I.Lx_f;
     c.Ly = I.Ly_f;
+    c.c_rad = I.c_rad_f;
+    c.sq2dt = I.sq2dt_f;
+    c.delta = I.delta_f;
     c.cells = (const GLOBAL f32x4 *)I.cells;
     return c;
 }
 
 struct PathF {
     float x, y;   // position in [0,1]^2 (periodic axes wrapped)
+    float m;      // distance of (x, y) to the nearest Dirichlet side (1e30 without one)
     int wx, wy;   // winding numbers
     int k;        // substeps done
 };
@@ -127,23 +133,36 @@ __device__ __forceinline__ int cell_of(float s, int n1, float &t)
     return c;
 }
 
+// Distance of (x, y) to the nearest Dirichlet side; negative when outside.
+__device__ __forceinline__ float side_distance(const ConstF &C, float x, float y)
+{
+    float m = 1.0e30f;
+    if (!C.per_xi) m = fminf(m, fminf(x, 1.0f - x));
+    if (!C.per_eta) m = fminf(m, fminf(y, 1.0f - y));
+    return m;
+}
+
 // One EM substep of the FP32 path (a3-a6).  Returns the exit side (0: xi=0,
 // 1: xi=1, 2: eta=0, 3: eta=1) with the position moved onto it, or -1.
 __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t wa, uint32_t wb, uint32_t wc,
                                            float *trace4)
 {
-    // a3: Box-Muller on two stream words; hardware log2 / sqrt / sin / cos
-    // (sin and cos take revolutions: sin(2 pi u)).
+    // a3: Box-Muller on two stream words with the hardware log2 / sqrt /
+    // sin / cos (sin and cos take revolutions); sqrt(2 dt) is folded into
+    // the radius: rad = sqrt(2 dt) sqrt(-2 ln u0).
     const float u0 = uniform_f32(wa);
     const float u1 = uniform_f32(wb);
-    const float rad = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u0));
-    const float n1 = rad * __builtin_amdgcn_cosf(u1);
-    const float n2 = rad * __builtin_amdgcn_sinf(u1);
+    const float rad = __builtin_amdgcn_sqrtf(C.c_rad * __builtin_amdgcn_logf(u0));
+    const float cs = __builtin_amdgcn_cosf(u1);
+    const float sn = __builtin_amdgcn_sinf(u1);
 
-    // a4: bilinear interpolation of (rho, rho_xi, rho_eta) on the cell.
+    // a4: bilinear interpolation of (rho, dt rho_xi, dt rho_eta) on the cell
+    // (x, y lie in [0, 1], so the truncation is the floor).
     float tx, ty;
-    const int cx = cell_of(P.x * C.fnx1, C.nx1, tx);
-    const int cy = cell_of(P.y * C.fny1, C.ny1, ty);
+    const int cx = min((int)(P.x * C.fnx1), C.nx1 - 1);
+    const int cy = min((int)(P.y * C.fny1), C.ny1 - 1);
+    tx = P.x * C.fnx1 - (float)cx;
+    ty = P.y * C.fny1 - (float)cy;
     const GLOBAL f32x4 *cell = C.cells + (uint32_t)(3 * (cy * C.nx1 + cx));
     const f32x4 A = cell[0], B = cell[1], G = cell[2];
     const float rho = fmaf(ty, fmaf(A.w, tx, A.z), fmaf(A.y, tx, A.x));
@@ -151,9 +170,9 @@ __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t w
     const float gy = fmaf(ty, fmaf(G.w, tx, G.z), fmaf(G.y, tx, G.x));
     const float inv_rho = __builtin_amdgcn_rcpf(rho);
 
-    // a5: Euler-Maruyama.
-    float nx = fmaf(C.sq2dt, n1, fmaf(gx * inv_rho, C.dt, P.x));
-    float ny = fmaf(C.sq2dt, n2, fmaf(gy * inv_rho, C.dt, P.y));
+    // a5: Euler-Maruyama, x + (grad rho / rho) dt + sqrt(2 dt) N.
+    float nx = fmaf(rad, cs, fmaf(gx, inv_rho, P.x));
+    float ny = fmaf(rad, sn, fmaf(gy, inv_rho, P.y));
 
     // a6: periodic wrap with winding.
     if (C.per_xi) {
@@ -174,40 +193,41 @@ __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t w
             P.wy += 1;
         }
     }
-
     if (trace4) {   // diagnostics: position after the wrap, before any exit projection
         trace4[0] = nx;
         trace4[1] = ny;
-        trace4[2] = n1;
-        trace4[3] = n2;
+        trace4[2] = rad * cs / C.sq2dt;
+        trace4[3] = rad * sn / C.sq2dt;
     }
 
-    // a6: endpoint outside a Dirichlet side.
+    // a6: one distance serves both tests: negative -> the endpoint left a
+    // Dirichlet side; below delta at either end -> a bridge crossing may matter.
+    const float m = side_distance(C, nx, ny);
     int side = -1;
-    if (!C.per_xi) {
-        if (nx < 0.0f) {
-            side = 0;
-            nx = 0.0f;
-        } else if (nx > 1.0f) {
-            side = 1;
-            nx = 1.0f;
+    if (m < 0.0f) {
+        // endpoint outside; several sides out -> corner, first side crossed
+        if (!C.per_xi) {
+            if (nx < 0.0f) {
+                side = 0;
+                nx = 0.0f;
+            } else if (nx > 1.0f) {
+                side = 1;
+                nx = 1.0f;
+            }
         }
-    }
-    if (!C.per_eta) {
-        if (ny < 0.0f) {
-            side = side < 0 ? 2 : side;
-            ny = 0.0f;
-        } else if (ny > 1.0f) {
-            side = side < 0 ? 3 : side;
-            ny = 1.0f;
+        if (!C.per_eta) {
+            if (ny < 0.0f) {
+                side = side < 0 ? 2 : side;
+                ny = 0.0f;
+            } else if (ny > 1.0f) {
+                side = side < 0 ? 3 : side;
+                ny = 1.0f;
+            }
         }
-    }
-
-    // a6: Brownian bridge between the two inside points.  A side with
-    // d0 d1 / dt > 18.5 has crossing probability < 2^-26.6, too small to
-    // beat the smallest uniform (2^-24) even summed over four sides, so the
-    // exponentials are evaluated only when some side is that close.
-    if (side < 0 && C.bridge) {
+    } else if (C.bridge && fminf(P.m, m) < C.delta) {
+        // Brownian bridge between the two inside points: crossing probability
+        // exp(-d0 d1 / dt) per side; d0 d1 / dt > 18.5 gives < 2^-26.6, below
+        // the smallest uniform even summed over four sides.
         const float big = 1.0e30f;
         const float a0 = C.per_xi ? big : P.x * nx * C.inv_dt;
         const float a1 = C.per_xi ? big : (1.0f - P.x) * (1.0f - nx) * C.inv_dt;
@@ -241,6 +261,7 @@ __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t w
     }
     P.x = nx;
     P.y = ny;
+    P.m = m;
     return side;
 }
 
@@ -346,79 +367,6 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
     return v;
 }
 
-// Runs one work item with one wave (lanes refilled from the chunk).
-__device__ __forceinline__ void run_item_f32(const InstView &I, uint32_t node, uint32_t p_begin, uint32_t count,
-                                             GLOBAL Partial *out)
-{
-    const ConstF C = load_const_f(I);
-    const int i0 = gptr(I.node_i)[node], j0 = gptr(I.node_j)[node];
-    const float x0 = (float)((double)i0 / (double)C.nx1);
-    const float y0 = (float)((double)j0 / (double)C.ny1);
-    const double refx = gptr(I.x64)[(uint32_t)(j0 * C.n_xi + i0)];
-    const double refy = gptr(I.y64)[(uint32_t)(j0 * C.n_xi + i0)];
-    const uint32_t key0 = I.key0, key1 = I.key1, ctr3 = I.ctr3;
-
-    double s1x = 0.0, s2x = 0.0, s1y = 0.0, s2y = 0.0;
-    unsigned long long exits = 0, steps = 0;
-
-    PathF P{x0, y0, 0, 0, 0};
-    uint32_t path = 0;
-    bool has = false;
-    uint32_t issued = 0;          // paths of the chunk handed out (wave-uniform)
-
-    for (;;) {
-        // refill lanes that have no path with the chunk's next paths, in lane order
-        if (issued < count) {
-            const uint64_t need = __ballot(!has);
-            const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(need >> 32),
-                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
-            if (!has && issued + below < count) {
-                has = true;
-                path = p_begin + issued + below;
-                P.x = x0;
-                P.y = y0;
-                P.wx = 0;
-                P.wy = 0;
-                P.k = 0;
-            }
-            issued += (uint32_t)__popcll(need);
-        }
-        if (__ballot(has) == 0) break;
-        if (has) {
-            bool ended;
-            const int side = group_f32<false>(P, C, path, node, ctr3, key0, key1, ended, nullptr);
-            if (ended) {
-                float vx, vy;
-                path_value_f32(I, C, P, side, vx, vy);
-                const double dx = (double)vx - refx, dy = (double)vy - refy;
-                s1x += dx;
-                s2x = fma(dx, dx, s2x);
-                s1y += dy;
-                s2y = fma(dy, dy, s2y);
-                exits += side >= 0 ? 1u : 0u;
-                steps += (unsigned long long)P.k;
-                has = false;
-            }
-        }
-    }
-    s1x = wave_sum(s1x);
-    s2x = wave_sum(s2x);
-    s1y = wave_sum(s1y);
-    s2y = wave_sum(s2y);
-    exits = wave_sum_u64(exits);
-    steps = wave_sum_u64(steps);
-    // Every lane holds the same totals after the butterfly and stores them:
-    // no lane-conditional branch is left next to the item loop, which the
-    // compiler could otherwise merge with the pop of the next item into a
-    // path where lane 0 leaves the loop that the others keep shuffling in.
-    out->s1x = s1x;
-    out->s2x = s2x;
-    out->s1y = s1y;
-    out->s2y = s2y;
-    out->exits = exits;
-    out->steps = steps;
-}
-
 // Next item of the queue for the whole wave.  Every lane takes part in the
 // atomic (lane 0 adds 1, the others 0), so the pop has no lane-conditional
 // branch; lane 0's old value is the wave's item.
@@ -428,34 +376,206 @@ __device__ __forceinline__ uint32_t pop_item(uint32_t *head, int lane)
     return __builtin_amdgcn_readfirstlane(old);
 }
 
+// Decoded work item (wave-uniform).
+struct ItemF {
+    uint32_t inst, node, p_begin, count, partial;
+};
+
+__device__ __forceinline__ ItemF decode_item(const GLOBAL WorkRange *rg, uint32_t n_ranges, uint32_t it)
+{
+    // range holding launch item `it` (ranges are sorted by base, base[0] = 0)
+    uint32_t lo = 0, hi = n_ranges;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (rg[mid].base <= it)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    const GLOBAL WorkRange &R = rg[lo];
+    const uint32_t M = R.M, chunk_paths = R.chunk_paths;
+    const uint32_t q = R.first + (it - R.base);   // request-wide item, chunk-major
+    const uint32_t c = q / M;
+    ItemF f;
+    f.inst = R.inst;
+    f.node = q - c * M;
+    f.p_begin = c * chunk_paths;
+    f.count = min(chunk_paths, R.N - f.p_begin);
+    f.partial = f.node * R.chunks + c;
+    return f;
+}
+
+// Fixed-order reduction of one item's per-path values held in LDS (dx at
+// buf[0..count), dy at buf[cap..cap+count)), plus the lanes' exit and step
+// counts of that item; every lane stores the identical totals.
+__device__ __forceinline__ void flush_item(const float *buf, uint32_t cap, uint32_t count, int lane, uint32_t exits,
+                                           unsigned long long steps, GLOBAL Partial *out)
+{
+    double s1x = 0.0, s2x = 0.0, s1y = 0.0, s2y = 0.0;
+    for (uint32_t j = (uint32_t)lane; j < count; j += 64u) {
+        const double dx = (double)buf[j], dy = (double)buf[cap + j];
+        s1x += dx;
+        s2x = fma(dx, dx, s2x);
+        s1y += dy;
+        s2y = fma(dy, dy, s2y);
+    }
+    s1x = wave_sum(s1x);
+    s2x = wave_sum(s2x);
+    s1y = wave_sum(s1y);
+    s2y = wave_sum(s2y);
+    const unsigned long long ex = wave_sum_u64((unsigned long long)exits);
+    const unsigned long long st = wave_sum_u64(steps);
+    out->s1x = s1x;
+    out->s2x = s2x;
+    out->s1y = s1y;
+    out->s2y = s2y;
+    out->exits = ex;
+    out->steps = st;
+}
+
+// Persistent batched kernel.  Each wave keeps up to two work items in
+// flight: the one whose paths it is handing out and the one whose last
+// paths are finishing, so lanes never wait for an item to drain.  A lane
+// whose path ended takes the next path at a four-substep boundary; its
+// value (v - v_ref) goes to the item's LDS slot at the path's index, and a
+// drained item is reduced in a fixed order, so the sums do not depend on
+// which lane ran which path.  Items of another instance start once both
+// slots are drained (the per-instance constants are wave-uniform).
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void paths_fp32(const InstView *__restrict__ insts,
                                                     const WorkRange *__restrict__ ranges, uint32_t n_ranges,
-                                                    uint32_t n_items, uint32_t *__restrict__ head)
+                                                    uint32_t n_items, uint32_t *__restrict__ head, uint32_t cap)
 {
+    extern __shared__ float lds[];
     const int lane = threadIdx.x & 63;
+    float *buf = lds + (size_t)(threadIdx.x >> 6) * 4u * cap;   // [slot][dx | dy][cap]
     const GLOBAL WorkRange *rg = gptr(ranges);
-    uint32_t it = pop_item(head, lane);
-    while (it < n_items) {
-        // range holding launch item `it` (ranges are sorted by base, base[0] = 0)
-        uint32_t lo = 0, hi = n_ranges;
-        while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (rg[mid].base <= it)
-                lo = mid;
-            else
-                hi = mid;
+
+    // wave-uniform state
+    uint32_t next = pop_item(head, lane);
+    uint32_t cur_inst = 0xFFFFFFFFu;
+    const InstView *Ip = insts;
+    ConstF C{};
+    uint32_t key0 = 0, key1 = 0, ctr3 = 0;
+    uint32_t act0 = 0, act1 = 0, cnt0 = 0, cnt1 = 0, rem0 = 0, rem1 = 0;
+    uint32_t node0 = 0, node1 = 0, pb0 = 0, pb1 = 0, part0 = 0, part1 = 0;
+    float x00 = 0.f, y00 = 0.f, m00 = 0.f, x01 = 0.f, y01 = 0.f, m01 = 0.f;
+    double rx0 = 0.0, ry0 = 0.0, rx1 = 0.0, ry1 = 0.0;
+    uint32_t cur = 0, issued = 0;
+    bool issuing = false;
+
+    // lane state
+    bool has = false;
+    uint32_t which = 0, slot = 0, path = 0, node = 0;
+    PathF P{0.f, 0.f, 0.f, 0, 0, 0};
+    uint32_t ex0 = 0, ex1 = 0;
+    unsigned long long st0 = 0, st1 = 0;
+
+    for (;;) {
+        // start the next item in the free slot (another instance only when
+        // both slots are drained)
+        if (!issuing && next < n_items) {
+            const ItemF f = decode_item(rg, n_ranges, next);
+            if (f.count == 0u) {   // never produced by the host; skipped so that no slot waits on it
+                next = pop_item(head, lane);
+                continue;
+            }
+            const uint32_t tgt = act0 ? (act1 ? 2u : 1u) : 0u;
+            const bool same = f.inst == cur_inst;
+            if (tgt < 2u && (same || (act0 == 0u && act1 == 0u))) {
+                if (!same) {
+                    cur_inst = f.inst;
+                    Ip = insts + f.inst;
+                    C = load_const_f(*Ip);
+                    key0 = Ip->key0;
+                    key1 = Ip->key1;
+                    ctr3 = Ip->ctr3;
+                }
+                const int i0 = gptr(Ip->node_i)[f.node], j0 = gptr(Ip->node_j)[f.node];
+                const float x0 = (float)((double)i0 / (double)C.nx1);
+                const float y0 = (float)((double)j0 / (double)C.ny1);
+                const float m0 = side_distance(C, x0, y0);
+                const double rx = gptr(Ip->x64)[(uint32_t)(j0 * C.n_xi + i0)];
+                const double ry = gptr(Ip->y64)[(uint32_t)(j0 * C.n_xi + i0)];
+                if (tgt == 0u) {
+                    act0 = 1u; cnt0 = f.count; rem0 = f.count; node0 = f.node; pb0 = f.p_begin;
+                    part0 = f.partial; x00 = x0; y00 = y0; m00 = m0; rx0 = rx; ry0 = ry;
+                } else {
+                    act1 = 1u; cnt1 = f.count; rem1 = f.count; node1 = f.node; pb1 = f.p_begin;
+                    part1 = f.partial; x01 = x0; y01 = y0; m01 = m0; rx1 = rx; ry1 = ry;
+                }
+                cur = tgt;
+                issued = 0;
+                issuing = f.count > 0;
+                next = pop_item(head, lane);
+            }
         }
-        const GLOBAL WorkRange &R = rg[lo];
-        const uint32_t M = R.M, chunk_paths = R.chunk_paths;
-        const uint32_t q = R.first + (it - R.base);    // request-wide item, chunk-major
-        const uint32_t c = q / M;
-        const uint32_t node = q - c * M;
-        const uint32_t p_begin = c * chunk_paths;
-        const uint32_t count = min(chunk_paths, R.N - p_begin);
-        const InstView &I = insts[R.inst];
-        run_item_f32(I, node, p_begin, count, gptr_rw(I.partials) + (node * R.chunks + c));
-        it = pop_item(head, lane);
+        // refill lanes without a path from the item being handed out, in lane order
+        if (issuing) {
+            const uint32_t count = cur ? cnt1 : cnt0;
+            const uint64_t need = __ballot(!has);
+            const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(need >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
+            if (!has && issued + below < count) {
+                has = true;
+                which = cur;
+                slot = issued + below;
+                path = (cur ? pb1 : pb0) + slot;
+                node = cur ? node1 : node0;
+                P.x = cur ? x01 : x00;
+                P.y = cur ? y01 : y00;
+                P.m = cur ? m01 : m00;
+                P.wx = 0;
+                P.wy = 0;
+                P.k = 0;
+            }
+            issued = min(count, issued + (uint32_t)__popcll(need));
+            issuing = issued < count;
+        }
+        if (__ballot(has) == 0) {
+            if (issuing) continue;
+            if (next >= n_items && act0 == 0u && act1 == 0u) break;
+            continue;   // both slots drained: the next item starts at the top
+        }
+        // advance every path by one group of four substeps
+        bool ended = false;
+        if (has) {
+            const int side = group_f32<false>(P, C, path, node, ctr3, key0, key1, ended, nullptr);
+            if (ended) {
+                float vx, vy;
+                path_value_f32(*Ip, C, P, side, vx, vy);
+                const double rx = which ? rx1 : rx0, ry = which ? ry1 : ry0;
+                float *b = buf + (size_t)which * 2u * cap;
+                b[slot] = (float)((double)vx - rx);
+                b[cap + slot] = (float)((double)vy - ry);
+                const uint32_t e = side >= 0 ? 1u : 0u;
+                if (which) {
+                    ex1 += e;
+                    st1 += (unsigned long long)P.k;
+                } else {
+                    ex0 += e;
+                    st0 += (unsigned long long)P.k;
+                }
+                has = false;
+            }
+        }
+        const uint64_t end_mask = __ballot(ended);
+        const uint64_t in1 = __ballot(which != 0u);
+        rem0 -= (uint32_t)__popcll(end_mask & ~in1);
+        rem1 -= (uint32_t)__popcll(end_mask & in1);
+        // reduce and write the items whose paths have all ended
+        if (act0 && rem0 == 0u && !(issuing && cur == 0u)) {
+            flush_item(buf, cap, cnt0, lane, ex0, st0, gptr_rw(Ip->partials) + part0);
+            ex0 = 0;
+            st0 = 0;
+            act0 = 0u;
+        }
+        if (act1 && rem1 == 0u && !(issuing && cur == 1u)) {
+            flush_item(buf + 2u * cap, cap, cnt1, lane, ex1, st1, gptr_rw(Ip->partials) + part1);
+            ex1 = 0;
+            st1 = 0;
+            act1 = 0u;
+        }
     }
 }
 
@@ -759,7 +879,8 @@ __global__ void prep_gradient_kernel(const double *__restrict__ in, int n_xi, in
 }
 
 __global__ void prep_cells_kernel(const double *__restrict__ rho, const double *__restrict__ rx,
-                                  const double *__restrict__ ry, int n_xi, int n_eta, float4 *cells)
+                                  const double *__restrict__ ry, int n_xi, int n_eta, double grad_scale,
+                                  float4 *cells)
 {
     const int nx1 = n_xi - 1, ny1 = n_eta - 1;
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
@@ -768,7 +889,8 @@ __global__ void prep_cells_kernel(const double *__restrict__ rho, const double *
     const size_t a = (size_t)cy * n_xi + cx, b = a + n_xi;
     const double *f[3] = {rho, rx, ry};
     for (int c = 0; c < 3; ++c) {
-        const double f00 = f[c][a], f10 = f[c][a + 1], f01 = f[c][b], f11 = f[c][b + 1];
+        const double sc = c == 0 ? 1.0 : grad_scale;   // gradient fields carry the factor dt
+        const double f00 = sc * f[c][a], f10 = sc * f[c][a + 1], f01 = sc * f[c][b], f11 = sc * f[c][b + 1];
         cells[3 * (size_t)idx + c] = make_float4((float)f00, (float)(f10 - f00), (float)(f01 - f00),
                                                  (float)(f11 - f10 - f01 + f00));
     }
@@ -867,7 +989,8 @@ __global__ void debug_paths_kernel(const InstView *__restrict__ inst, int fp64, 
     }
     const ConstF C = load_const_f(I);
     const int i0 = I.node_i[node], j0 = I.node_j[node];
-    PathF P{(float)((double)i0 / (double)C.nx1), (float)((double)j0 / (double)C.ny1), 0, 0, 0};
+    PathF P{(float)((double)i0 / (double)C.nx1), (float)((double)j0 / (double)C.ny1), 0.0f, 0, 0, 0};
+    P.m = side_distance(C, P.x, P.y);
     int side = -1;
     bool ended = false;
     while (!ended) {
@@ -898,11 +1021,11 @@ hipError_t launch_prep_gradient(const double *rho_in, int n_xi, int n_eta, int p
 }
 
 hipError_t launch_prep_cells(const double *rho, const double *rho_xi, const double *rho_eta, int n_xi, int n_eta,
-                             float4 *cells, hipStream_t s)
+                             double grad_scale, float4 *cells, hipStream_t s)
 {
     const size_t n = (size_t)(n_xi - 1) * (n_eta - 1);
     hipLaunchKernelGGL(prep_cells_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, rho, rho_xi, rho_eta, n_xi,
-                       n_eta, cells);
+                       n_eta, grad_scale, cells);
     return hipGetLastError();
 }
 
@@ -930,29 +1053,32 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t s)
 }
 
 hipError_t launch_paths_fp32(const InstView *insts, const WorkRange *ranges, uint32_t n_ranges, uint32_t n_items,
-                             uint32_t *head, int grid, int block, hipStream_t s)
+                             uint32_t *head, uint32_t cap, int grid, int block, hipStream_t s)
 {
     hipError_t e = launch_fill_u32(head, 0u, 1, s);
     if (e != hipSuccess) return e;
     if (n_items == 0) return hipSuccess;
+    const size_t lds = paths_fp32_lds_bytes(block, cap);
     switch (block) {
     case 64:
-        hipLaunchKernelGGL(paths_fp32<64>, dim3(grid), dim3(64), 0, s, insts, ranges, n_ranges, n_items, head);
+        hipLaunchKernelGGL(paths_fp32<64>, dim3(grid), dim3(64), lds, s, insts, ranges, n_ranges, n_items, head, cap);
         break;
     case 128:
-        hipLaunchKernelGGL(paths_fp32<128>, dim3(grid), dim3(128), 0, s, insts, ranges, n_ranges, n_items, head);
+        hipLaunchKernelGGL(paths_fp32<128>, dim3(grid), dim3(128), lds, s, insts, ranges, n_ranges, n_items, head, cap);
         break;
     case 256:
-        hipLaunchKernelGGL(paths_fp32<256>, dim3(grid), dim3(256), 0, s, insts, ranges, n_ranges, n_items, head);
+        hipLaunchKernelGGL(paths_fp32<256>, dim3(grid), dim3(256), lds, s, insts, ranges, n_ranges, n_items, head, cap);
         break;
     case 512:
-        hipLaunchKernelGGL(paths_fp32<512>, dim3(grid), dim3(512), 0, s, insts, ranges, n_ranges, n_items, head);
+        hipLaunchKernelGGL(paths_fp32<512>, dim3(grid), dim3(512), lds, s, insts, ranges, n_ranges, n_items, head, cap);
         break;
     default:
         return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
+
+size_t paths_fp32_lds_bytes(int block, uint32_t cap) { return (size_t)(block / 64) * 4u * cap * sizeof(float); }
 
 hipError_t launch_paths_fp64(const InstView *inst, uint32_t M, uint32_t n_paths, uint32_t chunks_per_node,
                              Partial *partials, hipStream_t s)
@@ -985,15 +1111,16 @@ hipError_t launch_debug_paths(const InstView *inst, int fp64, uint32_t node, uin
     return hipGetLastError();
 }
 
-int paths_fp32_blocks_per_cu(int block)
+int paths_fp32_blocks_per_cu(int block, uint32_t cap)
 {
     int n = 0;
     hipError_t e = hipErrorInvalidValue;
+    const size_t lds = paths_fp32_lds_bytes(block, cap);
     switch (block) {
-    case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32<64>, 64, 0); break;
-    case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32<128>, 128, 0); break;
-    case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32<256>, 256, 0); break;
-    case 512: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32<512>, 512, 0); break;
+    case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32<64>, 64, lds); break;
+    case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32<128>, 128, lds); break;
+    case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32<256>, 256, lds); break;
+    case 512: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32<512>, 512, lds); break;
     default: break;
     }
     return e == hipSuccess ? n : 0;

@@ -44,12 +44,14 @@ struct InstView {
     uint32_t ctr3;                // instance_id << 16 | mesh_step & 0xffff
     uint32_t pad1;
     double Lx, Ly, tau, dt;       // extents, mesh step, substep
-    float Lx_f, Ly_f, dt_f, sq2dt_f, inv_dt_f, inv_tau_f, pad2, pad3;
+    float Lx_f, Ly_f, dt_f, sq2dt_f, inv_dt_f, inv_tau_f;
+    float c_rad_f;                // -4 ln2 dt
+    float delta_f;                // sqrt(18.5 dt)
 
     const int32_t *node_i, *node_j;   // interface nodes in rank order
 
     // FP32 path: per-cell bilinear coefficients (three float4 per cell:
-    // rho, rho_xi, rho_eta as a + b tx + c ty + d tx ty), (n_xi-1)(n_eta-1)
+    // rho, dt rho_xi, dt rho_eta as a + b tx + c ty + d tx ty), (n_xi-1)(n_eta-1)
     // cells; padded mesh [n_eta+2][n_xi+2] with ghost / wrapped values,
     // origin at node (-1, -1); boundary arrays in the C-ABI layout.
     const float4 *cells;

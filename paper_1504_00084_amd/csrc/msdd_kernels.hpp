@@ -14,9 +14,10 @@ namespace msdd {
 hipError_t launch_prep_gradient(const double *rho_in, int n_xi, int n_eta, int per_xi, int per_eta,
                                 double *rho, double *rho_xi, double *rho_eta, hipStream_t s);
 
-// a0 (FP32 path): per-cell bilinear coefficients of (rho, rho_xi, rho_eta).
+// a0 (FP32 path): per-cell bilinear coefficients of (rho, s rho_xi, s rho_eta)
+// with s = grad_scale (the substep dt).
 hipError_t launch_prep_cells(const double *rho, const double *rho_xi, const double *rho_eta, int n_xi,
-                             int n_eta, float4 *cells, hipStream_t s);
+                             int n_eta, double grad_scale, float4 *cells, hipStream_t s);
 
 // a7 set-up: padded mesh [n_eta+2][n_xi+2] (ghost rows / columns by Keys'
 // rule on Dirichlet axes, wrapped with quasi-periodic offsets on periodic
@@ -31,8 +32,11 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t s)
 // a2-a8, FP32: persistent batched kernel over a work queue of n_items items
 // described by n_ranges ranges (sorted by base, contiguous from 0).  `head`
 // is the queue counter (zeroed by this launcher).
+// `cap` >= every range's chunk_paths: each wave holds two items' per-path
+// values in LDS (4 * cap floats per wave).
 hipError_t launch_paths_fp32(const InstView *insts, const WorkRange *ranges, uint32_t n_ranges, uint32_t n_items,
-                             uint32_t *head, int grid, int block, hipStream_t s);
+                             uint32_t *head, uint32_t cap, int grid, int block, hipStream_t s);
+size_t paths_fp32_lds_bytes(int block, uint32_t cap);
 
 // a2-a8, FP64 plain: one thread per path, one launch per instance; the
 // partial of (node, chunk) goes to partials[node * chunks + chunk].
@@ -50,8 +54,9 @@ hipError_t launch_debug_paths(const InstView *inst, int fp64, uint32_t node, uin
                               double *vx, double *vy, int32_t *exited, int32_t *side, int32_t *steps,
                               double *trace, hipStream_t s);
 
-// Occupancy of the FP32 kernel: resident workgroups per CU for `block`.
-int paths_fp32_blocks_per_cu(int block);
+// Occupancy of the FP32 kernel: resident workgroups per CU for `block` and
+// LDS capacity `cap`.
+int paths_fp32_blocks_per_cu(int block, uint32_t cap);
 // Register / LDS usage of the FP32 kernel for `block` (for reports).
 int paths_fp32_attributes(int block, int *vgprs, int *sgprs, int *lds_bytes);
 

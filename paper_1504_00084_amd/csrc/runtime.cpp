@@ -376,7 +376,7 @@ mesh_sdd_launch default_launch()
     l.struct_size = sizeof(mesh_sdd_launch);
     l.block = 256;
     l.waves_per_simd = 0;   // 0: as many as the registers allow
-    l.chunk_paths = 1024;
+    l.chunk_paths = 512;
     l.table_in_lds = 0;
     return l;
 }
@@ -390,10 +390,10 @@ mesh_sdd_launch launch_for(mesh_sdd_ctx *ctx, const mesh_sdd_desc &d)
     return default_launch();
 }
 
-int grid_for(mesh_sdd_ctx *ctx, const mesh_sdd_launch &l)
+int grid_for(mesh_sdd_ctx *ctx, const mesh_sdd_launch &l, uint32_t cap)
 {
     const int waves_per_block = l.block / 64;
-    int per_cu = msdd::paths_fp32_blocks_per_cu(l.block);   // resident blocks per CU
+    int per_cu = msdd::paths_fp32_blocks_per_cu(l.block, cap);   // resident blocks per CU (registers, LDS)
     if (per_cu < 1) per_cu = 1;
     if (l.waves_per_simd > 0) {
         const int want = std::max(1, (l.waves_per_simd * 4) / waves_per_block);
@@ -513,6 +513,8 @@ int stage_request(Request &r, const mesh_sdd_step *dev_step)
     v.sq2dt_f = (float)std::sqrt(2.0 * v.dt);
     v.inv_dt_f = (float)(1.0 / v.dt);
     v.inv_tau_f = (float)(1.0 / d.tau);
+    v.c_rad_f = (float)(-4.0 * std::log(2.0) * v.dt);
+    v.delta_f = (float)std::sqrt(18.5 * v.dt);
     v.node_i = inst.dev_i.as<int32_t>();
     v.node_j = inst.dev_j.as<int32_t>();
     v.cells = inst.cells.as<float4>();
@@ -574,6 +576,9 @@ int run_fp32_launch(mesh_sdd_ctx *ctx, const std::vector<InstView> &views, const
         return MESH_SDD_OK;
     }
     if (n_items > 0xFFFFFFF0u) return fail(MESH_SDD_E_INVAL, "too many work items in one launch");
+    uint32_t cap = 64;   // LDS slots per item: the largest chunk of the launch
+    for (const WorkRange &w : ranges) cap = std::max(cap, w.chunk_paths);
+    cap = (cap + 63u) / 64u * 64u;
     if (ctx->views.reserve(views.size() * sizeof(InstView)) ||
         ctx->ranges.reserve(ranges.size() * sizeof(WorkRange)) || ctx->head.reserve(64))
         return fail(MESH_SDD_E_NOMEM, "device allocation for the work queue failed");
@@ -585,7 +590,7 @@ int run_fp32_launch(mesh_sdd_ctx *ctx, const std::vector<InstView> &views, const
     HIP_TRY(hipEventRecord(e0, st));
     hipError_t le = msdd::launch_paths_fp32(ctx->views.as<InstView>(), ctx->ranges.as<WorkRange>(),
                                             (uint32_t)ranges.size(), (uint32_t)n_items, ctx->head.as<uint32_t>(),
-                                            grid_for(ctx, l), l.block, st);
+                                            cap, grid_for(ctx, l, cap), l.block, st);
     HIP_TRY(hipEventRecord(e1, st));
     hipError_t se = hipEventSynchronize(e1);
     float t = 0.0f;
@@ -1013,8 +1018,9 @@ int mesh_sdd_set_launch(mesh_sdd_ctx *ctx, const mesh_sdd_launch *launch)
         return fail(MESH_SDD_E_INVAL, "block must be 64, 128, 256 or 512");
     if (launch->waves_per_simd < 0 || launch->waves_per_simd > 8)
         return fail(MESH_SDD_E_INVAL, "waves_per_simd must be in [0, 8]");
-    if (launch->chunk_paths < 64 || launch->chunk_paths % 64 || launch->chunk_paths > (1 << 24))
-        return fail(MESH_SDD_E_INVAL, "chunk_paths must be a multiple of 64 in [64, 2^24]");
+    if (launch->chunk_paths < 64 || launch->chunk_paths % 64 || launch->chunk_paths > 2048 ||
+        msdd::paths_fp32_lds_bytes(launch->block, (uint32_t)launch->chunk_paths) > 160u * 1024u)
+        return fail(MESH_SDD_E_INVAL, "chunk_paths must be a multiple of 64 in [64, 2048] and fit in LDS");
     ctx->override_launch = *launch;
     ctx->has_override = true;
     return MESH_SDD_OK;
@@ -1025,7 +1031,7 @@ int mesh_sdd_get_launch(mesh_sdd *inst, mesh_sdd_launch *out)
     if (!inst || !out) return fail(MESH_SDD_E_INVAL, "NULL argument");
     *out = launch_for(inst->ctx, inst->d);
     if (out->waves_per_simd == 0) {
-        const int per_cu = msdd::paths_fp32_blocks_per_cu(out->block);
+        const int per_cu = msdd::paths_fp32_blocks_per_cu(out->block, (uint32_t)out->chunk_paths);
         out->waves_per_simd = per_cu * (out->block / 64) / 4;
     }
     return MESH_SDD_OK;
@@ -1121,7 +1127,7 @@ int mesh_sdd_set_monitor(mesh_sdd *inst, const double *rho, int is_device_ptr)
     HIP_TRY(msdd::launch_prep_gradient(inst->rho_in.as<double>(), d.n_xi, d.n_eta, d.periodic_xi, d.periodic_eta,
                                        inst->rho.as<double>(), inst->rho_xi.as<double>(), inst->rho_eta.as<double>(), st));
     HIP_TRY(msdd::launch_prep_cells(inst->rho.as<double>(), inst->rho_xi.as<double>(), inst->rho_eta.as<double>(),
-                                    d.n_xi, d.n_eta, inst->cells.as<float4>(), st));
+                                    d.n_xi, d.n_eta, d.tau / (double)d.K, inst->cells.as<float4>(), st));
     HIP_TRY(hipStreamSynchronize(st));
     inst->monitor_set = true;
     return MESH_SDD_OK;
@@ -1313,10 +1319,8 @@ int mesh_sdd_autotune(mesh_sdd *inst, const mesh_sdd_step *step, mesh_sdd_launch
     mesh_sdd_ctx *ctx = inst->ctx;
     // candidates: residency x chunk size, timed on a reduced path count
     const int blocks[] = {256};
-    const int chunks[] = {256, 512, 1024, 2048};
-    const int max_waves = std::max(1, msdd::paths_fp32_blocks_per_cu(256) * 4 / 4);
-    std::vector<int> waves;
-    for (int w = 1; w <= max_waves; ++w) waves.push_back(w);
+    const int chunks[] = {128, 256, 512, 1024};
+    std::vector<int> waves = {2, 3, 4, 5, 6, 8};
     mesh_sdd_step s = *step;
     s.target_se = 0.0;
     s.paths_per_node = std::min<int64_t>(N, std::max<int64_t>(4096, 2000000 / std::max(1, inst->M)));
@@ -1336,6 +1340,8 @@ int mesh_sdd_autotune(mesh_sdd *inst, const mesh_sdd_step *step, mesh_sdd_launch
                 l.block = b;
                 l.chunk_paths = c;
                 l.waves_per_simd = w;
+                // skip shapes whose registers or LDS do not allow w waves per SIMD
+                if (msdd::paths_fp32_blocks_per_cu(b, (uint32_t)c) * (b / 64) < w * 4) continue;
                 {
                     std::lock_guard<std::mutex> lk(ctx->mu);
                     ctx->override_launch = l;
