@@ -393,12 +393,13 @@ __device__ __forceinline__ ItemF decode_item(const GLOBAL WorkRange *rg, uint32_
             hi = mid;
     }
     const GLOBAL WorkRange &R = rg[lo];
-    const uint32_t M = R.M, chunk_paths = R.chunk_paths;
-    const uint32_t q = R.first + (it - R.base);   // request-wide item, chunk-major
-    const uint32_t c = q / M;
+    const uint32_t chunks = R.chunks, chunk_paths = R.chunk_paths;
+    const uint32_t q = R.first + (it - R.base);   // request-wide item, node-major
+    const uint32_t node = q / chunks;
+    const uint32_t c = q - node * chunks;
     ItemF f;
     f.inst = R.inst;
-    f.node = q - c * M;
+    f.node = node;
     f.p_begin = c * chunk_paths;
     f.count = min(chunk_paths, R.N - f.p_begin);
     f.partial = f.node * R.chunks + c;

@@ -8,10 +8,11 @@
 namespace msdd {
 
 // The work of one request inside one launch of the batched kernel.  A
-// request's work items are numbered chunk-major (item = chunk * M + node):
+// request's work items are numbered node-major (item = node * chunks + c):
 // item q covers paths [c * chunk_paths, min(N, (c + 1) * chunk_paths)) of
-// node q mod M, with c = q div M, and its sums go to partial slot
-// node * chunks + c.  The range holds the request's items
+// node q div chunks, with c = q mod chunks, and its sums go to partial slot
+// q itself.  Concurrent waves then work on a few neighbouring nodes, whose
+// paths visit the same cells, so the cell gathers hit in the L1 cache.  The range holds the request's items
 // [first, first + count), which are items [base, base + count) of the launch.
 struct WorkRange {
     uint32_t inst;         // InstView slot in the launch

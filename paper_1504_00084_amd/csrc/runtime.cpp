@@ -200,7 +200,7 @@ struct Request {
     DevBuf x64, y64, b0, b1, xpad, ypad, xpad_f, ypad_f, b0f, b1f;
     DevBuf view, partials, spans, out, steps_total;
     InstView v{};
-    size_t n_items = 0;            // FP32 work items (chunk-major, see WorkRange)
+    size_t n_items = 0;            // FP32 work items (node-major, see WorkRange)
     size_t next_item = 0;          // first item not yet handed to a tick
     size_t done_items = 0;
     uint32_t chunks_per_node = 0;
@@ -540,9 +540,9 @@ int stage_request(Request &r, const mesh_sdd_step *dev_step)
     if (M) HIP_TRY(hipMemcpyAsync(r.spans.p, spans.data(), spans.size() * sizeof(NodeSpan), hipMemcpyHostToDevice, st));
     HIP_TRY(msdd::launch_fill_u32(r.steps_total.as<uint32_t>(), 0u, 2, st));
 
-    // FP32 work: every (node, chunk), numbered chunk-major so that chunk c of
-    // every node comes before chunk c+1 (concurrent waves spread over the
-    // nodes, and each node's short last chunk comes at the end)
+    // FP32 work: every (node, chunk), numbered node-major, so that the waves
+    // running at one time share a few neighbouring nodes (L1 locality of the
+    // cell gathers)
     r.n_items = fp64 ? 0 : n_part;
     r.next_item = 0;
     r.done_items = 0;
