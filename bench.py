@@ -25,10 +25,11 @@ sys.path.insert(0, ROOT)
 # VALU issue peak of MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz (one
 # non-packed VALU lane-operation per lane per clock).
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-# Algorithmic VALU issue slots per executed path-step (see the design notes:
-# Philox 0.75 blocks, Box-Muller, bilinear of three fields, drift, EM, exit
-# test), weighted by the measured issue cost of each instruction class.
-W_SLOTS_PER_STEP = 99.5
+# Algorithmic VALU issue slots per executed path-step (Philox 0.75 blocks,
+# two uniforms, Box-Muller, bilinear cell location and three fields, drift,
+# EM, side distance, exit and bridge pre-tests, substep counter), weighted by
+# the measured issue cost of each instruction class.
+W_SLOTS_PER_STEP = 86.5
 
 
 def log(*a):

@@ -143,7 +143,7 @@ typedef struct {
     int32_t block;                   /* threads per workgroup (64, 128, 256, 512)    */
     int32_t waves_per_simd;          /* persistent residency target (1..8)           */
     int32_t chunk_paths;             /* paths per work item (multiple of 64)         */
-    int32_t table_in_lds;            /* 1: stage the monitor table in LDS when it fits */
+    int32_t reserved;                /* must be 0                                    */
 } mesh_sdd_launch;
 
 /* ---- context ------------------------------------------------------------ */

@@ -375,9 +375,11 @@ mesh_sdd_launch default_launch()
     mesh_sdd_launch l{};
     l.struct_size = sizeof(mesh_sdd_launch);
     l.block = 256;
-    l.waves_per_simd = 0;   // 0: as many as the registers allow
+    // three waves per SIMD: the cell gathers saturate the L1 pipeline there,
+    // and more resident waves only add L1 misses (measured on gfx950)
+    l.waves_per_simd = 3;
     l.chunk_paths = 512;
-    l.table_in_lds = 0;
+    l.reserved = 0;
     return l;
 }
 
@@ -1021,6 +1023,7 @@ int mesh_sdd_set_launch(mesh_sdd_ctx *ctx, const mesh_sdd_launch *launch)
     if (launch->chunk_paths < 64 || launch->chunk_paths % 64 || launch->chunk_paths > 2048 ||
         msdd::paths_fp32_lds_bytes(launch->block, (uint32_t)launch->chunk_paths) > 160u * 1024u)
         return fail(MESH_SDD_E_INVAL, "chunk_paths must be a multiple of 64 in [64, 2048] and fit in LDS");
+    if (launch->reserved != 0) return fail(MESH_SDD_E_INVAL, "launch.reserved must be 0");
     ctx->override_launch = *launch;
     ctx->has_override = true;
     return MESH_SDD_OK;

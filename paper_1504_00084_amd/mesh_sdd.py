@@ -75,7 +75,7 @@ class Stats(ctypes.Structure):
 
 class Launch(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("block", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32),
-                ("chunk_paths", ctypes.c_int32), ("table_in_lds", ctypes.c_int32)]
+                ("chunk_paths", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 _lib = None
@@ -188,8 +188,8 @@ def mesh_sdd_get_launch(inst) -> Launch:
     return lo
 
 
-def make_launch(block=256, waves_per_simd=0, chunk_paths=1024, table_in_lds=0) -> Launch:
-    return Launch(ctypes.sizeof(Launch), block, waves_per_simd, chunk_paths, table_in_lds)
+def make_launch(block=256, waves_per_simd=3, chunk_paths=512) -> Launch:
+    return Launch(ctypes.sizeof(Launch), block, waves_per_simd, chunk_paths, 0)
 
 
 def mesh_sdd_autotune(inst, step: Step) -> Launch:
