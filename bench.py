@@ -31,6 +31,27 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # the measured issue cost of each instruction class.
 W_SLOTS_PER_STEP = 86.5
 
+# HBM traffic of one paths_fp32 launch on the 129x129, 4x4 workload at the
+# default launch shape (block 256, 3 waves per SIMD, 512-path chunks), from
+# two rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE, KiB
+# per dispatch), each scaled by what the counter reads for a 1 GiB device
+# copy in the same run (FETCH_SIZE reads 524308 KiB: x2.0; WRITE_SIZE reads
+# 1048576 KiB: x1.0).  Valid only for the kernel source it was measured on
+# (SHA-1 of csrc/kernels.hip); reported as null otherwise.
+TRAFFIC_RECORD = {"kernels_sha1": "4b6dd3b3f592464498021edb8ef1f4d88eac0056", "fetch_kib": 4212.25, "write_kib": 13615.2,
+                  "fetch_scale": 2.0, "write_scale": 1.0}
+
+
+def recorded_traffic():
+    import hashlib
+    src = os.path.join(ROOT, "paper_1504_00084_amd", "csrc", "kernels.hip")
+    with open(src, "rb") as f:
+        sha = hashlib.sha1(f.read()).hexdigest()
+    r = TRAFFIC_RECORD
+    if sha != r["kernels_sha1"]:
+        return None
+    return 1024.0 * (r["fetch_kib"] * r["fetch_scale"] + r["write_kib"] * r["write_scale"])
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -44,8 +65,10 @@ def parse():
     ap.add_argument("--paths", type=int, default=100_000)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 plain comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-tune", action="store_true", help="use the default launch shape")
-    ap.add_argument("--launch", default="", help="fixed launch shape BLOCK,WAVES_PER_SIMD,CHUNK (skips autotuning)")
+    ap.add_argument("--tune", action="store_true",
+                    help="run the library's autotuner first (default: the library's default launch shape, the "
+                         "one the recorded HBM traffic was measured with)")
+    ap.add_argument("--launch", default="", help="fixed launch shape BLOCK,WAVES_PER_SIMD,CHUNK")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU work of the oracle sample")
     ap.add_argument("--mode", default="step", choices=["step", "batch", "serve"],
                     help="step: the metric line (rotating bump 129^2); batch: the 64-instance mix in one "
@@ -55,7 +78,8 @@ def parse():
     ap.add_argument("--requests", type=int, default=40, help="requests in serve mode")
     ap.add_argument("--rate", type=float, default=0.0,
                     help="arrival rate in req/s for serve mode (0: 0.7 x the measured capacity)")
-    ap.add_argument("--serve-sizes", default="33,65,129,257,513", help="grid sizes of the serving mix")
+    ap.add_argument("--serve-sizes", default="33,65,129", help="grid sizes of the serving mix")
+    ap.add_argument("--serve-max-paths", type=int, default=200_000, help="cap on a request's paths per node")
     ap.add_argument("--serve-precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--budget-mb", type=int, default=0, help="HBM budget of the serving context (0: 90%% free)")
     ap.add_argument("--copy-mb", type=int, default=0,
@@ -111,7 +135,7 @@ def main():
     if args.launch:
         b, w, c = (int(v) for v in args.launch.split(","))
         M.mesh_sdd_set_launch(ctx, M.make_launch(b, w, c))
-    elif not args.no_tune:
+    elif args.tune:
         t = time.time()
         lo = M.mesh_sdd_autotune(h32, step)
         log("autotune: block %d, waves/SIMD %d, chunk %d (%.1f s)" % (lo.block, lo.waves_per_simd, lo.chunk_paths,
@@ -169,7 +193,7 @@ def main():
     per_launch = executed / args.steps
     achieved = W_SLOTS_PER_STEP * per_launch / kern_s / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 3), "unit": "TOP/s",
-                "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
+                "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": recorded_traffic(),
                 "kernel": "paths_fp32", "kernel_ms": round(kern_s * 1e3, 3),
                 "path_steps_per_launch": per_launch, "slots_per_path_step": W_SLOTS_PER_STEP}
 
@@ -283,7 +307,8 @@ def run_serve(args):
     M.load()
     sizes = tuple(int(v) for v in args.serve_sizes.split(","))
     prec = M.FP32 if args.serve_precision == "fp32" else M.FP64
-    stream = W.serving_stream(args.requests, rate_hz=1.0, sizes=sizes)   # unit rate, rescaled below
+    stream = W.serving_stream(args.requests, rate_hz=1.0, sizes=sizes,   # unit rate, rescaled below
+                              max_paths=args.serve_max_paths)
     work = []
     for _, it, _ in stream:
         m = len(M.mesh_sdd_desc_interface_nodes(M.desc_for(it))[0])
@@ -321,6 +346,9 @@ def run_serve(args):
         with lock:
             done.append(int(r.executed_path_steps))
             e2e.append(time.perf_counter() - ts)
+            log("request %d done (%d of %d): %.3e path-steps, %.1f ms" % (k, len(done), len(stream),
+                                                                         float(r.executed_path_steps),
+                                                                         1e3 * e2e[-1]))
 
     threads = [threading.Thread(target=client, args=(k,)) for k in range(len(stream))]
     for th in threads:
