@@ -172,8 +172,8 @@ int mesh_sdd_get_launch(mesh_sdd *inst, mesh_sdd_launch *out);
 
 /* Autotune the batched kernel for the shape bucket of `inst` (grid size,
  * periodicity) by timing candidate shapes on a reduced path count of
- * `step`; the result is cached in the context (and in the file named by
- * MESH_SDD_TUNE_CACHE when set).  Writes the winner to *out if non-NULL. */
+ * `step`; the result is cached in the context for later launches of that
+ * bucket.  Writes the winner to *out if non-NULL. */
 int mesh_sdd_autotune(mesh_sdd *inst, const mesh_sdd_step *step, mesh_sdd_launch *out);
 
 /* ---- host-only helpers (no device needed) --------------------------------- */
@@ -245,6 +245,96 @@ int mesh_sdd_wait(mesh_sdd_ctx *ctx, mesh_sdd_ticket ticket, mesh_sdd_result *re
 
 /* Cancel a queued request (E_STATE if it is already running). */
 int mesh_sdd_cancel(mesh_sdd_ctx *ctx, mesh_sdd_ticket ticket);
+
+/* ---- the mesh step around the interface estimate (sections 2, 3.5-3.7) ------ */
+
+/* Options of the deterministic parts of a mesh step (all FP64). */
+typedef struct {
+    uint32_t struct_size;
+    int32_t fe_substeps;             /* forward-Euler steps over tau of the 2-D solves;
+                                        0: the smallest L with tau / L <= fe_cfl /
+                                        (2 / h_xi^2 + 2 / h_eta^2)                    */
+    int32_t edge_substeps;           /* same for the 1-D edge generator (limit h^2/2)  */
+    int32_t edge_generator;          /* mesh_sdd_mp_step only: 1 = tangential boundary
+                                        values at t^{n+1} from the 1-D generator,
+                                        0 = taken from step->bnd_t1                    */
+    int32_t solver;                  /* subdomain solves: 0 automatic, 1 each subdomain
+                                        resident in LDS (E_INVAL if one does not fit:
+                                        at most 4096 interior nodes), 2 whole-grid
+                                        sweeps in global memory                        */
+    int32_t reserved;                /* must be 0                                      */
+    double fe_cfl;                   /* fraction of the stability limit, (0, 1];
+                                        0 means 0.9                                    */
+} mesh_sdd_mp_opts;
+
+/* Tangential boundary values at t^{n+1} (section 2): on every physical side
+ * the component along the side follows the one-dimensional form of the
+ * generator, v_t = (rho_s / rho) v_s + v_ss, with the monitor frozen at t^n
+ * (the instance's table: set_monitor first), the end values fixed on a
+ * Dirichlet axis and wrapped with the period on a periodic one; forward Euler
+ * with centred differences.  Normal components, and the sides normal to a
+ * periodic axis, are copied.  bnd_cur, bnd_new: boundary arrays in the layout
+ * above (may be the same array), host or device memory (pointers_on_device).
+ * E_STATE before set_monitor; E_INVAL on null pointers or bad options. */
+int mesh_sdd_edge_generate(mesh_sdd *inst, const double *bnd_cur, double *bnd_new, const mesh_sdd_mp_opts *opts,
+                           int pointers_on_device);
+
+/* Subdomain solves (section 3.5): each subdomain of the partition is a
+ * Dirichlet problem of eq. (Gen) with the monitor frozen at t^n, integrated
+ * over tau from the mesh at t^n (x_cur, y_cur) by forward Euler with centred
+ * differences.  Dirichlet data move linearly in time from the mesh at t^n to
+ * their values at t^{n+1}: interface nodes take iface_x / iface_y (length M,
+ * rank order, e.g. a result's mean_x / mean_y), physical-boundary nodes the
+ * boundary arrays bnd_new, the images of a periodic seam their original plus
+ * the period.  Writes the new mesh x_new, y_new ([n_eta][n_xi]; must not
+ * alias the inputs).  Host or device memory (pointers_on_device).
+ * E_STATE before set_monitor; E_INVAL on null pointers or bad options. */
+int mesh_sdd_subdomain_solve(mesh_sdd *inst, const double *x_cur, const double *y_cur, const double *bnd_new,
+                             const double *iface_x, const double *iface_y, double *x_new, double *y_new,
+                             const mesh_sdd_mp_opts *opts, int pointers_on_device);
+
+/* Single-domain reference of the same step (section 3.7): as
+ * mesh_sdd_subdomain_solve without interfaces (Dirichlet data on the physical
+ * boundary only; periodic axes wrap).  Always runs whole-grid sweeps. */
+int mesh_sdd_single_domain_solve(mesh_sdd *inst, const double *x_cur, const double *y_cur, const double *bnd_new,
+                                 double *x_new, double *y_new, const mesh_sdd_mp_opts *opts, int pointers_on_device);
+
+/* One mesh step (sections 3.4-3.6): the boundary arrays at t^{n+1} (edge
+ * generator, or step->bnd_t1), the interface estimate with the boundary data
+ * moving from step->bnd_t0 to them (as mesh_sdd_solve_interfaces), then the
+ * subdomain solves.  Writes the new mesh (x_new, y_new), the new boundary
+ * arrays (bnd_new) and the interface estimate (result).  Inputs follow
+ * step->inputs_on_device, outputs result->outputs_on_device.  Blocking.
+ * Errors as the calls it is made of. */
+int mesh_sdd_mp_step(mesh_sdd *inst, const mesh_sdd_step *step, const mesh_sdd_mp_opts *opts, double *x_new,
+                     double *y_new, double *bnd_new, mesh_sdd_result *result);
+
+/* Monitor of the next step from the solution on the new mesh (section 3.6):
+ * rho = sqrt(1 + a |grad u|^2) at every node, u, x, y nodal [n_eta][n_xi];
+ * grad u in physical coordinates from centred computational differences
+ * (one-sided second order at Dirichlet edges; wrapped, with the period added
+ * to the winding coordinate, on periodic axes) through the inverse mesh
+ * Jacobian; a = alpha, or alpha / max |grad u|^2 when normalize != 0.
+ * Installs rho as mesh_sdd_set_monitor does.  E_INVAL if alpha is negative
+ * or not finite, or if |grad u| is not finite somewhere (vanishing mesh
+ * Jacobian); E_STATE with requests in flight. */
+int mesh_sdd_set_monitor_arclength(mesh_sdd *inst, const double *u, const double *x, const double *y, double alpha,
+                                   int normalize, int pointers_on_device);
+
+/* Copy the frozen monitor rho ([n_eta][n_xi], as installed) into rho_out
+ * (host or device memory).  E_STATE before set_monitor. */
+int mesh_sdd_get_monitor(mesh_sdd *inst, double *rho_out, int pointer_on_device);
+
+/* Geometric mesh quality (section 3.7, eq. Q): Q(K) = tr(J^T J) / (2 |det J|)
+ * per cell K, J the Jacobian of the bilinear cell map at the cell centre
+ * (computational spacing 1/(n-1)); R(K) = Q_SD(K) / Q_SDD(K) of a
+ * single-domain mesh (x_sd, y_sd) and a decomposed one (x_dd, y_dd) on the
+ * instance's grid.  Writes *r_max and *r_mean (host) and, when r_cells is not
+ * NULL, R per cell [(n_eta - 1)][(n_xi - 1)] (memory kind as the meshes).
+ * E_INVAL on null pointers or a degenerate cell (R not finite). */
+int mesh_sdd_mesh_quality(mesh_sdd *inst, const double *x_sd, const double *y_sd, const double *x_dd,
+                          const double *y_dd, double *r_cells, double *r_max, double *r_mean,
+                          int pointers_on_device);
 
 /* ---- diagnostics ----------------------------------------------------------- */
 

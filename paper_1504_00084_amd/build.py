@@ -27,7 +27,9 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", "-I" + INCLUDE, "-I" + CSRC, "-Wall", "-
 
 SOURCES = [
     ("kernels.hip", ["--offload-arch=" + ARCH] + DEVICE_FLAGS),
+    ("mesh_step.hip", ["--offload-arch=" + ARCH] + DEVICE_FLAGS),
     ("runtime.cpp", []),
+    ("mesh_step.cpp", []),
 ]
 
 
@@ -36,7 +38,7 @@ def hipcc() -> str:
 
 
 def _compile(src: str, extra: list[str]) -> str:
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+    obj = os.path.join(BUILD, src.replace(".", "_") + ".o")
     cmd = [hipcc(), "-c"] + COMMON + extra + [os.path.join(CSRC, src), "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:

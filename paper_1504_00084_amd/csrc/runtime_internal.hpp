@@ -1,0 +1,245 @@
+// Internals of the host runtime shared by its source files (runtime.cpp:
+// contexts, instances, requests, scheduler; mesh_step.cpp: the mesh step
+// around the interface estimate).  Not part of the C-ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstddef>
+#include <cstdint>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <tuple>
+#include <unordered_map>
+#include <vector>
+
+#include "mesh_sdd.h"
+#include "msdd_device.hpp"
+#include "msdd_kernels.hpp"
+
+namespace msdd_rt {
+
+// Sets the calling thread's last-error text (mesh_sdd_last_error) and
+// returns `code`.
+int fail(int code, const char *fmt, ...);
+
+#define HIP_TRY(expr)                                                                                     \
+    do {                                                                                                  \
+        hipError_t e_ = (expr);                                                                           \
+        if (e_ != hipSuccess) return fail(MESH_SDD_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+using Clock = std::chrono::steady_clock;
+
+inline double ms_since(Clock::time_point t0)
+{
+    return std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+}
+
+// Free device blocks kept for reuse, keyed by their exact size (requests of
+// the same shape reuse the same blocks, so steady-state solves call neither
+// hipMalloc nor hipFree).  Bounded: blocks beyond `cap` bytes are freed.
+struct DevPool {
+    std::mutex mu;
+    std::multimap<size_t, void *> free_blocks;
+    size_t pooled = 0;
+    size_t cap = (size_t)1 << 30;
+    ~DevPool() { trim(0); }
+    void *get(size_t n)
+    {
+        {
+            std::lock_guard<std::mutex> g(mu);
+            auto it = free_blocks.find(n);
+            if (it != free_blocks.end()) {
+                void *p = it->second;
+                free_blocks.erase(it);
+                pooled -= n;
+                return p;
+            }
+        }
+        void *p = nullptr;
+        if (hipMalloc(&p, n) != hipSuccess) {
+            trim(0);   // give cached blocks back and try once more
+            if (hipMalloc(&p, n) != hipSuccess) return nullptr;
+        }
+        return p;
+    }
+    void put(void *p, size_t n)
+    {
+        std::lock_guard<std::mutex> g(mu);
+        free_blocks.emplace(n, p);
+        pooled += n;
+        while (pooled > cap && !free_blocks.empty()) {
+            auto it = free_blocks.begin();
+            pooled -= it->first;
+            (void)hipFree(it->second);
+            free_blocks.erase(it);
+        }
+    }
+    void trim(size_t keep)
+    {
+        std::lock_guard<std::mutex> g(mu);
+        while (pooled > keep && !free_blocks.empty()) {
+            auto it = free_blocks.begin();
+            pooled -= it->first;
+            (void)hipFree(it->second);
+            free_blocks.erase(it);
+        }
+    }
+};
+
+// Device allocation owned by one object (from a pool when one is given).
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevPool *pool = nullptr;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    void release()
+    {
+        if (p) {
+            if (pool)
+                pool->put(p, bytes);
+            else
+                (void)hipFree(p);
+        }
+        p = nullptr;
+        bytes = 0;
+    }
+    hipError_t alloc(size_t n)
+    {
+        release();
+        n = n == 0 ? 256 : (n + 255) / 256 * 256;
+        if (pool) {
+            p = pool->get(n);
+            if (!p) return hipErrorOutOfMemory;
+            bytes = n;
+            return hipSuccess;
+        }
+        hipError_t e = hipMalloc(&p, n);
+        if (e == hipSuccess)
+            bytes = n;
+        else
+            p = nullptr;
+        return e;
+    }
+    // grow-only reuse
+    hipError_t reserve(size_t n)
+    {
+        if (n <= bytes && p) return hipSuccess;
+        return alloc(n);
+    }
+    template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+inline size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+}  // namespace msdd_rt
+
+using msdd_rt::Clock;
+using msdd_rt::DevBuf;
+using msdd_rt::DevPool;
+using msdd::InstView;
+
+// ---------------------------------------------------------------------------
+// Objects behind the opaque handles
+// ---------------------------------------------------------------------------
+struct Request;
+
+struct mesh_sdd {
+    mesh_sdd_ctx *ctx = nullptr;
+    mesh_sdd_desc d{};
+    int32_t M = 0;
+    std::vector<int32_t> node_i, node_j;
+    DevBuf dev_i, dev_j;                    // interface nodes
+    DevBuf rho_in, rho, rho_xi, rho_eta;    // FP64 monitor staging and node tables
+    DevBuf cells;                           // FP32 per-cell bilinear coefficients
+    DevBuf node_rank;                       // [n_eta][n_xi] interface rank or -1 (mesh step; built on first use)
+    bool monitor_set = false;
+    std::atomic<int> inflight{0};
+    size_t resident_bytes = 0;
+};
+
+struct Request {
+    uint64_t ticket = 0;
+    mesh_sdd *inst = nullptr;      // valid until the request finishes
+    int32_t M = 0;                 // interface nodes (kept for poll after finish)
+    int64_t N = 0;
+    uint32_t mesh_step = 0;
+    int chunk_paths = 0;
+    // host snapshots of host inputs
+    std::vector<double> hx, hy, hb0, hb1;
+    // device buffers owned by the request
+    DevBuf x64, y64, b0, b1, xpad, ypad, xpad_f, ypad_f, b0f, b1f;
+    DevBuf view, partials, spans, out, steps_total;
+    InstView v{};
+    size_t n_items = 0;            // FP32 work items (node-major, see WorkRange)
+    size_t next_item = 0;          // first item not yet handed to a tick
+    size_t done_items = 0;
+    uint32_t chunks_per_node = 0;
+    size_t cost_bytes = 0;
+    // completion
+    int status = MESH_SDD_PENDING;
+    std::string error;
+    std::vector<double> host_out;  // 5 * M
+    uint64_t executed_steps = 0;
+    double device_ms = 0.0;
+    Clock::time_point t_submit, t_done;
+    bool finished = false;
+    bool admitted = false;
+    bool cancelled = false;
+};
+
+struct TuneKey {
+    int n_xi, n_eta, per_xi, per_eta;
+    bool operator<(const TuneKey &o) const
+    {
+        return std::tie(n_xi, n_eta, per_xi, per_eta) < std::tie(o.n_xi, o.n_eta, o.per_xi, o.per_eta);
+    }
+};
+
+struct mesh_sdd_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int cu_count = 0;
+    size_t budget = 0;
+
+    DevPool pool;        // recycled request buffers (declared before users)
+    std::mutex gpu_mu;   // serialises use of the stream and the launch scratch below
+    DevBuf head, views, ranges;
+
+    std::mutex mu;       // guards everything below
+    std::condition_variable cv, done_cv;
+    size_t in_use = 0;
+    int n_instances = 0;
+    std::deque<std::shared_ptr<Request>> queue;    // submitted, not admitted
+    std::vector<std::shared_ptr<Request>> running; // admitted, not finished
+    std::unordered_map<uint64_t, std::shared_ptr<Request>> tickets;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    std::thread worker;
+
+    // stats
+    uint64_t submitted = 0, completed = 0, failed = 0, cancelled = 0, ticks = 0, executed = 0;
+    double busy_ms = 0.0;
+    std::vector<double> latencies;
+
+    // launch shapes
+    bool has_override = false;
+    mesh_sdd_launch override_launch{};
+    std::map<TuneKey, mesh_sdd_launch> tuned;
+};
+
+namespace msdd_rt {
+int install_monitor(mesh_sdd *inst, hipStream_t st);
+}  // namespace msdd_rt

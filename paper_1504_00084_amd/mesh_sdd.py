@@ -30,7 +30,9 @@ EXPORTS = (
     "mesh_sdd_num_interface_nodes", "mesh_sdd_interface_nodes", "mesh_sdd_solve_interfaces",
     "mesh_sdd_solve_batch", "mesh_sdd_submit", "mesh_sdd_poll", "mesh_sdd_wait", "mesh_sdd_cancel",
     "mesh_sdd_debug_paths", "mesh_sdd_last_error", "mesh_sdd_version", "mesh_sdd_desc_check",
-    "mesh_sdd_desc_interface_nodes",
+    "mesh_sdd_desc_interface_nodes", "mesh_sdd_edge_generate", "mesh_sdd_subdomain_solve",
+    "mesh_sdd_single_domain_solve", "mesh_sdd_mp_step", "mesh_sdd_set_monitor_arclength", "mesh_sdd_get_monitor",
+    "mesh_sdd_mesh_quality",
 )
 
 
@@ -62,6 +64,12 @@ class Result(ctypes.Structure):
                 ("se_y", ctypes.c_void_p), ("exit_frac", ctypes.c_void_p),
                 ("executed_path_steps", ctypes.c_uint64), ("paths_per_node", ctypes.c_int64),
                 ("device_ms", ctypes.c_double)]
+
+
+class MpOpts(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("fe_substeps", ctypes.c_int32), ("edge_substeps", ctypes.c_int32),
+                ("edge_generator", ctypes.c_int32), ("solver", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("fe_cfl", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -114,6 +122,13 @@ def load(path: str = LIB_PATH):
         "mesh_sdd_desc_interface_nodes": [P(Desc), vp, vp],
         "mesh_sdd_last_error": [],
         "mesh_sdd_version": [],
+        "mesh_sdd_edge_generate": [vp, vp, vp, P(MpOpts), ctypes.c_int],
+        "mesh_sdd_subdomain_solve": [vp, vp, vp, vp, vp, vp, vp, vp, P(MpOpts), ctypes.c_int],
+        "mesh_sdd_single_domain_solve": [vp, vp, vp, vp, vp, vp, P(MpOpts), ctypes.c_int],
+        "mesh_sdd_mp_step": [vp, P(Step), P(MpOpts), vp, vp, vp, P(Result)],
+        "mesh_sdd_set_monitor_arclength": [vp, vp, vp, vp, ctypes.c_double, ctypes.c_int, ctypes.c_int],
+        "mesh_sdd_get_monitor": [vp, vp, ctypes.c_int],
+        "mesh_sdd_mesh_quality": [vp, vp, vp, vp, vp, vp, P(ctypes.c_double), P(ctypes.c_double), ctypes.c_int],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -357,3 +372,66 @@ def solve_instance(ctx, inst, precision=FP32, n_paths=None, mesh_step=None):
         return result_dict(arrs, res, m)
     finally:
         mesh_sdd_destroy(h)
+
+
+# --------------------------------------------------------------------------
+# the mesh step around the interface estimate
+# --------------------------------------------------------------------------
+def make_mp_opts(fe_substeps=0, edge_substeps=0, edge_generator=1, solver=0, fe_cfl=0.0) -> MpOpts:
+    return MpOpts(ctypes.sizeof(MpOpts), int(fe_substeps), int(edge_substeps), int(edge_generator), int(solver), 0,
+                  float(fe_cfl))
+
+
+def _same_kind(*arrays):
+    ptrs = [_ptr(a) for a in arrays]
+    devs = {d for p, d in ptrs if p is not None}
+    if len(devs) > 1:
+        raise ValueError("arrays must be all host arrays or all device tensors")
+    return [p for p, _ in ptrs], int(devs.pop() if devs else False)
+
+
+def _opts(opts):
+    return ctypes.byref(opts) if opts is not None else None
+
+
+def mesh_sdd_edge_generate(inst, bnd_cur, bnd_new, opts: MpOpts | None = None) -> None:
+    (pc, pn), dev = _same_kind(bnd_cur, bnd_new)
+    _check(load().mesh_sdd_edge_generate(inst, pc, pn, _opts(opts), dev))
+
+
+def mesh_sdd_subdomain_solve(inst, x_cur, y_cur, bnd_new, iface_x, iface_y, x_new, y_new,
+                             opts: MpOpts | None = None) -> None:
+    ptrs, dev = _same_kind(x_cur, y_cur, bnd_new, iface_x, iface_y, x_new, y_new)
+    _check(load().mesh_sdd_subdomain_solve(inst, *ptrs, _opts(opts), dev))
+
+
+def mesh_sdd_single_domain_solve(inst, x_cur, y_cur, bnd_new, x_new, y_new, opts: MpOpts | None = None) -> None:
+    ptrs, dev = _same_kind(x_cur, y_cur, bnd_new, x_new, y_new)
+    _check(load().mesh_sdd_single_domain_solve(inst, *ptrs, _opts(opts), dev))
+
+
+def mesh_sdd_mp_step(inst, step: Step, x_new, y_new, bnd_new, result: Result, opts: MpOpts | None = None) -> Result:
+    (px, py, pb), dev = _same_kind(x_new, y_new, bnd_new)
+    if dev != result.outputs_on_device and inst is not None:
+        raise ValueError("mesh outputs and result arrays must be of the same memory kind")
+    _check(load().mesh_sdd_mp_step(inst, ctypes.byref(step), _opts(opts), px, py, pb, ctypes.byref(result)))
+    return result
+
+
+def mesh_sdd_set_monitor_arclength(inst, u, x, y, alpha: float, normalize: bool = False) -> None:
+    (pu, px, py), dev = _same_kind(u, x, y)
+    _check(load().mesh_sdd_set_monitor_arclength(inst, pu, px, py, float(alpha), int(bool(normalize)), dev))
+
+
+def mesh_sdd_get_monitor(inst, rho_out) -> None:
+    p, dev = _ptr(rho_out)
+    _check(load().mesh_sdd_get_monitor(inst, p, int(dev)))
+
+
+def mesh_sdd_mesh_quality(inst, x_sd, y_sd, x_dd, y_dd, r_cells=None):
+    """(R_max, R_mean); fills r_cells ([(n_eta-1), (n_xi-1)]) when given."""
+    ptrs, dev = _same_kind(x_sd, y_sd, x_dd, y_dd, r_cells)
+    rmax, rmean = ctypes.c_double(), ctypes.c_double()
+    _check(load().mesh_sdd_mesh_quality(inst, *ptrs, ctypes.byref(rmax), ctypes.byref(rmean), dev))
+    return rmax.value, rmean.value
+

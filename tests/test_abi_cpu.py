@@ -46,15 +46,17 @@ def test_header_declarations_are_exported(M):
 def test_struct_layouts_match_header(M, tmp_path):
     src = tmp_path / "sz.c"
     src.write_text('#include "mesh_sdd.h"\n#include <stdio.h>\n#include <stddef.h>\n'
-                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(mesh_sdd_desc), '
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(mesh_sdd_desc), '
                    'sizeof(mesh_sdd_step), sizeof(mesh_sdd_result), sizeof(mesh_sdd_stats), sizeof(mesh_sdd_launch), '
                    'offsetof(mesh_sdd_desc, seed), offsetof(mesh_sdd_step, mesh_step), '
-                   'offsetof(mesh_sdd_result, device_ms));return 0;}\n')
+                   'offsetof(mesh_sdd_result, device_ms), sizeof(mesh_sdd_mp_opts), '
+                   'offsetof(mesh_sdd_mp_opts, fe_cfl));return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
     got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     want = [ctypes.sizeof(M.Desc), ctypes.sizeof(M.Step), ctypes.sizeof(M.Result), ctypes.sizeof(M.Stats),
-            ctypes.sizeof(M.Launch), M.Desc.seed.offset, M.Step.mesh_step.offset, M.Result.device_ms.offset]
+            ctypes.sizeof(M.Launch), M.Desc.seed.offset, M.Step.mesh_step.offset, M.Result.device_ms.offset,
+            ctypes.sizeof(M.MpOpts), M.MpOpts.fe_cfl.offset]
     assert got == want
 
 
