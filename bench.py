@@ -70,9 +70,14 @@ def parse():
                          "one the recorded HBM traffic was measured with)")
     ap.add_argument("--launch", default="", help="fixed launch shape BLOCK,WAVES_PER_SIMD,CHUNK")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU work of the oracle sample")
-    ap.add_argument("--mode", default="step", choices=["step", "batch", "serve"],
+    ap.add_argument("--mode", default="step", choices=["step", "batch", "serve", "mp", "quality"],
                     help="step: the metric line (rotating bump 129^2); batch: the 64-instance mix in one "
-                         "persistent launch; serve: Poisson request stream through submit/poll")
+                         "persistent launch; serve: Poisson request stream through submit/poll; mp: the "
+                         "rotating-bump moving-mesh loop; quality: five-ring mesh quality R against the "
+                         "single-domain mesh")
+    ap.add_argument("--mp-steps", type=int, default=50, help="mesh steps of the mp mode")
+    ap.add_argument("--quality-subs", default="2,3,4", help="subdomains per axis of the quality mode")
+    ap.add_argument("--quality-K", default="1,10", help="path substeps per mesh step of the quality mode")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--batch-scale", type=float, default=1.0, help="scale the mix's path counts (batch mode)")
     ap.add_argument("--requests", type=int, default=40, help="requests in serve mode")
@@ -97,6 +102,10 @@ def main():
         return run_batch(args)
     if args.mode == "serve":
         return run_serve(args)
+    if args.mode == "mp":
+        return run_mp(args)
+    if args.mode == "quality":
+        return run_quality(args)
     import numpy as np
     import torch
 
@@ -365,6 +374,95 @@ def run_serve(args):
             "sizes": list(sizes), "data": "synthetic"}
     print(json.dumps(line), flush=True)
     M.mesh_sdd_ctx_destroy(ctx)
+
+
+def run_mp(args):
+    """The rotating-bump moving-mesh loop (129x129, 4x4, tau = 0.01, K = 500):
+    each step samples u on the current mesh, builds the arc-length monitor
+    on the GPU and runs one MP step (edge generator, FP32 interface
+    estimate, subdomain solves).  Reports path-steps/s of the whole loop and
+    the time split of one step."""
+    import numpy as np
+    import torch
+
+    from paper_1504_00084_amd import mesh_sdd as M
+    from paper_1504_00084_amd import mp_loop
+    from paper_1504_00084_amd import workloads as W
+
+    M.load()
+    loop = W.rotating_bump_loop(n_paths=args.paths, steps=args.mp_steps)
+    ctx = M.mesh_sdd_ctx_create(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = mp_loop.run(ctx, loop, M.FP32, decomposed=True, log=log)
+    wall = time.perf_counter() - t0
+    sd = mp_loop.run(ctx, loop, M.FP32, decomposed=False, log=log)      # single-domain reference mesh
+    rmax, rmean, r = mp_loop.quality(ctx, loop, sd, out)
+    # time split of one step on the final mesh
+    h = M.mesh_sdd_create(ctx, M.make_desc(129, 129, 4, 4, K=loop.K, tau=loop.tau))
+    x, y, b = out["x"], out["y"], out["bnd"]
+    m = M.mesh_sdd_num_interface_nodes(h)
+    split = {}
+
+    def timed(name, fn):
+        t = time.perf_counter()
+        fn()
+        split[name] = 1e3 * (time.perf_counter() - t)
+
+    u = loop.u(x, y, loop.steps * loop.tau)
+    timed("monitor_ms", lambda: M.mesh_sdd_set_monitor_arclength(h, u, x, y, loop.alpha))
+    bn = np.empty_like(b)
+    timed("edge_ms", lambda: M.mesh_sdd_edge_generate(h, b, bn))
+    arrs, res = M.host_result(m)
+    step = M.make_step(x, y, b, bn, paths_per_node=loop.n_paths, mesh_step=loop.steps)
+    timed("interface_ms", lambda: M.mesh_sdd_solve_interfaces(h, step, res))
+    xn, yn = np.empty_like(x), np.empty_like(y)
+    timed("subdomain_ms", lambda: M.mesh_sdd_subdomain_solve(h, x, y, bn, arrs[0][:m], arrs[1][:m], xn, yn))
+    split["interface_kernel_ms"] = float(res.device_ms)
+    M.mesh_sdd_destroy(h)
+    M.mesh_sdd_ctx_destroy(ctx)
+    line = {"metric": "moving-mesh loop path-steps/s (rotating bump, edge generator + interface estimate + "
+                      "subdomain solves + monitor per step)",
+            "value": out["executed_path_steps"] / wall, "unit": "path-steps/s", "steps": loop.steps,
+            "ms_per_mesh_step": 1e3 * wall / loop.steps, "executed_path_steps": out["executed_path_steps"],
+            "split_of_one_step": split, "quality_vs_single_domain": {"R_max": rmax, "R_mean": rmean,
+                                                                     "R_min": float(r.min())},
+            "dtype": "f32 (paths) / f64 (mesh, sums)", "data": "synthetic",
+            "config": {"workload": loop.name, "grid": [129, 129], "subdomains": [4, 4], "paths_per_node": loop.n_paths,
+                       "K": loop.K, "tau": loop.tau, "alpha": "10 / max |grad u|^2"}}
+    print(json.dumps(line), flush=True)
+
+
+def run_quality(args):
+    """Five-ring periodic mesh test: 100 steps of dt = 5e-4 (K = 1), 1e4 paths,
+    alpha = 0.2, R = 30, on [-1, 1[^2; the decomposed mesh against the
+    single-domain mesh, R_max and R_mean of R = Q_SD / Q_SDD.  41 nodes per
+    axis (40 distinct) for 2x2 and 4x4; 43 for 3x3 (40 is not a multiple
+    of 3)."""
+    from paper_1504_00084_amd import mesh_sdd as M
+    from paper_1504_00084_amd import mp_loop
+    from paper_1504_00084_amd import workloads as W
+
+    M.load()
+    ctx = M.mesh_sdd_ctx_create(0)
+    rows = []
+    for K in (int(v) for v in args.quality_K.split(",")):
+        for sub in (int(v) for v in args.quality_subs.split(",")):
+            n = 41 if 40 % sub == 0 else next(k for k in range(41, 200) if (k - 1) % sub == 0)
+            loop = W.five_ring_loop(sub, n=n, K=K)
+            t = time.perf_counter()
+            sd = mp_loop.run(ctx, loop, M.FP32, decomposed=False, log=log)
+            sdd = mp_loop.run(ctx, loop, M.FP32, decomposed=True, log=log)
+            rmax, rmean, r = mp_loop.quality(ctx, loop, sd, sdd)
+            rows.append({"subdomains": sub, "n": n, "K": K, "interface_nodes": sdd["interface_nodes"],
+                         "R_max": rmax, "R_mean": rmean, "R_min": float(r.min()), "steps": loop.steps,
+                         "wall_s": time.perf_counter() - t})
+            log("five ring %dx%d (n=%d, K=%d): R_max %.4f R_mean %.4f R_min %.4f"
+                % (sub, sub, n, K, rmax, rmean, r.min()))
+    M.mesh_sdd_ctx_destroy(ctx)
+    print(json.dumps({"metric": "five-ring mesh quality R = Q_SD / Q_SDD (max, mean over cells) at t = 0.05",
+                      "results": rows, "paper": "R_max = R_mean = 1 at 2x2, 3x3 and 4x4",
+                      "dtype": "f32 (paths) / f64 (mesh)", "data": "synthetic (analytic u)"}), flush=True)
 
 
 if __name__ == "__main__":

@@ -336,3 +336,44 @@ def quality_ratio(x_sd, y_sd, x_dd, y_dd):
     """R(K) = Q_SD / Q_SDD per cell, with its maximum and mean."""
     r = cell_quality(x_sd, y_sd) / cell_quality(x_dd, y_dd)
     return r, float(np.max(r)), float(np.mean(r))
+
+
+# ---------------------------------------------------------------------------
+# the moving-mesh loop (section 3.2 MP procedure, sections 3.4-3.6)
+# ---------------------------------------------------------------------------
+def boundary_arrays(x, y):
+    """Boundary arrays of a mesh in the layout of ``_side_slice``."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    return np.concatenate([x[:, 0], y[:, 0], x[:, -1], y[:, -1], x[0, :], y[0, :], x[-1, :], y[-1, :]])
+
+
+def mp_loop(u_of, x0, y0, steps: int, tau: float, K: int, n_paths: int, sub_xi: int, sub_eta: int,
+            periodic_xi: int = 0, periodic_eta: int = 0, Lx: float = 1.0, Ly: float = 1.0, alpha: float = 1.0,
+            normalize: bool = False, decomposed: bool = True, seed: int = 0, instance_id: int = 0,
+            threads: int | None = None):
+    """Mesh after `steps` MP steps.  Each step n: u = u_of(x, y, n tau) at the
+    nodes, the arc-length monitor on the current mesh, the boundary arrays at
+    t^{n+1} from the edge generator, then either the interface estimate
+    (Monte Carlo, mesh_step = n) and the subdomain solves, or the
+    single-domain solve."""
+    from . import solve as mc_solve
+    x = np.array(x0, dtype=np.float64)
+    y = np.array(y0, dtype=np.float64)
+    n_eta, n_xi = x.shape
+    b = boundary_arrays(x, y)
+    for n in range(steps):
+        u = u_of(x, y, n * tau)
+        rho = arclength_monitor(u, x, y, alpha, normalize, periodic_xi, periodic_eta, Lx, Ly)
+        b1 = edge_generate(rho, b, tau, periodic_xi, periodic_eta, Lx, Ly)
+        if decomposed:
+            prob = Problem(n_xi=n_xi, n_eta=n_eta, sub_xi=sub_xi, sub_eta=sub_eta, periodic_xi=periodic_xi,
+                           periodic_eta=periodic_eta, Lx=Lx, Ly=Ly, tau=tau, K=K, seed=seed,
+                           instance_id=instance_id, mesh_step=n)
+            est = mc_solve(prob, rho, x, y, b, b1, n_paths, threads=threads)
+            x, y = subdomain_solve(rho, x, y, b1, est["mean_x"], est["mean_y"], tau, sub_xi, sub_eta,
+                                   periodic_xi, periodic_eta, Lx, Ly)
+        else:
+            x, y = single_domain_solve(rho, x, y, b1, tau, periodic_xi, periodic_eta, Lx, Ly)
+        b = b1
+    return x, y, b

@@ -233,6 +233,75 @@ def serving_stream(n_requests: int, rate_hz: float = 200.0, seed: int = 0, se_lo
 
 
 # --------------------------------------------------------------------------
+# solutions sampled at the nodes of a moving mesh (the MP loop)
+# --------------------------------------------------------------------------
+def rotating_bump_u(x, y, t: float, w: float = 0.005):
+    """u = exp(-|x - c(t)|^2 / w) of the rotating-bump workload."""
+    cx, cy = rotating_bump_centre(t)
+    return np.exp(-((x - cx) ** 2 + (y - cy) ** 2) / w)
+
+
+def five_ring_u(x, y, R: float = 30.0):
+    """The five-ring solution of the periodic mesh test (section 4.2): five
+    tanh rings of squared radius 1/8 centred at (0, 0) and (+-1/2, +-1/2) on
+    [-1, 1[^2, sharpness R."""
+    u = np.zeros(np.broadcast(x, y).shape)
+    for cx, cy in ((0.0, 0.0), (0.5, 0.5), (0.5, -0.5), (-0.5, 0.5), (-0.5, -0.5)):
+        u = u + np.tanh(R * ((x - cx) ** 2 + (y - cy) ** 2 - 0.125))
+    return u
+
+
+@dataclass
+class MeshLoop:
+    """A moving-mesh run: grid, partition, step, the solution u(x, y, t)
+    whose arc-length monitor drives the mesh, and the starting mesh."""
+    name: str
+    n_xi: int
+    n_eta: int
+    sub_xi: int
+    sub_eta: int
+    periodic_xi: int
+    periodic_eta: int
+    Lx: float
+    Ly: float
+    tau: float
+    K: int
+    n_paths: int
+    steps: int
+    alpha: float
+    normalize: bool
+    x0: np.ndarray
+    y0: np.ndarray
+    u: object                     # callable (x, y, t) -> u at the nodes
+
+    def problem_kwargs(self, mesh_step: int = 0) -> dict:
+        return dict(n_xi=self.n_xi, n_eta=self.n_eta, sub_xi=self.sub_xi, sub_eta=self.sub_eta,
+                    periodic_xi=self.periodic_xi, periodic_eta=self.periodic_eta, Lx=self.Lx, Ly=self.Ly,
+                    tau=self.tau, K=self.K, mesh_step=mesh_step)
+
+
+def rotating_bump_loop(n_paths: int = 100_000, steps: int = 50) -> MeshLoop:
+    """The 129x129, 4x4 rotating bump advanced over `steps` mesh steps of
+    tau = 0.01 (K = 500): u re-evaluated on every new mesh, with the
+    normalised arc-length monitor alpha = 10 / max |grad u|^2 of the paper's
+    Dirichlet test (rho <= sqrt(11)).  Unnormalised alpha = 10 (rho up to 38)
+    folds even the single-domain mesh within four such steps."""
+    x, y = uniform_mesh(129, 129)
+    return MeshLoop("mp_rotbump129_4x4", 129, 129, 4, 4, 0, 0, 1.0, 1.0, 0.01, 500, n_paths, steps, 10.0, True,
+                    x, y, lambda xx, yy, t: rotating_bump_u(xx, yy, t))
+
+
+def five_ring_loop(sub: int, n: int = 41, n_paths: int = 10_000, steps: int = 100, K: int = 1) -> MeshLoop:
+    """The five-ring periodic mesh test (section 4.2): [-1, 1[^2 periodic in
+    both axes, n x n nodes (node n-1 is the image of node 0), sub x sub
+    subdomains, R = 30, alpha = 0.2, dt = 5e-4 with K substeps (the paper
+    uses one), 1e4 paths, 100 steps to t = 0.05."""
+    x, y = uniform_mesh(n, n, 2.0, 2.0)
+    return MeshLoop("five_ring%d_%dx%d_K%d" % (n, sub, sub, K), n, n, sub, sub, 1, 1, 2.0, 2.0, 5e-4, K, n_paths,
+                    steps, 0.2, False, x - 1.0, y - 1.0, lambda xx, yy, t: five_ring_u(xx, yy))
+
+
+# --------------------------------------------------------------------------
 # small special-case inputs used by the closed-form checks
 # --------------------------------------------------------------------------
 def constant_problem(n: int, sub: int, periodic_xi: int, periodic_eta: int, tau: float, K: int,

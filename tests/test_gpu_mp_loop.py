@@ -1,0 +1,80 @@
+"""The moving-mesh loop on the GPU (monitor on the new mesh, edge generator,
+interface estimate, subdomain solves; or the single-domain reference)
+against the oracle's loop, step for step on the same inputs and streams."""
+import numpy as np
+import pytest
+
+from oracle import mp_oracle as mp
+from paper_1504_00084_amd import workloads as W
+from gpu_helpers import THREADS, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def M():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1504_00084_amd import mesh_sdd
+    mesh_sdd.load()
+    return mesh_sdd
+
+
+@pytest.fixture(scope="module")
+def ctx(M):
+    c = M.mesh_sdd_ctx_create(0)
+    yield c
+    M.mesh_sdd_ctx_destroy(c)
+
+
+def small_bump_loop(steps=3):
+    x, y = W.uniform_mesh(33, 33)
+    return W.MeshLoop("mp_bump33_4x4", 33, 33, 4, 4, 0, 0, 1.0, 1.0, 0.01, 40, 1000, steps, 10.0, False, x, y,
+                      lambda xx, yy, t: W.rotating_bump_u(xx, yy, t, 0.02))
+
+
+def oracle_loop(loop, steps, decomposed):
+    return mp.mp_loop(loop.u, loop.x0, loop.y0, steps, loop.tau, loop.K, loop.n_paths, loop.sub_xi, loop.sub_eta,
+                      loop.periodic_xi, loop.periodic_eta, loop.Lx, loop.Ly, loop.alpha, loop.normalize,
+                      decomposed=decomposed, threads=THREADS)
+
+
+@pytest.mark.parametrize("which", ["five_ring41_2x2", "bump33_4x4"])
+@pytest.mark.parametrize("decomposed", [True, False], ids=["sdd", "sd"])
+def test_fp64_loop_matches_oracle(M, ctx, which, decomposed):
+    from paper_1504_00084_amd import mp_loop
+    if which.startswith("five"):
+        loop = W.five_ring_loop(2, n_paths=2000)
+        steps = 4
+    else:
+        loop = small_bump_loop()
+        steps = 3
+    got = mp_loop.run(ctx, loop, M.FP64, decomposed=decomposed, steps=steps)
+    wx, wy, wb = oracle_loop(loop, steps, decomposed)
+    err = max(float(np.max(np.abs(got["x"] - wx))), float(np.max(np.abs(got["y"] - wy))))
+    eb = float(np.max(np.abs(got["bnd"] - wb)))
+    moved = float(np.max(np.abs(wx - loop.x0)))
+    say("%s %s FP64 loop, %d steps: max |gpu - oracle| mesh %.3e, boundary %.3e (mesh moved %.3e)"
+        % (which, "SDD" if decomposed else "SD", steps, err, eb, moved))
+    assert err <= 1e-11 and eb <= 1e-13
+
+
+def test_fp32_five_ring_quality_close_to_one(M, ctx):
+    """Shortened five-ring run (20 of the 100 steps) with ten path substeps
+    per mesh step: the decomposed mesh's cell quality stays within a few
+    percent of the single-domain mesh's.  (With one substep the interface
+    estimate is a single Euler-Maruyama step of the whole mesh step, which
+    on this sharp monitor disagrees with the four forward-Euler substeps of
+    the subdomain solves by tens of standard errors and the mesh folds
+    within 20 steps, on the oracle as on the GPU.)"""
+    from paper_1504_00084_amd import mp_loop
+    loop = W.five_ring_loop(2, K=10)
+    sd = mp_loop.run(ctx, loop, M.FP32, decomposed=False, steps=20)
+    sdd = mp_loop.run(ctx, loop, M.FP32, decomposed=True, steps=20)
+    rmax, rmean, r = mp_loop.quality(ctx, loop, sd, sdd)
+    wr, wmax, wmean = mp.quality_ratio(sd["x"], sd["y"], sdd["x"], sdd["y"])
+    say("five ring 2x2, 20 steps, FP32: R_max %.4f R_mean %.4f (oracle on the same meshes %.4f %.4f), "
+        "R_min %.4f" % (rmax, rmean, wmax, wmean, float(np.min(r))))
+    assert abs(rmax - wmax) < 1e-13 and abs(rmean - wmean) < 1e-13
+    assert 0.9 < float(np.min(r)) and rmax < 1.1 and abs(rmean - 1.0) < 0.02
