@@ -143,7 +143,11 @@ typedef struct {
     int32_t block;                   /* threads per workgroup (64, 128, 256, 512)    */
     int32_t waves_per_simd;          /* persistent residency target (1..8)           */
     int32_t chunk_paths;             /* paths per work item (multiple of 64)         */
-    int32_t reserved;                /* must be 0                                    */
+    int32_t monitor_table;           /* 0: automatic -- a launch that holds one
+                                        instance whose rho node table fits in LDS
+                                        reads rho there (one 768-thread workgroup per
+                                        CU; identical results); 1: always from the
+                                        cell records in L2                             */
 } mesh_sdd_launch;
 
 /* ---- context ------------------------------------------------------------ */

@@ -144,8 +144,9 @@ __device__ __forceinline__ float side_distance(const ConstF &C, float x, float y
 
 // One EM substep of the FP32 path (a3-a6).  Returns the exit side (0: xi=0,
 // 1: xi=1, 2: eta=0, 3: eta=1) with the position moved onto it, or -1.
+template <bool LDS_RHO>
 __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t wa, uint32_t wb, uint32_t wc,
-                                           float *trace4)
+                                           float *trace4, const float *rho_tab)
 {
     // a3: Box-Muller on two stream words with the hardware log2 / sqrt /
     // sin / cos (sin and cos take revolutions); sqrt(2 dt) is folded into
@@ -164,8 +165,23 @@ __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t w
     tx = P.x * C.fnx1 - (float)cx;
     ty = P.y * C.fny1 - (float)cy;
     const GLOBAL f32x4 *cell = C.cells + (uint32_t)(3 * (cy * C.nx1 + cx));
-    const f32x4 A = cell[0], B = cell[1], G = cell[2];
-    const float rho = fmaf(ty, fmaf(A.w, tx, A.z), fmaf(A.y, tx, A.x));
+    float r00, r10, r01, r11;
+    if (LDS_RHO) {   // corner values from the LDS copy of the node table
+        const int base = cy * C.n_xi + cx;
+        r00 = rho_tab[base];
+        r10 = rho_tab[base + 1];
+        r01 = rho_tab[base + C.n_xi];
+        r11 = rho_tab[base + C.n_xi + 1];
+    } else {         // the same values from the cell record
+        const f32x4 A = cell[0];
+        r00 = A.x;
+        r10 = A.y;
+        r01 = A.z;
+        r11 = A.w;
+    }
+    const f32x4 B = cell[1], G = cell[2];
+    const float v0 = fmaf(tx, r10 - r00, r00), v1 = fmaf(tx, r11 - r01, r01);
+    const float rho = fmaf(ty, v1 - v0, v0);
     const float gx = fmaf(ty, fmaf(B.w, tx, B.z), fmaf(B.y, tx, B.x));
     const float gy = fmaf(ty, fmaf(G.w, tx, G.z), fmaf(G.y, tx, G.x));
     const float inv_rho = __builtin_amdgcn_rcpf(rho);
@@ -322,9 +338,10 @@ __device__ __forceinline__ void path_value_f32(const InstView &I, const ConstF &
 // Up to four substeps of one path: the three Philox blocks of the group are
 // drawn at once (words 3s..3s+2 of substep s of the group).  Returns the exit
 // side or -1; `ended` is set when the path exited or reached K.
-template <bool TRACE>
+template <bool TRACE, bool LDS_RHO>
 __device__ __forceinline__ int group_f32(PathF &P, const ConstF &C, uint32_t path, uint32_t node, uint32_t ctr3,
-                                         uint32_t key0, uint32_t key1, bool &ended, double *trace)
+                                         uint32_t key0, uint32_t key1, bool &ended, double *trace,
+                                         const float *rho_tab)
 {
     const uint32_t blk = 3u * ((uint32_t)P.k >> 2);
     const Words4 A = philox4x32_10(blk, path, node, ctr3, key0, key1);
@@ -337,7 +354,7 @@ __device__ __forceinline__ int group_f32(PathF &P, const ConstF &C, uint32_t pat
     for (int s = 0; s < 4; ++s) {
         if (!ended && P.k < C.K) {
             float t4[4];
-            side = substep_f32(P, C, w[3 * s], w[3 * s + 1], w[3 * s + 2], TRACE ? t4 : nullptr);
+            side = substep_f32<LDS_RHO>(P, C, w[3 * s], w[3 * s + 1], w[3 * s + 2], TRACE ? t4 : nullptr, rho_tab);
             if (TRACE) {
                 double *t = trace + 4 * (size_t)P.k;
                 t[0] = t4[0];
@@ -442,7 +459,14 @@ __device__ __forceinline__ void flush_item(const float *buf, uint32_t cap, uint3
 // drained item is reduced in a fixed order, so the sums do not depend on
 // which lane ran which path.  Items of another instance start once both
 // slots are drained (the per-instance constants are wave-uniform).
-template <int BLOCK>
+//
+// LDS_RHO: the launch holds one instance (the host guarantees it), whose
+// FP32 rho node table the workgroup copies into LDS behind the wave
+// buffers; the bilinear rho then reads its four corners there instead of
+// from the cell record (the same values, so the results are identical).
+// That takes one of the three L1 gathers of a substep off the texture
+// path, which bounds this kernel.
+template <int BLOCK, bool LDS_RHO>
 __global__ __launch_bounds__(BLOCK) void paths_fp32(const InstView *__restrict__ insts,
                                                     const WorkRange *__restrict__ ranges, uint32_t n_ranges,
                                                     uint32_t n_items, uint32_t *__restrict__ head, uint32_t cap)
@@ -450,6 +474,14 @@ __global__ __launch_bounds__(BLOCK) void paths_fp32(const InstView *__restrict__
     extern __shared__ float lds[];
     const int lane = threadIdx.x & 63;
     float *buf = lds + (size_t)(threadIdx.x >> 6) * 4u * cap;   // [slot][dx | dy][cap]
+    float *rho_tab = nullptr;
+    if (LDS_RHO) {
+        rho_tab = lds + (size_t)(BLOCK / 64) * 4u * cap;
+        const int n = insts[0].n_xi * insts[0].n_eta;
+        const GLOBAL float *src = gptr(insts[0].rho_f);
+        for (int q = threadIdx.x; q < n; q += BLOCK) rho_tab[q] = src[q];
+        __syncthreads();
+    }
     const GLOBAL WorkRange *rg = gptr(ranges);
 
     // wave-uniform state
@@ -541,7 +573,7 @@ __global__ __launch_bounds__(BLOCK) void paths_fp32(const InstView *__restrict__
         // advance every path by one group of four substeps
         bool ended = false;
         if (has) {
-            const int side = group_f32<false>(P, C, path, node, ctr3, key0, key1, ended, nullptr);
+            const int side = group_f32<false, LDS_RHO>(P, C, path, node, ctr3, key0, key1, ended, nullptr, rho_tab);
             if (ended) {
                 float vx, vy;
                 path_value_f32(*Ip, C, P, side, vx, vy);
@@ -889,9 +921,11 @@ __global__ void prep_cells_kernel(const double *__restrict__ rho, const double *
     const int cx = idx % nx1, cy = idx / nx1;
     const size_t a = (size_t)cy * n_xi + cx, b = a + n_xi;
     const double *f[3] = {rho, rx, ry};
-    for (int c = 0; c < 3; ++c) {
-        const double sc = c == 0 ? 1.0 : grad_scale;   // gradient fields carry the factor dt
-        const double f00 = sc * f[c][a], f10 = sc * f[c][a + 1], f01 = sc * f[c][b], f11 = sc * f[c][b + 1];
+    // rho: the four corner values, exactly the FP32 node table's
+    cells[3 * (size_t)idx] = make_float4((float)rho[a], (float)rho[a + 1], (float)rho[b], (float)rho[b + 1]);
+    for (int c = 1; c < 3; ++c) {   // gradient fields carry the factor dt, coefficient form
+        const double f00 = grad_scale * f[c][a], f10 = grad_scale * f[c][a + 1];
+        const double f01 = grad_scale * f[c][b], f11 = grad_scale * f[c][b + 1];
         cells[3 * (size_t)idx + c] = make_float4((float)f00, (float)(f10 - f00), (float)(f01 - f00),
                                                  (float)(f11 - f10 - f01 + f00));
     }
@@ -995,8 +1029,8 @@ __global__ void debug_paths_kernel(const InstView *__restrict__ inst, int fp64, 
     int side = -1;
     bool ended = false;
     while (!ended) {
-        side = tr ? group_f32<true>(P, C, path, node, I.ctr3, I.key0, I.key1, ended, tr)
-                  : group_f32<false>(P, C, path, node, I.ctr3, I.key0, I.key1, ended, nullptr);
+        side = tr ? group_f32<true, false>(P, C, path, node, I.ctr3, I.key0, I.key1, ended, tr, nullptr)
+                  : group_f32<false, false>(P, C, path, node, I.ctr3, I.key0, I.key1, ended, nullptr, nullptr);
     }
     float fx, fy;
     path_value_f32(I, C, P, side, fx, fy);
@@ -1062,21 +1096,50 @@ hipError_t launch_paths_fp32(const InstView *insts, const WorkRange *ranges, uin
     const size_t lds = paths_fp32_lds_bytes(block, cap);
     switch (block) {
     case 64:
-        hipLaunchKernelGGL(paths_fp32<64>, dim3(grid), dim3(64), lds, s, insts, ranges, n_ranges, n_items, head, cap);
+        hipLaunchKernelGGL((paths_fp32<64, false>), dim3(grid), dim3(64), lds, s, insts, ranges, n_ranges, n_items,
+                           head, cap);
         break;
     case 128:
-        hipLaunchKernelGGL(paths_fp32<128>, dim3(grid), dim3(128), lds, s, insts, ranges, n_ranges, n_items, head, cap);
+        hipLaunchKernelGGL((paths_fp32<128, false>), dim3(grid), dim3(128), lds, s, insts, ranges, n_ranges, n_items,
+                           head, cap);
         break;
     case 256:
-        hipLaunchKernelGGL(paths_fp32<256>, dim3(grid), dim3(256), lds, s, insts, ranges, n_ranges, n_items, head, cap);
+        hipLaunchKernelGGL((paths_fp32<256, false>), dim3(grid), dim3(256), lds, s, insts, ranges, n_ranges, n_items,
+                           head, cap);
         break;
     case 512:
-        hipLaunchKernelGGL(paths_fp32<512>, dim3(grid), dim3(512), lds, s, insts, ranges, n_ranges, n_items, head, cap);
+        hipLaunchKernelGGL((paths_fp32<512, false>), dim3(grid), dim3(512), lds, s, insts, ranges, n_ranges, n_items,
+                           head, cap);
         break;
     default:
         return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+size_t paths_fp32_lds_rho_bytes(uint32_t cap, int n_nodes)
+{
+    return paths_fp32_lds_bytes(kLdsRhoBlock, cap) + (size_t)n_nodes * sizeof(float);
+}
+
+hipError_t launch_paths_fp32_lds_rho(const InstView *insts, const WorkRange *ranges, uint32_t n_items,
+                                     uint32_t *head, uint32_t cap, int n_nodes, int grid, hipStream_t s)
+{
+    hipError_t e = launch_fill_u32(head, 0u, 1, s);
+    if (e != hipSuccess) return e;
+    if (n_items == 0) return hipSuccess;
+    hipLaunchKernelGGL((paths_fp32<kLdsRhoBlock, true>), dim3(grid), dim3(kLdsRhoBlock),
+                       paths_fp32_lds_rho_bytes(cap, n_nodes), s, insts, ranges, 1u, n_items, head, cap);
+    return hipGetLastError();
+}
+
+int paths_fp32_lds_rho_blocks_per_cu(uint32_t cap, int n_nodes)
+{
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32<kLdsRhoBlock, true>, kLdsRhoBlock,
+                                                     paths_fp32_lds_rho_bytes(cap, n_nodes)) != hipSuccess)
+        return 0;
+    return n;
 }
 
 size_t paths_fp32_lds_bytes(int block, uint32_t cap) { return (size_t)(block / 64) * 4u * cap * sizeof(float); }
@@ -1118,10 +1181,10 @@ int paths_fp32_blocks_per_cu(int block, uint32_t cap)
     hipError_t e = hipErrorInvalidValue;
     const size_t lds = paths_fp32_lds_bytes(block, cap);
     switch (block) {
-    case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32<64>, 64, lds); break;
-    case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32<128>, 128, lds); break;
-    case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32<256>, 256, lds); break;
-    case 512: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32<512>, 512, lds); break;
+    case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32<64, false>, 64, lds); break;
+    case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32<128, false>, 128, lds); break;
+    case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32<256, false>, 256, lds); break;
+    case 512: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32<512, false>, 512, lds); break;
     default: break;
     }
     return e == hipSuccess ? n : 0;
@@ -1132,10 +1195,10 @@ int paths_fp32_attributes(int block, int *vgprs, int *sgprs, int *lds_bytes)
     hipFuncAttributes a;
     hipError_t e = hipErrorInvalidValue;
     switch (block) {
-    case 64: e = hipFuncGetAttributes(&a, reinterpret_cast<const void *>(paths_fp32<64>)); break;
-    case 128: e = hipFuncGetAttributes(&a, reinterpret_cast<const void *>(paths_fp32<128>)); break;
-    case 256: e = hipFuncGetAttributes(&a, reinterpret_cast<const void *>(paths_fp32<256>)); break;
-    case 512: e = hipFuncGetAttributes(&a, reinterpret_cast<const void *>(paths_fp32<512>)); break;
+    case 64: e = hipFuncGetAttributes(&a, reinterpret_cast<const void *>(paths_fp32<64, false>)); break;
+    case 128: e = hipFuncGetAttributes(&a, reinterpret_cast<const void *>(paths_fp32<128, false>)); break;
+    case 256: e = hipFuncGetAttributes(&a, reinterpret_cast<const void *>(paths_fp32<256, false>)); break;
+    case 512: e = hipFuncGetAttributes(&a, reinterpret_cast<const void *>(paths_fp32<512, false>)); break;
     default: break;
     }
     if (e != hipSuccess) return -1;

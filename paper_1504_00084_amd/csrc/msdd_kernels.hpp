@@ -14,8 +14,9 @@ namespace msdd {
 hipError_t launch_prep_gradient(const double *rho_in, int n_xi, int n_eta, int per_xi, int per_eta,
                                 double *rho, double *rho_xi, double *rho_eta, hipStream_t s);
 
-// a0 (FP32 path): per-cell bilinear coefficients of (rho, s rho_xi, s rho_eta)
-// with s = grad_scale (the substep dt).
+// a0 (FP32 path): per-cell records: rho at the four corners, then s rho_xi
+// and s rho_eta in bilinear coefficient form, with s = grad_scale (the
+// substep dt).
 hipError_t launch_prep_cells(const double *rho, const double *rho_xi, const double *rho_eta, int n_xi,
                              int n_eta, double grad_scale, float4 *cells, hipStream_t s);
 
@@ -37,6 +38,16 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t s)
 hipError_t launch_paths_fp32(const InstView *insts, const WorkRange *ranges, uint32_t n_ranges, uint32_t n_items,
                              uint32_t *head, uint32_t cap, int grid, int block, hipStream_t s);
 size_t paths_fp32_lds_bytes(int block, uint32_t cap);
+
+// The same kernel for a launch that holds ONE instance (n_ranges = 1): one
+// 768-thread workgroup per CU copies that instance's FP32 rho node table
+// (n_nodes floats) into LDS behind the wave buffers and reads the bilinear
+// rho corners there.  Results are identical to launch_paths_fp32's.
+constexpr int kLdsRhoBlock = 768;
+size_t paths_fp32_lds_rho_bytes(uint32_t cap, int n_nodes);
+hipError_t launch_paths_fp32_lds_rho(const InstView *insts, const WorkRange *ranges, uint32_t n_items,
+                                     uint32_t *head, uint32_t cap, int n_nodes, int grid, hipStream_t s);
+int paths_fp32_lds_rho_blocks_per_cu(uint32_t cap, int n_nodes);
 
 // a2-a8, FP64 plain: one thread per path, one launch per instance; the
 // partial of (node, chunk) goes to partials[node * chunks + chunk].

@@ -62,6 +62,7 @@ int install_monitor(mesh_sdd *inst, hipStream_t st)
                                        inst->rho.as<double>(), inst->rho_xi.as<double>(), inst->rho_eta.as<double>(), st));
     HIP_TRY(msdd::launch_prep_cells(inst->rho.as<double>(), inst->rho_xi.as<double>(), inst->rho_eta.as<double>(),
                                     d.n_xi, d.n_eta, d.tau / (double)d.K, inst->cells.as<float4>(), st));
+    HIP_TRY(msdd::launch_to_f32(inst->rho.as<double>(), inst->rho_f.as<float>(), (size_t)d.n_xi * d.n_eta, st));
     HIP_TRY(hipStreamSynchronize(st));
     inst->monitor_set = true;
     return MESH_SDD_OK;
@@ -70,6 +71,10 @@ int install_monitor(mesh_sdd *inst, hipStream_t st)
 }  // namespace msdd_rt
 
 using namespace msdd_rt;
+
+namespace {
+constexpr size_t kLdsBytes = 160u * 1024u;   // LDS of one CU on gfx950
+}
 
 
 
@@ -126,7 +131,7 @@ size_t instance_bytes(const mesh_sdd_desc &d, int M)
 {
     const size_t n = (size_t)d.n_xi * d.n_eta;
     const size_t cells = (size_t)(d.n_xi - 1) * (d.n_eta - 1);
-    return 4 * n * sizeof(double) + 3 * cells * sizeof(float4) + 2 * (size_t)M * sizeof(int32_t);
+    return 4 * n * sizeof(double) + n * sizeof(float) + 3 * cells * sizeof(float4) + 2 * (size_t)M * sizeof(int32_t);
 }
 
 int64_t resolve_paths(const mesh_sdd &inst, const mesh_sdd_step &s)
@@ -193,8 +198,8 @@ mesh_sdd_launch default_launch()
     // three waves per SIMD: the cell gathers saturate the L1 pipeline there,
     // and more resident waves only add L1 misses (measured on gfx950)
     l.waves_per_simd = 3;
-    l.chunk_paths = 512;
-    l.reserved = 0;
+    l.chunk_paths = 128;   // small enough that the LDS variant's wave buffers leave room for a 129x129 rho table
+    l.monitor_table = 0;
     return l;
 }
 
@@ -335,6 +340,7 @@ int stage_request(Request &r, const mesh_sdd_step *dev_step)
     v.node_i = inst.dev_i.as<int32_t>();
     v.node_j = inst.dev_j.as<int32_t>();
     v.cells = inst.cells.as<float4>();
+    v.rho_f = inst.rho_f.as<float>();
     v.xpad_f = r.xpad_f.as<float>();
     v.ypad_f = r.ypad_f.as<float>();
     v.bnd0_f = r.b0f.as<float>();
@@ -401,13 +407,24 @@ int run_fp32_launch(mesh_sdd_ctx *ctx, const std::vector<InstView> &views, const
         return fail(MESH_SDD_E_NOMEM, "device allocation for the work queue failed");
     HIP_TRY(hipMemcpyAsync(ctx->views.p, views.data(), views.size() * sizeof(InstView), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(ctx->ranges.p, ranges.data(), ranges.size() * sizeof(WorkRange), hipMemcpyHostToDevice, st));
+    // A launch that holds one instance whose rho node table fits in LDS next
+    // to the wave buffers runs the LDS variant (one 768-thread workgroup per
+    // CU, three waves per SIMD); its results are identical.
+    const int n_nodes = views.size() == 1 ? views[0].n_xi * views[0].n_eta : 0;
+    const bool lds_rho = views.size() == 1 && ranges.size() == 1 && l.monitor_table == 0 &&
+                         msdd::paths_fp32_lds_rho_bytes(cap, n_nodes) <= kLdsBytes &&
+                         msdd::paths_fp32_lds_rho_blocks_per_cu(cap, n_nodes) >= 1;
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     HIP_TRY(hipEventRecord(e0, st));
-    hipError_t le = msdd::launch_paths_fp32(ctx->views.as<InstView>(), ctx->ranges.as<WorkRange>(),
-                                            (uint32_t)ranges.size(), (uint32_t)n_items, ctx->head.as<uint32_t>(),
-                                            cap, grid_for(ctx, l, cap), l.block, st);
+    hipError_t le = lds_rho ? msdd::launch_paths_fp32_lds_rho(ctx->views.as<InstView>(), ctx->ranges.as<WorkRange>(),
+                                                             (uint32_t)n_items, ctx->head.as<uint32_t>(), cap, n_nodes,
+                                                             ctx->cu_count, st)
+                            : msdd::launch_paths_fp32(ctx->views.as<InstView>(), ctx->ranges.as<WorkRange>(),
+                                                      (uint32_t)ranges.size(), (uint32_t)n_items,
+                                                      ctx->head.as<uint32_t>(), cap, grid_for(ctx, l, cap), l.block,
+                                                      st);
     HIP_TRY(hipEventRecord(e1, st));
     hipError_t se = hipEventSynchronize(e1);
     float t = 0.0f;
@@ -836,9 +853,10 @@ int mesh_sdd_set_launch(mesh_sdd_ctx *ctx, const mesh_sdd_launch *launch)
     if (launch->waves_per_simd < 0 || launch->waves_per_simd > 8)
         return fail(MESH_SDD_E_INVAL, "waves_per_simd must be in [0, 8]");
     if (launch->chunk_paths < 64 || launch->chunk_paths % 64 || launch->chunk_paths > 2048 ||
-        msdd::paths_fp32_lds_bytes(launch->block, (uint32_t)launch->chunk_paths) > 160u * 1024u)
+        msdd::paths_fp32_lds_bytes(launch->block, (uint32_t)launch->chunk_paths) > kLdsBytes)
         return fail(MESH_SDD_E_INVAL, "chunk_paths must be a multiple of 64 in [64, 2048] and fit in LDS");
-    if (launch->reserved != 0) return fail(MESH_SDD_E_INVAL, "launch.reserved must be 0");
+    if (launch->monitor_table != 0 && launch->monitor_table != 1)
+        return fail(MESH_SDD_E_INVAL, "launch.monitor_table must be 0 or 1");
     ctx->override_launch = *launch;
     ctx->has_override = true;
     return MESH_SDD_OK;
@@ -895,7 +913,7 @@ int mesh_sdd_create(mesh_sdd_ctx *ctx, const mesh_sdd_desc *desc, mesh_sdd **out
     HIP_TRY(hipSetDevice(ctx->device));
     if (inst->dev_i.alloc((size_t)inst->M * 4) || inst->dev_j.alloc((size_t)inst->M * 4) ||
         inst->rho_in.alloc(n * 8) || inst->rho.alloc(n * 8) || inst->rho_xi.alloc(n * 8) ||
-        inst->rho_eta.alloc(n * 8) || inst->cells.alloc(cells * 3 * sizeof(float4)))
+        inst->rho_eta.alloc(n * 8) || inst->rho_f.alloc(n * 4) || inst->cells.alloc(cells * 3 * sizeof(float4)))
         return fail(MESH_SDD_E_NOMEM, "device allocation for the instance tables failed");
     if (inst->M) {
         HIP_TRY(hipMemcpy(inst->dev_i.p, inst->node_i.data(), (size_t)inst->M * 4, hipMemcpyHostToDevice));

@@ -162,7 +162,8 @@ struct mesh_sdd {
     std::vector<int32_t> node_i, node_j;
     DevBuf dev_i, dev_j;                    // interface nodes
     DevBuf rho_in, rho, rho_xi, rho_eta;    // FP64 monitor staging and node tables
-    DevBuf cells;                           // FP32 per-cell bilinear coefficients
+    DevBuf rho_f;                           // FP32 node table of rho (staged in LDS by single-instance launches)
+    DevBuf cells;                           // FP32 per-cell records (rho corners, gradient coefficients)
     DevBuf node_rank;                       // [n_eta][n_xi] interface rank or -1 (mesh step; built on first use)
     bool monitor_set = false;
     std::atomic<int> inflight{0};

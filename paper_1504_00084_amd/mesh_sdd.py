@@ -83,7 +83,7 @@ class Stats(ctypes.Structure):
 
 class Launch(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("block", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32),
-                ("chunk_paths", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("chunk_paths", ctypes.c_int32), ("monitor_table", ctypes.c_int32)]
 
 
 _lib = None
@@ -97,6 +97,13 @@ def load(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError("libmesh_sdd.so not found at %s; build it with "
                            "`python -m paper_1504_00084_amd.build`" % path)
+    # torch ships its own HIP runtime; loading it first makes the library bind
+    # to that same runtime, so device pointers and streams from torch tensors
+    # are valid inside the library (two runtimes in one process see no device)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     vp, i32, i64, sz, P = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.POINTER
     sig = {
@@ -203,8 +210,8 @@ def mesh_sdd_get_launch(inst) -> Launch:
     return lo
 
 
-def make_launch(block=256, waves_per_simd=3, chunk_paths=512) -> Launch:
-    return Launch(ctypes.sizeof(Launch), block, waves_per_simd, chunk_paths, 0)
+def make_launch(block=256, waves_per_simd=3, chunk_paths=128, monitor_table=0) -> Launch:
+    return Launch(ctypes.sizeof(Launch), block, waves_per_simd, chunk_paths, monitor_table)
 
 
 def mesh_sdd_autotune(inst, step: Step) -> Launch:

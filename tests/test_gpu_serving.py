@@ -259,3 +259,26 @@ def test_target_se_sets_path_count(M, ctx):
         assert np.max(np.maximum(g["se_x"], g["se_y"])) <= se
     finally:
         M.mesh_sdd_destroy(h)
+
+
+def test_lds_and_l2_monitor_give_identical_results(M, ctx):
+    """A single-instance launch reads rho from an LDS copy of the node table
+    (when it fits); with monitor_table = 1 it reads the same corner values
+    from the cell records in L2.  Both must give bitwise equal results."""
+    insts = W.config4(count=4, seed=9, n_paths=4000, sizes=(33, 65, 129))
+    for q, it in enumerate(insts):
+        it.K = 60 + 13 * q
+        it.instance_id = 300 + q
+    H = Handles(M, ctx, insts, M.FP32)
+    try:
+        lds = solve_alone(M, H, insts)
+        M.mesh_sdd_set_launch(ctx, M.make_launch(monitor_table=1))
+        try:
+            l2 = solve_alone(M, H, insts)
+        finally:
+            M.mesh_sdd_set_launch(ctx, None)
+        for q in range(len(insts)):
+            assert same(lds[q], l2[q]), insts[q].name
+        say("LDS rho == L2 rho (bitwise) on %s" % ", ".join(it.name for it in insts))
+    finally:
+        H.close()
