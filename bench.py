@@ -32,14 +32,15 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 W_SLOTS_PER_STEP = 86.5
 
 # HBM traffic of one paths_fp32 launch on the 129x129, 4x4 workload at the
-# default launch shape (block 256, 3 waves per SIMD, 512-path chunks), from
-# two rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE, KiB
-# per dispatch), each scaled by what the counter reads for a 1 GiB device
-# copy in the same run (FETCH_SIZE reads 524308 KiB: x2.0; WRITE_SIZE reads
-# 1048576 KiB: x1.0).  Valid only for the kernel source it was measured on
-# (SHA-1 of csrc/kernels.hip); reported as null otherwise.
-TRAFFIC_RECORD = {"kernels_sha1": "4b6dd3b3f592464498021edb8ef1f4d88eac0056", "fetch_kib": 4212.25, "write_kib": 13615.2,
-                  "fetch_scale": 2.0, "write_scale": 1.0}
+# default launch (single instance: the LDS-rho variant, 1024 threads per
+# workgroup, one workgroup per CU, 128-path chunks), from two rocprofv3 --pmc
+# runs of this script (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each
+# scaled by what the counter reads for a 1 GiB device copy in the same run
+# (FETCH_SIZE reads 524308 KiB: x2.0; WRITE_SIZE reads 1048576 KiB: x1.0).
+# Valid only for the kernel source it was measured on (SHA-1 of
+# csrc/kernels.hip); reported as null otherwise.
+TRAFFIC_RECORD = {"kernels_sha1": "a1855efbc12c51a9b6e979753766ea1f7a6b9950", "fetch_kib": 4471.69,
+                  "write_kib": 54131.8, "fetch_scale": 2.0, "write_scale": 1.0}
 
 
 def recorded_traffic():
@@ -199,11 +200,15 @@ def main():
         M.mesh_sdd_destroy(h64)
 
     kern_s = sum(kernel_ms) / len(kernel_ms) / 1e3
+    # a single-instance launch stages the FP32 rho node table in LDS when it
+    # fits next to the 16 waves' item buffers (the library's rule)
+    lds_rho = lo.monitor_table == 0 and inst.n_xi * inst.n_eta * 4 + 16 * 4 * lo.chunk_paths * 4 <= 160 * 1024
     per_launch = executed / args.steps
     achieved = W_SLOTS_PER_STEP * per_launch / kern_s / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 3), "unit": "TOP/s",
                 "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": recorded_traffic(),
-                "kernel": "paths_fp32", "kernel_ms": round(kern_s * 1e3, 3),
+                "kernel": "paths_fp32 (LDS-rho variant, 1024 threads x 1 workgroup per CU)" if lds_rho
+                else "paths_fp32", "kernel_ms": round(kern_s * 1e3, 3),
                 "path_steps_per_launch": per_launch, "slots_per_path_step": W_SLOTS_PER_STEP}
 
     cpu = None
@@ -238,8 +243,8 @@ def main():
         "config": {"workload": inst.name, "grid": [inst.n_xi, inst.n_eta], "subdomains": [inst.sub_xi, inst.sub_eta],
                    "interface_nodes": m, "paths_per_node": inst.n_paths, "K": inst.K, "tau": inst.tau,
                    "nominal_path_steps": nominal, "executed_path_steps_per_step": per_launch,
-                   "max_se": se_max, "launch": {"block": lo.block, "waves_per_simd": lo.waves_per_simd,
-                                                "chunk_paths": lo.chunk_paths}},
+                   "max_se": se_max, "launch": {"block": 1024 if lds_rho else lo.block, "waves_per_simd": 4 if lds_rho else lo.waves_per_simd,
+                                         "chunk_paths": lo.chunk_paths, "rho_table": "LDS" if lds_rho else "L2"}},
         "fp64_plain": fp64,
         "roofline": roofline,
         "cpu_baseline": cpu,

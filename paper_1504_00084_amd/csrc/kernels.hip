@@ -68,10 +68,13 @@ __device__ __forceinline__ Words4 philox4x32_10(uint32_t x0, uint32_t x1, uint32
     return Words4{x0, x1, x2, x3};
 }
 
-// (2 floor(r / 2^9) + 1) 2^-24: exact in binary32.
+// (2 floor(r / 2^9) + 1) 2^-24, exactly: v_alignbit puts r[31:9] under the
+// exponent of 1.0, giving 1 + floor(r / 2^9) 2^-23 in [1, 2), and the
+// subtraction of 1 - 2^-24 is exact (the difference needs at most 24
+// significant bits).
 __device__ __forceinline__ float uniform_f32(uint32_t r)
 {
-    return fmaf((float)(r >> 9), 0x1.0p-23f, 0x1.0p-24f);
+    return __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, r, 9u)) - 0x1.fffffep-1f;
 }
 
 __device__ __forceinline__ double uniform_f64(uint32_t r)

@@ -39,11 +39,12 @@ hipError_t launch_paths_fp32(const InstView *insts, const WorkRange *ranges, uin
                              uint32_t *head, uint32_t cap, int grid, int block, hipStream_t s);
 size_t paths_fp32_lds_bytes(int block, uint32_t cap);
 
-// The same kernel for a launch that holds ONE instance (n_ranges = 1): one
-// 768-thread workgroup per CU copies that instance's FP32 rho node table
-// (n_nodes floats) into LDS behind the wave buffers and reads the bilinear
-// rho corners there.  Results are identical to launch_paths_fp32's.
-constexpr int kLdsRhoBlock = 768;
+// The same kernel for a launch that holds ONE instance (n_ranges = 1): each
+// 1024-thread workgroup (16 waves: 4 per SIMD, as many as one LDS copy of
+// the table can serve) copies that instance's FP32 rho node table (n_nodes
+// floats) into LDS behind the wave buffers and reads the bilinear rho
+// corners there.  Results are identical to launch_paths_fp32's.
+constexpr int kLdsRhoBlock = 1024;
 size_t paths_fp32_lds_rho_bytes(uint32_t cap, int n_nodes);
 hipError_t launch_paths_fp32_lds_rho(const InstView *insts, const WorkRange *ranges, uint32_t n_items,
                                      uint32_t *head, uint32_t cap, int n_nodes, int grid, hipStream_t s);

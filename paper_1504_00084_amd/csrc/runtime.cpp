@@ -408,19 +408,20 @@ int run_fp32_launch(mesh_sdd_ctx *ctx, const std::vector<InstView> &views, const
     HIP_TRY(hipMemcpyAsync(ctx->views.p, views.data(), views.size() * sizeof(InstView), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(ctx->ranges.p, ranges.data(), ranges.size() * sizeof(WorkRange), hipMemcpyHostToDevice, st));
     // A launch that holds one instance whose rho node table fits in LDS next
-    // to the wave buffers runs the LDS variant (one 768-thread workgroup per
-    // CU, three waves per SIMD); its results are identical.
+    // to the wave buffers runs the LDS variant (1024-thread workgroups, as
+    // many per CU as registers and LDS allow); its results are identical.
     const int n_nodes = views.size() == 1 ? views[0].n_xi * views[0].n_eta : 0;
-    const bool lds_rho = views.size() == 1 && ranges.size() == 1 && l.monitor_table == 0 &&
-                         msdd::paths_fp32_lds_rho_bytes(cap, n_nodes) <= kLdsBytes &&
-                         msdd::paths_fp32_lds_rho_blocks_per_cu(cap, n_nodes) >= 1;
+    const int lds_per_cu = views.size() == 1 && msdd::paths_fp32_lds_rho_bytes(cap, n_nodes) <= kLdsBytes
+                               ? msdd::paths_fp32_lds_rho_blocks_per_cu(cap, n_nodes)
+                               : 0;
+    const bool lds_rho = ranges.size() == 1 && l.monitor_table == 0 && lds_per_cu >= 1;
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     HIP_TRY(hipEventRecord(e0, st));
     hipError_t le = lds_rho ? msdd::launch_paths_fp32_lds_rho(ctx->views.as<InstView>(), ctx->ranges.as<WorkRange>(),
                                                              (uint32_t)n_items, ctx->head.as<uint32_t>(), cap, n_nodes,
-                                                             ctx->cu_count, st)
+                                                             ctx->cu_count * lds_per_cu, st)
                             : msdd::launch_paths_fp32(ctx->views.as<InstView>(), ctx->ranges.as<WorkRange>(),
                                                       (uint32_t)ranges.size(), (uint32_t)n_items,
                                                       ctx->head.as<uint32_t>(), cap, grid_for(ctx, l, cap), l.block,
