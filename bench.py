@@ -66,6 +66,7 @@ def parse():
     ap.add_argument("--paths", type=int, default=100_000)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 plain comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving burst of the step mode")
     ap.add_argument("--tune", action="store_true",
                     help="run the library's autotuner first (default: the library's default launch shape, the "
                          "one the recorded HBM traffic was measured with)")
@@ -211,6 +212,14 @@ def main():
                 else "paths_fp32", "kernel_ms": round(kern_s * 1e3, 3),
                 "path_steps_per_launch": per_launch, "slots_per_path_step": W_SLOTS_PER_STEP}
 
+    # p50 / p99 of a short FP32 serving burst (0.7 x capacity) beside the throughput
+    serving = None
+    if not args.no_serve:
+        serving = serve_measure(24, "fp32", [int(v) for v in args.serve_sizes.split(",")], args.serve_max_paths,
+                                quiet=True)
+        log("serving: %d requests at %.2f req/s: p50 %.1f ms, p99 %.1f ms"
+            % (serving["requests"], serving["rate_req_s"], serving["p50_ms"], serving["p99_ms"]))
+
     cpu = None
     if not args.no_cpu:
         import oracle
@@ -248,6 +257,7 @@ def main():
         "fp64_plain": fp64,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "serving_fp32": serving,
     }
     print(json.dumps(line), flush=True)
     M.mesh_sdd_destroy(h32)
@@ -304,41 +314,40 @@ def run_batch(args):
     M.mesh_sdd_ctx_destroy(ctx)
 
 
-def run_serve(args):
+def serve_measure(requests: int, precision: str, sizes, max_paths: int, rate: float = 0.0, budget_mb: int = 0,
+                  launch: str = "", quiet: bool = False) -> dict:
     """Poisson stream of interface-solve requests from the batched mix, with
     a per-request standard-error target setting N; requests are created,
-    frozen and submitted at their arrival times and served by the library's
-    continuous-batching scheduler.  p50 / p99 are the library's
-    submit-to-completion latencies."""
+    frozen and submitted at their arrival times by client threads and
+    served by the library's continuous-batching scheduler.  p50 / p99 are
+    the library's submit-to-completion latencies."""
     import threading
 
     import numpy as np
-    import torch
 
     from paper_1504_00084_amd import mesh_sdd as M
     from paper_1504_00084_amd import workloads as W
 
     M.load()
-    sizes = tuple(int(v) for v in args.serve_sizes.split(","))
-    prec = M.FP32 if args.serve_precision == "fp32" else M.FP64
-    stream = W.serving_stream(args.requests, rate_hz=1.0, sizes=sizes,   # unit rate, rescaled below
-                              max_paths=args.serve_max_paths)
+    prec = M.FP32 if precision == "fp32" else M.FP64
+    stream = W.serving_stream(requests, rate_hz=1.0, sizes=tuple(sizes),   # unit rate, rescaled below
+                              max_paths=max_paths)
     work = []
     for _, it, _ in stream:
         m = len(M.mesh_sdd_desc_interface_nodes(M.desc_for(it))[0])
         work.append(m * it.n_paths * it.K)
-    rate = args.rate
     if rate <= 0.0:
-        # 0.7 x capacity: capacity from a short FP32 solve of the rotating bump
-        cap = 2.0e11 if prec == M.FP32 else 6.0e10
+        # 0.7 x capacity, capacity from the measured single-GPU rates of the
+        # two paths (executed path-steps are about 0.85 of nominal)
+        cap = 2.5e11 if prec == M.FP32 else 6.0e10
         rate = 0.7 * cap * 0.85 / float(np.mean(work))
     arrivals = [t / rate for t, _, _ in stream]
-    ctx = M.mesh_sdd_ctx_create(0, args.budget_mb << 20)
-    if args.launch:
-        b, w, c = (int(v) for v in args.launch.split(","))
+    ctx = M.mesh_sdd_ctx_create(0, budget_mb << 20)
+    if launch:
+        b, w, c = (int(v) for v in launch.split(","))
         M.mesh_sdd_set_launch(ctx, M.make_launch(b, w, c))
     log("serve: %d requests at %.3f req/s (%s), mean nominal work %.3e path-steps"
-        % (len(stream), rate, args.serve_precision, float(np.mean(work))))
+        % (len(stream), rate, precision, float(np.mean(work))))
     done, e2e = [], []
     lock = threading.Lock()
     t0 = time.perf_counter()
@@ -360,9 +369,9 @@ def run_serve(args):
         with lock:
             done.append(int(r.executed_path_steps))
             e2e.append(time.perf_counter() - ts)
-            log("request %d done (%d of %d): %.3e path-steps, %.1f ms" % (k, len(done), len(stream),
-                                                                         float(r.executed_path_steps),
-                                                                         1e3 * e2e[-1]))
+            if not quiet:
+                log("request %d done (%d of %d): %.3e path-steps, %.1f ms"
+                    % (k, len(done), len(stream), float(r.executed_path_steps), 1e3 * e2e[-1]))
 
     threads = [threading.Thread(target=client, args=(k,)) for k in range(len(stream))]
     for th in threads:
@@ -371,14 +380,22 @@ def run_serve(args):
         th.join()
     wall = time.perf_counter() - t0
     st = M.mesh_sdd_ctx_stats(ctx)
-    line = {"metric": "serving p50/p99 latency and throughput", "precision": args.serve_precision,
-            "requests": len(stream), "rate_req_s": rate, "completed": int(st.completed), "failed": int(st.failed),
-            "p50_ms": st.p50_ms, "p99_ms": st.p99_ms, "mean_ms": st.mean_ms,
-            "client_p50_ms": 1e3 * float(np.percentile(e2e, 50)), "client_p99_ms": 1e3 * float(np.percentile(e2e, 99)),
-            "throughput_path_steps_s": sum(done) / wall, "busy_ms": st.busy_ms, "wall_s": wall, "ticks": int(st.ticks),
-            "sizes": list(sizes), "data": "synthetic"}
-    print(json.dumps(line), flush=True)
+    out = {"precision": precision, "requests": len(stream), "rate_req_s": rate, "completed": int(st.completed),
+           "failed": int(st.failed), "p50_ms": st.p50_ms, "p99_ms": st.p99_ms, "mean_ms": st.mean_ms,
+           "client_p50_ms": 1e3 * float(np.percentile(e2e, 50)), "client_p99_ms": 1e3 * float(np.percentile(e2e, 99)),
+           "throughput_path_steps_s": sum(done) / wall, "busy_ms": st.busy_ms, "wall_s": wall,
+           "ticks": int(st.ticks), "sizes": list(sizes), "max_paths": max_paths}
     M.mesh_sdd_ctx_destroy(ctx)
+    return out
+
+
+def run_serve(args):
+    sizes = [int(v) for v in args.serve_sizes.split(",")]
+    line = {"metric": "serving p50/p99 latency and throughput"}
+    line.update(serve_measure(args.requests, args.serve_precision, sizes, args.serve_max_paths, args.rate,
+                              args.budget_mb, args.launch))
+    line["data"] = "synthetic"
+    print(json.dumps(line), flush=True)
 
 
 def run_mp(args):

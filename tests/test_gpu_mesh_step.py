@@ -282,3 +282,59 @@ def test_mesh_step_error_paths(M, ctx):
         assert np.max(np.abs(gx - XI)) < 1e-13 and np.max(np.abs(gy - ETA)) < 1e-13
     finally:
         M.mesh_sdd_destroy(h)
+
+
+def test_mp_step_edge_cases(M, ctx):
+    """No interface node at all (1x1 Dirichlet: the step is the edge generator
+    plus one subdomain = the whole grid); a periodic axis with one subdomain
+    (the seam alone is the interface); device arrays in and out; the edge
+    generator in place; K not a multiple of 4."""
+    import torch
+    dev = torch.device("cuda:0")
+    # 1x1 Dirichlet: M = 0, the mesh step equals edge generator + single domain
+    n, tau = 21, 0.01
+    rho, x, y, b0 = case_inputs(n, n, 0, 0, seed=31)
+    h = make_inst(M, ctx, n, n, 1, 1, 0, 0, tau=tau, K=30, rho=rho)
+    try:
+        assert M.mesh_sdd_num_interface_nodes(h) == 0
+        arrs, res = M.host_result(0)
+        xn, yn, bn = np.empty_like(x), np.empty_like(y), np.empty_like(b0)
+        M.mesh_sdd_mp_step(h, M.make_step(x, y, b0, b0, paths_per_node=100), xn, yn, bn, res)
+        assert res.executed_path_steps == 0
+        b1 = mp.edge_generate(rho, b0, tau)
+        wx, wy = mp.single_domain_solve(rho, x, y, b1, tau)
+        e = max(float(np.max(np.abs(xn - wx))), float(np.max(np.abs(yn - wy))), float(np.max(np.abs(bn - b1))))
+        say("1x1 Dirichlet mesh step (no interface node): max |gpu - oracle| %.3e" % e)
+        assert e <= 1e-13
+    finally:
+        M.mesh_sdd_destroy(h)
+    # xi periodic with one subdomain: interface = the seam; device arrays; K = 30
+    nx, ny, Lx = 25, 17, 2.0
+    rho, x, y, b0 = case_inputs(nx, ny, 1, 0, Lx, 1.0, seed=32)
+    h = make_inst(M, ctx, nx, ny, 1, 2, 1, 0, Lx, 1.0, tau=tau, K=30, rho=rho)
+    try:
+        m = M.mesh_sdd_num_interface_nodes(h)
+        I, J = M.mesh_sdd_interface_nodes(h)
+        assert np.all((I == 0) | (J == (ny - 1) // 2))
+        T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+        outs = [torch.empty(m, dtype=torch.float64, device=dev) for _ in range(5)]
+        res = M.make_result(*outs)
+        xn, yn, bn = T(np.zeros_like(x)), T(np.zeros_like(y)), T(np.zeros_like(b0))
+        step = M.make_step(T(x), T(y), T(b0), T(b0), paths_per_node=700, mesh_step=5)
+        M.mesh_sdd_mp_step(h, step, xn, yn, bn, res)
+        torch.cuda.synchronize()
+        b1 = mp.edge_generate(rho, b0, tau, 1, 0, Lx, 1.0)
+        est = oracle.solve(oracle.Problem(nx, ny, 1, 2, 1, 0, Lx, 1.0, tau=tau, K=30, mesh_step=5), rho, x, y, b0,
+                           b1, 700, threads=8)
+        wx, wy = mp.subdomain_solve(rho, x, y, b1, est["mean_x"], est["mean_y"], tau, 1, 2, 1, 0, Lx, 1.0)
+        gx, gy, gb = xn.cpu().numpy(), yn.cpu().numpy(), bn.cpu().numpy()
+        e = max(float(np.max(np.abs(gx - wx))), float(np.max(np.abs(gy - wy))), float(np.max(np.abs(gb - b1))))
+        say("seam-only periodic mesh step on device arrays (M=%d, K=30): max |gpu - oracle| %.3e" % (m, e))
+        assert e <= 1e-12
+        # the edge generator in place on a device array
+        bd = T(b0)
+        M.mesh_sdd_edge_generate(h, bd, bd)
+        torch.cuda.synchronize()
+        assert np.max(np.abs(bd.cpu().numpy() - b1)) <= 1e-14
+    finally:
+        M.mesh_sdd_destroy(h)
