@@ -109,7 +109,27 @@ typedef struct {
     double target_se;                /* > 0: N = min(max_paths, ceil(2 tau L^2/se^2)) */
     int64_t max_paths;               /* cap for target_se (0: 1e6)                   */
     uint32_t mesh_step;              /* enters the RNG counter (low 16 bits)         */
-    uint32_t reserved;
+    uint32_t interface_stride;       /* 0 or 1: every interface node runs paths.
+                                        s > 1 (section 3.6, subsampled interface):
+                                        on each interface line only the nodes at
+                                        multiples of s along the line run paths
+                                        (line crossings always do); every other
+                                        interface node takes the Keys cubic
+                                        interpolant (a = -1/2) along its line of
+                                        those estimates, of the boundary values at
+                                        t^{n+1} where the line meets a Dirichlet side
+                                        (Keys' end rule beyond it) and of the
+                                        periodic images (plus the period) across a
+                                        seam; its se is that of the same linear
+                                        combination of independent estimates, its
+                                        exit_frac NaN.  A node that runs paths keeps
+                                        its own random stream, so its results equal
+                                        those of the full run bit for bit.  s must
+                                        divide (n_xi-1)/sub_xi and (n_eta-1)/sub_eta
+                                        and leave >= 2 segments per grid line
+                                        ((n-1)/s >= 2 on both axes): E_INVAL
+                                        otherwise.  executed_path_steps counts the
+                                        sampled nodes' paths only.                */
 } mesh_sdd_step;
 
 /* Per-node results, caller-owned arrays of length M (interface-node count). */

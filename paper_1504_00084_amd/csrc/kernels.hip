@@ -528,16 +528,17 @@ __global__ __launch_bounds__(BLOCK) void paths_fp32(const InstView *__restrict__
                     ctr3 = Ip->ctr3;
                 }
                 const int i0 = gptr(Ip->node_i)[f.node], j0 = gptr(Ip->node_j)[f.node];
+                const uint32_t rk = gptr(Ip->node_r)[f.node];   // random-stream identity
                 const float x0 = (float)((double)i0 / (double)C.nx1);
                 const float y0 = (float)((double)j0 / (double)C.ny1);
                 const float m0 = side_distance(C, x0, y0);
                 const double rx = gptr(Ip->x64)[(uint32_t)(j0 * C.n_xi + i0)];
                 const double ry = gptr(Ip->y64)[(uint32_t)(j0 * C.n_xi + i0)];
                 if (tgt == 0u) {
-                    act0 = 1u; cnt0 = f.count; rem0 = f.count; node0 = f.node; pb0 = f.p_begin;
+                    act0 = 1u; cnt0 = f.count; rem0 = f.count; node0 = rk; pb0 = f.p_begin;
                     part0 = f.partial; x00 = x0; y00 = y0; m00 = m0; rx0 = rx; ry0 = ry;
                 } else {
-                    act1 = 1u; cnt1 = f.count; rem1 = f.count; node1 = f.node; pb1 = f.p_begin;
+                    act1 = 1u; cnt1 = f.count; rem1 = f.count; node1 = rk; pb1 = f.p_begin;
                     part1 = f.partial; x01 = x0; y01 = y0; m01 = m0; rx1 = rx; ry1 = ry;
                 }
                 cur = tgt;
@@ -693,7 +694,7 @@ __device__ __forceinline__ PathOutD run_path_f64(const InstView &I, uint32_t nod
 {
     const int nx1 = I.n_xi - 1, ny1 = I.n_eta - 1;
     const double dt = I.dt, sq = sqrt(2.0 * dt);
-    StreamF64 S{path, node, I.ctr3, I.key0, I.key1, 0xFFFFFFFFu, Words4{0, 0, 0, 0}};
+    StreamF64 S{path, I.node_r[node], I.ctr3, I.key0, I.key1, 0xFFFFFFFFu, Words4{0, 0, 0, 0}};
     double x = (double)I.node_i[node] / (double)nx1;
     double y = (double)I.node_j[node] / (double)ny1;
     long wx = 0, wy = 0;
@@ -855,19 +856,20 @@ __global__ void finalize_kernel(const Partial *__restrict__ partials, const Node
             my_steps += p.steps;
         }
         const int i0 = I.node_i[node], j0 = I.node_j[node];
+        const uint32_t r = I.node_r[node];
         const double N = (double)n_paths;
-        mean_x[node] = I.x64[(size_t)j0 * I.n_xi + i0] + s1x / N;
-        mean_y[node] = I.y64[(size_t)j0 * I.n_xi + i0] + s1y / N;
+        mean_x[r] = I.x64[(size_t)j0 * I.n_xi + i0] + s1x / N;
+        mean_y[r] = I.y64[(size_t)j0 * I.n_xi + i0] + s1y / N;
         if (n_paths > 1) {
             const double vx = (s2x - s1x * s1x / N) / (N - 1.0);
             const double vy = (s2y - s1y * s1y / N) / (N - 1.0);
-            se_x[node] = sqrt(fmax(vx, 0.0) / N);
-            se_y[node] = sqrt(fmax(vy, 0.0) / N);
+            se_x[r] = sqrt(fmax(vx, 0.0) / N);
+            se_y[r] = sqrt(fmax(vy, 0.0) / N);
         } else {
-            se_x[node] = __longlong_as_double(0x7FF8000000000000ll);
-            se_y[node] = __longlong_as_double(0x7FF8000000000000ll);
+            se_x[r] = __longlong_as_double(0x7FF8000000000000ll);
+            se_y[r] = __longlong_as_double(0x7FF8000000000000ll);
         }
-        exit_frac[node] = (double)ex / N;
+        exit_frac[r] = (double)ex / N;
     }
     // one atomic per wave for the executed-step total
     my_steps = wave_sum_u64(my_steps);
@@ -1005,6 +1007,116 @@ __global__ void fill_u32_kernel(uint32_t *p, uint32_t v, size_t n)
 }
 
 // ---------------------------------------------------------------------------
+// Interpolation of the interface nodes that ran no paths (a10)
+// ---------------------------------------------------------------------------
+// Keys' cubic-convolution kernel (a = -1/2) at distance d >= 0.
+__device__ __forceinline__ double keys_kernel(double d)
+{
+    if (d <= 1.0) return (1.5 * d - 2.5) * d * d + 1.0;
+    if (d < 2.0) return ((-0.5 * d + 2.5) * d - 4.0) * d + 2.0;
+    return 0.0;
+}
+
+// One thread per interface rank; nodes that ran paths return at once.  A
+// node without paths lies on exactly one interface line (line crossings sit
+// on multiples of the stride, which divides the subdomain sizes), at
+// position t between the known positions base and base + s.  The stencil
+// base - s .. base + 2s holds estimates, boundary values at t^{n+1} (line
+// ends on a Dirichlet side), Keys' end rule f(-s) = 3f(0) - 3f(s) + f(2s)
+// for a position beyond such an end, and periodic images plus the period
+// of the winding coordinate across a seam.  Every position the host allows
+// is an interface node or a line end; any other reads as NaN.
+__global__ void interpolate_kernel(InterpArgs a)
+{
+    const int r = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (r >= a.M) return;
+    const int i = a.node_i[r], j = a.node_j[r];
+    const int s = a.stride;
+    const bool on_v = i % a.P_xi == 0, on_h = j % a.P_eta == 0;
+    if ((on_v && j % s == 0) || (on_h && i % s == 0)) return;
+    const bool vert = on_v;
+    const int n = vert ? a.n_eta : a.n_xi;
+    const bool per = vert ? a.per_eta != 0 : a.per_xi != 0;
+    const int t = vert ? j : i;
+    const int base = t - t % s;
+    const double u = (double)(t - base) / (double)s;
+    const double wk[4] = {keys_kernel(1.0 + u), keys_kernel(u), keys_kernel(1.0 - u), keys_kernel(2.0 - u)};
+
+    // stencil terms (position on the line, weight), at most six
+    int tp[6];
+    double tw[6];
+    int nt = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int p = base + (k - 1) * s;
+        if (!per && p < 0) {
+            tp[nt] = 0, tw[nt++] = 3.0 * wk[k];
+            tp[nt] = s, tw[nt++] = -3.0 * wk[k];
+            tp[nt] = 2 * s, tw[nt++] = wk[k];
+        } else if (!per && p > n - 1) {
+            tp[nt] = n - 1, tw[nt++] = 3.0 * wk[k];
+            tp[nt] = n - 1 - s, tw[nt++] = -3.0 * wk[k];
+            tp[nt] = n - 1 - 2 * s, tw[nt++] = wk[k];
+        } else {
+            tp[nt] = p, tw[nt++] = wk[k];
+        }
+    }
+    const int ne = a.n_eta, nx = a.n_xi;
+    const double qnan = __longlong_as_double(0x7FF8000000000000ll);
+    int tq[6];   // interface rank of each term's value, -1 for a boundary value
+    double vx = 0.0, vy = 0.0;
+    for (int e = 0; e < nt; ++e) {
+        int p = tp[e];
+        double ox = 0.0, oy = 0.0, fx, fy;
+        int q = -1;
+        if (per) {
+            if (p < 0) {
+                p += n - 1;
+                (vert ? oy : ox) = -(vert ? a.Ly : a.Lx);
+            } else if (p > n - 2) {
+                p -= n - 1;
+                (vert ? oy : ox) = vert ? a.Ly : a.Lx;
+            }
+        }
+        if (!per && (p == 0 || p == n - 1)) {
+            const int side = p == 0 ? 0 : 1;
+            const int o = vert ? 4 * ne + side * 2 * nx + i : side * 2 * ne + j;
+            const int stride_y = vert ? nx : ne;
+            fx = a.bnd1[o];
+            fy = a.bnd1[o + stride_y];
+        } else if (p >= 0 && p < n) {
+            q = vert ? a.rank_of[p * nx + i] : a.rank_of[j * nx + p];
+            fx = q >= 0 ? a.mean_x[q] + ox : qnan;
+            fy = q >= 0 ? a.mean_y[q] + oy : qnan;
+        } else {
+            fx = fy = qnan;
+        }
+        tq[e] = q;
+        vx += tw[e] * fx;
+        vy += tw[e] * fy;
+    }
+    // variance of the combination: the weights of repeated estimates merged
+    double vsx = 0.0, vsy = 0.0;
+    for (int e = 0; e < nt; ++e) {
+        const int q = tq[e];
+        bool first = q >= 0;
+        for (int b = 0; b < e; ++b) first = first && tq[b] != q;
+        if (!first) continue;
+        double W = 0.0;
+        for (int b = e; b < nt; ++b)
+            if (tq[b] == q) W += tw[b];
+        const double sx = a.se_x[q], sy = a.se_y[q];
+        vsx += W * W * (sx * sx);
+        vsy += W * W * (sy * sy);
+    }
+    a.mean_x[r] = vx;
+    a.mean_y[r] = vy;
+    a.se_x[r] = sqrt(vsx);
+    a.se_y[r] = sqrt(vsy);
+    a.exit_frac[r] = qnan;
+}
+
+// ---------------------------------------------------------------------------
 // Diagnostics: one path per thread
 // ---------------------------------------------------------------------------
 __global__ void debug_paths_kernel(const InstView *__restrict__ inst, int fp64, uint32_t node, uint32_t p_begin,
@@ -1032,8 +1144,9 @@ __global__ void debug_paths_kernel(const InstView *__restrict__ inst, int fp64, 
     int side = -1;
     bool ended = false;
     while (!ended) {
-        side = tr ? group_f32<true, false>(P, C, path, node, I.ctr3, I.key0, I.key1, ended, tr, nullptr)
-                  : group_f32<false, false>(P, C, path, node, I.ctr3, I.key0, I.key1, ended, nullptr, nullptr);
+        side = tr ? group_f32<true, false>(P, C, path, I.node_r[node], I.ctr3, I.key0, I.key1, ended, tr, nullptr)
+                  : group_f32<false, false>(P, C, path, I.node_r[node], I.ctr3, I.key0, I.key1, ended, nullptr,
+                                            nullptr);
     }
     float fx, fy;
     path_value_f32(I, C, P, side, fx, fy);
@@ -1165,6 +1278,13 @@ hipError_t launch_finalize(const Partial *partials, const NodeSpan *spans, const
     if (M == 0) return hipSuccess;
     hipLaunchKernelGGL(finalize_kernel, dim3(blocks_for(M, 256)), dim3(256), 0, s, partials, spans, inst, M, n_paths,
                        mean_x, mean_y, se_x, se_y, exit_frac, steps_total);
+    return hipGetLastError();
+}
+
+hipError_t launch_interpolate(const InterpArgs &a, hipStream_t s)
+{
+    if (a.M <= 0) return hipSuccess;
+    hipLaunchKernelGGL(interpolate_kernel, dim3(blocks_for((size_t)a.M, 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

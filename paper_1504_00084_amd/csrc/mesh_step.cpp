@@ -128,19 +128,6 @@ struct SyncOnExit {
     ~SyncOnExit() { (void)hipStreamSynchronize(s); }
 };
 
-int ensure_node_rank(mesh_sdd *inst, hipStream_t st)
-{
-    if (inst->node_rank.p) return MESH_SDD_OK;
-    const mesh_sdd_desc &d = inst->d;
-    std::vector<int32_t> rank(grid_size(d), -1);
-    for (int r = 0; r < inst->M; ++r) rank[(size_t)inst->node_j[r] * d.n_xi + inst->node_i[r]] = r;
-    if (inst->node_rank.alloc(rank.size() * sizeof(int32_t)) != hipSuccess)
-        return fail(MESH_SDD_E_NOMEM, "device allocation of the node-rank map failed");
-    HIP_TRY(hipMemcpyAsync(inst->node_rank.p, rank.data(), rank.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipStreamSynchronize(st));   // the host vector goes out of scope
-    return MESH_SDD_OK;
-}
-
 // 1-D generator on every physical side, in place on device boundary arrays.
 int edge_dev(mesh_sdd *inst, const MpOpts &o, double *bnd, hipStream_t st)
 {
@@ -167,8 +154,6 @@ int solve_dev(mesh_sdd *inst, const MpOpts &o, const double *x0, const double *y
     mesh_sdd_ctx *ctx = inst->ctx;
     int L = 1;
     int rc = fe_substeps(d, o, &L);
-    if (rc != MESH_SDD_OK) return rc;
-    rc = ensure_node_rank(inst, st);
     if (rc != MESH_SDD_OK) return rc;
     const size_t n = grid_size(d);
     DevBuf tx1, ty1, mask, ax, ay, bx, by;

@@ -39,7 +39,7 @@ struct InstView {
     int32_t per_xi, per_eta;      // periodic flags
     int32_t K;                    // substeps
     int32_t bridge;               // Brownian-bridge test on/off
-    int32_t M;                    // interface nodes
+    int32_t M;                    // nodes that run paths (entries of node_i / node_j / node_r)
     int32_t pad0;
     uint32_t key0, key1;          // Philox key (seed low / high word)
     uint32_t ctr3;                // instance_id << 16 | mesh_step & 0xffff
@@ -49,7 +49,12 @@ struct InstView {
     float c_rad_f;                // -4 ln2 dt
     float delta_f;                // sqrt(18.5 dt)
 
-    const int32_t *node_i, *node_j;   // interface nodes in rank order
+    // The nodes that run paths, in order: grid indices and interface rank.
+    // The rank is the node's random-stream identity and its result slot, so
+    // a node's estimate does not depend on which other nodes run.  All
+    // interface nodes (node_r[k] = k) unless the step subsamples them.
+    const int32_t *node_i, *node_j;
+    const uint32_t *node_r;
 
     // FP32 path: per-cell records of three float4, (n_xi-1)(n_eta-1) cells:
     // rho at the four corners (00, 10, 01, 11), then dt rho_xi and dt rho_eta
@@ -80,6 +85,23 @@ struct InstView {
 struct NodeSpan {
     uint32_t first;
     uint32_t count;
+};
+
+// Interpolation of the interface nodes that ran no paths (section 3.6,
+// equispaced sampling with stride `stride` along every interface line).
+// Result arrays have one entry per interface rank; the estimated entries
+// are read, the others written.
+struct InterpArgs {
+    int32_t n_xi, n_eta;          // nodes per axis
+    int32_t P_xi, P_eta;          // subdomain cells per axis
+    int32_t per_xi, per_eta;      // periodic flags
+    int32_t stride;               // > 1
+    int32_t M;                    // interface nodes
+    double Lx, Ly;                // quasi-periodic offsets
+    const int32_t *node_i, *node_j;   // all interface nodes in rank order
+    const int32_t *rank_of;           // [n_eta][n_xi]: interface rank or -1
+    const double *bnd1;               // boundary arrays at t^{n+1} (C-ABI layout)
+    double *mean_x, *mean_y, *se_x, *se_y, *exit_frac;
 };
 
 }  // namespace msdd

@@ -56,10 +56,19 @@ hipError_t launch_paths_fp64(const InstView *inst, uint32_t M, uint32_t n_paths,
                              Partial *partials, hipStream_t s);
 constexpr int kFp64Block = 256;
 
-// a9: fixed-order combine of each node's partials; mean, SE, exit fraction.
+// a9: fixed-order combine of each node's partials; mean, SE, exit fraction,
+// written at the node's interface rank (inst->node_r).
 hipError_t launch_finalize(const Partial *partials, const NodeSpan *spans, const InstView *inst, uint32_t M,
                            uint64_t n_paths, double *mean_x, double *mean_y, double *se_x, double *se_y,
                            double *exit_frac, unsigned long long *steps_total, hipStream_t s);
+
+// a10 (subsampled steps): every interface node that ran no paths takes
+// the Keys cubic interpolant along its interface line of the estimates at
+// the multiples of the stride, the boundary values at t^{n+1} where the
+// line meets a Dirichlet side (with Keys' end rule beyond it) and the
+// periodic images across a seam; its standard error is that of the same
+// combination of independent estimates, its exit fraction NaN.
+hipError_t launch_interpolate(const InterpArgs &a, hipStream_t s);
 
 // Diagnostics: one path per thread with the FP32 or FP64 path arithmetic.
 hipError_t launch_debug_paths(const InstView *inst, int fp64, uint32_t node, uint32_t p_begin, uint32_t count,

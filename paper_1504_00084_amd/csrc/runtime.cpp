@@ -68,6 +68,21 @@ int install_monitor(mesh_sdd *inst, hipStream_t st)
     return MESH_SDD_OK;
 }
 
+// Equispaced sampling (section 3.6): on an interface line the nodes at
+// multiples of the stride along the line run paths; line crossings sit on
+// such multiples (the stride divides the subdomain sizes).
+std::vector<int32_t> sampled_ranks(const mesh_sdd &inst, int stride)
+{
+    std::vector<int32_t> out;
+    out.reserve((size_t)inst.M);
+    const int Px = (inst.d.n_xi - 1) / inst.d.sub_xi, Py = (inst.d.n_eta - 1) / inst.d.sub_eta;
+    for (int32_t r = 0; r < inst.M; ++r) {
+        const int i = inst.node_i[r], j = inst.node_j[r];
+        if (stride <= 1 || (i % Px == 0 && j % stride == 0) || (j % Py == 0 && i % stride == 0)) out.push_back(r);
+    }
+    return out;
+}
+
 }  // namespace msdd_rt
 
 using namespace msdd_rt;
@@ -131,7 +146,9 @@ size_t instance_bytes(const mesh_sdd_desc &d, int M)
 {
     const size_t n = (size_t)d.n_xi * d.n_eta;
     const size_t cells = (size_t)(d.n_xi - 1) * (d.n_eta - 1);
-    return 4 * n * sizeof(double) + n * sizeof(float) + 3 * cells * sizeof(float4) + 2 * (size_t)M * sizeof(int32_t);
+    // monitor tables, FP32 rho, cell records, node-rank map, stride-1 node lists
+    return 4 * n * sizeof(double) + n * sizeof(float) + 3 * cells * sizeof(float4) + n * sizeof(int32_t) +
+           3 * (size_t)M * sizeof(int32_t);
 }
 
 int64_t resolve_paths(const mesh_sdd &inst, const mesh_sdd_step &s)
@@ -155,6 +172,15 @@ int validate_step(const mesh_sdd &inst, const mesh_sdd_step *s, int64_t *N_out)
     if (s->target_se < 0.0 || !std::isfinite(s->target_se)) return fail(MESH_SDD_E_INVAL, "target_se < 0");
     const int64_t N = resolve_paths(inst, *s);
     if (N < 1 || N > (int64_t)1 << 31) return fail(MESH_SDD_E_INVAL, "paths per node %lld outside [1, 2^31]", (long long)N);
+    if (s->interface_stride > 1) {
+        const mesh_sdd_desc &d = inst.d;
+        const uint32_t st = s->interface_stride;
+        const uint32_t Px = (uint32_t)((d.n_xi - 1) / d.sub_xi), Py = (uint32_t)((d.n_eta - 1) / d.sub_eta);
+        if (Px % st || Py % st)
+            return fail(MESH_SDD_E_INVAL, "interface_stride %u does not divide the subdomain sizes %u x %u", st, Px, Py);
+        if ((uint32_t)(d.n_xi - 1) / st < 2 || (uint32_t)(d.n_eta - 1) / st < 2)
+            return fail(MESH_SDD_E_INVAL, "interface_stride %u leaves fewer than two segments along a grid line", st);
+    }
     *N_out = N;
     if (s->inputs_on_device) return MESH_SDD_OK;   // device inputs are not inspected
     const mesh_sdd_desc &d = inst.d;
@@ -227,7 +253,7 @@ int grid_for(mesh_sdd_ctx *ctx, const mesh_sdd_launch &l, uint32_t cap)
 // ---------------------------------------------------------------------------
 // Requests
 // ---------------------------------------------------------------------------
-size_t request_bytes(const mesh_sdd &inst, int64_t N, int chunk)
+size_t request_bytes(const mesh_sdd &inst, int64_t N, int chunk, int32_t Ms)
 {
     const mesh_sdd_desc &d = inst.d;
     const size_t n = (size_t)d.n_xi * d.n_eta;
@@ -238,8 +264,8 @@ size_t request_bytes(const mesh_sdd &inst, int64_t N, int chunk)
         chunks = (size_t)((N + msdd::kFp64Block - 1) / msdd::kFp64Block);
     else
         chunks = (size_t)((N + chunk - 1) / chunk);
-    return 2 * n * 8 + 2 * np * 12 + 2 * nb * 12 + (size_t)inst.M * chunks * sizeof(Partial) +
-           (size_t)inst.M * (sizeof(NodeSpan) + 5 * sizeof(double)) + sizeof(InstView) + 64;
+    return 2 * n * 8 + 2 * np * 12 + 2 * nb * 12 + (size_t)Ms * (chunks * sizeof(Partial) + sizeof(NodeSpan)) +
+           (size_t)inst.M * 5 * sizeof(double) + sizeof(InstView) + 64;
 }
 
 // Snapshot host inputs (the caller may free them once submit returns).
@@ -248,10 +274,12 @@ std::shared_ptr<Request> make_request(mesh_sdd *inst, const mesh_sdd_step &s, in
     auto r = std::make_shared<Request>();
     r->inst = inst;
     r->M = inst->M;
+    r->stride = s.interface_stride > 1 ? (int)s.interface_stride : 1;
+    r->Ms = r->stride > 1 ? (int32_t)sampled_ranks(*inst, r->stride).size() : inst->M;
     r->N = N;
     r->mesh_step = s.mesh_step;
     r->chunk_paths = std::max(64, launch_for(inst->ctx, inst->d).chunk_paths / 64 * 64);
-    r->cost_bytes = request_bytes(*inst, N, r->chunk_paths);
+    r->cost_bytes = request_bytes(*inst, N, r->chunk_paths, r->Ms);
     const size_t n = (size_t)inst->d.n_xi * inst->d.n_eta;
     const size_t nb = 4 * (size_t)inst->d.n_eta + 4 * (size_t)inst->d.n_xi;
     if (!s.inputs_on_device) {
@@ -261,6 +289,39 @@ std::shared_ptr<Request> make_request(mesh_sdd *inst, const mesh_sdd_step &s, in
         r->hb1.assign(s.bnd_t1, s.bnd_t1 + nb);
     }
     return r;
+}
+
+// Node lists of `stride` (built on first use and kept by the instance).
+// Caller holds gpu_mu.
+int sample_set(mesh_sdd &inst, int stride, const SampleSet **out)
+{
+    auto it = inst.samples.find(stride);
+    if (it != inst.samples.end()) {
+        *out = it->second.get();
+        return MESH_SDD_OK;
+    }
+    const std::vector<int32_t> ranks = sampled_ranks(inst, stride);
+    const size_t Ms = ranks.size();
+    std::vector<int32_t> host(3 * Ms);
+    for (size_t k = 0; k < Ms; ++k) {
+        host[k] = inst.node_i[ranks[k]];
+        host[Ms + k] = inst.node_j[ranks[k]];
+        host[2 * Ms + k] = ranks[k];
+    }
+    auto set = std::make_unique<SampleSet>();
+    set->stride = stride;
+    set->Ms = (int32_t)Ms;
+    if (set->lists.alloc(host.size() * sizeof(int32_t)) != hipSuccess)
+        return fail(MESH_SDD_E_NOMEM, "device allocation of the sampled node lists failed");
+    if (Ms) HIP_TRY(hipMemcpy(set->lists.p, host.data(), host.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    if (stride > 1) {
+        std::lock_guard<std::mutex> lk(inst.ctx->mu);
+        inst.resident_bytes += set->lists.bytes;
+        inst.ctx->in_use += set->lists.bytes;
+    }
+    *out = set.get();
+    inst.samples.emplace(stride, std::move(set));
+    return MESH_SDD_OK;
 }
 
 // Allocate the request's device buffers, stage its inputs and run the prep
@@ -276,6 +337,9 @@ int stage_request(Request &r, const mesh_sdd_step *dev_step)
     const size_t nb = 4 * (size_t)d.n_eta + 4 * (size_t)d.n_xi;
     const int M = inst.M;
     const bool fp64 = d.precision == MESH_SDD_FP64;
+    int rc = sample_set(inst, r.stride, &r.ss);
+    if (rc != MESH_SDD_OK) return rc;
+    const int Ms = r.ss->Ms;
 
     uint32_t chunks;
     if (fp64)
@@ -283,7 +347,7 @@ int stage_request(Request &r, const mesh_sdd_step *dev_step)
     else
         chunks = (uint32_t)((r.N + r.chunk_paths - 1) / r.chunk_paths);
     r.chunks_per_node = chunks;
-    const size_t n_part = (size_t)M * chunks;
+    const size_t n_part = (size_t)Ms * chunks;
 
     for (DevBuf *b : {&r.x64, &r.y64, &r.b0, &r.b1, &r.xpad, &r.ypad, &r.xpad_f, &r.ypad_f, &r.b0f, &r.b1f,
                       &r.view, &r.partials, &r.spans, &r.out, &r.steps_total})
@@ -291,7 +355,7 @@ int stage_request(Request &r, const mesh_sdd_step *dev_step)
     if (r.x64.alloc(n * 8) || r.y64.alloc(n * 8) || r.b0.alloc(nb * 8) || r.b1.alloc(nb * 8) ||
         r.xpad.alloc(np * 8) || r.ypad.alloc(np * 8) || r.xpad_f.alloc(np * 4) || r.ypad_f.alloc(np * 4) ||
         r.b0f.alloc(nb * 4) || r.b1f.alloc(nb * 4) || r.view.alloc(sizeof(InstView)) ||
-        r.partials.alloc(n_part * sizeof(Partial)) || r.spans.alloc((size_t)M * sizeof(NodeSpan)) ||
+        r.partials.alloc(n_part * sizeof(Partial)) || r.spans.alloc((size_t)Ms * sizeof(NodeSpan)) ||
         r.out.alloc((size_t)5 * M * sizeof(double)) || r.steps_total.alloc(sizeof(unsigned long long)))
         return fail(MESH_SDD_E_NOMEM, "device allocation for a request failed");
 
@@ -321,7 +385,7 @@ int stage_request(Request &r, const mesh_sdd_step *dev_step)
     v.per_eta = d.periodic_eta;
     v.K = d.K;
     v.bridge = d.bridge;
-    v.M = M;
+    v.M = Ms;
     v.key0 = (uint32_t)(d.seed & 0xFFFFFFFFu);
     v.key1 = (uint32_t)(d.seed >> 32);
     v.ctr3 = (d.instance_id << 16) | (r.mesh_step & 0xFFFFu);
@@ -337,8 +401,9 @@ int stage_request(Request &r, const mesh_sdd_step *dev_step)
     v.inv_tau_f = (float)(1.0 / d.tau);
     v.c_rad_f = (float)(-4.0 * std::log(2.0) * v.dt);
     v.delta_f = (float)std::sqrt(18.5 * v.dt);
-    v.node_i = inst.dev_i.as<int32_t>();
-    v.node_j = inst.dev_j.as<int32_t>();
+    v.node_i = r.ss->node_i();
+    v.node_j = r.ss->node_j();
+    v.node_r = r.ss->node_r();
     v.cells = inst.cells.as<float4>();
     v.rho_f = inst.rho_f.as<float>();
     v.xpad_f = r.xpad_f.as<float>();
@@ -358,9 +423,9 @@ int stage_request(Request &r, const mesh_sdd_step *dev_step)
     HIP_TRY(hipMemcpyAsync(r.view.p, &v, sizeof v, hipMemcpyHostToDevice, st));
 
     // node spans: node-major chunk slots
-    std::vector<NodeSpan> spans((size_t)M);
-    for (int m = 0; m < M; ++m) spans[m] = NodeSpan{(uint32_t)((size_t)m * chunks), chunks};
-    if (M) HIP_TRY(hipMemcpyAsync(r.spans.p, spans.data(), spans.size() * sizeof(NodeSpan), hipMemcpyHostToDevice, st));
+    std::vector<NodeSpan> spans((size_t)Ms);
+    for (int m = 0; m < Ms; ++m) spans[m] = NodeSpan{(uint32_t)((size_t)m * chunks), chunks};
+    if (Ms) HIP_TRY(hipMemcpyAsync(r.spans.p, spans.data(), spans.size() * sizeof(NodeSpan), hipMemcpyHostToDevice, st));
     HIP_TRY(msdd::launch_fill_u32(r.steps_total.as<uint32_t>(), 0u, 2, st));
 
     // FP32 work: every (node, chunk), numbered node-major, so that the waves
@@ -446,7 +511,7 @@ WorkRange range_of(const Request &r, uint32_t slot, size_t base, size_t first, s
     w.base = (uint32_t)base;
     w.count = (uint32_t)count;
     w.first = (uint32_t)first;
-    w.M = (uint32_t)r.M;
+    w.M = (uint32_t)r.Ms;
     w.chunks = r.chunks_per_node;
     w.chunk_paths = (uint32_t)r.chunk_paths;
     w.N = (uint32_t)r.N;
@@ -461,7 +526,7 @@ int run_fp64_launch(mesh_sdd_ctx *ctx, Request &r, double *ms)
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     HIP_TRY(hipEventRecord(e0, st));
-    hipError_t le = msdd::launch_paths_fp64(r.view.as<InstView>(), (uint32_t)r.inst->M, (uint32_t)r.N,
+    hipError_t le = msdd::launch_paths_fp64(r.view.as<InstView>(), (uint32_t)r.Ms, (uint32_t)r.N,
                                             r.chunks_per_node, r.partials.as<Partial>(), st);
     HIP_TRY(hipEventRecord(e1, st));
     hipError_t se = hipEventSynchronize(e1);
@@ -475,15 +540,41 @@ int run_fp64_launch(mesh_sdd_ctx *ctx, Request &r, double *ms)
     return MESH_SDD_OK;
 }
 
-// Finalize (a9) into the request's output buffer and copy it to the host.
+// Finalize (a9) into the request's output buffer, interpolate the nodes
+// that ran no paths (a10), and copy the results to the host.
 int finalize_request(mesh_sdd_ctx *ctx, Request &r)
 {
     hipStream_t st = ctx->stream;
-    const int M = r.inst->M;
+    const mesh_sdd &inst = *r.inst;
+    const int M = inst.M;
     double *o = r.out.as<double>();
     HIP_TRY(msdd::launch_finalize(r.partials.as<Partial>(), r.spans.as<NodeSpan>(), r.view.as<InstView>(),
-                                  (uint32_t)M, (uint64_t)r.N, o, o + M, o + 2 * (size_t)M, o + 3 * (size_t)M,
+                                  (uint32_t)r.Ms, (uint64_t)r.N, o, o + M, o + 2 * (size_t)M, o + 3 * (size_t)M,
                                   o + 4 * (size_t)M, r.steps_total.as<unsigned long long>(), st));
+    if (r.Ms < M) {
+        const SampleSet &all = *inst.samples.at(1);
+        msdd::InterpArgs a{};
+        a.n_xi = inst.d.n_xi;
+        a.n_eta = inst.d.n_eta;
+        a.P_xi = (inst.d.n_xi - 1) / inst.d.sub_xi;
+        a.P_eta = (inst.d.n_eta - 1) / inst.d.sub_eta;
+        a.per_xi = inst.d.periodic_xi;
+        a.per_eta = inst.d.periodic_eta;
+        a.stride = r.stride;
+        a.M = M;
+        a.Lx = inst.d.Lx;
+        a.Ly = inst.d.Ly;
+        a.node_i = all.node_i();
+        a.node_j = all.node_j();
+        a.rank_of = inst.node_rank.as<int32_t>();
+        a.bnd1 = r.b1.as<double>();
+        a.mean_x = o;
+        a.mean_y = o + M;
+        a.se_x = o + 2 * (size_t)M;
+        a.se_y = o + 3 * (size_t)M;
+        a.exit_frac = o + 4 * (size_t)M;
+        HIP_TRY(msdd::launch_interpolate(a, st));
+    }
     r.host_out.resize((size_t)5 * M);
     unsigned long long steps = 0;
     if (M) HIP_TRY(hipMemcpyAsync(r.host_out.data(), o, r.host_out.size() * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -912,14 +1003,18 @@ int mesh_sdd_create(mesh_sdd_ctx *ctx, const mesh_sdd_desc *desc, mesh_sdd **out
     const size_t cells = (size_t)(desc->n_xi - 1) * (desc->n_eta - 1);
     std::lock_guard<std::mutex> g(ctx->gpu_mu);
     HIP_TRY(hipSetDevice(ctx->device));
-    if (inst->dev_i.alloc((size_t)inst->M * 4) || inst->dev_j.alloc((size_t)inst->M * 4) ||
-        inst->rho_in.alloc(n * 8) || inst->rho.alloc(n * 8) || inst->rho_xi.alloc(n * 8) ||
-        inst->rho_eta.alloc(n * 8) || inst->rho_f.alloc(n * 4) || inst->cells.alloc(cells * 3 * sizeof(float4)))
+    if (inst->rho_in.alloc(n * 8) || inst->rho.alloc(n * 8) || inst->rho_xi.alloc(n * 8) ||
+        inst->rho_eta.alloc(n * 8) || inst->rho_f.alloc(n * 4) || inst->cells.alloc(cells * 3 * sizeof(float4)) ||
+        inst->node_rank.alloc(n * 4))
         return fail(MESH_SDD_E_NOMEM, "device allocation for the instance tables failed");
-    if (inst->M) {
-        HIP_TRY(hipMemcpy(inst->dev_i.p, inst->node_i.data(), (size_t)inst->M * 4, hipMemcpyHostToDevice));
-        HIP_TRY(hipMemcpy(inst->dev_j.p, inst->node_j.data(), (size_t)inst->M * 4, hipMemcpyHostToDevice));
+    {
+        std::vector<int32_t> rank(n, -1);
+        for (int32_t r = 0; r < inst->M; ++r) rank[(size_t)inst->node_j[r] * desc->n_xi + inst->node_i[r]] = r;
+        HIP_TRY(hipMemcpy(inst->node_rank.p, rank.data(), n * 4, hipMemcpyHostToDevice));
     }
+    const SampleSet *all = nullptr;
+    rc = sample_set(*inst, 1, &all);
+    if (rc != MESH_SDD_OK) return rc;
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
         ctx->in_use += inst->resident_bytes;
@@ -1216,7 +1311,9 @@ int mesh_sdd_debug_paths(mesh_sdd *inst, const mesh_sdd_step *step, int32_t node
     if (rc != MESH_SDD_OK) return rc;
     mesh_sdd_ctx *ctx = inst->ctx;
     const uint32_t count = (uint32_t)(p_end - p_begin);
-    auto r = make_request(inst, *step, std::max<int64_t>(1, count));
+    mesh_sdd_step full = *step;
+    full.interface_stride = 0;   // node_rank indexes the full node lists
+    auto r = make_request(inst, full, std::max<int64_t>(1, count));
     std::lock_guard<std::mutex> g(ctx->gpu_mu);
     inst->inflight.fetch_add(1);
     rc = stage_request(*r, step->inputs_on_device ? step : nullptr);

@@ -155,16 +155,30 @@ using msdd::InstView;
 // ---------------------------------------------------------------------------
 struct Request;
 
+// The interface nodes that run paths under one sampling stride (1: all of
+// them): device lists node_i[Ms], node_j[Ms], node_r[Ms] (int32, in that
+// order, contiguous) in rank order.
+struct SampleSet {
+    int stride = 1;
+    int32_t Ms = 0;
+    DevBuf lists;
+    const int32_t *node_i() const { return lists.as<int32_t>(); }
+    const int32_t *node_j() const { return lists.as<int32_t>() + Ms; }
+    const uint32_t *node_r() const { return reinterpret_cast<const uint32_t *>(lists.as<int32_t>() + 2 * (size_t)Ms); }
+};
+
 struct mesh_sdd {
     mesh_sdd_ctx *ctx = nullptr;
     mesh_sdd_desc d{};
     int32_t M = 0;
     std::vector<int32_t> node_i, node_j;
-    DevBuf dev_i, dev_j;                    // interface nodes
+    // sample sets by stride; stride 1 is built at create, the others on
+    // first use (under ctx->gpu_mu), and all live until destroy
+    std::map<int, std::unique_ptr<SampleSet>> samples;
     DevBuf rho_in, rho, rho_xi, rho_eta;    // FP64 monitor staging and node tables
     DevBuf rho_f;                           // FP32 node table of rho (staged in LDS by single-instance launches)
     DevBuf cells;                           // FP32 per-cell records (rho corners, gradient coefficients)
-    DevBuf node_rank;                       // [n_eta][n_xi] interface rank or -1 (mesh step; built on first use)
+    DevBuf node_rank;                       // [n_eta][n_xi] interface rank or -1
     bool monitor_set = false;
     std::atomic<int> inflight{0};
     size_t resident_bytes = 0;
@@ -174,6 +188,9 @@ struct Request {
     uint64_t ticket = 0;
     mesh_sdd *inst = nullptr;      // valid until the request finishes
     int32_t M = 0;                 // interface nodes (kept for poll after finish)
+    int32_t Ms = 0;                // of which run paths (all unless subsampled)
+    int stride = 1;                // interface sampling stride
+    const SampleSet *ss = nullptr; // set by stage_request
     int64_t N = 0;
     uint32_t mesh_step = 0;
     int chunk_paths = 0;
@@ -243,4 +260,8 @@ struct mesh_sdd_ctx {
 
 namespace msdd_rt {
 int install_monitor(mesh_sdd *inst, hipStream_t st);
+
+// Ranks of the interface nodes that run paths under `stride` (0 or 1: all),
+// in rank order.  The stride must have passed the step validation.
+std::vector<int32_t> sampled_ranks(const mesh_sdd &inst, int stride);
 }  // namespace msdd_rt

@@ -55,7 +55,8 @@ class Step(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("inputs_on_device", ctypes.c_int32),
                 ("x_cur", ctypes.c_void_p), ("y_cur", ctypes.c_void_p), ("bnd_t0", ctypes.c_void_p),
                 ("bnd_t1", ctypes.c_void_p), ("paths_per_node", ctypes.c_int64), ("target_se", ctypes.c_double),
-                ("max_paths", ctypes.c_int64), ("mesh_step", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("max_paths", ctypes.c_int64), ("mesh_step", ctypes.c_uint32),
+                ("interface_stride", ctypes.c_uint32)]
 
 
 class Result(ctypes.Structure):
@@ -265,8 +266,11 @@ def mesh_sdd_interface_nodes(inst):
     return i[:m], j[:m]
 
 
-def make_step(x_cur, y_cur, bnd_t0, bnd_t1, paths_per_node=0, target_se=0.0, max_paths=0, mesh_step=0) -> Step:
-    """Step descriptor; the arrays must stay alive until the call returns."""
+def make_step(x_cur, y_cur, bnd_t0, bnd_t1, paths_per_node=0, target_se=0.0, max_paths=0, mesh_step=0,
+              interface_stride=0) -> Step:
+    """Step descriptor; the arrays must stay alive until the call returns.
+    interface_stride > 1 runs paths at every stride-th node of each interface
+    line only and interpolates the others."""
     px, dx = _ptr(x_cur)
     py, dy = _ptr(y_cur)
     p0, d0 = _ptr(bnd_t0)
@@ -274,7 +278,7 @@ def make_step(x_cur, y_cur, bnd_t0, bnd_t1, paths_per_node=0, target_se=0.0, max
     if len({dx, dy, d0, d1}) != 1:
         raise ValueError("step inputs must be all host arrays or all device tensors")
     st = Step(ctypes.sizeof(Step), int(dx), px, py, p0, p1, int(paths_per_node), float(target_se),
-              int(max_paths), int(mesh_step), 0)
+              int(max_paths), int(mesh_step), int(interface_stride))
     st._keep = (x_cur, y_cur, bnd_t0, bnd_t1)
     return st
 
