@@ -36,11 +36,11 @@ W_SLOTS_PER_STEP = 86.5
 # workgroup, one workgroup per CU, 128-path chunks), from two rocprofv3 --pmc
 # runs of this script (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each
 # scaled by what the counter reads for a 1 GiB device copy in the same run
-# (FETCH_SIZE reads 524308 KiB: x2.0; WRITE_SIZE reads 1048576 KiB: x1.0).
+# (FETCH_SIZE reads 524708 KiB: x2.0; WRITE_SIZE reads 1.0492e6 KiB: x1.0).
 # Valid only for the kernel source it was measured on (SHA-1 of
 # csrc/kernels.hip); reported as null otherwise.
-TRAFFIC_RECORD = {"kernels_sha1": "a1855efbc12c51a9b6e979753766ea1f7a6b9950", "fetch_kib": 4471.69,
-                  "write_kib": 54131.8, "fetch_scale": 2.0, "write_scale": 1.0}
+TRAFFIC_RECORD = {"kernels_sha1": "54c4209e0d8d4e83feb3dc84996467b32d9fb71a", "fetch_kib": 4493.69,
+                  "write_kib": 54137.8, "fetch_scale": 2.0, "write_scale": 1.0}
 
 
 def recorded_traffic():
@@ -80,6 +80,10 @@ def parse():
     ap.add_argument("--mp-steps", type=int, default=50, help="mesh steps of the mp mode")
     ap.add_argument("--quality-subs", default="2,3,4", help="subdomains per axis of the quality mode")
     ap.add_argument("--quality-K", default="1,10", help="path substeps per mesh step of the quality mode")
+    ap.add_argument("--quality-stride", default="1,2",
+                    help="interface sampling strides of the quality mode (skipped where a stride does not divide "
+                         "the subdomain size)")
+    ap.add_argument("--mp-stride", default="1,2,4", help="interface sampling strides of the mp mode")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--batch-scale", type=float, default=1.0, help="scale the mix's path counts (batch mode)")
     ap.add_argument("--requests", type=int, default=40, help="requests in serve mode")
@@ -414,12 +418,20 @@ def run_mp(args):
     M.load()
     loop = W.rotating_bump_loop(n_paths=args.paths, steps=args.mp_steps)
     ctx = M.mesh_sdd_ctx_create(0)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    out = mp_loop.run(ctx, loop, M.FP32, decomposed=True, log=log)
-    wall = time.perf_counter() - t0
     sd = mp_loop.run(ctx, loop, M.FP32, decomposed=False, log=log)      # single-domain reference mesh
-    rmax, rmean, r = mp_loop.quality(ctx, loop, sd, out)
+    strides = [int(v) for v in args.mp_stride.split(",")]
+    if 1 not in strides:
+        strides.insert(0, 1)
+    by_stride = []
+    for s in strides:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        o = mp_loop.run(ctx, loop, M.FP32, decomposed=True, log=log, stride=s)
+        w = time.perf_counter() - t0
+        q = mp_loop.quality(ctx, loop, sd, o)
+        by_stride.append((s, o, w, q))
+        log("mp loop stride %d: %.1f ms per mesh step, R_max %.4f R_mean %.4f" % (s, 1e3 * w / loop.steps, q[0], q[1]))
+    _, out, wall, (rmax, rmean, r) = next(t for t in by_stride if t[0] == 1)
     # time split of one step on the final mesh
     h = M.mesh_sdd_create(ctx, M.make_desc(129, 129, 4, 4, K=loop.K, tau=loop.tau))
     x, y, b = out["x"], out["y"], out["bnd"]
@@ -449,6 +461,10 @@ def run_mp(args):
             "ms_per_mesh_step": 1e3 * wall / loop.steps, "executed_path_steps": out["executed_path_steps"],
             "split_of_one_step": split, "quality_vs_single_domain": {"R_max": rmax, "R_mean": rmean,
                                                                      "R_min": float(r.min())},
+            "interface_subsampling": [{"stride": s, "ms_per_mesh_step": 1e3 * w / loop.steps,
+                                       "path_steps_per_mesh_step": o["executed_path_steps"] / loop.steps,
+                                       "R_max": q[0], "R_mean": q[1], "R_min": float(q[2].min())}
+                                      for s, o, w, q in by_stride],
             "dtype": "f32 (paths) / f64 (mesh, sums)", "data": "synthetic",
             "config": {"workload": loop.name, "grid": [129, 129], "subdomains": [4, 4], "paths_per_node": loop.n_paths,
                        "K": loop.K, "tau": loop.tau, "alpha": "10 / max |grad u|^2"}}
@@ -468,19 +484,23 @@ def run_quality(args):
     M.load()
     ctx = M.mesh_sdd_ctx_create(0)
     rows = []
+    strides = [int(v) for v in args.quality_stride.split(",")]
     for K in (int(v) for v in args.quality_K.split(",")):
         for sub in (int(v) for v in args.quality_subs.split(",")):
             n = 41 if 40 % sub == 0 else next(k for k in range(41, 200) if (k - 1) % sub == 0)
             loop = W.five_ring_loop(sub, n=n, K=K)
-            t = time.perf_counter()
             sd = mp_loop.run(ctx, loop, M.FP32, decomposed=False, log=log)
-            sdd = mp_loop.run(ctx, loop, M.FP32, decomposed=True, log=log)
-            rmax, rmean, r = mp_loop.quality(ctx, loop, sd, sdd)
-            rows.append({"subdomains": sub, "n": n, "K": K, "interface_nodes": sdd["interface_nodes"],
-                         "R_max": rmax, "R_mean": rmean, "R_min": float(r.min()), "steps": loop.steps,
-                         "wall_s": time.perf_counter() - t})
-            log("five ring %dx%d (n=%d, K=%d): R_max %.4f R_mean %.4f R_min %.4f"
-                % (sub, sub, n, K, rmax, rmean, r.min()))
+            for s in strides:
+                if s > 1 and ((n - 1) // sub) % s:
+                    continue
+                t = time.perf_counter()
+                sdd = mp_loop.run(ctx, loop, M.FP32, decomposed=True, log=log, stride=s)
+                rmax, rmean, r = mp_loop.quality(ctx, loop, sd, sdd)
+                rows.append({"subdomains": sub, "n": n, "K": K, "interface_stride": s,
+                             "interface_nodes": sdd["interface_nodes"], "R_max": rmax, "R_mean": rmean,
+                             "R_min": float(r.min()), "steps": loop.steps, "wall_s": time.perf_counter() - t})
+                log("five ring %dx%d (n=%d, K=%d, stride %d): R_max %.4f R_mean %.4f R_min %.4f"
+                    % (sub, sub, n, K, s, rmax, rmean, r.min()))
     M.mesh_sdd_ctx_destroy(ctx)
     print(json.dumps({"metric": "five-ring mesh quality R = Q_SD / Q_SDD (max, mean over cells) at t = 0.05",
                       "results": rows, "paper": "R_max = R_mean = 1 at 2x2, 3x3 and 4x4",

@@ -26,8 +26,10 @@ def _desc(loop: W.MeshLoop, precision: int, seed: int, instance_id: int):
 
 
 def run(ctx, loop: W.MeshLoop, precision: int = M.FP32, decomposed: bool = True, steps: int | None = None,
-        opts: M.MpOpts | None = None, seed: int = 0, instance_id: int = 0, log=None) -> dict:
+        opts: M.MpOpts | None = None, seed: int = 0, instance_id: int = 0, log=None, stride: int = 0) -> dict:
     """Advance loop.x0, loop.y0 over `steps` (default loop.steps) mesh steps.
+    stride > 1 estimates every stride-th node of each interface line and
+    interpolates the others (section 3.6).
 
     Returns the final mesh and boundary arrays, the executed path-steps and
     the per-step wall and device times."""
@@ -47,7 +49,7 @@ def run(ctx, loop: W.MeshLoop, precision: int = M.FP32, decomposed: bool = True,
             xn, yn, bn = np.empty_like(x), np.empty_like(y), np.empty_like(b)
             if decomposed:
                 arrs, res = M.host_result(m)
-                step = M.make_step(x, y, b, b, paths_per_node=loop.n_paths, mesh_step=n)
+                step = M.make_step(x, y, b, b, paths_per_node=loop.n_paths, mesh_step=n, interface_stride=stride)
                 M.mesh_sdd_mp_step(h, step, xn, yn, bn, res, opts)
                 executed += int(res.executed_path_steps)
                 dev.append(float(res.device_ms))
