@@ -360,6 +360,23 @@ int mesh_sdd_mesh_quality(mesh_sdd *inst, const double *x_sd, const double *y_sd
                           const double *y_dd, double *r_cells, double *r_max, double *r_mean,
                           int pointers_on_device);
 
+/* Monitor transfer of the MᵏP variant (section 5: the monitor of each
+ * sub-step is the piecewise-linear interpolant of (x^n, rho^n) at the nodes
+ * of the current sub-mesh).  f_new [n_eta][n_xi] at the nodes (x_new, y_new)
+ * from the nodal values f_old on the mesh (x_old, y_old), all on the
+ * instance's grid: every old cell (i, j)-(i+1, j+1) is split along its
+ * diagonal from node (i, j) to node (i+1, j+1); a new node takes the linear
+ * interpolant of the triangle that contains it, or, outside the old mesh,
+ * the linear extension of the triangle whose smallest barycentric coordinate
+ * is largest.  Periodic axes extend the old mesh by its images (x + Lx along
+ * xi, y + Ly along eta, f unchanged); image nodes of f_new take node 0's
+ * value.  All six arrays are host or all device memory (pointers_on_device);
+ * f_new must not alias an input.  Blocking.  Does not change the installed
+ * monitor (pass f_new to mesh_sdd_set_monitor for that).  E_INVAL on null
+ * pointers or non-finite host inputs. */
+int mesh_sdd_transfer_field(mesh_sdd *inst, const double *x_old, const double *y_old, const double *f_old,
+                            const double *x_new, const double *y_new, double *f_new, int pointers_on_device);
+
 /* ---- diagnostics ----------------------------------------------------------- */
 
 /* Per-path outcomes of interface node `node_rank`, paths [p_begin, p_end),

@@ -392,6 +392,53 @@ int mesh_sdd_mp_step(mesh_sdd *inst, const mesh_sdd_step *step, const mesh_sdd_m
     return MESH_SDD_OK;
 }
 
+int mesh_sdd_transfer_field(mesh_sdd *inst, const double *x_old, const double *y_old, const double *f_old,
+                            const double *x_new, const double *y_new, double *f_new, int pointers_on_device)
+{
+    if (!inst) return fail(MESH_SDD_E_INVAL, "instance is NULL");
+    if (!x_old || !y_old || !f_old || !x_new || !y_new || !f_new) return fail(MESH_SDD_E_INVAL, "NULL array");
+    mesh_sdd_ctx *ctx = inst->ctx;
+    const mesh_sdd_desc &d = inst->d;
+    const size_t n = grid_size(d);
+    if (!pointers_on_device) {
+        for (size_t k = 0; k < n; ++k)
+            if (!std::isfinite(x_old[k]) || !std::isfinite(y_old[k]) || !std::isfinite(f_old[k]) ||
+                !std::isfinite(x_new[k]) || !std::isfinite(y_new[k]))
+                return fail(MESH_SDD_E_INVAL, "input value %zu is not finite", k);
+    }
+    std::lock_guard<std::mutex> g(ctx->gpu_mu);
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    DevIn xo, yo, fo, xn, yn;
+    DevOut out;
+    SyncOnExit sync{st};
+    int rc;
+    if ((rc = stage_in(ctx, x_old, n, pointers_on_device, xo, st)) ||
+        (rc = stage_in(ctx, y_old, n, pointers_on_device, yo, st)) ||
+        (rc = stage_in(ctx, f_old, n, pointers_on_device, fo, st)) ||
+        (rc = stage_in(ctx, x_new, n, pointers_on_device, xn, st)) ||
+        (rc = stage_in(ctx, y_new, n, pointers_on_device, yn, st)) ||
+        (rc = stage_out(ctx, f_new, n, pointers_on_device, out)))
+        return rc;
+    msdd::TransferArgs a{};
+    a.n_xi = d.n_xi;
+    a.n_eta = d.n_eta;
+    a.per_xi = d.periodic_xi;
+    a.per_eta = d.periodic_eta;
+    a.Lx = d.Lx;
+    a.Ly = d.Ly;
+    a.x_old = xo.p;
+    a.y_old = yo.p;
+    a.f_old = fo.p;
+    a.x_new = xn.p;
+    a.y_new = yn.p;
+    a.f_new = out.p;
+    HIP_TRY(msdd::launch_transfer_p1(a, st));
+    if ((rc = finish(out, st)) != MESH_SDD_OK) return rc;
+    HIP_TRY(hipStreamSynchronize(st));
+    return MESH_SDD_OK;
+}
+
 int mesh_sdd_set_monitor_arclength(mesh_sdd *inst, const double *u, const double *x, const double *y, double alpha,
                                    int normalize, int pointers_on_device)
 {

@@ -478,6 +478,101 @@ __global__ __launch_bounds__(kQualityBlock) void quality_final_kernel(const doub
 
 inline unsigned blocks_of(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
 
+// ---------------------------------------------------------------------------
+// Piecewise-linear transfer of a nodal field between meshes (MᵏP, section 5)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int floor_div(int a, int m) { return a >= 0 ? a / m : -((-a + m - 1) / m); }
+
+// Old-mesh node at grid indices (ii, jj) that may lie beyond a periodic
+// seam: wrapped into range, with the period added to the winding coordinate.
+__device__ __forceinline__ void old_node(const TransferArgs &a, int ii, int jj, double &x, double &y, double &f)
+{
+    double ox = 0.0, oy = 0.0;
+    if (a.per_xi) {
+        const int q = floor_div(ii, a.n_xi - 1);
+        ii -= q * (a.n_xi - 1);
+        ox = (double)q * a.Lx;
+    }
+    if (a.per_eta) {
+        const int q = floor_div(jj, a.n_eta - 1);
+        jj -= q * (a.n_eta - 1);
+        oy = (double)q * a.Ly;
+    }
+    const size_t k = (size_t)jj * a.n_xi + ii;
+    x = a.x_old[k] + ox;
+    y = a.y_old[k] + oy;
+    f = a.f_old[k];
+}
+
+// Barycentric test of point p against triangle (A, B, C): the smallest
+// coordinate and the linear interpolant of the vertex values.
+__device__ __forceinline__ void tri_test(double px, double py, double ax, double ay, double af, double bx, double by,
+                                         double bf, double cx, double cy, double cf, double &lmin, double &val)
+{
+    const double e1x = bx - ax, e1y = by - ay, e2x = cx - ax, e2y = cy - ay;
+    const double det = e1x * e2y - e1y * e2x;
+    const double dx = px - ax, dy = py - ay;
+    const double lb = (dx * e2y - dy * e2x) / det;
+    const double lc = (e1x * dy - e1y * dx) / det;
+    const double la = 1.0 - lb - lc;
+    lmin = fmin(fmin(la, lb), lc);
+    val = la * af + lb * bf + lc * cf;
+}
+
+// One thread per new node.  The search starts with the 4 x 4 old cells
+// around the node's own grid position (a mesh step moves a node by about a
+// cell at most) and doubles the window until a triangle contains the point
+// (smallest coordinate >= -1e-10: a point on a shared edge or a rounding
+// error outside the mesh) or the window covers the whole mesh (with its
+// periodic images), so every thread ends.
+__global__ void transfer_p1_kernel(TransferArgs a)
+{
+    const int idx = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (idx >= a.n_xi * a.n_eta) return;
+    int i = idx % a.n_xi, j = idx / a.n_xi;
+    if (a.per_xi && i == a.n_xi - 1) i = 0;     // image node: node 0's value
+    if (a.per_eta && j == a.n_eta - 1) j = 0;
+    const double px = a.x_new[(size_t)j * a.n_xi + i], py = a.y_new[(size_t)j * a.n_xi + i];
+    const int cxm = a.n_xi - 2, cym = a.n_eta - 2;   // last cell index per axis
+    double best = -INFINITY, bval = 0.0;
+    for (int w = 2;; w *= 2) {
+        int i0 = i - w, i1 = i + w - 1, j0 = j - w, j1 = j + w - 1;
+        if (!a.per_xi) {
+            i0 = max(i0, 0);
+            i1 = min(i1, cxm);
+        }
+        if (!a.per_eta) {
+            j0 = max(j0, 0);
+            j1 = min(j1, cym);
+        }
+        for (int cj = j0; cj <= j1; ++cj) {
+            for (int ci = i0; ci <= i1; ++ci) {
+                double ax, ay, af, bx, by, bf, cx, cy, cf, dx, dy, df;
+                old_node(a, ci, cj, ax, ay, af);
+                old_node(a, ci + 1, cj, bx, by, bf);
+                old_node(a, ci + 1, cj + 1, cx, cy, cf);
+                old_node(a, ci, cj + 1, dx, dy, df);
+                double l, v;
+                tri_test(px, py, ax, ay, af, bx, by, bf, cx, cy, cf, l, v);
+                if (l > best) {
+                    best = l;
+                    bval = v;
+                }
+                tri_test(px, py, ax, ay, af, cx, cy, cf, dx, dy, df, l, v);
+                if (l > best) {
+                    best = l;
+                    bval = v;
+                }
+            }
+        }
+        if (best >= -1e-10) break;
+        const bool all_xi = a.per_xi ? w >= 2 * (a.n_xi - 1) : (i0 == 0 && i1 == cxm);
+        const bool all_eta = a.per_eta ? w >= 2 * (a.n_eta - 1) : (j0 == 0 && j1 == cym);
+        if (all_xi && all_eta) break;
+    }
+    a.f_new[idx] = bval;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -540,6 +635,13 @@ hipError_t launch_arclength(const double *u, const double *x, const double *y, i
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(arclength_rho_kernel, dim3(blocks_of(n, 256)), dim3(256), 0, s, g_scratch, (int)n, alpha,
                        normalize, gmax_bits, rho);
+    return hipGetLastError();
+}
+
+hipError_t launch_transfer_p1(const TransferArgs &a, hipStream_t s)
+{
+    const size_t n = (size_t)a.n_xi * a.n_eta;
+    hipLaunchKernelGGL(transfer_p1_kernel, dim3(blocks_of(n, 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -1,7 +1,8 @@
 // Device-side interface of the mesh-step kernels (mesh_step.hip): the 1-D
 // edge generator, the Dirichlet targets of the decomposed problem, the
-// subdomain solves (LDS-resident or global sweeps), the arc-length monitor
-// and the mesh-quality ratio.  All FP64.
+// subdomain solves (LDS-resident or global sweeps), the arc-length monitor,
+// the mesh-quality ratio and the piecewise-linear monitor transfer of the
+// MᵏP variant.  All FP64.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -43,6 +44,23 @@ hipError_t launch_fe_sweep(const MeshStepArgs &a, const double *cx, const double
 hipError_t launch_arclength(const double *u, const double *x, const double *y, int n_xi, int n_eta, int per_xi,
                             int per_eta, double Lx, double Ly, double alpha, int normalize, double *g_scratch,
                             unsigned long long *gmax_bits, unsigned int *bad, double *rho, hipStream_t s);
+// MᵏP monitor update (section 5): f at the nodes of a new mesh from the
+// piecewise-linear interpolant of nodal values on an old mesh of the same
+// grid.  Each old cell (i, j)-(i+1, j+1) is split along its diagonal from
+// node (i, j) to node (i+1, j+1); a point takes the linear interpolant of
+// the triangle that contains it (outside the old mesh: of the triangle
+// whose smallest barycentric coordinate is largest).  Periodic axes extend
+// the old mesh by its images (+Lx along xi, +Ly along eta); image nodes of
+// the new mesh take node 0's value.
+struct TransferArgs {
+    int n_xi, n_eta, per_xi, per_eta;
+    double Lx, Ly;
+    const double *x_old, *y_old, *f_old;   // [n_eta][n_xi]
+    const double *x_new, *y_new;
+    double *f_new;
+};
+hipError_t launch_transfer_p1(const TransferArgs &a, hipStream_t s);
+
 int quality_parts(int n_xi, int n_eta);
 hipError_t launch_quality(const double *xs, const double *ys, const double *xd, const double *yd, int n_xi,
                           int n_eta, double *r_cells, double *part_max, double *part_sum, double *out2,

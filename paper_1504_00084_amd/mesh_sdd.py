@@ -32,7 +32,7 @@ EXPORTS = (
     "mesh_sdd_debug_paths", "mesh_sdd_last_error", "mesh_sdd_version", "mesh_sdd_desc_check",
     "mesh_sdd_desc_interface_nodes", "mesh_sdd_edge_generate", "mesh_sdd_subdomain_solve",
     "mesh_sdd_single_domain_solve", "mesh_sdd_mp_step", "mesh_sdd_set_monitor_arclength", "mesh_sdd_get_monitor",
-    "mesh_sdd_mesh_quality",
+    "mesh_sdd_mesh_quality", "mesh_sdd_transfer_field",
 )
 
 
@@ -136,6 +136,7 @@ def load(path: str = LIB_PATH):
         "mesh_sdd_mp_step": [vp, P(Step), P(MpOpts), vp, vp, vp, P(Result)],
         "mesh_sdd_set_monitor_arclength": [vp, vp, vp, vp, ctypes.c_double, ctypes.c_int, ctypes.c_int],
         "mesh_sdd_get_monitor": [vp, vp, ctypes.c_int],
+        "mesh_sdd_transfer_field": [vp, vp, vp, vp, vp, vp, vp, ctypes.c_int],
         "mesh_sdd_mesh_quality": [vp, vp, vp, vp, vp, vp, P(ctypes.c_double), P(ctypes.c_double), ctypes.c_int],
     }
     for name, args in sig.items():
@@ -437,6 +438,13 @@ def mesh_sdd_set_monitor_arclength(inst, u, x, y, alpha: float, normalize: bool 
 def mesh_sdd_get_monitor(inst, rho_out) -> None:
     p, dev = _ptr(rho_out)
     _check(load().mesh_sdd_get_monitor(inst, p, int(dev)))
+
+
+def mesh_sdd_transfer_field(inst, x_old, y_old, f_old, x_new, y_new, f_new) -> None:
+    """f_new at the nodes of (x_new, y_new) from the piecewise-linear
+    interpolant of f_old on the mesh (x_old, y_old)."""
+    ptrs, dev = _same_kind(x_old, y_old, f_old, x_new, y_new, f_new)
+    _check(load().mesh_sdd_transfer_field(inst, *ptrs, dev))
 
 
 def mesh_sdd_mesh_quality(inst, x_sd, y_sd, x_dd, y_dd, r_cells=None):
