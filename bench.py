@@ -72,7 +72,7 @@ def parse():
                          "one the recorded HBM traffic was measured with)")
     ap.add_argument("--launch", default="", help="fixed launch shape BLOCK,WAVES_PER_SIMD,CHUNK")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU work of the oracle sample")
-    ap.add_argument("--mode", default="step", choices=["step", "batch", "serve", "mp", "quality"],
+    ap.add_argument("--mode", default="step", choices=["step", "batch", "serve", "mp", "quality", "variants"],
                     help="step: the metric line (rotating bump 129^2); batch: the 64-instance mix in one "
                          "persistent launch; serve: Poisson request stream through submit/poll; mp: the "
                          "rotating-bump moving-mesh loop; quality: five-ring mesh quality R against the "
@@ -84,6 +84,9 @@ def parse():
                     help="interface sampling strides of the quality mode (skipped where a stride does not divide "
                          "the subdomain size)")
     ap.add_argument("--mp-stride", default="1,2,4", help="interface sampling strides of the mp mode")
+    ap.add_argument("--variants", default="1x1,2x1,4x1,1x2,1x3",
+                    help="kxl schedules of the variants mode: k MᵏP sub-steps, l (MP)ˡ passes")
+    ap.add_argument("--variant-steps", type=int, default=20, help="mesh steps of the variants mode")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--batch-scale", type=float, default=1.0, help="scale the mix's path counts (batch mode)")
     ap.add_argument("--requests", type=int, default=40, help="requests in serve mode")
@@ -112,6 +115,8 @@ def main():
         return run_mp(args)
     if args.mode == "quality":
         return run_quality(args)
+    if args.mode == "variants":
+        return run_variants(args)
     import numpy as np
     import torch
 
@@ -469,6 +474,71 @@ def run_mp(args):
             "config": {"workload": loop.name, "grid": [129, 129], "subdomains": [4, 4], "paths_per_node": loop.n_paths,
                        "K": loop.K, "tau": loop.tau, "alpha": "10 / max |grad u|^2"}}
     print(json.dumps(line), flush=True)
+
+
+def equidistribution_cv(M, ctx, loop, x, y, t):
+    """Spread of rho * cell area over the cells (coefficient of variation):
+    0 for a mesh that equidistributes the monitor of u(., t) exactly.  The
+    monitor comes from the library on the given mesh; the cell sums are a
+    benchmark-side diagnostic."""
+    import numpy as np
+    h = M.mesh_sdd_create(ctx, M.make_desc(loop.n_xi, loop.n_eta, 1, 1, loop.periodic_xi, loop.periodic_eta,
+                                           K=loop.K, Lx=loop.Lx, Ly=loop.Ly, tau=loop.tau, precision=M.FP64))
+    try:
+        u = np.ascontiguousarray(loop.u(x, y, t))
+        M.mesh_sdd_set_monitor_arclength(h, u, x, y, loop.alpha, loop.normalize)
+        rho = np.empty_like(x)
+        M.mesh_sdd_get_monitor(h, rho)
+    finally:
+        M.mesh_sdd_destroy(h)
+    rc = 0.25 * (rho[:-1, :-1] + rho[:-1, 1:] + rho[1:, :-1] + rho[1:, 1:])
+    area = 0.5 * np.abs((x[1:, 1:] - x[:-1, :-1]) * (y[1:, :-1] - y[:-1, 1:])
+                        - (x[1:, :-1] - x[:-1, 1:]) * (y[1:, 1:] - y[:-1, :-1]))
+    m = rc * area
+    return float(np.std(m) / np.mean(m))
+
+
+def run_variants(args):
+    """The MᵏP and (MP)ˡ schedules (section 5) on the rotating-bump loop
+    (129x129, 4x4, N = 1e5, K = 500, tau = 0.01): per schedule, the time per
+    mesh step of the decomposed loop, R against the single-domain loop of
+    the same schedule, and how evenly the final meshes distribute the
+    monitor (coefficient of variation of rho * cell area)."""
+    import torch
+
+    from paper_1504_00084_amd import mesh_sdd as M
+    from paper_1504_00084_amd import mp_loop
+    from paper_1504_00084_amd import workloads as W
+
+    M.load()
+    loop = W.rotating_bump_loop(n_paths=args.paths, steps=args.variant_steps)
+    ctx = M.mesh_sdd_ctx_create(0)
+    rows = []
+    t_end = loop.steps * loop.tau
+    for v in args.variants.split(","):
+        k, l = (int(a) for a in v.split("x"))
+        sd = mp_loop.run(ctx, loop, M.FP32, decomposed=False, k_sub=k, l_iter=l)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sdd = mp_loop.run(ctx, loop, M.FP32, decomposed=True, k_sub=k, l_iter=l, log=log)
+        wall = time.perf_counter() - t0
+        rmax, rmean, r = mp_loop.quality(ctx, loop, sd, sdd)
+        row = {"k_sub": k, "l_iter": l, "ms_per_mesh_step": 1e3 * wall / loop.steps,
+               "path_steps_per_s": sdd["executed_path_steps"] / wall, "R_max": rmax, "R_mean": rmean,
+               "R_min": float(r.min()), "equidistribution_cv_sdd": equidistribution_cv(M, ctx, loop, sdd["x"],
+                                                                                        sdd["y"], t_end),
+               "equidistribution_cv_sd": equidistribution_cv(M, ctx, loop, sd["x"], sd["y"], t_end)}
+        rows.append(row)
+        log("variant k=%d l=%d: %.1f ms per mesh step, R_max %.4f R_mean %.4f, equidistribution CV %.4f (SD %.4f)"
+            % (k, l, row["ms_per_mesh_step"], rmax, rmean, row["equidistribution_cv_sdd"],
+               row["equidistribution_cv_sd"]))
+    M.mesh_sdd_ctx_destroy(ctx)
+    print(json.dumps({"metric": "MᵏP / (MP)ˡ schedules on the rotating-bump loop: time per mesh step, R = Q_SD / "
+                                "Q_SDD, equidistribution spread at the final time",
+                      "results": rows, "steps": loop.steps, "dtype": "f32 (paths) / f64 (mesh)",
+                      "data": "synthetic", "config": {"workload": loop.name, "grid": [129, 129], "subdomains": [4, 4],
+                                                      "paths_per_node": loop.n_paths, "K": loop.K, "tau": loop.tau}}),
+          flush=True)
 
 
 def run_quality(args):
