@@ -210,14 +210,13 @@ def main():
         M.mesh_sdd_destroy(h64)
 
     kern_s = sum(kernel_ms) / len(kernel_ms) / 1e3
-    # a single-instance launch stages the FP32 rho node table in LDS when it
-    # fits next to the 16 waves' item buffers (the library's rule)
-    lds_rho = lo.monitor_table == 0 and inst.n_xi * inst.n_eta * 4 + 16 * 4 * lo.chunk_paths * 4 <= 160 * 1024
+    # node tables the library stages in LDS for this single-instance launch
+    tables = {0: None, 1: "rho", 2: "rho + dt rho_xi"}[lo.table_level]
     per_launch = executed / args.steps
     achieved = W_SLOTS_PER_STEP * per_launch / kern_s / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 3), "unit": "TOP/s",
                 "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": recorded_traffic(),
-                "kernel": "paths_fp32 (LDS-rho variant, 1024 threads x 1 workgroup per CU)" if lds_rho
+                "kernel": ("paths_fp32 (LDS table: %s; 1024 threads x 1 workgroup per CU)" % tables) if tables
                 else "paths_fp32", "kernel_ms": round(kern_s * 1e3, 3),
                 "path_steps_per_launch": per_launch, "slots_per_path_step": W_SLOTS_PER_STEP}
 
@@ -261,8 +260,9 @@ def main():
         "config": {"workload": inst.name, "grid": [inst.n_xi, inst.n_eta], "subdomains": [inst.sub_xi, inst.sub_eta],
                    "interface_nodes": m, "paths_per_node": inst.n_paths, "K": inst.K, "tau": inst.tau,
                    "nominal_path_steps": nominal, "executed_path_steps_per_step": per_launch,
-                   "max_se": se_max, "launch": {"block": 1024 if lds_rho else lo.block, "waves_per_simd": 4 if lds_rho else lo.waves_per_simd,
-                                         "chunk_paths": lo.chunk_paths, "rho_table": "LDS" if lds_rho else "L2"}},
+                   "max_se": se_max, "launch": {"block": 1024 if tables else lo.block,
+                                                "waves_per_simd": 4 if tables else lo.waves_per_simd,
+                                                "chunk_paths": lo.chunk_paths, "lds_tables": tables or "none (L2)"}},
         "fp64_plain": fp64,
         "roofline": roofline,
         "cpu_baseline": cpu,

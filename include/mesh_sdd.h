@@ -164,10 +164,17 @@ typedef struct {
     int32_t waves_per_simd;          /* persistent residency target (1..8)           */
     int32_t chunk_paths;             /* paths per work item (multiple of 64)         */
     int32_t monitor_table;           /* 0: automatic -- a launch that holds one
-                                        instance whose rho node table fits in LDS
-                                        reads rho there (one 768-thread workgroup per
-                                        CU; identical results); 1: always from the
-                                        cell records in L2                             */
+                                        instance stages its FP32 node tables in LDS,
+                                        rho and dt rho_xi when both fit (8 B per
+                                        node), else rho (4 B per node), and reads
+                                        them there (1024-thread workgroups, item end
+                                        states in a context buffer; identical
+                                        results); 1: always from the cell records
+                                        in L2                                        */
+    int32_t table_level;             /* out (mesh_sdd_get_launch): node tables a
+                                        launch holding this instance alone stages in
+                                        LDS: 0 none, 1 rho, 2 rho and dt rho_xi.
+                                        Ignored by mesh_sdd_set_launch.              */
 } mesh_sdd_launch;
 
 /* ---- context ------------------------------------------------------------ */

@@ -147,9 +147,20 @@ __device__ __forceinline__ float side_distance(const ConstF &C, float x, float y
 
 // One EM substep of the FP32 path (a3-a6).  Returns the exit side (0: xi=0,
 // 1: xi=1, 2: eta=0, 3: eta=1) with the position moved onto it, or -1.
-template <bool LDS_RHO>
+// Bilinear interpolant from the four corner values of a cell.
+__device__ __forceinline__ float bilerp(float tx, float ty, float f00, float f10, float f01, float f11)
+{
+    const float v0 = fmaf(tx, f10 - f00, f00), v1 = fmaf(tx, f11 - f01, f01);
+    return fmaf(ty, v1 - v0, v0);
+}
+
+// TAB: where the corner values of rho and dt rho_xi come from.  0: the cell
+// record; 1: rho from the LDS node table, dt rho_xi from the record; 2: both
+// from the LDS node table (rho, dt rho_xi interleaved).  The values are the
+// same in every case, so the results are identical.
+template <int TAB>
 __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t wa, uint32_t wb, uint32_t wc,
-                                           float *trace4, const float *rho_tab)
+                                           float *trace4, const float *tab)
 {
     // a3: Box-Muller on two stream words with the hardware log2 / sqrt /
     // sin / cos (sin and cos take revolutions); sqrt(2 dt) is folded into
@@ -168,24 +179,26 @@ __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t w
     tx = P.x * C.fnx1 - (float)cx;
     ty = P.y * C.fny1 - (float)cy;
     const GLOBAL f32x4 *cell = C.cells + (uint32_t)(3 * (cy * C.nx1 + cx));
-    float r00, r10, r01, r11;
-    if (LDS_RHO) {   // corner values from the LDS copy of the node table
-        const int base = cy * C.n_xi + cx;
-        r00 = rho_tab[base];
-        r10 = rho_tab[base + 1];
-        r01 = rho_tab[base + C.n_xi];
-        r11 = rho_tab[base + C.n_xi + 1];
-    } else {         // the same values from the cell record
-        const f32x4 A = cell[0];
-        r00 = A.x;
-        r10 = A.y;
-        r01 = A.z;
-        r11 = A.w;
+    float r00, r10, r01, r11, g00, g10, g01, g11;
+    if (TAB == 2) {
+        const float2 *t2 = (const float2 *)tab + (cy * C.n_xi + cx);
+        const float2 c00 = t2[0], c10 = t2[1], c01 = t2[C.n_xi], c11 = t2[C.n_xi + 1];
+        r00 = c00.x, r10 = c10.x, r01 = c01.x, r11 = c11.x;
+        g00 = c00.y, g10 = c10.y, g01 = c01.y, g11 = c11.y;
+    } else {
+        if (TAB == 1) {
+            const float *t1 = tab + (cy * C.n_xi + cx);
+            r00 = t1[0], r10 = t1[1], r01 = t1[C.n_xi], r11 = t1[C.n_xi + 1];
+        } else {
+            const f32x4 A = cell[0];
+            r00 = A.x, r10 = A.y, r01 = A.z, r11 = A.w;
+        }
+        const f32x4 B = cell[1];
+        g00 = B.x, g10 = B.y, g01 = B.z, g11 = B.w;
     }
-    const f32x4 B = cell[1], G = cell[2];
-    const float v0 = fmaf(tx, r10 - r00, r00), v1 = fmaf(tx, r11 - r01, r01);
-    const float rho = fmaf(ty, v1 - v0, v0);
-    const float gx = fmaf(ty, fmaf(B.w, tx, B.z), fmaf(B.y, tx, B.x));
+    const f32x4 G = cell[2];
+    const float rho = bilerp(tx, ty, r00, r10, r01, r11);
+    const float gx = bilerp(tx, ty, g00, g10, g01, g11);
     const float gy = fmaf(ty, fmaf(G.w, tx, G.z), fmaf(G.y, tx, G.x));
     const float inv_rho = __builtin_amdgcn_rcpf(rho);
 
@@ -341,10 +354,10 @@ __device__ __forceinline__ void path_value_f32(const InstView &I, const ConstF &
 // Up to four substeps of one path: the three Philox blocks of the group are
 // drawn at once (words 3s..3s+2 of substep s of the group).  Returns the exit
 // side or -1; `ended` is set when the path exited or reached K.
-template <bool TRACE, bool LDS_RHO>
+template <bool TRACE, int TAB>
 __device__ __forceinline__ int group_f32(PathF &P, const ConstF &C, uint32_t path, uint32_t node, uint32_t ctr3,
                                          uint32_t key0, uint32_t key1, bool &ended, double *trace,
-                                         const float *rho_tab)
+                                         const float *tab)
 {
     const uint32_t blk = 3u * ((uint32_t)P.k >> 2);
     const Words4 A = philox4x32_10(blk, path, node, ctr3, key0, key1);
@@ -357,7 +370,7 @@ __device__ __forceinline__ int group_f32(PathF &P, const ConstF &C, uint32_t pat
     for (int s = 0; s < 4; ++s) {
         if (!ended && P.k < C.K) {
             float t4[4];
-            side = substep_f32<LDS_RHO>(P, C, w[3 * s], w[3 * s + 1], w[3 * s + 2], TRACE ? t4 : nullptr, rho_tab);
+            side = substep_f32<TAB>(P, C, w[3 * s], w[3 * s + 1], w[3 * s + 2], TRACE ? t4 : nullptr, tab);
             if (TRACE) {
                 double *t = trace + 4 * (size_t)P.k;
                 t[0] = t4[0];
@@ -426,15 +439,81 @@ __device__ __forceinline__ ItemF decode_item(const GLOBAL WorkRange *rg, uint32_
     return f;
 }
 
-// Fixed-order reduction of one item's per-path values held in LDS (dx at
-// buf[0..count), dy at buf[cap..cap+count)), plus the lanes' exit and step
-// counts of that item; every lane stores the identical totals.
-__device__ __forceinline__ void flush_item(const float *buf, uint32_t cap, uint32_t count, int lane, uint32_t exits,
-                                           unsigned long long steps, GLOBAL Partial *out)
+// End state of a path, kept in three words of its item's LDS slot until
+// the item drains (the value of a path is evaluated then, by all lanes at
+// once, instead of by the whole wave whenever one lane's path ends):
+//   w2 = wx & 0x3fff | (wy & 0x3fff) << 14 | (side + 1) << 28  (side -1: survived)
+//   survived: w0, w1 = x, y;  exited: w0 = k (substeps done), w1 = the
+//   coordinate along the side (the other one is fixed by the side).
+// A path whose winding does not fit 14 bits stores its values instead:
+// w2 = 0x80000000, w0, w1 = vx, vy.
+constexpr uint32_t kValueStored = 0x80000000u;
+
+__device__ __forceinline__ void store_end(float *b, uint32_t cap, uint32_t slot, const InstView &I, const ConstF &C,
+                                          const PathF &P, int side)
+{
+    uint32_t w0, w1, w2;
+    if (P.wx >= -8192 && P.wx < 8192 && P.wy >= -8192 && P.wy < 8192) {
+        w2 = ((uint32_t)P.wx & 0x3FFFu) | (((uint32_t)P.wy & 0x3FFFu) << 14) | ((uint32_t)(side + 1) << 28);
+        if (side >= 0) {
+            w0 = (uint32_t)P.k;
+            w1 = __float_as_uint(side < 2 ? P.y : P.x);
+        } else {
+            w0 = __float_as_uint(P.x);
+            w1 = __float_as_uint(P.y);
+        }
+    } else {
+        float vx, vy;
+        path_value_f32(I, C, P, side, vx, vy);
+        w0 = __float_as_uint(vx);
+        w1 = __float_as_uint(vy);
+        w2 = kValueStored;
+    }
+    b[slot] = __uint_as_float(w0);
+    b[cap + slot] = __uint_as_float(w1);
+    b[2u * cap + slot] = __uint_as_float(w2);
+}
+
+__device__ __forceinline__ void stored_value(const float *b, uint32_t cap, uint32_t j, const InstView &I,
+                                             const ConstF &C, float &vx, float &vy)
+{
+    const uint32_t w0 = __float_as_uint(b[j]), w1 = __float_as_uint(b[cap + j]);
+    const uint32_t w2 = __float_as_uint(b[2u * cap + j]);
+    if (w2 & kValueStored) {
+        vx = __uint_as_float(w0);
+        vy = __uint_as_float(w1);
+        return;
+    }
+    const int side = (int)(w2 >> 28) - 1;
+    PathF P;
+    P.wx = (int)(w2 << 18) >> 18;   // sign-extend the 14-bit fields
+    P.wy = (int)(w2 << 4) >> 18;
+    P.m = 0.0f;
+    if (side < 0) {
+        P.x = __uint_as_float(w0);
+        P.y = __uint_as_float(w1);
+        P.k = C.K;
+    } else {
+        P.k = (int)w0;
+        P.x = side < 2 ? 0.0f : __uint_as_float(w1);
+        P.y = side < 2 ? __uint_as_float(w1) : 0.0f;
+    }
+    path_value_f32(I, C, P, side, vx, vy);
+}
+
+// Values and fixed-order reduction of one drained item: lane l evaluates
+// the paths l, l + 64, ... from their end states, v - v_ref is rounded to
+// FP32 and summed in FP64, then the lanes' sums and the exit and step counts
+// are combined by butterflies; every lane stores the identical totals.
+__device__ __forceinline__ void finish_item(const float *buf, uint32_t cap, uint32_t count, int lane, uint32_t exits,
+                                            unsigned long long steps, const InstView &I, const ConstF &C, double rx,
+                                            double ry, GLOBAL Partial *out)
 {
     double s1x = 0.0, s2x = 0.0, s1y = 0.0, s2y = 0.0;
     for (uint32_t j = (uint32_t)lane; j < count; j += 64u) {
-        const double dx = (double)buf[j], dy = (double)buf[cap + j];
+        float vx, vy;
+        stored_value(buf, cap, j, I, C, vx, vy);
+        const double dx = (double)(float)((double)vx - rx), dy = (double)(float)((double)vy - ry);
         s1x += dx;
         s2x = fma(dx, dx, s2x);
         s1y += dy;
@@ -457,32 +536,47 @@ __device__ __forceinline__ void flush_item(const float *buf, uint32_t cap, uint3
 // Persistent batched kernel.  Each wave keeps up to two work items in
 // flight: the one whose paths it is handing out and the one whose last
 // paths are finishing, so lanes never wait for an item to drain.  A lane
-// whose path ended takes the next path at a four-substep boundary; its
-// value (v - v_ref) goes to the item's LDS slot at the path's index, and a
-// drained item is reduced in a fixed order, so the sums do not depend on
-// which lane ran which path.  Items of another instance start once both
-// slots are drained (the per-instance constants are wave-uniform).
+// whose path ended takes the next path at a four-substep boundary; its end
+// state goes to the item's LDS slot at the path's index, and a drained item
+// is evaluated (bicubic or boundary value) and reduced by all lanes in a
+// fixed order, so the sums do not depend on which lane ran which path, and
+// the wave does not run the value code whenever one lane's path ends.
+// Items of another instance start once both slots are drained (the
+// per-instance constants are wave-uniform).
 //
-// LDS_RHO: the launch holds one instance (the host guarantees it), whose
-// FP32 rho node table the workgroup copies into LDS behind the wave
-// buffers; the bilinear rho then reads its four corners there instead of
-// from the cell record (the same values, so the results are identical).
-// That takes one of the three L1 gathers of a substep off the texture
-// path, which bounds this kernel.
-template <int BLOCK, bool LDS_RHO>
+// TAB > 0: the launch holds one instance (the host guarantees it), whose
+// FP32 node table -- rho (TAB 1) or rho and dt rho_xi interleaved (TAB 2) --
+// the workgroup copies into LDS; the bilinear interpolation then reads those
+// corner values there instead of from the cell record (the same values, so
+// the results are identical).  Each moved field takes one of the three L1
+// gathers of a substep off the texture path, which bounds this kernel
+// together with VALU issue.  The table fills the LDS, so the waves keep the
+// end states of their items in `ends` (global memory, 6 * cap words per
+// wave, room for `end_waves` waves; read back by the same wave only).
+template <int BLOCK, int TAB>
 __global__ __launch_bounds__(BLOCK) void paths_fp32(const InstView *__restrict__ insts,
                                                     const WorkRange *__restrict__ ranges, uint32_t n_ranges,
-                                                    uint32_t n_items, uint32_t *__restrict__ head, uint32_t cap)
+                                                    uint32_t n_items, uint32_t *__restrict__ head, uint32_t cap,
+                                                    float *__restrict__ ends, uint32_t end_waves)
 {
     extern __shared__ float lds[];
     const int lane = threadIdx.x & 63;
-    float *buf = lds + (size_t)(threadIdx.x >> 6) * 4u * cap;   // [slot][dx | dy][cap]
-    float *rho_tab = nullptr;
-    if (LDS_RHO) {
-        rho_tab = lds + (size_t)(BLOCK / 64) * 4u * cap;
+    const uint32_t wave = blockIdx.x * (uint32_t)(BLOCK / 64) + (threadIdx.x >> 6);
+    if (TAB > 0 && (blockIdx.x + 1u) * (uint32_t)(BLOCK / 64) > end_waves) return;   // whole block: no room
+    float *buf = TAB > 0 ? ends + (size_t)wave * 6u * cap
+                         : lds + (size_t)(threadIdx.x >> 6) * 6u * cap;   // [slot][w0 | w1 | w2][cap]
+    float *tab = nullptr;
+    if (TAB > 0) {
+        tab = lds;
         const int n = insts[0].n_xi * insts[0].n_eta;
         const GLOBAL float *src = gptr(insts[0].rho_f);
-        for (int q = threadIdx.x; q < n; q += BLOCK) rho_tab[q] = src[q];
+        if (TAB == 2) {
+            const GLOBAL float *srx = gptr(insts[0].rhox_f);
+            float2 *t2 = (float2 *)tab;
+            for (int q = threadIdx.x; q < n; q += BLOCK) t2[q] = make_float2(src[q], srx[q]);
+        } else {
+            for (int q = threadIdx.x; q < n; q += BLOCK) tab[q] = src[q];
+        }
         __syncthreads();
     }
     const GLOBAL WorkRange *rg = gptr(ranges);
@@ -577,14 +671,9 @@ __global__ __launch_bounds__(BLOCK) void paths_fp32(const InstView *__restrict__
         // advance every path by one group of four substeps
         bool ended = false;
         if (has) {
-            const int side = group_f32<false, LDS_RHO>(P, C, path, node, ctr3, key0, key1, ended, nullptr, rho_tab);
+            const int side = group_f32<false, TAB>(P, C, path, node, ctr3, key0, key1, ended, nullptr, tab);
             if (ended) {
-                float vx, vy;
-                path_value_f32(*Ip, C, P, side, vx, vy);
-                const double rx = which ? rx1 : rx0, ry = which ? ry1 : ry0;
-                float *b = buf + (size_t)which * 2u * cap;
-                b[slot] = (float)((double)vx - rx);
-                b[cap + slot] = (float)((double)vy - ry);
+                store_end(buf + (size_t)which * 3u * cap, cap, slot, *Ip, C, P, side);
                 const uint32_t e = side >= 0 ? 1u : 0u;
                 if (which) {
                     ex1 += e;
@@ -602,13 +691,13 @@ __global__ __launch_bounds__(BLOCK) void paths_fp32(const InstView *__restrict__
         rem1 -= (uint32_t)__popcll(end_mask & in1);
         // reduce and write the items whose paths have all ended
         if (act0 && rem0 == 0u && !(issuing && cur == 0u)) {
-            flush_item(buf, cap, cnt0, lane, ex0, st0, gptr_rw(Ip->partials) + part0);
+            finish_item(buf, cap, cnt0, lane, ex0, st0, *Ip, C, rx0, ry0, gptr_rw(Ip->partials) + part0);
             ex0 = 0;
             st0 = 0;
             act0 = 0u;
         }
         if (act1 && rem1 == 0u && !(issuing && cur == 1u)) {
-            flush_item(buf + 2u * cap, cap, cnt1, lane, ex1, st1, gptr_rw(Ip->partials) + part1);
+            finish_item(buf + 3u * cap, cap, cnt1, lane, ex1, st1, *Ip, C, rx1, ry1, gptr_rw(Ip->partials) + part1);
             ex1 = 0;
             st1 = 0;
             act1 = 0u;
@@ -926,12 +1015,14 @@ __global__ void prep_cells_kernel(const double *__restrict__ rho, const double *
     const int cx = idx % nx1, cy = idx / nx1;
     const size_t a = (size_t)cy * n_xi + cx, b = a + n_xi;
     const double *f[3] = {rho, rx, ry};
-    // rho: the four corner values, exactly the FP32 node table's
+    // rho and dt rho_xi: the four corner values, exactly the FP32 node tables'
     cells[3 * (size_t)idx] = make_float4((float)rho[a], (float)rho[a + 1], (float)rho[b], (float)rho[b + 1]);
-    for (int c = 1; c < 3; ++c) {   // gradient fields carry the factor dt, coefficient form
-        const double f00 = grad_scale * f[c][a], f10 = grad_scale * f[c][a + 1];
-        const double f01 = grad_scale * f[c][b], f11 = grad_scale * f[c][b + 1];
-        cells[3 * (size_t)idx + c] = make_float4((float)f00, (float)(f10 - f00), (float)(f01 - f00),
+    cells[3 * (size_t)idx + 1] = make_float4((float)(grad_scale * rx[a]), (float)(grad_scale * rx[a + 1]),
+                                             (float)(grad_scale * rx[b]), (float)(grad_scale * rx[b + 1]));
+    {   // dt rho_eta in coefficient form a + b tx + c ty + d tx ty
+        const double f00 = grad_scale * f[2][a], f10 = grad_scale * f[2][a + 1];
+        const double f01 = grad_scale * f[2][b], f11 = grad_scale * f[2][b + 1];
+        cells[3 * (size_t)idx + 2] = make_float4((float)f00, (float)(f10 - f00), (float)(f01 - f00),
                                                  (float)(f11 - f10 - f01 + f00));
     }
 }
@@ -998,6 +1089,12 @@ __global__ void to_f32_kernel(const double *__restrict__ in, float *out, size_t 
 {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) out[i] = (float)in[i];
+}
+
+__global__ void scaled_to_f32_kernel(const double *__restrict__ in, double scale, float *out, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (float)(scale * in[i]);
 }
 
 __global__ void fill_u32_kernel(uint32_t *p, uint32_t v, size_t n)
@@ -1144,9 +1241,8 @@ __global__ void debug_paths_kernel(const InstView *__restrict__ inst, int fp64, 
     int side = -1;
     bool ended = false;
     while (!ended) {
-        side = tr ? group_f32<true, false>(P, C, path, I.node_r[node], I.ctr3, I.key0, I.key1, ended, tr, nullptr)
-                  : group_f32<false, false>(P, C, path, I.node_r[node], I.ctr3, I.key0, I.key1, ended, nullptr,
-                                            nullptr);
+        side = tr ? group_f32<true, 0>(P, C, path, I.node_r[node], I.ctr3, I.key0, I.key1, ended, tr, nullptr)
+                  : group_f32<false, 0>(P, C, path, I.node_r[node], I.ctr3, I.key0, I.key1, ended, nullptr, nullptr);
     }
     float fx, fy;
     path_value_f32(I, C, P, side, fx, fy);
@@ -1196,6 +1292,13 @@ hipError_t launch_to_f32(const double *in, float *out, size_t n, hipStream_t s)
     return hipGetLastError();
 }
 
+hipError_t launch_scaled_to_f32(const double *in, double scale, float *out, size_t n, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(scaled_to_f32_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, in, scale, out, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
@@ -1212,20 +1315,20 @@ hipError_t launch_paths_fp32(const InstView *insts, const WorkRange *ranges, uin
     const size_t lds = paths_fp32_lds_bytes(block, cap);
     switch (block) {
     case 64:
-        hipLaunchKernelGGL((paths_fp32<64, false>), dim3(grid), dim3(64), lds, s, insts, ranges, n_ranges, n_items,
-                           head, cap);
+        hipLaunchKernelGGL((paths_fp32<64, 0>), dim3(grid), dim3(64), lds, s, insts, ranges, n_ranges, n_items, head,
+                           cap, nullptr, 0u);
         break;
     case 128:
-        hipLaunchKernelGGL((paths_fp32<128, false>), dim3(grid), dim3(128), lds, s, insts, ranges, n_ranges, n_items,
-                           head, cap);
+        hipLaunchKernelGGL((paths_fp32<128, 0>), dim3(grid), dim3(128), lds, s, insts, ranges, n_ranges, n_items,
+                           head, cap, nullptr, 0u);
         break;
     case 256:
-        hipLaunchKernelGGL((paths_fp32<256, false>), dim3(grid), dim3(256), lds, s, insts, ranges, n_ranges, n_items,
-                           head, cap);
+        hipLaunchKernelGGL((paths_fp32<256, 0>), dim3(grid), dim3(256), lds, s, insts, ranges, n_ranges, n_items,
+                           head, cap, nullptr, 0u);
         break;
     case 512:
-        hipLaunchKernelGGL((paths_fp32<512, false>), dim3(grid), dim3(512), lds, s, insts, ranges, n_ranges, n_items,
-                           head, cap);
+        hipLaunchKernelGGL((paths_fp32<512, 0>), dim3(grid), dim3(512), lds, s, insts, ranges, n_ranges, n_items,
+                           head, cap, nullptr, 0u);
         break;
     default:
         return hipErrorInvalidValue;
@@ -1233,32 +1336,40 @@ hipError_t launch_paths_fp32(const InstView *insts, const WorkRange *ranges, uin
     return hipGetLastError();
 }
 
-size_t paths_fp32_lds_rho_bytes(uint32_t cap, int n_nodes)
-{
-    return paths_fp32_lds_bytes(kLdsRhoBlock, cap) + (size_t)n_nodes * sizeof(float);
-}
+size_t paths_fp32_table_lds_bytes(int level, int n_nodes) { return (size_t)n_nodes * (size_t)level * sizeof(float); }
 
-hipError_t launch_paths_fp32_lds_rho(const InstView *insts, const WorkRange *ranges, uint32_t n_items,
-                                     uint32_t *head, uint32_t cap, int n_nodes, int grid, hipStream_t s)
+hipError_t launch_paths_fp32_table(const InstView *insts, const WorkRange *ranges, uint32_t n_items, uint32_t *head,
+                                   uint32_t cap, int level, int n_nodes, int grid, float *ends, uint32_t end_waves,
+                                   hipStream_t s)
 {
     hipError_t e = launch_fill_u32(head, 0u, 1, s);
     if (e != hipSuccess) return e;
     if (n_items == 0) return hipSuccess;
-    hipLaunchKernelGGL((paths_fp32<kLdsRhoBlock, true>), dim3(grid), dim3(kLdsRhoBlock),
-                       paths_fp32_lds_rho_bytes(cap, n_nodes), s, insts, ranges, 1u, n_items, head, cap);
+    if ((size_t)grid * (kTableBlock / 64) > end_waves) return hipErrorInvalidValue;
+    const size_t lds = paths_fp32_table_lds_bytes(level, n_nodes);
+    if (level == 2)
+        hipLaunchKernelGGL((paths_fp32<kTableBlock, 2>), dim3(grid), dim3(kTableBlock), lds, s, insts, ranges, 1u,
+                           n_items, head, cap, ends, end_waves);
+    else if (level == 1)
+        hipLaunchKernelGGL((paths_fp32<kTableBlock, 1>), dim3(grid), dim3(kTableBlock), lds, s, insts, ranges, 1u,
+                           n_items, head, cap, ends, end_waves);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
-int paths_fp32_lds_rho_blocks_per_cu(uint32_t cap, int n_nodes)
+int paths_fp32_table_blocks_per_cu(int level, int n_nodes)
 {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32<kLdsRhoBlock, true>, kLdsRhoBlock,
-                                                     paths_fp32_lds_rho_bytes(cap, n_nodes)) != hipSuccess)
-        return 0;
-    return n;
+    const size_t lds = paths_fp32_table_lds_bytes(level, n_nodes);
+    hipError_t e = level == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32<kTableBlock, 2>,
+                                                                             kTableBlock, lds)
+                              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32<kTableBlock, 1>,
+                                                                             kTableBlock, lds);
+    return e == hipSuccess ? n : 0;
 }
 
-size_t paths_fp32_lds_bytes(int block, uint32_t cap) { return (size_t)(block / 64) * 4u * cap * sizeof(float); }
+size_t paths_fp32_lds_bytes(int block, uint32_t cap) { return (size_t)(block / 64) * 6u * cap * sizeof(float); }
 
 hipError_t launch_paths_fp64(const InstView *inst, uint32_t M, uint32_t n_paths, uint32_t chunks_per_node,
                              Partial *partials, hipStream_t s)
@@ -1304,10 +1415,10 @@ int paths_fp32_blocks_per_cu(int block, uint32_t cap)
     hipError_t e = hipErrorInvalidValue;
     const size_t lds = paths_fp32_lds_bytes(block, cap);
     switch (block) {
-    case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32<64, false>, 64, lds); break;
-    case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32<128, false>, 128, lds); break;
-    case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32<256, false>, 256, lds); break;
-    case 512: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32<512, false>, 512, lds); break;
+    case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32<64, 0>, 64, lds); break;
+    case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32<128, 0>, 128, lds); break;
+    case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32<256, 0>, 256, lds); break;
+    case 512: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32<512, 0>, 512, lds); break;
     default: break;
     }
     return e == hipSuccess ? n : 0;
@@ -1318,10 +1429,10 @@ int paths_fp32_attributes(int block, int *vgprs, int *sgprs, int *lds_bytes)
     hipFuncAttributes a;
     hipError_t e = hipErrorInvalidValue;
     switch (block) {
-    case 64: e = hipFuncGetAttributes(&a, reinterpret_cast<const void *>(paths_fp32<64, false>)); break;
-    case 128: e = hipFuncGetAttributes(&a, reinterpret_cast<const void *>(paths_fp32<128, false>)); break;
-    case 256: e = hipFuncGetAttributes(&a, reinterpret_cast<const void *>(paths_fp32<256, false>)); break;
-    case 512: e = hipFuncGetAttributes(&a, reinterpret_cast<const void *>(paths_fp32<512, false>)); break;
+    case 64: e = hipFuncGetAttributes(&a, reinterpret_cast<const void *>(paths_fp32<64, 0>)); break;
+    case 128: e = hipFuncGetAttributes(&a, reinterpret_cast<const void *>(paths_fp32<128, 0>)); break;
+    case 256: e = hipFuncGetAttributes(&a, reinterpret_cast<const void *>(paths_fp32<256, 0>)); break;
+    case 512: e = hipFuncGetAttributes(&a, reinterpret_cast<const void *>(paths_fp32<512, 0>)); break;
     default: break;
     }
     if (e != hipSuccess) return -1;

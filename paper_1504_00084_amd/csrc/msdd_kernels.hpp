@@ -14,8 +14,8 @@ namespace msdd {
 hipError_t launch_prep_gradient(const double *rho_in, int n_xi, int n_eta, int per_xi, int per_eta,
                                 double *rho, double *rho_xi, double *rho_eta, hipStream_t s);
 
-// a0 (FP32 path): per-cell records: rho at the four corners, then s rho_xi
-// and s rho_eta in bilinear coefficient form, with s = grad_scale (the
+// a0 (FP32 path): per-cell records: rho and s rho_xi at the four corners,
+// then s rho_eta in bilinear coefficient form, with s = grad_scale (the
 // substep dt).
 hipError_t launch_prep_cells(const double *rho, const double *rho_xi, const double *rho_eta, int n_xi,
                              int n_eta, double grad_scale, float4 *cells, hipStream_t s);
@@ -28,27 +28,32 @@ hipError_t launch_prep_mesh(const double *x, const double *y, int n_xi, int n_et
                             hipStream_t s);
 
 hipError_t launch_to_f32(const double *in, float *out, size_t n, hipStream_t s);
+// out = (float)(scale * in), elementwise (the FP32 node table of dt rho_xi).
+hipError_t launch_scaled_to_f32(const double *in, double scale, float *out, size_t n, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t s);
 
 // a2-a8, FP32: persistent batched kernel over a work queue of n_items items
 // described by n_ranges ranges (sorted by base, contiguous from 0).  `head`
 // is the queue counter (zeroed by this launcher).
 // `cap` >= every range's chunk_paths: each wave holds two items' per-path
-// values in LDS (4 * cap floats per wave).
+// end states in LDS (6 * cap words per wave).
 hipError_t launch_paths_fp32(const InstView *insts, const WorkRange *ranges, uint32_t n_ranges, uint32_t n_items,
                              uint32_t *head, uint32_t cap, int grid, int block, hipStream_t s);
 size_t paths_fp32_lds_bytes(int block, uint32_t cap);
 
 // The same kernel for a launch that holds ONE instance (n_ranges = 1): each
-// 1024-thread workgroup (16 waves: 4 per SIMD, as many as one LDS copy of
-// the table can serve) copies that instance's FP32 rho node table (n_nodes
-// floats) into LDS behind the wave buffers and reads the bilinear rho
-// corners there.  Results are identical to launch_paths_fp32's.
-constexpr int kLdsRhoBlock = 1024;
-size_t paths_fp32_lds_rho_bytes(uint32_t cap, int n_nodes);
-hipError_t launch_paths_fp32_lds_rho(const InstView *insts, const WorkRange *ranges, uint32_t n_items,
-                                     uint32_t *head, uint32_t cap, int n_nodes, int grid, hipStream_t s);
-int paths_fp32_lds_rho_blocks_per_cu(uint32_t cap, int n_nodes);
+// 1024-thread workgroup (16 waves, 4 per SIMD) copies that instance's FP32
+// node table into LDS -- rho (level 1) or rho and dt rho_xi interleaved
+// (level 2; n_nodes * 4 * level bytes) -- and reads those corner values
+// there instead of from the cell records; `ends` holds the waves' item end
+// states (6 * cap floats per wave, room for `end_waves` >= grid * 16 waves).
+// Results are identical to launch_paths_fp32's.
+constexpr int kTableBlock = 1024;
+size_t paths_fp32_table_lds_bytes(int level, int n_nodes);
+hipError_t launch_paths_fp32_table(const InstView *insts, const WorkRange *ranges, uint32_t n_items, uint32_t *head,
+                                   uint32_t cap, int level, int n_nodes, int grid, float *ends, uint32_t end_waves,
+                                   hipStream_t s);
+int paths_fp32_table_blocks_per_cu(int level, int n_nodes);
 
 // a2-a8, FP64 plain: one thread per path, one launch per instance; the
 // partial of (node, chunk) goes to partials[node * chunks + chunk].

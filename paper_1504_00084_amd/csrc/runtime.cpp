@@ -63,6 +63,8 @@ int install_monitor(mesh_sdd *inst, hipStream_t st)
     HIP_TRY(msdd::launch_prep_cells(inst->rho.as<double>(), inst->rho_xi.as<double>(), inst->rho_eta.as<double>(),
                                     d.n_xi, d.n_eta, d.tau / (double)d.K, inst->cells.as<float4>(), st));
     HIP_TRY(msdd::launch_to_f32(inst->rho.as<double>(), inst->rho_f.as<float>(), (size_t)d.n_xi * d.n_eta, st));
+    HIP_TRY(msdd::launch_scaled_to_f32(inst->rho_xi.as<double>(), d.tau / (double)d.K, inst->rhox_f.as<float>(),
+                                       (size_t)d.n_xi * d.n_eta, st));
     HIP_TRY(hipStreamSynchronize(st));
     inst->monitor_set = true;
     return MESH_SDD_OK;
@@ -146,8 +148,8 @@ size_t instance_bytes(const mesh_sdd_desc &d, int M)
 {
     const size_t n = (size_t)d.n_xi * d.n_eta;
     const size_t cells = (size_t)(d.n_xi - 1) * (d.n_eta - 1);
-    // monitor tables, FP32 rho, cell records, node-rank map, stride-1 node lists
-    return 4 * n * sizeof(double) + n * sizeof(float) + 3 * cells * sizeof(float4) + n * sizeof(int32_t) +
+    // monitor tables, FP32 rho and dt rho_xi, cell records, node-rank map, stride-1 node lists
+    return 4 * n * sizeof(double) + 2 * n * sizeof(float) + 3 * cells * sizeof(float4) + n * sizeof(int32_t) +
            3 * (size_t)M * sizeof(int32_t);
 }
 
@@ -226,7 +228,26 @@ mesh_sdd_launch default_launch()
     l.waves_per_simd = 3;
     l.chunk_paths = 128;   // small enough that the LDS variant's wave buffers leave room for a 129x129 rho table
     l.monitor_table = 0;
+    l.table_level = 0;
     return l;
+}
+
+// Node tables that a launch holding one instance of n_nodes nodes stages in
+// LDS: 2 (rho and dt rho_xi) when they fit, else 1 (rho), else 0; *per_cu
+// receives the resident 1024-thread workgroups per CU.
+int table_level(int n_nodes, int monitor_table, int *per_cu)
+{
+    *per_cu = 0;
+    if (monitor_table != 0) return 0;
+    for (int lv = 2; lv >= 1; --lv) {
+        if (msdd::paths_fp32_table_lds_bytes(lv, n_nodes) > kLdsBytes) continue;
+        const int n = msdd::paths_fp32_table_blocks_per_cu(lv, n_nodes);
+        if (n >= 1) {
+            *per_cu = n;
+            return lv;
+        }
+    }
+    return 0;
 }
 
 mesh_sdd_launch launch_for(mesh_sdd_ctx *ctx, const mesh_sdd_desc &d)
@@ -406,6 +427,7 @@ int stage_request(Request &r, const mesh_sdd_step *dev_step)
     v.node_r = r.ss->node_r();
     v.cells = inst.cells.as<float4>();
     v.rho_f = inst.rho_f.as<float>();
+    v.rhox_f = inst.rhox_f.as<float>();
     v.xpad_f = r.xpad_f.as<float>();
     v.ypad_f = r.ypad_f.as<float>();
     v.bnd0_f = r.b0f.as<float>();
@@ -472,22 +494,25 @@ int run_fp32_launch(mesh_sdd_ctx *ctx, const std::vector<InstView> &views, const
         return fail(MESH_SDD_E_NOMEM, "device allocation for the work queue failed");
     HIP_TRY(hipMemcpyAsync(ctx->views.p, views.data(), views.size() * sizeof(InstView), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(ctx->ranges.p, ranges.data(), ranges.size() * sizeof(WorkRange), hipMemcpyHostToDevice, st));
-    // A launch that holds one instance whose rho node table fits in LDS next
-    // to the wave buffers runs the LDS variant (1024-thread workgroups, as
-    // many per CU as registers and LDS allow); its results are identical.
+    // A launch that holds one instance stages that instance's node tables in
+    // LDS (1024-thread workgroups): rho and dt rho_xi when both fit, else rho
+    // alone; the waves then keep their items' end states in the context's
+    // end-state buffer.  Results are identical to the L2 variant's.
     const int n_nodes = views.size() == 1 ? views[0].n_xi * views[0].n_eta : 0;
-    const int lds_per_cu = views.size() == 1 && msdd::paths_fp32_lds_rho_bytes(cap, n_nodes) <= kLdsBytes
-                               ? msdd::paths_fp32_lds_rho_blocks_per_cu(cap, n_nodes)
-                               : 0;
-    const bool lds_rho = ranges.size() == 1 && l.monitor_table == 0 && lds_per_cu >= 1;
+    int per_cu = 0;
+    const int level = views.size() == 1 && ranges.size() == 1 ? table_level(n_nodes, l.monitor_table, &per_cu) : 0;
+    const int table_grid = ctx->cu_count * per_cu;
+    const uint32_t end_waves = (uint32_t)table_grid * (uint32_t)(msdd::kTableBlock / 64);
+    if (level > 0 && ctx->ends.reserve((size_t)end_waves * 6u * cap * sizeof(float)))
+        return fail(MESH_SDD_E_NOMEM, "device allocation of the end-state buffer failed");
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     HIP_TRY(hipEventRecord(e0, st));
-    hipError_t le = lds_rho ? msdd::launch_paths_fp32_lds_rho(ctx->views.as<InstView>(), ctx->ranges.as<WorkRange>(),
-                                                             (uint32_t)n_items, ctx->head.as<uint32_t>(), cap, n_nodes,
-                                                             ctx->cu_count * lds_per_cu, st)
-                            : msdd::launch_paths_fp32(ctx->views.as<InstView>(), ctx->ranges.as<WorkRange>(),
+    hipError_t le = level > 0 ? msdd::launch_paths_fp32_table(ctx->views.as<InstView>(), ctx->ranges.as<WorkRange>(),
+                                                              (uint32_t)n_items, ctx->head.as<uint32_t>(), cap, level,
+                                                              n_nodes, table_grid, ctx->ends.as<float>(), end_waves, st)
+                              : msdd::launch_paths_fp32(ctx->views.as<InstView>(), ctx->ranges.as<WorkRange>(),
                                                       (uint32_t)ranges.size(), (uint32_t)n_items,
                                                       ctx->head.as<uint32_t>(), cap, grid_for(ctx, l, cap), l.block,
                                                       st);
@@ -962,6 +987,8 @@ int mesh_sdd_get_launch(mesh_sdd *inst, mesh_sdd_launch *out)
         const int per_cu = msdd::paths_fp32_blocks_per_cu(out->block, (uint32_t)out->chunk_paths);
         out->waves_per_simd = per_cu * (out->block / 64) / 4;
     }
+    int per_cu = 0;
+    out->table_level = table_level(inst->d.n_xi * inst->d.n_eta, out->monitor_table, &per_cu);
     return MESH_SDD_OK;
 }
 
@@ -1004,7 +1031,7 @@ int mesh_sdd_create(mesh_sdd_ctx *ctx, const mesh_sdd_desc *desc, mesh_sdd **out
     std::lock_guard<std::mutex> g(ctx->gpu_mu);
     HIP_TRY(hipSetDevice(ctx->device));
     if (inst->rho_in.alloc(n * 8) || inst->rho.alloc(n * 8) || inst->rho_xi.alloc(n * 8) ||
-        inst->rho_eta.alloc(n * 8) || inst->rho_f.alloc(n * 4) || inst->cells.alloc(cells * 3 * sizeof(float4)) ||
+        inst->rho_eta.alloc(n * 8) || inst->rho_f.alloc(n * 4) || inst->rhox_f.alloc(n * 4) || inst->cells.alloc(cells * 3 * sizeof(float4)) ||
         inst->node_rank.alloc(n * 4))
         return fail(MESH_SDD_E_NOMEM, "device allocation for the instance tables failed");
     {

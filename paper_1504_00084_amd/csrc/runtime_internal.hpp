@@ -176,7 +176,8 @@ struct mesh_sdd {
     // first use (under ctx->gpu_mu), and all live until destroy
     std::map<int, std::unique_ptr<SampleSet>> samples;
     DevBuf rho_in, rho, rho_xi, rho_eta;    // FP64 monitor staging and node tables
-    DevBuf rho_f;                           // FP32 node table of rho (staged in LDS by single-instance launches)
+    DevBuf rho_f, rhox_f;                   // FP32 node tables of rho and dt rho_xi (staged in LDS by
+                                            // single-instance launches)
     DevBuf cells;                           // FP32 per-cell records (rho corners, gradient coefficients)
     DevBuf node_rank;                       // [n_eta][n_xi] interface rank or -1
     bool monitor_set = false;
@@ -235,6 +236,7 @@ struct mesh_sdd_ctx {
     DevPool pool;        // recycled request buffers (declared before users)
     std::mutex gpu_mu;   // serialises use of the stream and the launch scratch below
     DevBuf head, views, ranges;
+    DevBuf ends;         // item end states of single-instance launches (grow-only)
 
     std::mutex mu;       // guards everything below
     std::condition_variable cv, done_cv;

@@ -84,7 +84,7 @@ class Stats(ctypes.Structure):
 
 class Launch(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("block", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32),
-                ("chunk_paths", ctypes.c_int32), ("monitor_table", ctypes.c_int32)]
+                ("chunk_paths", ctypes.c_int32), ("monitor_table", ctypes.c_int32), ("table_level", ctypes.c_int32)]
 
 
 _lib = None
@@ -213,7 +213,7 @@ def mesh_sdd_get_launch(inst) -> Launch:
 
 
 def make_launch(block=256, waves_per_simd=3, chunk_paths=128, monitor_table=0) -> Launch:
-    return Launch(ctypes.sizeof(Launch), block, waves_per_simd, chunk_paths, monitor_table)
+    return Launch(ctypes.sizeof(Launch), block, waves_per_simd, chunk_paths, monitor_table, 0)
 
 
 def mesh_sdd_autotune(inst, step: Step) -> Launch:

@@ -262,23 +262,29 @@ def test_target_se_sets_path_count(M, ctx):
 
 
 def test_lds_and_l2_monitor_give_identical_results(M, ctx):
-    """A single-instance launch reads rho from an LDS copy of the node table
-    (when it fits); with monitor_table = 1 it reads the same corner values
-    from the cell records in L2.  Both must give bitwise equal results."""
-    insts = W.config4(count=4, seed=9, n_paths=4000, sizes=(33, 65, 129))
+    """A single-instance launch reads rho and dt rho_xi from an LDS copy of
+    the node tables (level 2, 8 B per node), or rho alone (level 1, grids
+    too large for both); with monitor_table = 1 it reads the same corner
+    values from the cell records in L2.  All must give bitwise equal
+    results."""
+    rng = np.random.default_rng(9)
+    insts = [W.random_instance(rng, q, n_paths=4000, sizes=(n,)) for q, n in enumerate((33, 129, 161, 65))]
     for q, it in enumerate(insts):
         it.K = 60 + 13 * q
         it.instance_id = 300 + q
     H = Handles(M, ctx, insts, M.FP32)
     try:
+        levels = [M.mesh_sdd_get_launch(h).table_level for h in H.h]
+        assert levels == [2, 2, 1, 2], levels
         lds = solve_alone(M, H, insts)
         M.mesh_sdd_set_launch(ctx, M.make_launch(monitor_table=1))
         try:
+            assert all(M.mesh_sdd_get_launch(h).table_level == 0 for h in H.h)
             l2 = solve_alone(M, H, insts)
         finally:
             M.mesh_sdd_set_launch(ctx, None)
         for q in range(len(insts)):
             assert same(lds[q], l2[q]), insts[q].name
-        say("LDS rho == L2 rho (bitwise) on %s" % ", ".join(it.name for it in insts))
+        say("LDS tables (levels %s) == L2 records (bitwise) on %s" % (levels, ", ".join(it.name for it in insts)))
     finally:
         H.close()
