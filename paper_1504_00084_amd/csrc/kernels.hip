@@ -92,9 +92,14 @@ struct ConstF {
     float c_rad;   // -4 ln2 dt, so that sqrt(c_rad log2 u) = sqrt(2 dt) sqrt(-2 ln u)
     float sq2dt;   // sqrt(2 dt) (diagnostics only)
     float delta;   // sqrt(18.5 dt): farther from every side, no bridge crossing can matter
-    const GLOBAL f32x4 *cells;   // per cell: rho, dt rho_xi, dt rho_eta in coefficient form
+    uint32_t ncell;              // cells per record plane, (n_xi - 1)(n_eta - 1)
+    const GLOBAL f32x4 *cells;   // record planes: rho corners, dt rho_xi corners, dt rho_eta coefficients
 };
 
+// PER >= 0: the periodic flags are the compile-time constants PER & 1 (xi)
+// and PER >> 1 (eta) -- the launch holds one instance of that kind -- so the
+// tests and selects they guard vanish from the code; PER < 0: from I.
+template <int PER>
 __device__ __forceinline__ ConstF load_const_f(const InstView &I)
 {
     ConstF c;
@@ -102,8 +107,9 @@ __device__ __forceinline__ ConstF load_const_f(const InstView &I)
     c.n_eta = I.n_eta;
     c.nx1 = I.n_xi - 1;
     c.ny1 = I.n_eta - 1;
-    c.per_xi = I.per_xi;
-    c.per_eta = I.per_eta;
+    c.per_xi = PER < 0 ? I.per_xi : (PER & 1);
+    c.per_eta = PER < 0 ? I.per_eta : (PER >> 1);
+    c.ncell = (uint32_t)(c.nx1 * c.ny1);
     c.bridge = I.bridge;
     c.K = I.K;
     c.fnx1 = (float)(I.n_xi - 1);
@@ -178,7 +184,7 @@ __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t w
     const int cy = min((int)(P.y * C.fny1), C.ny1 - 1);
     tx = P.x * C.fnx1 - (float)cx;
     ty = P.y * C.fny1 - (float)cy;
-    const GLOBAL f32x4 *cell = C.cells + (uint32_t)(3 * (cy * C.nx1 + cx));
+    const GLOBAL f32x4 *cell = C.cells + (uint32_t)(cy * C.nx1 + cx);   // plane 0 of the cell's records
     float r00, r10, r01, r11, g00, g10, g01, g11;
     if (TAB == 2) {
         const float2 *t2 = (const float2 *)tab + (cy * C.n_xi + cx);
@@ -193,10 +199,10 @@ __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t w
             const f32x4 A = cell[0];
             r00 = A.x, r10 = A.y, r01 = A.z, r11 = A.w;
         }
-        const f32x4 B = cell[1];
+        const f32x4 B = cell[C.ncell];
         g00 = B.x, g10 = B.y, g01 = B.z, g11 = B.w;
     }
-    const f32x4 G = cell[2];
+    const f32x4 G = cell[2u * C.ncell];
     const float rho = bilerp(tx, ty, r00, r10, r01, r11);
     const float gx = bilerp(tx, ty, g00, g10, g01, g11);
     const float gy = fmaf(ty, fmaf(G.w, tx, G.z), fmaf(G.y, tx, G.x));
@@ -553,13 +559,17 @@ __device__ __forceinline__ void finish_item(const float *buf, uint32_t cap, uint
 // together with VALU issue.  The table fills the LDS, so the waves keep the
 // end states of their items in `ends` (global memory, 6 * cap words per
 // wave, room for `end_waves` waves; read back by the same wave only).
-template <int BLOCK, int TAB>
+// PER >= 0 (single-instance launches): the instance's periodic flags as
+// compile-time constants (see load_const_f); a mismatching instance ends the
+// launch at once, untouched.
+template <int BLOCK, int TAB, int PER>
 __global__ __launch_bounds__(BLOCK) void paths_fp32(const InstView *__restrict__ insts,
                                                     const WorkRange *__restrict__ ranges, uint32_t n_ranges,
                                                     uint32_t n_items, uint32_t *__restrict__ head, uint32_t cap,
                                                     float *__restrict__ ends, uint32_t end_waves)
 {
     extern __shared__ float lds[];
+    if (PER >= 0 && (insts[0].per_xi != (PER & 1) || insts[0].per_eta != (PER >> 1))) return;
     const int lane = threadIdx.x & 63;
     const uint32_t wave = blockIdx.x * (uint32_t)(BLOCK / 64) + (threadIdx.x >> 6);
     if (TAB > 0 && (blockIdx.x + 1u) * (uint32_t)(BLOCK / 64) > end_waves) return;   // whole block: no room
@@ -585,7 +595,7 @@ __global__ __launch_bounds__(BLOCK) void paths_fp32(const InstView *__restrict__
     uint32_t next = pop_item(head, lane);
     uint32_t cur_inst = 0xFFFFFFFFu;
     const InstView *Ip = insts;
-    ConstF C{};
+    ConstF C = load_const_f<PER>(insts[0]);
     uint32_t key0 = 0, key1 = 0, ctr3 = 0;
     uint32_t act0 = 0, act1 = 0, cnt0 = 0, cnt1 = 0, rem0 = 0, rem1 = 0;
     uint32_t node0 = 0, node1 = 0, pb0 = 0, pb1 = 0, part0 = 0, part1 = 0;
@@ -616,7 +626,7 @@ __global__ __launch_bounds__(BLOCK) void paths_fp32(const InstView *__restrict__
                 if (!same) {
                     cur_inst = f.inst;
                     Ip = insts + f.inst;
-                    C = load_const_f(*Ip);
+                    C = load_const_f<PER>(*Ip);
                     key0 = Ip->key0;
                     key1 = Ip->key1;
                     ctr3 = Ip->ctr3;
@@ -1016,13 +1026,14 @@ __global__ void prep_cells_kernel(const double *__restrict__ rho, const double *
     const size_t a = (size_t)cy * n_xi + cx, b = a + n_xi;
     const double *f[3] = {rho, rx, ry};
     // rho and dt rho_xi: the four corner values, exactly the FP32 node tables'
-    cells[3 * (size_t)idx] = make_float4((float)rho[a], (float)rho[a + 1], (float)rho[b], (float)rho[b + 1]);
-    cells[3 * (size_t)idx + 1] = make_float4((float)(grad_scale * rx[a]), (float)(grad_scale * rx[a + 1]),
+    const size_t plane = (size_t)nx1 * ny1;
+    cells[(size_t)idx] = make_float4((float)rho[a], (float)rho[a + 1], (float)rho[b], (float)rho[b + 1]);
+    cells[plane + idx] = make_float4((float)(grad_scale * rx[a]), (float)(grad_scale * rx[a + 1]),
                                              (float)(grad_scale * rx[b]), (float)(grad_scale * rx[b + 1]));
     {   // dt rho_eta in coefficient form a + b tx + c ty + d tx ty
         const double f00 = grad_scale * f[2][a], f10 = grad_scale * f[2][a + 1];
         const double f01 = grad_scale * f[2][b], f11 = grad_scale * f[2][b + 1];
-        cells[3 * (size_t)idx + 2] = make_float4((float)f00, (float)(f10 - f00), (float)(f01 - f00),
+        cells[2 * plane + idx] = make_float4((float)f00, (float)(f10 - f00), (float)(f01 - f00),
                                                  (float)(f11 - f10 - f01 + f00));
     }
 }
@@ -1234,7 +1245,7 @@ __global__ void debug_paths_kernel(const InstView *__restrict__ inst, int fp64, 
         steps[t] = o.steps;
         return;
     }
-    const ConstF C = load_const_f(I);
+    const ConstF C = load_const_f<-1>(I);
     const int i0 = I.node_i[node], j0 = I.node_j[node];
     PathF P{(float)((double)i0 / (double)C.nx1), (float)((double)j0 / (double)C.ny1), 0.0f, 0, 0, 0};
     P.m = side_distance(C, P.x, P.y);
@@ -1315,19 +1326,19 @@ hipError_t launch_paths_fp32(const InstView *insts, const WorkRange *ranges, uin
     const size_t lds = paths_fp32_lds_bytes(block, cap);
     switch (block) {
     case 64:
-        hipLaunchKernelGGL((paths_fp32<64, 0>), dim3(grid), dim3(64), lds, s, insts, ranges, n_ranges, n_items, head,
+        hipLaunchKernelGGL((paths_fp32<64, 0, -1>), dim3(grid), dim3(64), lds, s, insts, ranges, n_ranges, n_items, head,
                            cap, nullptr, 0u);
         break;
     case 128:
-        hipLaunchKernelGGL((paths_fp32<128, 0>), dim3(grid), dim3(128), lds, s, insts, ranges, n_ranges, n_items,
+        hipLaunchKernelGGL((paths_fp32<128, 0, -1>), dim3(grid), dim3(128), lds, s, insts, ranges, n_ranges, n_items,
                            head, cap, nullptr, 0u);
         break;
     case 256:
-        hipLaunchKernelGGL((paths_fp32<256, 0>), dim3(grid), dim3(256), lds, s, insts, ranges, n_ranges, n_items,
+        hipLaunchKernelGGL((paths_fp32<256, 0, -1>), dim3(grid), dim3(256), lds, s, insts, ranges, n_ranges, n_items,
                            head, cap, nullptr, 0u);
         break;
     case 512:
-        hipLaunchKernelGGL((paths_fp32<512, 0>), dim3(grid), dim3(512), lds, s, insts, ranges, n_ranges, n_items,
+        hipLaunchKernelGGL((paths_fp32<512, 0, -1>), dim3(grid), dim3(512), lds, s, insts, ranges, n_ranges, n_items,
                            head, cap, nullptr, 0u);
         break;
     default:
@@ -1338,33 +1349,45 @@ hipError_t launch_paths_fp32(const InstView *insts, const WorkRange *ranges, uin
 
 size_t paths_fp32_table_lds_bytes(int level, int n_nodes) { return (size_t)n_nodes * (size_t)level * sizeof(float); }
 
+template <int TAB, int PER>
+static void launch_table(int grid, size_t lds, hipStream_t s, const InstView *insts, const WorkRange *ranges,
+                         uint32_t n_items, uint32_t *head, uint32_t cap, float *ends, uint32_t end_waves)
+{
+    hipLaunchKernelGGL((paths_fp32<kTableBlock, TAB, PER>), dim3(grid), dim3(kTableBlock), lds, s, insts, ranges, 1u,
+                       n_items, head, cap, ends, end_waves);
+}
+
 hipError_t launch_paths_fp32_table(const InstView *insts, const WorkRange *ranges, uint32_t n_items, uint32_t *head,
-                                   uint32_t cap, int level, int n_nodes, int grid, float *ends, uint32_t end_waves,
-                                   hipStream_t s)
+                                   uint32_t cap, int level, int periodic, int n_nodes, int grid, float *ends,
+                                   uint32_t end_waves, hipStream_t s)
 {
     hipError_t e = launch_fill_u32(head, 0u, 1, s);
     if (e != hipSuccess) return e;
     if (n_items == 0) return hipSuccess;
-    if ((size_t)grid * (kTableBlock / 64) > end_waves) return hipErrorInvalidValue;
-    const size_t lds = paths_fp32_table_lds_bytes(level, n_nodes);
-    if (level == 2)
-        hipLaunchKernelGGL((paths_fp32<kTableBlock, 2>), dim3(grid), dim3(kTableBlock), lds, s, insts, ranges, 1u,
-                           n_items, head, cap, ends, end_waves);
-    else if (level == 1)
-        hipLaunchKernelGGL((paths_fp32<kTableBlock, 1>), dim3(grid), dim3(kTableBlock), lds, s, insts, ranges, 1u,
-                           n_items, head, cap, ends, end_waves);
-    else
+    if ((size_t)grid * (kTableBlock / 64) > end_waves || level < 1 || level > 2 || periodic < 0 || periodic > 3)
         return hipErrorInvalidValue;
+    const size_t lds = paths_fp32_table_lds_bytes(level, n_nodes);
+    switch (level * 4 + periodic) {
+    case 4: launch_table<1, 0>(grid, lds, s, insts, ranges, n_items, head, cap, ends, end_waves); break;
+    case 5: launch_table<1, 1>(grid, lds, s, insts, ranges, n_items, head, cap, ends, end_waves); break;
+    case 6: launch_table<1, 2>(grid, lds, s, insts, ranges, n_items, head, cap, ends, end_waves); break;
+    case 7: launch_table<1, 3>(grid, lds, s, insts, ranges, n_items, head, cap, ends, end_waves); break;
+    case 8: launch_table<2, 0>(grid, lds, s, insts, ranges, n_items, head, cap, ends, end_waves); break;
+    case 9: launch_table<2, 1>(grid, lds, s, insts, ranges, n_items, head, cap, ends, end_waves); break;
+    case 10: launch_table<2, 2>(grid, lds, s, insts, ranges, n_items, head, cap, ends, end_waves); break;
+    default: launch_table<2, 3>(grid, lds, s, insts, ranges, n_items, head, cap, ends, end_waves); break;
+    }
     return hipGetLastError();
 }
 
 int paths_fp32_table_blocks_per_cu(int level, int n_nodes)
 {
+    // every periodicity instance has the same launch bounds and LDS use
     int n = 0;
     const size_t lds = paths_fp32_table_lds_bytes(level, n_nodes);
-    hipError_t e = level == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32<kTableBlock, 2>,
+    hipError_t e = level == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32<kTableBlock, 2, 0>,
                                                                              kTableBlock, lds)
-                              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32<kTableBlock, 1>,
+                              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32<kTableBlock, 1, 0>,
                                                                              kTableBlock, lds);
     return e == hipSuccess ? n : 0;
 }
@@ -1415,10 +1438,10 @@ int paths_fp32_blocks_per_cu(int block, uint32_t cap)
     hipError_t e = hipErrorInvalidValue;
     const size_t lds = paths_fp32_lds_bytes(block, cap);
     switch (block) {
-    case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32<64, 0>, 64, lds); break;
-    case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32<128, 0>, 128, lds); break;
-    case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32<256, 0>, 256, lds); break;
-    case 512: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32<512, 0>, 512, lds); break;
+    case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32<64, 0, -1>, 64, lds); break;
+    case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32<128, 0, -1>, 128, lds); break;
+    case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32<256, 0, -1>, 256, lds); break;
+    case 512: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32<512, 0, -1>, 512, lds); break;
     default: break;
     }
     return e == hipSuccess ? n : 0;
@@ -1429,10 +1452,10 @@ int paths_fp32_attributes(int block, int *vgprs, int *sgprs, int *lds_bytes)
     hipFuncAttributes a;
     hipError_t e = hipErrorInvalidValue;
     switch (block) {
-    case 64: e = hipFuncGetAttributes(&a, reinterpret_cast<const void *>(paths_fp32<64, 0>)); break;
-    case 128: e = hipFuncGetAttributes(&a, reinterpret_cast<const void *>(paths_fp32<128, 0>)); break;
-    case 256: e = hipFuncGetAttributes(&a, reinterpret_cast<const void *>(paths_fp32<256, 0>)); break;
-    case 512: e = hipFuncGetAttributes(&a, reinterpret_cast<const void *>(paths_fp32<512, 0>)); break;
+    case 64: e = hipFuncGetAttributes(&a, reinterpret_cast<const void *>(paths_fp32<64, 0, -1>)); break;
+    case 128: e = hipFuncGetAttributes(&a, reinterpret_cast<const void *>(paths_fp32<128, 0, -1>)); break;
+    case 256: e = hipFuncGetAttributes(&a, reinterpret_cast<const void *>(paths_fp32<256, 0, -1>)); break;
+    case 512: e = hipFuncGetAttributes(&a, reinterpret_cast<const void *>(paths_fp32<512, 0, -1>)); break;
     default: break;
     }
     if (e != hipSuccess) return -1;

@@ -14,9 +14,9 @@ namespace msdd {
 hipError_t launch_prep_gradient(const double *rho_in, int n_xi, int n_eta, int per_xi, int per_eta,
                                 double *rho, double *rho_xi, double *rho_eta, hipStream_t s);
 
-// a0 (FP32 path): per-cell records: rho and s rho_xi at the four corners,
-// then s rho_eta in bilinear coefficient form, with s = grad_scale (the
-// substep dt).
+// a0 (FP32 path): per-cell records in three planes of (n_xi-1)(n_eta-1)
+// float4: rho and s rho_xi at the four corners, then s rho_eta in bilinear
+// coefficient form, with s = grad_scale (the substep dt).
 hipError_t launch_prep_cells(const double *rho, const double *rho_xi, const double *rho_eta, int n_xi,
                              int n_eta, double grad_scale, float4 *cells, hipStream_t s);
 
@@ -50,9 +50,10 @@ size_t paths_fp32_lds_bytes(int block, uint32_t cap);
 // Results are identical to launch_paths_fp32's.
 constexpr int kTableBlock = 1024;
 size_t paths_fp32_table_lds_bytes(int level, int n_nodes);
+// `periodic` = per_xi + 2 per_eta of the instance (compiled in).
 hipError_t launch_paths_fp32_table(const InstView *insts, const WorkRange *ranges, uint32_t n_items, uint32_t *head,
-                                   uint32_t cap, int level, int n_nodes, int grid, float *ends, uint32_t end_waves,
-                                   hipStream_t s);
+                                   uint32_t cap, int level, int periodic, int n_nodes, int grid, float *ends,
+                                   uint32_t end_waves, hipStream_t s);
 int paths_fp32_table_blocks_per_cu(int level, int n_nodes);
 
 // a2-a8, FP64 plain: one thread per path, one launch per instance; the

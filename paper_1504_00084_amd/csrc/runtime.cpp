@@ -511,7 +511,8 @@ int run_fp32_launch(mesh_sdd_ctx *ctx, const std::vector<InstView> &views, const
     HIP_TRY(hipEventRecord(e0, st));
     hipError_t le = level > 0 ? msdd::launch_paths_fp32_table(ctx->views.as<InstView>(), ctx->ranges.as<WorkRange>(),
                                                               (uint32_t)n_items, ctx->head.as<uint32_t>(), cap, level,
-                                                              n_nodes, table_grid, ctx->ends.as<float>(), end_waves, st)
+                                                              views[0].per_xi + 2 * views[0].per_eta, n_nodes,
+                                                              table_grid, ctx->ends.as<float>(), end_waves, st)
                               : msdd::launch_paths_fp32(ctx->views.as<InstView>(), ctx->ranges.as<WorkRange>(),
                                                       (uint32_t)ranges.size(), (uint32_t)n_items,
                                                       ctx->head.as<uint32_t>(), cap, grid_for(ctx, l, cap), l.block,
