@@ -92,8 +92,8 @@ struct ConstF {
     float c_rad;   // -4 ln2 dt, so that sqrt(c_rad log2 u) = sqrt(2 dt) sqrt(-2 ln u)
     float sq2dt;   // sqrt(2 dt) (diagnostics only)
     float delta;   // sqrt(18.5 dt): farther from every side, no bridge crossing can matter
-    uint32_t ncell;              // cells per record plane, (n_xi - 1)(n_eta - 1)
-    const GLOBAL f32x4 *cells;   // record planes: rho corners, dt rho_xi corners, dt rho_eta coefficients
+    const GLOBAL f32x4 *cells;   // per cell: rho corners, dt rho_xi corners, dt rho_eta coefficients
+    const GLOBAL f32x4 *coef_y;  // per cell: the dt rho_eta coefficients alone (compact)
 };
 
 // PER >= 0: the periodic flags are the compile-time constants PER & 1 (xi)
@@ -109,7 +109,6 @@ __device__ __forceinline__ ConstF load_const_f(const InstView &I)
     c.ny1 = I.n_eta - 1;
     c.per_xi = PER < 0 ? I.per_xi : (PER & 1);
     c.per_eta = PER < 0 ? I.per_eta : (PER >> 1);
-    c.ncell = (uint32_t)(c.nx1 * c.ny1);
     c.bridge = I.bridge;
     c.K = I.K;
     c.fnx1 = (float)(I.n_xi - 1);
@@ -123,6 +122,7 @@ __device__ __forceinline__ ConstF load_const_f(const InstView &I)
     c.sq2dt = I.sq2dt_f;
     c.delta = I.delta_f;
     c.cells = (const GLOBAL f32x4 *)I.cells;
+    c.coef_y = (const GLOBAL f32x4 *)I.coef_y;
     return c;
 }
 
@@ -184,7 +184,8 @@ __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t w
     const int cy = min((int)(P.y * C.fny1), C.ny1 - 1);
     tx = P.x * C.fnx1 - (float)cx;
     ty = P.y * C.fny1 - (float)cy;
-    const GLOBAL f32x4 *cell = C.cells + (uint32_t)(cy * C.nx1 + cx);   // plane 0 of the cell's records
+    const uint32_t ci = (uint32_t)(cy * C.nx1 + cx);
+    const GLOBAL f32x4 *cell = C.cells + 3u * ci;
     float r00, r10, r01, r11, g00, g10, g01, g11;
     if (TAB == 2) {
         const float2 *t2 = (const float2 *)tab + (cy * C.n_xi + cx);
@@ -199,10 +200,12 @@ __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t w
             const f32x4 A = cell[0];
             r00 = A.x, r10 = A.y, r01 = A.z, r11 = A.w;
         }
-        const f32x4 B = cell[C.ncell];
+        const f32x4 B = cell[1];
         g00 = B.x, g10 = B.y, g01 = B.z, g11 = B.w;
     }
-    const f32x4 G = cell[2u * C.ncell];
+    // the two-field table kernel reads the coefficients from the compact
+    // plane (its only gather: better L1 reuse); the others from the record
+    const f32x4 G = TAB == 2 ? C.coef_y[ci] : cell[2];
     const float rho = bilerp(tx, ty, r00, r10, r01, r11);
     const float gx = bilerp(tx, ty, g00, g10, g01, g11);
     const float gy = fmaf(ty, fmaf(G.w, tx, G.z), fmaf(G.y, tx, G.x));
@@ -1017,7 +1020,7 @@ __global__ void prep_gradient_kernel(const double *__restrict__ in, int n_xi, in
 
 __global__ void prep_cells_kernel(const double *__restrict__ rho, const double *__restrict__ rx,
                                   const double *__restrict__ ry, int n_xi, int n_eta, double grad_scale,
-                                  float4 *cells)
+                                  float4 *cells, float4 *coef_y)
 {
     const int nx1 = n_xi - 1, ny1 = n_eta - 1;
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1026,15 +1029,16 @@ __global__ void prep_cells_kernel(const double *__restrict__ rho, const double *
     const size_t a = (size_t)cy * n_xi + cx, b = a + n_xi;
     const double *f[3] = {rho, rx, ry};
     // rho and dt rho_xi: the four corner values, exactly the FP32 node tables'
-    const size_t plane = (size_t)nx1 * ny1;
-    cells[(size_t)idx] = make_float4((float)rho[a], (float)rho[a + 1], (float)rho[b], (float)rho[b + 1]);
-    cells[plane + idx] = make_float4((float)(grad_scale * rx[a]), (float)(grad_scale * rx[a + 1]),
+    cells[3 * (size_t)idx] = make_float4((float)rho[a], (float)rho[a + 1], (float)rho[b], (float)rho[b + 1]);
+    cells[3 * (size_t)idx + 1] = make_float4((float)(grad_scale * rx[a]), (float)(grad_scale * rx[a + 1]),
                                              (float)(grad_scale * rx[b]), (float)(grad_scale * rx[b + 1]));
     {   // dt rho_eta in coefficient form a + b tx + c ty + d tx ty
         const double f00 = grad_scale * f[2][a], f10 = grad_scale * f[2][a + 1];
         const double f01 = grad_scale * f[2][b], f11 = grad_scale * f[2][b + 1];
-        cells[2 * plane + idx] = make_float4((float)f00, (float)(f10 - f00), (float)(f01 - f00),
-                                                 (float)(f11 - f10 - f01 + f00));
+        const float4 g = make_float4((float)f00, (float)(f10 - f00), (float)(f01 - f00),
+                                     (float)(f11 - f10 - f01 + f00));
+        cells[3 * (size_t)idx + 2] = g;
+        coef_y[idx] = g;
     }
 }
 
@@ -1279,11 +1283,11 @@ hipError_t launch_prep_gradient(const double *rho_in, int n_xi, int n_eta, int p
 }
 
 hipError_t launch_prep_cells(const double *rho, const double *rho_xi, const double *rho_eta, int n_xi, int n_eta,
-                             double grad_scale, float4 *cells, hipStream_t s)
+                             double grad_scale, float4 *cells, float4 *coef_y, hipStream_t s)
 {
     const size_t n = (size_t)(n_xi - 1) * (n_eta - 1);
     hipLaunchKernelGGL(prep_cells_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, rho, rho_xi, rho_eta, n_xi,
-                       n_eta, grad_scale, cells);
+                       n_eta, grad_scale, cells, coef_y);
     return hipGetLastError();
 }
 

@@ -56,15 +56,16 @@ struct InstView {
     const int32_t *node_i, *node_j;
     const uint32_t *node_r;
 
-    // FP32 path: per-cell records of three float4 in three planes of
-    // (n_xi-1)(n_eta-1) cells (plane-major, so a gather of one field reads a
-    // compact array): rho and dt rho_xi at the four corners (00, 10, 01, 11),
-    // then dt rho_eta in coefficient form a + b tx + c ty + d tx ty; the FP32 node tables of
-    // rho and dt rho_xi [n_eta][n_xi] (the same corner values, staged in LDS
-    // by launches that hold this instance alone); padded mesh
-    // [n_eta+2][n_xi+2] with ghost / wrapped values, origin at node (-1, -1);
-    // boundary arrays in the C-ABI layout.
-    const float4 *cells;
+    // FP32 path: per-cell records of three float4, (n_xi-1)(n_eta-1) cells:
+    // rho and dt rho_xi at the four corners (00, 10, 01, 11), then dt rho_eta
+    // in coefficient form a + b tx + c ty + d tx ty; the same coefficients
+    // again as a compact plane (coef_y, read by the kernel that takes rho and
+    // dt rho_xi from LDS); the FP32 node tables of rho and dt rho_xi
+    // [n_eta][n_xi] (the same corner values, staged in LDS by launches that
+    // hold this instance alone); padded mesh [n_eta+2][n_xi+2] with ghost /
+    // wrapped values, origin at node (-1, -1); boundary arrays in the C-ABI
+    // layout.
+    const float4 *cells, *coef_y;
     const float *rho_f, *rhox_f;
     const float *xpad_f, *ypad_f;
     const float *bnd0_f, *bnd1_f;

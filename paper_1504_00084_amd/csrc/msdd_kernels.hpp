@@ -14,11 +14,12 @@ namespace msdd {
 hipError_t launch_prep_gradient(const double *rho_in, int n_xi, int n_eta, int per_xi, int per_eta,
                                 double *rho, double *rho_xi, double *rho_eta, hipStream_t s);
 
-// a0 (FP32 path): per-cell records in three planes of (n_xi-1)(n_eta-1)
-// float4: rho and s rho_xi at the four corners, then s rho_eta in bilinear
-// coefficient form, with s = grad_scale (the substep dt).
+// a0 (FP32 path): per-cell records of three float4: rho and s rho_xi at the
+// four corners, then s rho_eta in bilinear coefficient form, with s =
+// grad_scale (the substep dt); coef_y gets the last float4 of every record
+// again, as a compact plane.
 hipError_t launch_prep_cells(const double *rho, const double *rho_xi, const double *rho_eta, int n_xi,
-                             int n_eta, double grad_scale, float4 *cells, hipStream_t s);
+                             int n_eta, double grad_scale, float4 *cells, float4 *coef_y, hipStream_t s);
 
 // a7 set-up: padded mesh [n_eta+2][n_xi+2] (ghost rows / columns by Keys'
 // rule on Dirichlet axes, wrapped with quasi-periodic offsets on periodic

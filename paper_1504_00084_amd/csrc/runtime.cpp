@@ -61,7 +61,8 @@ int install_monitor(mesh_sdd *inst, hipStream_t st)
     HIP_TRY(msdd::launch_prep_gradient(inst->rho_in.as<double>(), d.n_xi, d.n_eta, d.periodic_xi, d.periodic_eta,
                                        inst->rho.as<double>(), inst->rho_xi.as<double>(), inst->rho_eta.as<double>(), st));
     HIP_TRY(msdd::launch_prep_cells(inst->rho.as<double>(), inst->rho_xi.as<double>(), inst->rho_eta.as<double>(),
-                                    d.n_xi, d.n_eta, d.tau / (double)d.K, inst->cells.as<float4>(), st));
+                                    d.n_xi, d.n_eta, d.tau / (double)d.K, inst->cells.as<float4>(),
+                                    inst->coef_y.as<float4>(), st));
     HIP_TRY(msdd::launch_to_f32(inst->rho.as<double>(), inst->rho_f.as<float>(), (size_t)d.n_xi * d.n_eta, st));
     HIP_TRY(msdd::launch_scaled_to_f32(inst->rho_xi.as<double>(), d.tau / (double)d.K, inst->rhox_f.as<float>(),
                                        (size_t)d.n_xi * d.n_eta, st));
@@ -149,7 +150,7 @@ size_t instance_bytes(const mesh_sdd_desc &d, int M)
     const size_t n = (size_t)d.n_xi * d.n_eta;
     const size_t cells = (size_t)(d.n_xi - 1) * (d.n_eta - 1);
     // monitor tables, FP32 rho and dt rho_xi, cell records, node-rank map, stride-1 node lists
-    return 4 * n * sizeof(double) + 2 * n * sizeof(float) + 3 * cells * sizeof(float4) + n * sizeof(int32_t) +
+    return 4 * n * sizeof(double) + 2 * n * sizeof(float) + 4 * cells * sizeof(float4) + n * sizeof(int32_t) +
            3 * (size_t)M * sizeof(int32_t);
 }
 
@@ -426,6 +427,7 @@ int stage_request(Request &r, const mesh_sdd_step *dev_step)
     v.node_j = r.ss->node_j();
     v.node_r = r.ss->node_r();
     v.cells = inst.cells.as<float4>();
+    v.coef_y = inst.coef_y.as<float4>();
     v.rho_f = inst.rho_f.as<float>();
     v.rhox_f = inst.rhox_f.as<float>();
     v.xpad_f = r.xpad_f.as<float>();
@@ -1032,7 +1034,8 @@ int mesh_sdd_create(mesh_sdd_ctx *ctx, const mesh_sdd_desc *desc, mesh_sdd **out
     std::lock_guard<std::mutex> g(ctx->gpu_mu);
     HIP_TRY(hipSetDevice(ctx->device));
     if (inst->rho_in.alloc(n * 8) || inst->rho.alloc(n * 8) || inst->rho_xi.alloc(n * 8) ||
-        inst->rho_eta.alloc(n * 8) || inst->rho_f.alloc(n * 4) || inst->rhox_f.alloc(n * 4) || inst->cells.alloc(cells * 3 * sizeof(float4)) ||
+        inst->rho_eta.alloc(n * 8) || inst->rho_f.alloc(n * 4) || inst->rhox_f.alloc(n * 4) ||
+        inst->cells.alloc(cells * 3 * sizeof(float4)) || inst->coef_y.alloc(cells * sizeof(float4)) ||
         inst->node_rank.alloc(n * 4))
         return fail(MESH_SDD_E_NOMEM, "device allocation for the instance tables failed");
     {

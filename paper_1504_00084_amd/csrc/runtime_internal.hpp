@@ -178,7 +178,8 @@ struct mesh_sdd {
     DevBuf rho_in, rho, rho_xi, rho_eta;    // FP64 monitor staging and node tables
     DevBuf rho_f, rhox_f;                   // FP32 node tables of rho and dt rho_xi (staged in LDS by
                                             // single-instance launches)
-    DevBuf cells;                           // FP32 per-cell records (rho corners, gradient coefficients)
+    DevBuf cells;                           // FP32 per-cell records (rho and rho_xi corners, rho_eta coefficients)
+    DevBuf coef_y;                          // FP32 rho_eta coefficients alone, one float4 per cell
     DevBuf node_rank;                       // [n_eta][n_xi] interface rank or -1
     bool monitor_set = false;
     std::atomic<int> inflight{0};
