@@ -32,15 +32,16 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 W_SLOTS_PER_STEP = 86.5
 
 # HBM traffic of one paths_fp32 launch on the 129x129, 4x4 workload at the
-# default launch (single instance: the LDS-rho variant, 1024 threads per
-# workgroup, one workgroup per CU, 128-path chunks), from two rocprofv3 --pmc
-# runs of this script (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each
-# scaled by what the counter reads for a 1 GiB device copy in the same run
-# (FETCH_SIZE reads 524708 KiB: x2.0; WRITE_SIZE reads 1.0492e6 KiB: x1.0).
-# Valid only for the kernel source it was measured on (SHA-1 of
+# default launch (single instance: the LDS-table kernel at level 2, 1024
+# threads per workgroup, one workgroup per CU, 128-path chunks), from two
+# rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE, KiB per
+# dispatch), each scaled by what the counter reads for a 1 GiB device copy in
+# the same run (FETCH_SIZE reads 524708 KiB: x2.0; WRITE_SIZE reads 1.0492e6
+# KiB: x1.0).  Most of the writes are L2 write-backs of the waves' end-state
+# buffers.  Valid only for the kernel source it was measured on (SHA-1 of
 # csrc/kernels.hip); reported as null otherwise.
-TRAFFIC_RECORD = {"kernels_sha1": "54c4209e0d8d4e83feb3dc84996467b32d9fb71a", "fetch_kib": 4493.69,
-                  "write_kib": 54137.8, "fetch_scale": 2.0, "write_scale": 1.0}
+TRAFFIC_RECORD = {"kernels_sha1": "2d906ebdaae2f35ada501df93eaf97578d424725", "fetch_kib": 8883.94,
+                  "write_kib": 259427.0, "fetch_scale": 2.0, "write_scale": 1.0}
 
 
 def recorded_traffic():
