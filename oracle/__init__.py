@@ -101,8 +101,6 @@ def _load():
     lib.oracle_bridge_uniform.restype = d
     lib.oracle_stream_word.argtypes = [P(_Problem), i32, i64, i64]
     lib.oracle_stream_word.restype = u32
-    lib.oracle_bridge_word.argtypes = [P(_Problem), i32, i64, i64]
-    lib.oracle_bridge_word.restype = u32
     lib.oracle_monitor_gradient.argtypes = [i32, i32, i32, i32, pd, pd, pd]
     lib.oracle_interface_nodes.argtypes = [P(_Problem), pi32, pi32]
     lib.oracle_interface_nodes.restype = i32
@@ -160,12 +158,6 @@ def stream_word(prob: Problem, node: int, path: int, q: int) -> int:
     """Word q of the random stream of one path."""
     pc = prob.c()
     return int(_load().oracle_stream_word(ctypes.byref(pc), node, path, q))
-
-
-def bridge_word(prob: Problem, node: int, path: int, q: int) -> int:
-    """Word q of the bridge stream of one path."""
-    pc = prob.c()
-    return int(_load().oracle_bridge_word(ctypes.byref(pc), node, path, q))
 
 
 def bridge_uniform(prob: Problem, node: int, path: int, k: int) -> float:

@@ -49,15 +49,11 @@
  *   R14 unbiased variance from shifted sums.
  *
  * Stream layout (R13).  Path p of interface node `node` (its rank in the
- * row-major interface enumeration), instance id I and mesh step S owns two
- * word sequences, with key (seed & 0xffffffff, seed >> 32): the normal
- * stream, word q = word (q mod 4) of the Philox block with counter
- * (q div 4, p, node, I<<16 | S&0xffff), and the bridge stream, the same
- * with counter word 0 = 2^31 | (q div 4) (K <= 2^28 keeps the two counter
- * ranges apart).  Substep k uses words 2k and 2k+1 of the normal stream
- * (Box-Muller -> the two normals) and word k of the bridge stream (the
- * bridge uniform), so a bridge block is needed only where a bridge test is
- * made.
+ * row-major interface enumeration), instance id I and mesh step S owns the
+ * word sequence w_0, w_1, ... where w_q is word (q mod 4) of the Philox
+ * block with counter (q div 4, p, node, I<<16 | S&0xffff) and key
+ * (seed & 0xffffffff, seed >> 32).  Substep k uses w_{3k}, w_{3k+1}
+ * (Box-Muller -> the two normals) and w_{3k+2} (the bridge uniform).
  */
 #include <math.h>
 #include <pthread.h>
@@ -128,10 +124,11 @@ void oracle_box_muller(uint32_t r0, uint32_t r1, double *n1, double *n2)
     *n2 = radius * sin(two_pi * u1);
 }
 
-static uint32_t stream_word(const oracle_problem *P, int32_t node, int64_t path, int64_t q, uint32_t space)
+/* Word q of the stream of one path (stream layout R13). */
+uint32_t oracle_stream_word(const oracle_problem *P, int32_t node, int64_t path, int64_t q)
 {
     uint32_t ctr[4], key[2], r[4];
-    ctr[0] = space | (uint32_t)(q / 4);
+    ctr[0] = (uint32_t)(q / 4);
     ctr[1] = (uint32_t)path;
     ctr[2] = (uint32_t)node;
     ctr[3] = (P->instance_id << 16) | (P->mesh_step & 0xFFFFu);
@@ -141,31 +138,19 @@ static uint32_t stream_word(const oracle_problem *P, int32_t node, int64_t path,
     return r[q % 4];
 }
 
-/* Word q of the normal stream of one path (stream layout R13). */
-uint32_t oracle_stream_word(const oracle_problem *P, int32_t node, int64_t path, int64_t q)
-{
-    return stream_word(P, node, path, q, 0u);
-}
-
-/* Word q of the bridge stream of one path (stream layout R13). */
-uint32_t oracle_bridge_word(const oracle_problem *P, int32_t node, int64_t path, int64_t q)
-{
-    return stream_word(P, node, path, q, 0x80000000u);
-}
-
 /* The two standard normals that drive substep k of path `path` at `node`. */
 void oracle_normals(const oracle_problem *P, int32_t node, int64_t path, int32_t k,
                     double *n1, double *n2)
 {
-    uint32_t a = oracle_stream_word(P, node, path, 2 * (int64_t)k);
-    uint32_t b = oracle_stream_word(P, node, path, 2 * (int64_t)k + 1);
+    uint32_t a = oracle_stream_word(P, node, path, 3 * (int64_t)k);
+    uint32_t b = oracle_stream_word(P, node, path, 3 * (int64_t)k + 1);
     oracle_box_muller(a, b, n1, n2);
 }
 
 /* The uniform that drives the bridge test of substep k. */
 double oracle_bridge_uniform(const oracle_problem *P, int32_t node, int64_t path, int32_t k)
 {
-    return oracle_uniform(oracle_bridge_word(P, node, path, k));
+    return oracle_uniform(oracle_stream_word(P, node, path, 3 * (int64_t)k + 2));
 }
 
 /* ------------------------------------------------------------------------ */

@@ -87,26 +87,21 @@ def test_box_muller_identities(oracle_lib):
 
 
 def test_stream_layout(oracle_lib):
-    """Normal-stream word q of a path is word q mod 4 of the Philox block
-    with counter (q div 4, path, node, I<<16 | S); bridge-stream word q the
-    same with counter word 0 = 2^31 | q div 4; substep k takes normal words
-    2k, 2k+1 for Box-Muller and bridge word k for the bridge uniform."""
+    """Stream word q of a path is word q mod 4 of the Philox block with
+    counter (q div 4, path, node, I<<16 | S); substep k takes words 3k,
+    3k+1 for Box-Muller and word 3k+2 for the bridge uniform."""
     P = oracle_lib.Problem(n_xi=33, n_eta=33, sub_xi=2, sub_eta=1, seed=0x0123456789ABCDEF,
                            instance_id=9, mesh_step=4)
     key = [0x89ABCDEF, 0x01234567]
 
-    def word(node, path, q, space=0):
-        return oracle_lib.philox4x32_10([space | (q // 4), path, node, (9 << 16) | 4], key)[q % 4]
-    for (node, path, k) in [(0, 0, 0), (3, 17, 1), (3, 17, 2), (3, 17, 3), (3, 17, 4), (30, 9999, 498),
-                            (30, 9999, 499)]:
-        for q in (2 * k, 2 * k + 1):
+    def word(node, path, q):
+        return oracle_lib.philox4x32_10([q // 4, path, node, (9 << 16) | 4], key)[q % 4]
+    for (node, path, k) in [(0, 0, 0), (3, 17, 1), (3, 17, 2), (3, 17, 3), (30, 9999, 498), (30, 9999, 499)]:
+        for q in (3 * k, 3 * k + 1, 3 * k + 2):
             assert oracle_lib.stream_word(P, node, path, q) == word(node, path, q)
-        assert oracle_lib.bridge_word(P, node, path, k) == word(node, path, k, 0x80000000)
-        want = oracle_lib.box_muller(word(node, path, 2 * k), word(node, path, 2 * k + 1))
+        want = oracle_lib.box_muller(word(node, path, 3 * k), word(node, path, 3 * k + 1))
         assert oracle_lib.normals(P, node, path, k) == want
-        assert oracle_lib.bridge_uniform(P, node, path, k) == oracle_lib.uniform(word(node, path, k, 0x80000000))
-    # the two streams do not share a block below K = 2^28 substeps
-    assert oracle_lib.bridge_word(P, 3, 17, 0) != oracle_lib.stream_word(P, 3, 17, 0)
+        assert oracle_lib.bridge_uniform(P, node, path, k) == oracle_lib.uniform(word(node, path, 3 * k + 2))
     # mesh step uses only its low 16 bits; instance id sits above it
     P2 = oracle_lib.Problem(n_xi=33, n_eta=33, sub_xi=2, sub_eta=1, seed=0x0123456789ABCDEF,
                             instance_id=9, mesh_step=4 + 65536)
