@@ -12,10 +12,12 @@
 //
 // Two path kernels:
 //   * paths_fp32: the production kernel.  FP32 path arithmetic with the
-//     hardware transcendentals, per-cell bilinear coefficients read through
-//     the caches, a persistent grid of waves pulling (instance, node, chunk)
-//     items from a queue, lanes refilled with the chunk's next path when a
-//     path ends, FP64 per-lane sums reduced by wave shuffles.
+//     hardware transcendentals, per-cell records of the bilinear data read
+//     through the caches (or, for a launch of one instance, node tables of
+//     rho and dt rho_xi staged in LDS), a persistent grid of waves pulling
+//     (instance, node, chunk) items from a queue, lanes refilled with the
+//     chunk's next path when a path ends, path values evaluated when an
+//     item drains, FP64 per-lane sums reduced by wave shuffles.
 //   * paths_fp64: the plain baseline.  One thread per path, FP64 throughout
 //     (software transcendentals), one launch per instance, block reduction.
 //
