@@ -24,7 +24,7 @@
 // The random stream of path p of interface node r: word q is word (q mod 4)
 // of Philox4x32-10 (Salmon et al., SC'11) at counter
 // (q div 4, p, r, instance << 16 | mesh_step); substep k uses words 3k and
-// 3k+1 (Box-Muller) and 3k+2 (bridge uniform).  A wave advances its lanes
+// 3k+1 (Box-Muller) and 3k+2 (bridge uniform).  A lane advances its path
 // four substeps at a time, which is exactly three Philox blocks.
 
 #include <hip/hip_runtime.h>
@@ -362,35 +362,44 @@ __device__ __forceinline__ void path_value_f32(const InstView &I, const ConstF &
     if (C.per_eta) vy = fmaf((float)P.wy, C.Ly, vy);
 }
 
-// Up to four substeps of one path: the three Philox blocks of the group are
-// drawn at once (words 3s..3s+2 of substep s of the group).  Returns the exit
-// side or -1; `ended` is set when the path exited or reached K.
+// Advances one path by up to 64 substeps, in quarters of four: each quarter
+// draws its three Philox blocks at once (words 3s..3s+2 for substep s of the
+// quarter, block 3 (k / 4) onwards).  After each quarter the wave leaves the
+// loop when fewer than 56 of its 64 lanes still have a path in flight, so the
+// caller refills the ended lanes; a wave that stays full keeps stepping
+// without the refill bookkeeping.  The substeps and their random words do not
+// depend on where the loop is left.  Returns the exit side or -1; `ended` is
+// set when the path exited or reached K.
 template <bool TRACE, int TAB>
 __device__ __forceinline__ int group_f32(PathF &P, const ConstF &C, uint32_t path, uint32_t node, uint32_t ctr3,
                                          uint32_t key0, uint32_t key1, bool &ended, double *trace,
                                          const float *tab)
 {
-    const uint32_t blk = 3u * ((uint32_t)P.k >> 2);
-    const Words4 A = philox4x32_10(blk, path, node, ctr3, key0, key1);
-    const Words4 B = philox4x32_10(blk + 1u, path, node, ctr3, key0, key1);
-    const Words4 G = philox4x32_10(blk + 2u, path, node, ctr3, key0, key1);
-    const uint32_t w[12] = {A.w0, A.w1, A.w2, A.w3, B.w0, B.w1, B.w2, B.w3, G.w0, G.w1, G.w2, G.w3};
     int side = -1;
     ended = false;
+#pragma unroll 1
+    for (int q = 0; q < 16; ++q) {
+        if (q > 0 && (uint32_t)__popcll(__ballot(!ended && P.k < C.K)) < 56u) break;
+        const uint32_t blk = 3u * ((uint32_t)P.k >> 2);
+        const Words4 A = philox4x32_10(blk, path, node, ctr3, key0, key1);
+        const Words4 B = philox4x32_10(blk + 1u, path, node, ctr3, key0, key1);
+        const Words4 G = philox4x32_10(blk + 2u, path, node, ctr3, key0, key1);
+        const uint32_t w[12] = {A.w0, A.w1, A.w2, A.w3, B.w0, B.w1, B.w2, B.w3, G.w0, G.w1, G.w2, G.w3};
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        if (!ended && P.k < C.K) {
-            float t4[4];
-            side = substep_f32<TAB>(P, C, w[3 * s], w[3 * s + 1], w[3 * s + 2], TRACE ? t4 : nullptr, tab);
-            if (TRACE) {
-                double *t = trace + 4 * (size_t)P.k;
-                t[0] = t4[0];
-                t[1] = t4[1];
-                t[2] = t4[2];
-                t[3] = t4[3];
+        for (int s = 0; s < 4; ++s) {
+            if (!ended && P.k < C.K) {
+                float t4[4];
+                side = substep_f32<TAB>(P, C, w[3 * s], w[3 * s + 1], w[3 * s + 2], TRACE ? t4 : nullptr, tab);
+                if (TRACE) {
+                    double *t = trace + 4 * (size_t)P.k;
+                    t[0] = t4[0];
+                    t[1] = t4[1];
+                    t[2] = t4[2];
+                    t[3] = t4[3];
+                }
+                P.k += 1;
+                ended = side >= 0;
             }
-            P.k += 1;
-            ended = side >= 0;
         }
     }
     ended = ended || P.k >= C.K;
@@ -547,8 +556,9 @@ __device__ __forceinline__ void finish_item(const float *buf, uint32_t cap, uint
 // Persistent batched kernel.  Each wave keeps up to two work items in
 // flight: the one whose paths it is handing out and the one whose last
 // paths are finishing, so lanes never wait for an item to drain.  A lane
-// whose path ended takes the next path at a four-substep boundary; its end
-// state goes to the item's LDS slot at the path's index, and a drained item
+// whose path ended takes the next path when the wave leaves its stepping
+// loop (at a four-substep boundary, once fewer than 56 lanes are busy); its end
+// state goes to the item's end-state slot at the path's index, and a drained item
 // is evaluated (bicubic or boundary value) and reduced by all lanes in a
 // fixed order, so the sums do not depend on which lane ran which path, and
 // the wave does not run the value code whenever one lane's path ends.
@@ -683,7 +693,7 @@ __global__ __launch_bounds__(BLOCK) void paths_fp32(const InstView *__restrict__
             if (next >= n_items && act0 == 0u && act1 == 0u) break;
             continue;   // both slots drained: the next item starts at the top
         }
-        // advance every path by one group of four substeps
+        // advance every path until the wave has lanes to refill
         bool ended = false;
         if (has) {
             const int side = group_f32<false, TAB>(P, C, path, node, ctr3, key0, key1, ended, nullptr, tab);
