@@ -4,6 +4,11 @@
 // full-rate filler operation (add / xor), over a grid that fills every CU
 // with several waves per SIMD; the time per chain step, relative to a plain
 // FP32 FMA chain, gives the cost of the class in full-rate issue slots.
+// Two more kernels test whether a transcendental overlaps ordinary VALU work:
+// eight chains of a bare exp2 (the negation is a source modifier), and the
+// same eight chains interleaved with eight independent FMA chains.  If the
+// mixed kernel costs the sum of the two, nothing overlaps; if it costs their
+// maximum, the transcendental runs beside the FMAs.
 // Prints one JSON object on stdout.
 #include <hip/hip_runtime.h>
 
@@ -19,7 +24,7 @@
         }                                                                                \
     } while (0)
 
-enum Op { FMA, MAD64, MULHI, XOR, LOG2, SQRT, SIN, EXP2, RCP, PHILOX };
+enum Op { FMA, MAD64, MULHI, XOR, LOG2, SQRT, SIN, EXP2, RCP, PHILOX, EXPN, MIX };
 
 __device__ __forceinline__ float stepf(int op, float x)
 {
@@ -30,6 +35,7 @@ __device__ __forceinline__ float stepf(int op, float x)
     case SIN: return __builtin_amdgcn_sinf(x) + 0.5f;
     case EXP2: return __builtin_amdgcn_exp2f(-x) + 0.5f;
     case RCP: return __builtin_amdgcn_rcpf(x) + 1.0f;
+    case EXPN: return __builtin_amdgcn_exp2f(-x);
     default: return x;
     }
 }
@@ -98,6 +104,23 @@ __global__ __launch_bounds__(256) void probe(float *outf, uint32_t *outu, int it
     float x[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) x[k] = 1.0f + 0.001f * (float)((t + k) & 255);
+    if (OP == MIX) {   // eight exp2 chains beside eight FMA chains
+        float y[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) y[k] = 0.5f + 0.001f * (float)((t + 3 * k) & 255);
+        for (int i = 0; i < iters; ++i) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                x[k] = stepf(EXPN, x[k]);
+                y[k] = stepf(FMA, y[k]);
+            }
+        }
+        float s = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s += x[k] + y[k];
+        outf[t] = s;
+        return;
+    }
     for (int i = 0; i < iters; ++i) {
 #pragma unroll
         for (int k = 0; k < 8; ++k) x[k] = stepf(OP, x[k]);
@@ -153,6 +176,8 @@ int main()
         {"exp_f32+add", time_op<EXP2>(grid, iters, df, du), 1.0},
         {"rcp_f32+add", time_op<RCP>(grid, iters, df, du), 1.0},
         {"philox4x32_10_block", time_op<PHILOX>(grid, iters, df, du), 2.0 / 8.0},
+        {"exp_f32_bare", time_op<EXPN>(grid, iters, df, du), 1.0},
+        {"exp_f32_bare+independent_fma", time_op<MIX>(grid, iters, df, du), 1.0},
     };
     std::printf("{\"device\": \"%s\", \"cus\": %d, \"clock_mhz\": %d, \"fma_lane_slots_per_s\": %.6e, "
                 "\"effective_clock_ghz\": %.4f, \"slots\": {",
