@@ -137,7 +137,7 @@ def config1(n_paths: int = 10_000) -> Instance:
     ux, uy = gaussian_bump_grad(x, y, 0.5, 0.5, 0.01)
     rho = arc_length_monitor(ux, uy, 10.0)
     b = boundary_from_mesh(x, y)
-    return Instance("cfg1_bump33_2x1", n, n, 2, 1, 0, 0, 1.0, 1.0, 0.05, 500, n_paths,
+    return Instance("bump33_2x1", n, n, 2, 1, 0, 0, 1.0, 1.0, 0.05, 500, n_paths,
                     rho, x, y, b, b.copy())
 
 
@@ -158,7 +158,7 @@ def config2(n_paths: int = 100_000, t: float = 0.0, mesh=None, mesh_step: int = 
     ux, uy = gaussian_bump_grad(x, y, cx, cy, 0.005)
     rho = arc_length_monitor(ux, uy, 10.0)
     b = boundary_from_mesh(x, y)
-    return Instance("cfg2_rotbump129_4x4", n, n, 4, 4, 0, 0, 1.0, 1.0, 0.01, 500, n_paths,
+    return Instance("rotbump129_4x4", n, n, 4, 4, 0, 0, 1.0, 1.0, 0.01, 500, n_paths,
                     rho, x, y, b, b.copy(), mesh_step=mesh_step, meta={"t": t})
 
 
@@ -171,7 +171,7 @@ def config3(n_paths: int = 100_000) -> Instance:
     ux, uy = tanh_front_grad(x, y, 0.0, 0.01)
     rho = arc_length_monitor(ux, uy, 1.0)
     b = boundary_from_mesh(x, y)
-    return Instance("cfg3_front257_8x8_perx", n, n, 8, 8, 1, 0, 1.0, 1.0, 0.005, 500, n_paths,
+    return Instance("front257_8x8_perx", n, n, 8, 8, 1, 0, 1.0, 1.0, 0.005, 500, n_paths,
                     rho, x, y, b, b.copy())
 
 

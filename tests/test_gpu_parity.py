@@ -33,16 +33,16 @@ def ctx(M):
     M.mesh_sdd_ctx_destroy(c)
 
 
-def cfg1_oracle(oracle_lib):
-    if "cfg1" not in _cache:
+def bump33_oracle(oracle_lib):
+    if "bump33" not in _cache:
         inst = W.config1()
         say("oracle: bump33 2x1, 31 nodes, N=1e4, K=500")
-        _cache["cfg1"] = (inst, oracle_solve(oracle_lib, inst))
-    return _cache["cfg1"]
+        _cache["bump33"] = (inst, oracle_solve(oracle_lib, inst))
+    return _cache["bump33"]
 
 
 def test_fp64_plain_matches_oracle_bump33(M, ctx, oracle_lib):
-    inst, ora = cfg1_oracle(oracle_lib)
+    inst, ora = bump33_oracle(oracle_lib)
     say("gpu fp64: bump33 2x1 full size")
     g = gpu_solve(M, ctx, inst, M.FP64)
     assert g["paths_per_node"] == 10_000
@@ -54,7 +54,7 @@ def test_fp64_plain_matches_oracle_bump33(M, ctx, oracle_lib):
 
 
 def test_fp32_batched_matches_oracle_bump33(M, ctx, oracle_lib):
-    inst, ora = cfg1_oracle(oracle_lib)
+    inst, ora = bump33_oracle(oracle_lib)
     say("gpu fp32: bump33 2x1 full size")
     g = gpu_solve(M, ctx, inst, M.FP32)
     s = compare(g, ora, label="fp32 bump33")
