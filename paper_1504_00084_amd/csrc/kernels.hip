@@ -362,14 +362,17 @@ __device__ __forceinline__ void path_value_f32(const InstView &I, const ConstF &
     if (C.per_eta) vy = fmaf((float)P.wy, C.Ly, vy);
 }
 
-// Advances one path by up to 64 substeps, in quarters of four: each quarter
-// draws its three Philox blocks at once (words 3s..3s+2 for substep s of the
-// quarter, block 3 (k / 4) onwards).  After each quarter the wave leaves the
-// loop when fewer than 56 of its 64 lanes still have a path in flight, so the
-// caller refills the ended lanes; a wave that stays full keeps stepping
-// without the refill bookkeeping.  The substeps and their random words do not
-// depend on where the loop is left.  Returns the exit side or -1; `ended` is
-// set when the path exited or reached K.
+// Advances one path by quarters of four substeps: each quarter draws its
+// three Philox blocks at once (words 3s..3s+2 for substep s of the quarter,
+// block 3 (k / 4) onwards).  The LDS-table kernels (TAB > 0, VALU-bound) run
+// up to 16 quarters and leave after a quarter once fewer than 56 of the
+// wave's 64 lanes still have a path in flight, so the caller's refill and
+// item bookkeeping runs only when lanes are idle.  The multi-instance kernel
+// (TAB 0) is bound by its cell-record gathers, where idle lanes cost more
+// than the bookkeeping: it runs one quarter per call, so ended lanes are
+// refilled at once.  The substeps and their random words do not depend on
+// where the loop is left.  Returns the exit side or -1; `ended` is set when
+// the path exited or reached K.
 template <bool TRACE, int TAB>
 __device__ __forceinline__ int group_f32(PathF &P, const ConstF &C, uint32_t path, uint32_t node, uint32_t ctr3,
                                          uint32_t key0, uint32_t key1, bool &ended, double *trace,
@@ -377,8 +380,9 @@ __device__ __forceinline__ int group_f32(PathF &P, const ConstF &C, uint32_t pat
 {
     int side = -1;
     ended = false;
+    constexpr int QUARTERS = TAB > 0 ? 16 : 1;
 #pragma unroll 1
-    for (int q = 0; q < 16; ++q) {
+    for (int q = 0; q < QUARTERS; ++q) {
         if (q > 0 && (uint32_t)__popcll(__ballot(!ended && P.k < C.K)) < 56u) break;
         const uint32_t blk = 3u * ((uint32_t)P.k >> 2);
         const Words4 A = philox4x32_10(blk, path, node, ctr3, key0, key1);
@@ -557,7 +561,7 @@ __device__ __forceinline__ void finish_item(const float *buf, uint32_t cap, uint
 // flight: the one whose paths it is handing out and the one whose last
 // paths are finishing, so lanes never wait for an item to drain.  A lane
 // whose path ended takes the next path when the wave leaves its stepping
-// loop (at a four-substep boundary, once fewer than 56 lanes are busy); its end
+// loop (at a four-substep boundary; see group_f32); its end
 // state goes to the item's end-state slot at the path's index, and a drained item
 // is evaluated (bicubic or boundary value) and reduced by all lanes in a
 // fixed order, so the sums do not depend on which lane ran which path, and
