@@ -370,7 +370,7 @@ def serve_measure(requests: int, precision: str, sizes, max_paths: int, rate: fl
         M.mesh_sdd_set_launch(ctx, M.make_launch(b, w, c))
     log("serve: %d requests at %.3f req/s (%s), mean nominal work %.3e path-steps"
         % (len(stream), rate, precision, float(np.mean(work))))
-    done, e2e = [], []
+    done, e2e, rejected = [], [], []
     lock = threading.Lock()
     t0 = time.perf_counter()
 
@@ -382,12 +382,23 @@ def serve_measure(requests: int, precision: str, sizes, max_paths: int, rate: fl
         ts = time.perf_counter()
         _, it, _ = stream[k]
         h = M.mesh_sdd_create(ctx, M.desc_for(it, prec))
-        M.mesh_sdd_set_monitor(h, it.rho)
-        m = M.mesh_sdd_num_interface_nodes(h)
-        a, r = M.host_result(m)
-        tk = M.mesh_sdd_submit(h, M.make_step(it.x, it.y, it.bnd_t0, it.bnd_t1, paths_per_node=it.n_paths))
-        M.mesh_sdd_wait(ctx, tk, r, -1)
-        M.mesh_sdd_destroy(h)
+        try:
+            M.mesh_sdd_set_monitor(h, it.rho)
+            m = M.mesh_sdd_num_interface_nodes(h)
+            a, r = M.host_result(m)
+            try:
+                tk = M.mesh_sdd_submit(h, M.make_step(it.x, it.y, it.bnd_t0, it.bnd_t1, paths_per_node=it.n_paths))
+            except M.MeshSddError as e:
+                if e.code != M.E_BUDGET:
+                    raise
+                with lock:   # the request alone needs more device memory than the whole budget
+                    rejected.append(k)
+                    if not quiet:
+                        log("request %d rejected: %s" % (k, e))
+                return
+            M.mesh_sdd_wait(ctx, tk, r, -1)
+        finally:
+            M.mesh_sdd_destroy(h)
         with lock:
             done.append(int(r.executed_path_steps))
             e2e.append(time.perf_counter() - ts)
@@ -395,18 +406,32 @@ def serve_measure(requests: int, precision: str, sizes, max_paths: int, rate: fl
                 log("request %d done (%d of %d): %.3e path-steps, %.1f ms"
                     % (k, len(done), len(stream), float(r.executed_path_steps), 1e3 * e2e[-1]))
 
-    threads = [threading.Thread(target=client, args=(k,)) for k in range(len(stream))]
+    errors = []
+
+    def guarded(k):
+        try:
+            client(k)
+        except Exception as e:   # re-raised once every client has ended
+            with lock:
+                errors.append(e)
+
+    threads = [threading.Thread(target=guarded, args=(k,)) for k in range(len(stream))]
     for th in threads:
         th.start()
     for th in threads:
         th.join()
     wall = time.perf_counter() - t0
+    if errors:
+        M.mesh_sdd_ctx_destroy(ctx)
+        raise errors[0]
     st = M.mesh_sdd_ctx_stats(ctx)
     out = {"precision": precision, "requests": len(stream), "rate_req_s": rate, "completed": int(st.completed),
-           "failed": int(st.failed), "p50_ms": st.p50_ms, "p99_ms": st.p99_ms, "mean_ms": st.mean_ms,
-           "client_p50_ms": 1e3 * float(np.percentile(e2e, 50)), "client_p99_ms": 1e3 * float(np.percentile(e2e, 99)),
+           "failed": int(st.failed), "rejected_over_budget": len(rejected), "p50_ms": st.p50_ms, "p99_ms": st.p99_ms, "mean_ms": st.mean_ms,
+           "client_p50_ms": 1e3 * float(np.percentile(e2e, 50)) if e2e else None,
+           "client_p99_ms": 1e3 * float(np.percentile(e2e, 99)) if e2e else None,
            "throughput_path_steps_s": sum(done) / wall, "busy_ms": st.busy_ms, "wall_s": wall,
-           "ticks": int(st.ticks), "sizes": list(sizes), "max_paths": max_paths}
+           "ticks": int(st.ticks), "sizes": list(sizes), "max_paths": max_paths,
+           "budget_mb": budget_mb or None}
     M.mesh_sdd_ctx_destroy(ctx)
     return out
 
