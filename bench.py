@@ -224,7 +224,7 @@ def main():
 
     kern_s = sum(kernel_ms) / len(kernel_ms) / 1e3
     # node tables the library stages in LDS for this single-instance launch
-    tables = {0: None, 1: "rho", 2: "rho + dt rho_xi"}[lo.table_level]
+    tables = {0: None, 2: "rho + dt rho_xi", 3: "rho + dt rho_xi windows"}[lo.table_level]
     per_launch = executed / args.steps
     achieved = W_SLOTS_PER_STEP * per_launch / kern_s / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 3), "unit": "TOP/s",

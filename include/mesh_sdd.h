@@ -164,17 +164,23 @@ typedef struct {
     int32_t waves_per_simd;          /* persistent residency target (1..8)           */
     int32_t chunk_paths;             /* paths per work item (multiple of 64)         */
     int32_t monitor_table;           /* 0: automatic -- a launch that holds one
-                                        instance stages its FP32 node tables in LDS,
-                                        rho and dt rho_xi when both fit (8 B per
-                                        node), else rho (4 B per node), and reads
-                                        them there (1024-thread workgroups, item end
-                                        states in a context buffer; identical
-                                        results); 1: always from the cell records
-                                        in L2                                        */
-    int32_t table_level;             /* out (mesh_sdd_get_launch): node tables a
-                                        launch holding this instance alone stages in
-                                        LDS: 0 none, 1 rho, 2 rho and dt rho_xi.
-                                        Ignored by mesh_sdd_set_launch.              */
+                                        instance whose FP32 node tables of rho and
+                                        dt rho_xi fit the LDS (8 B per node) stages
+                                        them whole; any other launch (several
+                                        instances, or a larger grid) stages
+                                        140 x 140-node windows of them around
+                                        blocks of interface nodes, and paths that
+                                        leave a window read the cell records
+                                        (1024-thread workgroups, item end states in
+                                        a context buffer; identical results); 1:
+                                        always from the cell records in L2;
+                                        block / waves_per_simd apply to that kernel
+                                        only                                         */
+    int32_t table_level;             /* out (mesh_sdd_get_launch): how a launch
+                                        holding this instance alone reads the
+                                        tables: 0 cell records, 2 whole node tables
+                                        in LDS, 3 windows in LDS.  Ignored by
+                                        mesh_sdd_set_launch.                         */
 } mesh_sdd_launch;
 
 /* ---- context ------------------------------------------------------------ */

@@ -34,6 +34,15 @@
 #include "msdd_device.hpp"
 #include "msdd_kernels.hpp"
 
+// Multiply-add contraction only inside one expression (a * b + c written
+// as such becomes one FMA).  The compiler's default also fuses across
+// statements, where the choice depends on the surrounding code: the same
+// source line then rounds differently in different kernels (e.g. the cell
+// coordinate x * (n - 1) - cell, fused or not depending on whether the
+// rounded product is still in a register), and the kernel variants that
+// must give identical results would not.
+#pragma clang fp contract(on)
+
 namespace msdd {
 
 // Pointers into device global memory: loads through them compile to global
@@ -162,13 +171,21 @@ __device__ __forceinline__ float bilerp(float tx, float ty, float f00, float f10
     return fmaf(ty, v1 - v0, v0);
 }
 
+// Window of the node tables held in LDS by the windowed kernel: nodes
+// [i0, i0 + tw) x [j0, j0 + th), (rho, dt rho_xi) interleaved, row stride tw;
+// w1 = tw - 1 and h1 = th - 1 cells.
+struct Win {
+    int i0, j0, tw, w1, h1;
+};
+
 // TAB: where the corner values of rho and dt rho_xi come from.  0: the cell
 // record; 1: rho from the LDS node table, dt rho_xi from the record; 2: both
-// from the LDS node table (rho, dt rho_xi interleaved).  The values are the
-// same in every case, so the results are identical.
+// from the LDS node table (rho, dt rho_xi interleaved); 3: both from the LDS
+// window when the cell lies inside it, else from the cell record.  The
+// values are the same in every case, so the results are identical.
 template <int TAB>
 __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t wa, uint32_t wb, uint32_t wc,
-                                           float *trace4, const float *tab)
+                                           float *trace4, const float *tab, const Win &win)
 {
     // a3: Box-Muller on two stream words with the hardware log2 / sqrt /
     // sin / cos (sin and cos take revolutions); sqrt(2 dt) is folded into
@@ -194,6 +211,18 @@ __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t w
         const float2 c00 = t2[0], c10 = t2[1], c01 = t2[C.n_xi], c11 = t2[C.n_xi + 1];
         r00 = c00.x, r10 = c10.x, r01 = c01.x, r11 = c11.x;
         g00 = c00.y, g10 = c10.y, g01 = c01.y, g11 = c11.y;
+    } else if (TAB == 3) {
+        const int rx = cx - win.i0, ry = cy - win.j0;
+        if ((uint32_t)rx < (uint32_t)win.w1 && (uint32_t)ry < (uint32_t)win.h1) {
+            const float2 *t2 = (const float2 *)tab + (ry * win.tw + rx);
+            const float2 c00 = t2[0], c10 = t2[1], c01 = t2[win.tw], c11 = t2[win.tw + 1];
+            r00 = c00.x, r10 = c10.x, r01 = c01.x, r11 = c11.x;
+            g00 = c00.y, g10 = c10.y, g01 = c01.y, g11 = c11.y;
+        } else {
+            const f32x4 A = cell[0], B = cell[1];
+            r00 = A.x, r10 = A.y, r01 = A.z, r11 = A.w;
+            g00 = B.x, g10 = B.y, g01 = B.z, g11 = B.w;
+        }
     } else {
         if (TAB == 1) {
             const float *t1 = tab + (cy * C.n_xi + cx);
@@ -205,9 +234,10 @@ __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t w
         const f32x4 B = cell[1];
         g00 = B.x, g10 = B.y, g01 = B.z, g11 = B.w;
     }
-    // the two-field table kernel reads the coefficients from the compact
-    // plane (its only gather: better L1 reuse); the others from the record
-    const f32x4 G = TAB == 2 ? C.coef_y[ci] : cell[2];
+    // the two-field table and window kernels read the coefficients from the
+    // compact plane (their only gather: better L1 reuse); the others from
+    // the record
+    const f32x4 G = TAB >= 2 ? C.coef_y[ci] : cell[2];
     const float rho = bilerp(tx, ty, r00, r10, r01, r11);
     const float gx = bilerp(tx, ty, g00, g10, g01, g11);
     const float gy = fmaf(ty, fmaf(G.w, tx, G.z), fmaf(G.y, tx, G.x));
@@ -376,7 +406,7 @@ __device__ __forceinline__ void path_value_f32(const InstView &I, const ConstF &
 template <bool TRACE, int TAB>
 __device__ __forceinline__ int group_f32(PathF &P, const ConstF &C, uint32_t path, uint32_t node, uint32_t ctr3,
                                          uint32_t key0, uint32_t key1, bool &ended, double *trace,
-                                         const float *tab)
+                                         const float *tab, const Win &win)
 {
     int side = -1;
     ended = false;
@@ -393,7 +423,7 @@ __device__ __forceinline__ int group_f32(PathF &P, const ConstF &C, uint32_t pat
         for (int s = 0; s < 4; ++s) {
             if (!ended && P.k < C.K) {
                 float t4[4];
-                side = substep_f32<TAB>(P, C, w[3 * s], w[3 * s + 1], w[3 * s + 2], TRACE ? t4 : nullptr, tab);
+                side = substep_f32<TAB>(P, C, w[3 * s], w[3 * s + 1], w[3 * s + 2], TRACE ? t4 : nullptr, tab, win);
                 if (TRACE) {
                     double *t = trace + 4 * (size_t)P.k;
                     t[0] = t4[0];
@@ -557,7 +587,44 @@ __device__ __forceinline__ void finish_item(const float *buf, uint32_t cap, uint
     out->steps = st;
 }
 
-// Persistent batched kernel.  Each wave keeps up to two work items in
+// Item sources of the persistent kernels.  QueueSrc: the launch-wide queue,
+// one atomic per item, decoded through the launch's range table.
+struct QueueSrc {
+    uint32_t *head;
+    const GLOBAL WorkRange *rg;
+    uint32_t n_ranges;
+    __device__ __forceinline__ uint32_t pop(int lane) { return pop_item(head, lane); }
+    __device__ __forceinline__ ItemF decode(uint32_t it) const { return decode_item(rg, n_ranges, it); }
+};
+
+// JobSrc: the items q0 .. q0 + count of one range, handed out by a counter
+// in LDS that the workgroup's waves share.
+struct JobSrc {
+    uint32_t *next;   // LDS
+    WorkRange R;
+    uint32_t q0;
+    __device__ __forceinline__ uint32_t pop(int lane)
+    {
+        uint32_t v = 0;
+        if (lane == 0) v = atomicAdd(next, 1u);
+        return __builtin_amdgcn_readlane(v, 0);
+    }
+    __device__ __forceinline__ ItemF decode(uint32_t it) const
+    {
+        const uint32_t q = q0 + it;   // request-wide item, node-major
+        const uint32_t node = q / R.chunks;
+        const uint32_t c = q - node * R.chunks;
+        ItemF f;
+        f.inst = R.inst;
+        f.node = node;
+        f.p_begin = c * R.chunk_paths;
+        f.count = min(R.chunk_paths, R.N - f.p_begin);
+        f.partial = node * R.chunks + c;
+        return f;
+    }
+};
+
+// Wave loop of the persistent kernels.  Each wave keeps up to two work items in
 // flight: the one whose paths it is handing out and the one whose last
 // paths are finishing, so lanes never wait for an item to drain.  A lane
 // whose path ended takes the next path when the wave leaves its stepping
@@ -567,8 +634,137 @@ __device__ __forceinline__ void finish_item(const float *buf, uint32_t cap, uint
 // fixed order, so the sums do not depend on which lane ran which path, and
 // the wave does not run the value code whenever one lane's path ends.
 // Items of another instance start once both slots are drained (the
-// per-instance constants are wave-uniform).
-//
+// per-instance constants are wave-uniform).  The loop ends when the source
+// has no item left and both slots have drained.
+template <int TAB, int PER, class Src>
+__device__ __forceinline__ void item_loop(Src &src, uint32_t n_items, const InstView *__restrict__ insts, float *buf,
+                                          uint32_t cap, const float *tab, const Win &win, int lane)
+{
+    // wave-uniform state
+    uint32_t next = src.pop(lane);
+    uint32_t cur_inst = 0xFFFFFFFFu;
+    const InstView *Ip = insts;
+    ConstF C = load_const_f<PER>(insts[0]);
+    uint32_t key0 = 0, key1 = 0, ctr3 = 0;
+    uint32_t act0 = 0, act1 = 0, cnt0 = 0, cnt1 = 0, rem0 = 0, rem1 = 0;
+    uint32_t node0 = 0, node1 = 0, pb0 = 0, pb1 = 0, part0 = 0, part1 = 0;
+    float x00 = 0.f, y00 = 0.f, m00 = 0.f, x01 = 0.f, y01 = 0.f, m01 = 0.f;
+    double rx0 = 0.0, ry0 = 0.0, rx1 = 0.0, ry1 = 0.0;
+    uint32_t cur = 0, issued = 0;
+    bool issuing = false;
+
+    // lane state
+    bool has = false;
+    uint32_t which = 0, slot = 0, path = 0, node = 0;
+    PathF P{0.f, 0.f, 0.f, 0, 0, 0};
+    uint32_t ex0 = 0, ex1 = 0;
+    unsigned long long st0 = 0, st1 = 0;
+
+    for (;;) {
+        // start the next item in the free slot (another instance only when
+        // both slots are drained)
+        if (!issuing && next < n_items) {
+            const ItemF f = src.decode(next);
+            if (f.count == 0u) {   // never produced by the host; skipped so that no slot waits on it
+                next = src.pop(lane);
+                continue;
+            }
+            const uint32_t tgt = act0 ? (act1 ? 2u : 1u) : 0u;
+            const bool same = f.inst == cur_inst;
+            if (tgt < 2u && (same || (act0 == 0u && act1 == 0u))) {
+                if (!same) {
+                    cur_inst = f.inst;
+                    Ip = insts + f.inst;
+                    C = load_const_f<PER>(*Ip);
+                    key0 = Ip->key0;
+                    key1 = Ip->key1;
+                    ctr3 = Ip->ctr3;
+                }
+                const int i0 = gptr(Ip->node_i)[f.node], j0 = gptr(Ip->node_j)[f.node];
+                const uint32_t rk = gptr(Ip->node_r)[f.node];   // random-stream identity
+                const float x0 = (float)((double)i0 / (double)C.nx1);
+                const float y0 = (float)((double)j0 / (double)C.ny1);
+                const float m0 = side_distance(C, x0, y0);
+                const double rx = gptr(Ip->x64)[(uint32_t)(j0 * C.n_xi + i0)];
+                const double ry = gptr(Ip->y64)[(uint32_t)(j0 * C.n_xi + i0)];
+                if (tgt == 0u) {
+                    act0 = 1u; cnt0 = f.count; rem0 = f.count; node0 = rk; pb0 = f.p_begin;
+                    part0 = f.partial; x00 = x0; y00 = y0; m00 = m0; rx0 = rx; ry0 = ry;
+                } else {
+                    act1 = 1u; cnt1 = f.count; rem1 = f.count; node1 = rk; pb1 = f.p_begin;
+                    part1 = f.partial; x01 = x0; y01 = y0; m01 = m0; rx1 = rx; ry1 = ry;
+                }
+                cur = tgt;
+                issued = 0;
+                issuing = f.count > 0;
+                next = src.pop(lane);
+            }
+        }
+        // refill lanes without a path from the item being handed out, in lane order
+        if (issuing) {
+            const uint32_t count = cur ? cnt1 : cnt0;
+            const uint64_t need = __ballot(!has);
+            const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(need >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
+            if (!has && issued + below < count) {
+                has = true;
+                which = cur;
+                slot = issued + below;
+                path = (cur ? pb1 : pb0) + slot;
+                node = cur ? node1 : node0;
+                P.x = cur ? x01 : x00;
+                P.y = cur ? y01 : y00;
+                P.m = cur ? m01 : m00;
+                P.wx = 0;
+                P.wy = 0;
+                P.k = 0;
+            }
+            issued = min(count, issued + (uint32_t)__popcll(need));
+            issuing = issued < count;
+        }
+        if (__ballot(has) == 0) {
+            if (issuing) continue;
+            if (next >= n_items && act0 == 0u && act1 == 0u) break;
+            continue;   // both slots drained: the next item starts at the top
+        }
+        // advance every path until the wave has lanes to refill
+        bool ended = false;
+        if (has) {
+            const int side = group_f32<false, TAB>(P, C, path, node, ctr3, key0, key1, ended, nullptr, tab, win);
+            if (ended) {
+                store_end(buf + (size_t)which * 3u * cap, cap, slot, *Ip, C, P, side);
+                const uint32_t e = side >= 0 ? 1u : 0u;
+                if (which) {
+                    ex1 += e;
+                    st1 += (unsigned long long)P.k;
+                } else {
+                    ex0 += e;
+                    st0 += (unsigned long long)P.k;
+                }
+                has = false;
+            }
+        }
+        const uint64_t end_mask = __ballot(ended);
+        const uint64_t in1 = __ballot(which != 0u);
+        rem0 -= (uint32_t)__popcll(end_mask & ~in1);
+        rem1 -= (uint32_t)__popcll(end_mask & in1);
+        // reduce and write the items whose paths have all ended
+        if (act0 && rem0 == 0u && !(issuing && cur == 0u)) {
+            finish_item(buf, cap, cnt0, lane, ex0, st0, *Ip, C, rx0, ry0, gptr_rw(Ip->partials) + part0);
+            ex0 = 0;
+            st0 = 0;
+            act0 = 0u;
+        }
+        if (act1 && rem1 == 0u && !(issuing && cur == 1u)) {
+            finish_item(buf + 3u * cap, cap, cnt1, lane, ex1, st1, *Ip, C, rx1, ry1, gptr_rw(Ip->partials) + part1);
+            ex1 = 0;
+            st1 = 0;
+            act1 = 0u;
+        }
+    }
+}
+
+// Queue-driven persistent kernel (one launch-wide queue of items).
 // TAB > 0: the launch holds one instance (the host guarantees it), whose
 // FP32 node table -- rho (TAB 1) or rho and dt rho_xi interleaved (TAB 2) --
 // the workgroup copies into LDS; the bilinear interpolation then reads those
@@ -608,129 +804,66 @@ __global__ __launch_bounds__(BLOCK) void paths_fp32(const InstView *__restrict__
         }
         __syncthreads();
     }
-    const GLOBAL WorkRange *rg = gptr(ranges);
 
-    // wave-uniform state
-    uint32_t next = pop_item(head, lane);
-    uint32_t cur_inst = 0xFFFFFFFFu;
-    const InstView *Ip = insts;
-    ConstF C = load_const_f<PER>(insts[0]);
-    uint32_t key0 = 0, key1 = 0, ctr3 = 0;
-    uint32_t act0 = 0, act1 = 0, cnt0 = 0, cnt1 = 0, rem0 = 0, rem1 = 0;
-    uint32_t node0 = 0, node1 = 0, pb0 = 0, pb1 = 0, part0 = 0, part1 = 0;
-    float x00 = 0.f, y00 = 0.f, m00 = 0.f, x01 = 0.f, y01 = 0.f, m01 = 0.f;
-    double rx0 = 0.0, ry0 = 0.0, rx1 = 0.0, ry1 = 0.0;
-    uint32_t cur = 0, issued = 0;
-    bool issuing = false;
+    QueueSrc src{head, gptr(ranges), n_ranges};
+    const Win none{0, 0, 0, 0, 0};
+    item_loop<TAB, PER>(src, n_items, insts, buf, cap, tab, none, lane);
+}
 
-    // lane state
-    bool has = false;
-    uint32_t which = 0, slot = 0, path = 0, node = 0;
-    PathF P{0.f, 0.f, 0.f, 0, 0, 0};
-    uint32_t ex0 = 0, ex1 = 0;
-    unsigned long long st0 = 0, st1 = 0;
-
+// Windowed kernel for launches whose node tables do not fit the LDS whole:
+// several instances, or one large grid.  The host splits the launch into
+// jobs: the items of one range whose nodes lie in one block of the grid,
+// with a window of the node tables around that block (the block plus a
+// margin, clamped to the grid).  A workgroup (1024 threads, one per CU) pops
+// a job, copies the window of (rho, dt rho_xi) into LDS, and its waves run
+// the job's items with the wave loop above; a lane whose path has left the
+// window reads the corner values from the cell record instead (TAB 3 in
+// substep_f32), so the results are those of every other kernel.  The waves
+// keep their items' end states in `ends` as the table kernels do.
+// PER >= 0: every instance of the launch has that periodicity (compiled
+// in); a job of another kind is skipped, untouched.
+template <int PER>
+__global__ __launch_bounds__(kTableBlock) void paths_fp32_win(const InstView *__restrict__ insts,
+                                                            const WorkRange *__restrict__ ranges,
+                                                            const WinJob *__restrict__ jobs, uint32_t n_jobs,
+                                                            uint32_t *__restrict__ head, uint32_t cap,
+                                                            float *__restrict__ ends, uint32_t end_waves)
+{
+    constexpr int BLOCK = kTableBlock;
+    extern __shared__ float lds[];
+    __shared__ uint32_t s_job, s_next;
+    const int lane = threadIdx.x & 63;
+    const uint32_t wave = blockIdx.x * (uint32_t)(BLOCK / 64) + (threadIdx.x >> 6);
+    if ((blockIdx.x + 1u) * (uint32_t)(BLOCK / 64) > end_waves) return;   // whole block: no room
+    float *buf = ends + (size_t)wave * 6u * cap;   // [slot][w0 | w1 | w2][cap]
     for (;;) {
-        // start the next item in the free slot (another instance only when
-        // both slots are drained)
-        if (!issuing && next < n_items) {
-            const ItemF f = decode_item(rg, n_ranges, next);
-            if (f.count == 0u) {   // never produced by the host; skipped so that no slot waits on it
-                next = pop_item(head, lane);
-                continue;
-            }
-            const uint32_t tgt = act0 ? (act1 ? 2u : 1u) : 0u;
-            const bool same = f.inst == cur_inst;
-            if (tgt < 2u && (same || (act0 == 0u && act1 == 0u))) {
-                if (!same) {
-                    cur_inst = f.inst;
-                    Ip = insts + f.inst;
-                    C = load_const_f<PER>(*Ip);
-                    key0 = Ip->key0;
-                    key1 = Ip->key1;
-                    ctr3 = Ip->ctr3;
-                }
-                const int i0 = gptr(Ip->node_i)[f.node], j0 = gptr(Ip->node_j)[f.node];
-                const uint32_t rk = gptr(Ip->node_r)[f.node];   // random-stream identity
-                const float x0 = (float)((double)i0 / (double)C.nx1);
-                const float y0 = (float)((double)j0 / (double)C.ny1);
-                const float m0 = side_distance(C, x0, y0);
-                const double rx = gptr(Ip->x64)[(uint32_t)(j0 * C.n_xi + i0)];
-                const double ry = gptr(Ip->y64)[(uint32_t)(j0 * C.n_xi + i0)];
-                if (tgt == 0u) {
-                    act0 = 1u; cnt0 = f.count; rem0 = f.count; node0 = rk; pb0 = f.p_begin;
-                    part0 = f.partial; x00 = x0; y00 = y0; m00 = m0; rx0 = rx; ry0 = ry;
-                } else {
-                    act1 = 1u; cnt1 = f.count; rem1 = f.count; node1 = rk; pb1 = f.p_begin;
-                    part1 = f.partial; x01 = x0; y01 = y0; m01 = m0; rx1 = rx; ry1 = ry;
-                }
-                cur = tgt;
-                issued = 0;
-                issuing = f.count > 0;
-                next = pop_item(head, lane);
+        if (threadIdx.x == 0) {
+            s_job = atomicAdd(head, 1u);
+            s_next = 0u;
+        }
+        __syncthreads();
+        const uint32_t job = s_job;
+        if (job >= n_jobs) break;   // the same for the whole workgroup
+        const WinJob J = jobs[job];
+        const WorkRange R = ranges[J.range];
+        const InstView &I = insts[R.inst];
+        const bool ok = PER < 0 || (I.per_xi == (PER & 1) && I.per_eta == (PER >> 1));
+        {
+            const GLOBAL float *src = gptr(I.rho_f);
+            const GLOBAL float *srx = gptr(I.rhox_f);
+            float2 *t2 = (float2 *)lds;
+            const int n = J.tw * J.th;
+            for (int q = threadIdx.x; q < n; q += BLOCK) {
+                const int r = q / J.tw, c = q - r * J.tw;
+                const uint32_t g = (uint32_t)((J.j0 + r) * I.n_xi + J.i0 + c);
+                t2[q] = make_float2(src[g], srx[g]);
             }
         }
-        // refill lanes without a path from the item being handed out, in lane order
-        if (issuing) {
-            const uint32_t count = cur ? cnt1 : cnt0;
-            const uint64_t need = __ballot(!has);
-            const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(need >> 32),
-                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
-            if (!has && issued + below < count) {
-                has = true;
-                which = cur;
-                slot = issued + below;
-                path = (cur ? pb1 : pb0) + slot;
-                node = cur ? node1 : node0;
-                P.x = cur ? x01 : x00;
-                P.y = cur ? y01 : y00;
-                P.m = cur ? m01 : m00;
-                P.wx = 0;
-                P.wy = 0;
-                P.k = 0;
-            }
-            issued = min(count, issued + (uint32_t)__popcll(need));
-            issuing = issued < count;
-        }
-        if (__ballot(has) == 0) {
-            if (issuing) continue;
-            if (next >= n_items && act0 == 0u && act1 == 0u) break;
-            continue;   // both slots drained: the next item starts at the top
-        }
-        // advance every path until the wave has lanes to refill
-        bool ended = false;
-        if (has) {
-            const int side = group_f32<false, TAB>(P, C, path, node, ctr3, key0, key1, ended, nullptr, tab);
-            if (ended) {
-                store_end(buf + (size_t)which * 3u * cap, cap, slot, *Ip, C, P, side);
-                const uint32_t e = side >= 0 ? 1u : 0u;
-                if (which) {
-                    ex1 += e;
-                    st1 += (unsigned long long)P.k;
-                } else {
-                    ex0 += e;
-                    st0 += (unsigned long long)P.k;
-                }
-                has = false;
-            }
-        }
-        const uint64_t end_mask = __ballot(ended);
-        const uint64_t in1 = __ballot(which != 0u);
-        rem0 -= (uint32_t)__popcll(end_mask & ~in1);
-        rem1 -= (uint32_t)__popcll(end_mask & in1);
-        // reduce and write the items whose paths have all ended
-        if (act0 && rem0 == 0u && !(issuing && cur == 0u)) {
-            finish_item(buf, cap, cnt0, lane, ex0, st0, *Ip, C, rx0, ry0, gptr_rw(Ip->partials) + part0);
-            ex0 = 0;
-            st0 = 0;
-            act0 = 0u;
-        }
-        if (act1 && rem1 == 0u && !(issuing && cur == 1u)) {
-            finish_item(buf + 3u * cap, cap, cnt1, lane, ex1, st1, *Ip, C, rx1, ry1, gptr_rw(Ip->partials) + part1);
-            ex1 = 0;
-            st1 = 0;
-            act1 = 0u;
-        }
+        __syncthreads();
+        JobSrc js{&s_next, R, J.q0};
+        const Win win{J.i0, J.j0, J.tw, J.tw - 1, J.th - 1};
+        item_loop<3, PER>(js, ok ? J.count : 0u, insts, buf, cap, lds, win, lane);
+        __syncthreads();   // every wave is done with the window
     }
 }
 
@@ -1272,8 +1405,10 @@ __global__ void debug_paths_kernel(const InstView *__restrict__ inst, int fp64, 
     int side = -1;
     bool ended = false;
     while (!ended) {
-        side = tr ? group_f32<true, 0>(P, C, path, I.node_r[node], I.ctr3, I.key0, I.key1, ended, tr, nullptr)
-                  : group_f32<false, 0>(P, C, path, I.node_r[node], I.ctr3, I.key0, I.key1, ended, nullptr, nullptr);
+        const Win none{0, 0, 0, 0, 0};
+        side = tr ? group_f32<true, 0>(P, C, path, I.node_r[node], I.ctr3, I.key0, I.key1, ended, tr, nullptr, none)
+                  : group_f32<false, 0>(P, C, path, I.node_r[node], I.ctr3, I.key0, I.key1, ended, nullptr, nullptr,
+                                        none);
     }
     float fx, fy;
     path_value_f32(I, C, P, side, fx, fy);
@@ -1409,6 +1544,44 @@ int paths_fp32_table_blocks_per_cu(int level, int n_nodes)
                                                                              kTableBlock, lds)
                               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32<kTableBlock, 1, 0>,
                                                                              kTableBlock, lds);
+    return e == hipSuccess ? n : 0;
+}
+
+template <int PER>
+static void launch_win(int grid, size_t lds, hipStream_t s, const InstView *insts, const WorkRange *ranges,
+                       const WinJob *jobs, uint32_t n_jobs, uint32_t *head, uint32_t cap, float *ends,
+                       uint32_t end_waves)
+{
+    hipLaunchKernelGGL((paths_fp32_win<PER>), dim3(grid), dim3(kTableBlock), lds, s, insts, ranges, jobs, n_jobs, head,
+                       cap, ends, end_waves);
+}
+
+hipError_t launch_paths_fp32_window(const InstView *insts, const WorkRange *ranges, const WinJob *jobs,
+                                    uint32_t n_jobs, uint32_t *head, uint32_t cap, int periodic, int win_nodes,
+                                    int grid, float *ends, uint32_t end_waves, hipStream_t s)
+{
+    hipError_t e = launch_fill_u32(head, 0u, 1, s);
+    if (e != hipSuccess) return e;
+    if (n_jobs == 0) return hipSuccess;
+    if ((size_t)grid * (kTableBlock / 64) > end_waves || periodic < -1 || periodic > 3 || win_nodes < 4 ||
+        win_nodes > kWinNodes)
+        return hipErrorInvalidValue;
+    const size_t lds = (size_t)win_nodes * 2u * sizeof(float);
+    switch (periodic) {
+    case 0: launch_win<0>(grid, lds, s, insts, ranges, jobs, n_jobs, head, cap, ends, end_waves); break;
+    case 1: launch_win<1>(grid, lds, s, insts, ranges, jobs, n_jobs, head, cap, ends, end_waves); break;
+    case 2: launch_win<2>(grid, lds, s, insts, ranges, jobs, n_jobs, head, cap, ends, end_waves); break;
+    case 3: launch_win<3>(grid, lds, s, insts, ranges, jobs, n_jobs, head, cap, ends, end_waves); break;
+    default: launch_win<-1>(grid, lds, s, insts, ranges, jobs, n_jobs, head, cap, ends, end_waves); break;
+    }
+    return hipGetLastError();
+}
+
+int paths_fp32_window_blocks_per_cu(int win_nodes)
+{
+    int n = 0;
+    const size_t lds = (size_t)win_nodes * 2u * sizeof(float);
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32_win<-1>, kTableBlock, lds);
     return e == hipSuccess ? n : 0;
 }
 

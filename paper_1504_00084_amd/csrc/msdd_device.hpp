@@ -25,6 +25,18 @@ struct WorkRange {
     uint32_t N;            // paths per node
 };
 
+// One job of the windowed kernel: the request-wide items [q0, q0 + count)
+// of range `range`, whose nodes all lie in one block of the grid, and the
+// window of the node tables that the workgroup stages in LDS for them:
+// nodes [i0, i0 + tw) x [j0, j0 + th), inside the grid.
+struct WinJob {
+    uint32_t range;
+    uint32_t q0;
+    uint32_t count;
+    int32_t i0, j0, tw, th;
+    uint32_t pad;
+};
+
 // Shifted sums of one (node, chunk): S1 = sum(v - v_ref), S2 = sum((v - v_ref)^2).
 struct Partial {
     double s1x, s2x, s1y, s2y;

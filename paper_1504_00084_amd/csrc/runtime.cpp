@@ -233,20 +233,26 @@ mesh_sdd_launch default_launch()
     return l;
 }
 
-// Node tables that a launch holding one instance of n_nodes nodes stages in
-// LDS: 2 (rho and dt rho_xi) when they fit, else 1 (rho), else 0; *per_cu
+// How a launch reads the monitor tables.  2: it holds one instance of
+// n_nodes nodes (n_nodes > 0) whose node tables of rho and dt rho_xi fit the
+// LDS whole; 3: windows of those tables in LDS (several instances, or a grid
+// too large); 0: the cell records alone (monitor_table = 1).  *per_cu
 // receives the resident 1024-thread workgroups per CU.
 int table_level(int n_nodes, int monitor_table, int *per_cu)
 {
     *per_cu = 0;
     if (monitor_table != 0) return 0;
-    for (int lv = 2; lv >= 1; --lv) {
-        if (msdd::paths_fp32_table_lds_bytes(lv, n_nodes) > kLdsBytes) continue;
-        const int n = msdd::paths_fp32_table_blocks_per_cu(lv, n_nodes);
+    if (n_nodes > 0 && msdd::paths_fp32_table_lds_bytes(2, n_nodes) <= kLdsBytes) {
+        const int n = msdd::paths_fp32_table_blocks_per_cu(2, n_nodes);
         if (n >= 1) {
             *per_cu = n;
-            return lv;
+            return 2;
         }
+    }
+    const int n = msdd::paths_fp32_window_blocks_per_cu(msdd::kWinNodes);
+    if (n >= 1) {
+        *per_cu = n;
+        return 3;
     }
     return 0;
 }
@@ -313,6 +319,54 @@ std::shared_ptr<Request> make_request(mesh_sdd *inst, const mesh_sdd_step &s, in
     return r;
 }
 
+// Window of the windowed kernel along each axis: at most kWinNodes nodes
+// in all, the whole axis where it fits.
+void window_dims(int n_xi, int n_eta, int *wx, int *wy)
+{
+    const int side = 140;   // kWinNodes = 140 x 140
+    int y = std::min(n_eta, side);
+    const int x = std::min(n_xi, msdd::kWinNodes / y);
+    y = std::min(n_eta, msdd::kWinNodes / x);
+    *wx = x;
+    *wy = y;
+}
+
+constexpr int kWinMargin = 45;   // window nodes beyond a block on each side (where the axis does not fit)
+
+// Block length along an axis of n nodes whose window is w nodes long, and
+// the window origin of block b (centred on the block, clamped to the grid).
+int block_len(int n, int w) { return n <= w ? n : w - 2 * kWinMargin; }
+int window_origin(int b, int len, int n, int w) { return n <= w ? 0 : std::clamp(b * len - (w - len) / 2, 0, n - w); }
+
+// Sorts `ranks` (ascending) into block order -- blocks row-major, ranks
+// ascending inside a block -- and lists the runs of positions per block
+// with their windows.
+void order_by_blocks(const mesh_sdd &inst, std::vector<int32_t> &ranks, std::vector<BlockRun> &blocks)
+{
+    const int n_xi = inst.d.n_xi, n_eta = inst.d.n_eta;
+    int wx = 0, wy = 0;
+    window_dims(n_xi, n_eta, &wx, &wy);
+    const int lx = block_len(n_xi, wx), ly = block_len(n_eta, wy);
+    const int nbx = (n_xi + lx - 1) / lx;
+    auto block_of = [&](int32_t r) { return (inst.node_j[(size_t)r] / ly) * nbx + inst.node_i[(size_t)r] / lx; };
+    std::stable_sort(ranks.begin(), ranks.end(), [&](int32_t a, int32_t b) { return block_of(a) < block_of(b); });
+    blocks.clear();
+    for (size_t k = 0; k < ranks.size();) {
+        const int b = block_of(ranks[k]);
+        size_t e = k + 1;
+        while (e < ranks.size() && block_of(ranks[e]) == b) ++e;
+        BlockRun run;
+        run.pos_begin = (int32_t)k;
+        run.pos_end = (int32_t)e;
+        run.i0 = window_origin(b % nbx, lx, n_xi, wx);
+        run.j0 = window_origin(b / nbx, ly, n_eta, wy);
+        run.tw = wx;
+        run.th = wy;
+        blocks.push_back(run);
+        k = e;
+    }
+}
+
 // Node lists of `stride` (built on first use and kept by the instance).
 // Caller holds gpu_mu.
 int sample_set(mesh_sdd &inst, int stride, const SampleSet **out)
@@ -322,15 +376,18 @@ int sample_set(mesh_sdd &inst, int stride, const SampleSet **out)
         *out = it->second.get();
         return MESH_SDD_OK;
     }
-    const std::vector<int32_t> ranks = sampled_ranks(inst, stride);
+    std::vector<int32_t> ranks = sampled_ranks(inst, stride);
     const size_t Ms = ranks.size();
+    auto set = std::make_unique<SampleSet>();
+    order_by_blocks(inst, ranks, set->blocks);
+    set->pos_of_rank.assign((size_t)inst.M, -1);
+    for (size_t k = 0; k < Ms; ++k) set->pos_of_rank[(size_t)ranks[k]] = (int32_t)k;
     std::vector<int32_t> host(3 * Ms);
     for (size_t k = 0; k < Ms; ++k) {
         host[k] = inst.node_i[ranks[k]];
         host[Ms + k] = inst.node_j[ranks[k]];
         host[2 * Ms + k] = ranks[k];
     }
-    auto set = std::make_unique<SampleSet>();
     set->stride = stride;
     set->Ms = (int32_t)Ms;
     if (set->lists.alloc(host.size() * sizeof(int32_t)) != hipSuccess)
@@ -478,7 +535,7 @@ void release_request_buffers(Request &r)
 // inst fields index `views`).  Caller holds gpu_mu.  Returns the device time
 // in ms via *ms.
 int run_fp32_launch(mesh_sdd_ctx *ctx, const std::vector<InstView> &views, const std::vector<WorkRange> &ranges,
-                    const mesh_sdd_launch &l, double *ms)
+                    const std::vector<const SampleSet *> &sets, const mesh_sdd_launch &l, double *ms)
 {
     hipStream_t st = ctx->stream;
     size_t n_items = 0;
@@ -496,26 +553,62 @@ int run_fp32_launch(mesh_sdd_ctx *ctx, const std::vector<InstView> &views, const
         return fail(MESH_SDD_E_NOMEM, "device allocation for the work queue failed");
     HIP_TRY(hipMemcpyAsync(ctx->views.p, views.data(), views.size() * sizeof(InstView), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(ctx->ranges.p, ranges.data(), ranges.size() * sizeof(WorkRange), hipMemcpyHostToDevice, st));
-    // A launch that holds one instance stages that instance's node tables in
-    // LDS (1024-thread workgroups): rho and dt rho_xi when both fit, else rho
-    // alone; the waves then keep their items' end states in the context's
-    // end-state buffer.  Results are identical to the L2 variant's.
-    const int n_nodes = views.size() == 1 ? views[0].n_xi * views[0].n_eta : 0;
+    // A launch that holds one instance whose node tables of rho and dt rho_xi
+    // fit the LDS stages them whole (1024-thread workgroups); any other
+    // launch stages windows of them, job by job; the waves then keep their
+    // items' end states in the context's end-state buffer.  Results are
+    // identical to those of the cell-record kernel.
+    const int n_nodes = views.size() == 1 && ranges.size() == 1 ? views[0].n_xi * views[0].n_eta : 0;
     int per_cu = 0;
-    const int level = views.size() == 1 && ranges.size() == 1 ? table_level(n_nodes, l.monitor_table, &per_cu) : 0;
+    const int level = table_level(n_nodes, l.monitor_table, &per_cu);
     const int table_grid = ctx->cu_count * per_cu;
     const uint32_t end_waves = (uint32_t)table_grid * (uint32_t)(msdd::kTableBlock / 64);
     if (level > 0 && ctx->ends.reserve((size_t)end_waves * 6u * cap * sizeof(float)))
         return fail(MESH_SDD_E_NOMEM, "device allocation of the end-state buffer failed");
+    // windowed launch: one job per (range, grid block), split so that no job
+    // holds more than 1/32 of a workgroup's share of the items; largest first
+    std::vector<msdd::WinJob> jobs;
+    int win_nodes = 4, periodic = -2;
+    if (level == 3) {
+        const size_t per = (size_t)ctx->cu_count * (size_t)per_cu * 32u;
+        const size_t jmax = std::max<size_t>(64, (n_items + per - 1) / per);
+        for (size_t ri = 0; ri < ranges.size(); ++ri) {
+            const WorkRange &w = ranges[ri];
+            const InstView &v = views[w.inst];
+            const int p = v.per_xi + 2 * v.per_eta;
+            periodic = periodic == -2 || periodic == p ? p : -1;
+            const size_t lo = w.first, hi = (size_t)w.first + w.count;
+            for (const BlockRun &b : sets[w.inst]->blocks) {
+                const size_t qa = std::max(lo, (size_t)b.pos_begin * w.chunks);
+                const size_t qb = std::min(hi, (size_t)b.pos_end * w.chunks);
+                for (size_t q = qa; q < qb; q += jmax)
+                    jobs.push_back(msdd::WinJob{(uint32_t)ri, (uint32_t)q, (uint32_t)std::min(jmax, qb - q), b.i0,
+                                                b.j0, b.tw, b.th, 0u});
+                if (qa < qb) win_nodes = std::max(win_nodes, b.tw * b.th);
+            }
+        }
+        std::stable_sort(jobs.begin(), jobs.end(),
+                         [](const msdd::WinJob &a, const msdd::WinJob &b) { return a.count > b.count; });
+        if (ctx->jobs.reserve(std::max<size_t>(1, jobs.size()) * sizeof(msdd::WinJob)))
+            return fail(MESH_SDD_E_NOMEM, "device allocation of the job list failed");
+        if (!jobs.empty())
+            HIP_TRY(hipMemcpyAsync(ctx->jobs.p, jobs.data(), jobs.size() * sizeof(msdd::WinJob),
+                                   hipMemcpyHostToDevice, st));
+    }
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     HIP_TRY(hipEventRecord(e0, st));
-    hipError_t le = level > 0 ? msdd::launch_paths_fp32_table(ctx->views.as<InstView>(), ctx->ranges.as<WorkRange>(),
-                                                              (uint32_t)n_items, ctx->head.as<uint32_t>(), cap, level,
-                                                              views[0].per_xi + 2 * views[0].per_eta, n_nodes,
-                                                              table_grid, ctx->ends.as<float>(), end_waves, st)
-                              : msdd::launch_paths_fp32(ctx->views.as<InstView>(), ctx->ranges.as<WorkRange>(),
+    hipError_t le =
+        level == 3 ? msdd::launch_paths_fp32_window(ctx->views.as<InstView>(), ctx->ranges.as<WorkRange>(),
+                                                    ctx->jobs.as<msdd::WinJob>(), (uint32_t)jobs.size(),
+                                                    ctx->head.as<uint32_t>(), cap, periodic, win_nodes, table_grid,
+                                                    ctx->ends.as<float>(), end_waves, st)
+        : level > 0 ? msdd::launch_paths_fp32_table(ctx->views.as<InstView>(), ctx->ranges.as<WorkRange>(),
+                                                    (uint32_t)n_items, ctx->head.as<uint32_t>(), cap, level,
+                                                    views[0].per_xi + 2 * views[0].per_eta, n_nodes, table_grid,
+                                                    ctx->ends.as<float>(), end_waves, st)
+                    : msdd::launch_paths_fp32(ctx->views.as<InstView>(), ctx->ranges.as<WorkRange>(),
                                                       (uint32_t)ranges.size(), (uint32_t)n_items,
                                                       ctx->head.as<uint32_t>(), cap, grid_for(ctx, l, cap), l.block,
                                                       st);
@@ -643,6 +736,7 @@ int run_blocking(mesh_sdd_ctx *ctx, std::vector<std::shared_ptr<Request>> &reqs,
     status.assign(reqs.size(), MESH_SDD_OK);
     std::vector<InstView> views;
     std::vector<WorkRange> ranges;
+    std::vector<const SampleSet *> sets;
     std::vector<size_t> fp32_reqs;
     size_t base = 0;
     mesh_sdd_launch l = default_launch();
@@ -665,6 +759,7 @@ int run_blocking(mesh_sdd_ctx *ctx, std::vector<std::shared_ptr<Request>> &reqs,
         } else {
             const uint32_t slot = (uint32_t)views.size();
             views.push_back(r.v);
+            sets.push_back(r.ss);
             if (r.n_items) {
                 ranges.push_back(range_of(r, slot, base, 0, r.n_items));
                 base += r.n_items;
@@ -678,7 +773,7 @@ int run_blocking(mesh_sdd_ctx *ctx, std::vector<std::shared_ptr<Request>> &reqs,
     }
     if (!fp32_reqs.empty()) {
         double ms = 0.0;
-        int rc = run_fp32_launch(ctx, views, ranges, l, &ms);
+        int rc = run_fp32_launch(ctx, views, ranges, sets, l, &ms);
         for (size_t q : fp32_reqs) {
             Request &r = *reqs[q];
             int rq = rc;
@@ -774,6 +869,7 @@ void scheduler_loop(mesh_sdd_ctx *ctx)
         // tick's work for each, at least one item each
         std::vector<InstView> views;
         std::vector<WorkRange> ranges;
+        std::vector<const SampleSet *> sets;
         std::vector<std::pair<std::shared_ptr<Request>, size_t>> taken;
         mesh_sdd_launch l = default_launch();
         {
@@ -791,6 +887,7 @@ void scheduler_loop(mesh_sdd_ctx *ctx)
                 take = std::min(take, r->n_items - r->next_item);
                 const uint32_t slot = (uint32_t)views.size();
                 views.push_back(r->v);
+                sets.push_back(r->ss);
                 ranges.push_back(range_of(*r, slot, base, r->next_item, take));
                 base += take;
                 r->next_item += take;
@@ -810,7 +907,7 @@ void scheduler_loop(mesh_sdd_ctx *ctx)
         int rc;
         {
             std::lock_guard<std::mutex> g(ctx->gpu_mu);
-            rc = run_fp32_launch(ctx, views, ranges, l, &ms);
+            rc = run_fp32_launch(ctx, views, ranges, sets, l, &ms);
         }
         std::string err = rc == MESH_SDD_OK ? std::string() : g_last_error;
         std::vector<std::shared_ptr<Request>> complete;
@@ -916,6 +1013,8 @@ int mesh_sdd_ctx_destroy(mesh_sdd_ctx *ctx)
     ctx->head.release();
     ctx->views.release();
     ctx->ranges.release();
+    ctx->jobs.release();
+    ctx->ends.release();
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
     return MESH_SDD_OK;
@@ -1360,7 +1459,8 @@ int mesh_sdd_debug_paths(mesh_sdd *inst, const mesh_sdd_step *step, int32_t node
             if (trace) e = hipMemcpyAsync(dtr.p, trace, trace_n * 8, hipMemcpyHostToDevice, s);
             if (e == hipSuccess)
                 e = msdd::launch_debug_paths(r->view.as<InstView>(), inst->d.precision == MESH_SDD_FP64,
-                                             (uint32_t)node_rank, (uint32_t)p_begin, count, dvx.as<double>(),
+                                             (uint32_t)r->ss->pos_of_rank[(size_t)node_rank], (uint32_t)p_begin,
+                                             count, dvx.as<double>(),
                                              dvy.as<double>(), dex.as<int32_t>(), dsd.as<int32_t>(),
                                              dst.as<int32_t>(), trace ? dtr.as<double>() : nullptr, s);
             if (e == hipSuccess) e = hipStreamSynchronize(s);

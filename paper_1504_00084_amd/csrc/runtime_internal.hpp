@@ -158,10 +158,25 @@ struct Request;
 // The interface nodes that run paths under one sampling stride (1: all of
 // them): device lists node_i[Ms], node_j[Ms], node_r[Ms] (int32, in that
 // order, contiguous) in rank order.
+// A run of consecutive positions of a node list whose nodes lie in one
+// block of the grid, and the window of node tables the windowed kernel
+// stages in LDS for them (nodes [i0, i0 + tw) x [j0, j0 + th)).
+struct BlockRun {
+    int32_t pos_begin, pos_end;
+    int32_t i0, j0, tw, th;
+};
+
+// The nodes that run paths for one interface stride.  They are stored in
+// block order (grid blocks of the windowed kernel, ranks ascending inside a
+// block), so that a request's items -- node-major over these positions --
+// visit the grid block by block; the rank of each position is its random
+// stream and result slot, so the order does not change any result.
 struct SampleSet {
     int stride = 1;
     int32_t Ms = 0;
     DevBuf lists;
+    std::vector<BlockRun> blocks;        // covers positions [0, Ms) in order
+    std::vector<int32_t> pos_of_rank;    // position of interface rank r, or -1 (not sampled)
     const int32_t *node_i() const { return lists.as<int32_t>(); }
     const int32_t *node_j() const { return lists.as<int32_t>() + Ms; }
     const uint32_t *node_r() const { return reinterpret_cast<const uint32_t *>(lists.as<int32_t>() + 2 * (size_t)Ms); }
@@ -237,6 +252,7 @@ struct mesh_sdd_ctx {
     DevPool pool;        // recycled request buffers (declared before users)
     std::mutex gpu_mu;   // serialises use of the stream and the launch scratch below
     DevBuf head, views, ranges;
+    DevBuf jobs;         // job list of windowed launches (grow-only)
     DevBuf ends;         // item end states of single-instance launches (grow-only)
 
     std::mutex mu;       // guards everything below

@@ -263,19 +263,24 @@ def test_target_se_sets_path_count(M, ctx):
 
 def test_lds_and_l2_monitor_give_identical_results(M, ctx):
     """A single-instance launch reads rho and dt rho_xi from an LDS copy of
-    the node tables (level 2, 8 B per node), or rho alone (level 1, grids
-    too large for both); with monitor_table = 1 it reads the same corner
-    values from the cell records in L2.  All must give bitwise equal
-    results."""
+    the node tables (level 2, 8 B per node), or, on grids too large for
+    that, from 140 x 140-node windows of them around blocks of interface
+    nodes, falling back to the cell records for paths outside the window
+    (level 3); with monitor_table = 1 it reads the same corner values from
+    the cell records in L2.  All must give bitwise equal results.  The 257^2
+    instance runs with tau = 0.05 (path spread sqrt(2 tau) = 0.32, against
+    window margins of 45 cells = 0.18), so most of its paths leave their
+    window."""
     rng = np.random.default_rng(9)
-    insts = [W.random_instance(rng, q, n_paths=4000, sizes=(n,)) for q, n in enumerate((33, 129, 161, 65))]
+    insts = [W.random_instance(rng, q, n_paths=4000, sizes=(n,)) for q, n in enumerate((33, 129, 161, 65, 257))]
     for q, it in enumerate(insts):
         it.K = 60 + 13 * q
         it.instance_id = 300 + q
+    insts[4].tau = 0.05
     H = Handles(M, ctx, insts, M.FP32)
     try:
         levels = [M.mesh_sdd_get_launch(h).table_level for h in H.h]
-        assert levels == [2, 2, 1, 2], levels
+        assert levels == [2, 2, 3, 2, 3], levels
         lds = solve_alone(M, H, insts)
         M.mesh_sdd_set_launch(ctx, M.make_launch(monitor_table=1))
         try:
