@@ -814,8 +814,8 @@ __global__ __launch_bounds__(BLOCK) void paths_fp32(const InstView *__restrict__
 // several instances, or one large grid.  The host splits the launch into
 // jobs: the items of one range whose nodes lie in one block of the grid,
 // with a window of the node tables around that block (the block plus a
-// margin, clamped to the grid).  A workgroup (1024 threads, one per CU) pops
-// a job, copies the window of (rho, dt rho_xi) into LDS, and its waves run
+// margin, clamped to the grid), in block order, cut into per-XCD queues
+// (JobQueues).  A workgroup (1024 threads, one per CU) pops a job, copies the window of (rho, dt rho_xi) into LDS, and its waves run
 // the job's items with the wave loop above; a lane whose path has left the
 // window reads the corner values from the cell record instead (TAB 3 in
 // substep_f32), so the results are those of every other kernel.  The waves
@@ -825,7 +825,7 @@ __global__ __launch_bounds__(BLOCK) void paths_fp32(const InstView *__restrict__
 template <int PER>
 __global__ __launch_bounds__(kTableBlock) void paths_fp32_win(const InstView *__restrict__ insts,
                                                             const WorkRange *__restrict__ ranges,
-                                                            const WinJob *__restrict__ jobs, uint32_t n_jobs,
+                                                            const WinJob *__restrict__ jobs, JobQueues qs,
                                                             uint32_t *__restrict__ head, uint32_t cap,
                                                             float *__restrict__ ends, uint32_t end_waves)
 {
@@ -836,9 +836,20 @@ __global__ __launch_bounds__(kTableBlock) void paths_fp32_win(const InstView *__
     const uint32_t wave = blockIdx.x * (uint32_t)(BLOCK / 64) + (threadIdx.x >> 6);
     if ((blockIdx.x + 1u) * (uint32_t)(BLOCK / 64) > end_waves) return;   // whole block: no room
     float *buf = ends + (size_t)wave * 6u * cap;   // [slot][w0 | w1 | w2][cap]
+    const uint32_t n_jobs = qs.b[kJobQueues];
     for (;;) {
         if (threadIdx.x == 0) {
-            s_job = atomicAdd(head, 1u);
+            // own queue first, then the others in turn; head[q] counts pops of queue q
+            uint32_t j = n_jobs;
+            for (int t = 0; t < kJobQueues; ++t) {
+                const int q = (int)((blockIdx.x + (uint32_t)t) % (uint32_t)kJobQueues);
+                const uint32_t k = qs.b[q] + atomicAdd(head + q, 1u);
+                if (k < qs.b[q + 1]) {
+                    j = k;
+                    break;
+                }
+            }
+            s_job = j;
             s_next = 0u;
         }
         __syncthreads();
@@ -1549,30 +1560,32 @@ int paths_fp32_table_blocks_per_cu(int level, int n_nodes)
 
 template <int PER>
 static void launch_win(int grid, size_t lds, hipStream_t s, const InstView *insts, const WorkRange *ranges,
-                       const WinJob *jobs, uint32_t n_jobs, uint32_t *head, uint32_t cap, float *ends,
+                       const WinJob *jobs, const JobQueues &qs, uint32_t *head, uint32_t cap, float *ends,
                        uint32_t end_waves)
 {
-    hipLaunchKernelGGL((paths_fp32_win<PER>), dim3(grid), dim3(kTableBlock), lds, s, insts, ranges, jobs, n_jobs, head,
+    hipLaunchKernelGGL((paths_fp32_win<PER>), dim3(grid), dim3(kTableBlock), lds, s, insts, ranges, jobs, qs, head,
                        cap, ends, end_waves);
 }
 
 hipError_t launch_paths_fp32_window(const InstView *insts, const WorkRange *ranges, const WinJob *jobs,
-                                    uint32_t n_jobs, uint32_t *head, uint32_t cap, int periodic, int win_nodes,
+                                    const JobQueues &qs, uint32_t *head, uint32_t cap, int periodic, int win_nodes,
                                     int grid, float *ends, uint32_t end_waves, hipStream_t s)
 {
-    hipError_t e = launch_fill_u32(head, 0u, 1, s);
+    hipError_t e = launch_fill_u32(head, 0u, kJobQueues, s);
     if (e != hipSuccess) return e;
-    if (n_jobs == 0) return hipSuccess;
+    if (qs.b[kJobQueues] == 0) return hipSuccess;
+    for (int q = 0; q < kJobQueues; ++q)
+        if (qs.b[q] > qs.b[q + 1]) return hipErrorInvalidValue;
     if ((size_t)grid * (kTableBlock / 64) > end_waves || periodic < -1 || periodic > 3 || win_nodes < 4 ||
         win_nodes > kWinNodes)
         return hipErrorInvalidValue;
     const size_t lds = (size_t)win_nodes * 2u * sizeof(float);
     switch (periodic) {
-    case 0: launch_win<0>(grid, lds, s, insts, ranges, jobs, n_jobs, head, cap, ends, end_waves); break;
-    case 1: launch_win<1>(grid, lds, s, insts, ranges, jobs, n_jobs, head, cap, ends, end_waves); break;
-    case 2: launch_win<2>(grid, lds, s, insts, ranges, jobs, n_jobs, head, cap, ends, end_waves); break;
-    case 3: launch_win<3>(grid, lds, s, insts, ranges, jobs, n_jobs, head, cap, ends, end_waves); break;
-    default: launch_win<-1>(grid, lds, s, insts, ranges, jobs, n_jobs, head, cap, ends, end_waves); break;
+    case 0: launch_win<0>(grid, lds, s, insts, ranges, jobs, qs, head, cap, ends, end_waves); break;
+    case 1: launch_win<1>(grid, lds, s, insts, ranges, jobs, qs, head, cap, ends, end_waves); break;
+    case 2: launch_win<2>(grid, lds, s, insts, ranges, jobs, qs, head, cap, ends, end_waves); break;
+    case 3: launch_win<3>(grid, lds, s, insts, ranges, jobs, qs, head, cap, ends, end_waves); break;
+    default: launch_win<-1>(grid, lds, s, insts, ranges, jobs, qs, head, cap, ends, end_waves); break;
     }
     return hipGetLastError();
 }

@@ -37,6 +37,16 @@ struct WinJob {
     uint32_t pad;
 };
 
+// The job list of a windowed launch cut into kJobQueues contiguous queues:
+// queue x holds jobs [b[x], b[x + 1]).  Workgroup w serves queue w mod
+// kJobQueues first -- workgroups are dealt round-robin to the 8 XCDs, so each
+// XCD's L2 caches the tables of one region of the job list -- and takes jobs
+// from the following queues once its own is empty.
+constexpr int kJobQueues = 8;
+struct JobQueues {
+    uint32_t b[kJobQueues + 1];
+};
+
 // Shifted sums of one (node, chunk): S1 = sum(v - v_ref), S2 = sum((v - v_ref)^2).
 struct Partial {
     double s1x, s2x, s1y, s2y;

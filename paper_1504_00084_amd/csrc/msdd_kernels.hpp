@@ -58,10 +58,11 @@ hipError_t launch_paths_fp32_table(const InstView *insts, const WorkRange *range
 int paths_fp32_table_blocks_per_cu(int level, int n_nodes);
 
 // The windowed form for launches whose tables do not fit the LDS whole (many
-// instances, or one large grid): `jobs` lists n_jobs jobs (items of one
-// range whose nodes lie in one grid block, and the node-table window around
-// that block); each 1024-thread workgroup pops jobs from `head` (zeroed
-// here), stages the job's window of (rho, dt rho_xi) in LDS (8 bytes per
+// instances, or one large grid): `jobs` lists qs.b[kJobQueues] jobs (items of
+// one range whose nodes lie in one grid block, and the node-table window
+// around that block), cut into kJobQueues queues; each 1024-thread workgroup
+// pops jobs from its queue and then the others (`head`: kJobQueues counters,
+// zeroed here), stages the job's window of (rho, dt rho_xi) in LDS (8 bytes per
 // window node, at most kWinNodes nodes) and runs its items; lanes outside the
 // window read the cell records.  `periodic` = per_xi + 2 per_eta shared by
 // every instance of the launch (compiled in), or -1 (read per instance).
@@ -69,7 +70,7 @@ int paths_fp32_table_blocks_per_cu(int level, int n_nodes);
 // launch_paths_fp32's.
 constexpr int kWinNodes = 19600;   // 140 x 140 nodes, 156800 bytes of LDS
 hipError_t launch_paths_fp32_window(const InstView *insts, const WorkRange *ranges, const WinJob *jobs,
-                                    uint32_t n_jobs, uint32_t *head, uint32_t cap, int periodic, int win_nodes,
+                                    const JobQueues &qs, uint32_t *head, uint32_t cap, int periodic, int win_nodes,
                                     int grid, float *ends, uint32_t end_waves, hipStream_t s);
 int paths_fp32_window_blocks_per_cu(int win_nodes);
 

@@ -566,8 +566,10 @@ int run_fp32_launch(mesh_sdd_ctx *ctx, const std::vector<InstView> &views, const
     if (level > 0 && ctx->ends.reserve((size_t)end_waves * 6u * cap * sizeof(float)))
         return fail(MESH_SDD_E_NOMEM, "device allocation of the end-state buffer failed");
     // windowed launch: one job per (range, grid block), split so that no job
-    // holds more than 1/32 of a workgroup's share of the items; largest first
+    // holds more than 1/32 of a workgroup's share of the items, in block
+    // order, cut into per-XCD queues of equal nominal work
     std::vector<msdd::WinJob> jobs;
+    msdd::JobQueues qs{};
     int win_nodes = 4, periodic = -2;
     if (level == 3) {
         const size_t per = (size_t)ctx->cu_count * (size_t)per_cu * 32u;
@@ -587,8 +589,16 @@ int run_fp32_launch(mesh_sdd_ctx *ctx, const std::vector<InstView> &views, const
                 if (qa < qb) win_nodes = std::max(win_nodes, b.tw * b.th);
             }
         }
-        std::stable_sort(jobs.begin(), jobs.end(),
-                         [](const msdd::WinJob &a, const msdd::WinJob &b) { return a.count > b.count; });
+        std::vector<double> cum(jobs.size() + 1, 0.0);
+        for (size_t k = 0; k < jobs.size(); ++k) {
+            const WorkRange &w = ranges[jobs[k].range];
+            cum[k + 1] = cum[k] + (double)jobs[k].count * w.chunk_paths * views[w.inst].K;
+        }
+        for (int q = 0, k = 0; q <= msdd::kJobQueues; ++q) {
+            const double goal = cum.back() * q / msdd::kJobQueues;
+            while (q == msdd::kJobQueues ? k < (int)jobs.size() : (k < (int)jobs.size() && cum[k] < goal)) ++k;
+            qs.b[q] = (uint32_t)k;
+        }
         if (ctx->jobs.reserve(std::max<size_t>(1, jobs.size()) * sizeof(msdd::WinJob)))
             return fail(MESH_SDD_E_NOMEM, "device allocation of the job list failed");
         if (!jobs.empty())
@@ -601,8 +611,8 @@ int run_fp32_launch(mesh_sdd_ctx *ctx, const std::vector<InstView> &views, const
     HIP_TRY(hipEventRecord(e0, st));
     hipError_t le =
         level == 3 ? msdd::launch_paths_fp32_window(ctx->views.as<InstView>(), ctx->ranges.as<WorkRange>(),
-                                                    ctx->jobs.as<msdd::WinJob>(), (uint32_t)jobs.size(),
-                                                    ctx->head.as<uint32_t>(), cap, periodic, win_nodes, table_grid,
+                                                    ctx->jobs.as<msdd::WinJob>(), qs, ctx->head.as<uint32_t>(),
+                                                    cap, periodic, win_nodes, table_grid,
                                                     ctx->ends.as<float>(), end_waves, st)
         : level > 0 ? msdd::launch_paths_fp32_table(ctx->views.as<InstView>(), ctx->ranges.as<WorkRange>(),
                                                     (uint32_t)n_items, ctx->head.as<uint32_t>(), cap, level,
