@@ -102,6 +102,8 @@ def parse():
     ap.add_argument("--variant-steps", type=int, default=20, help="mesh steps of the variants mode")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--batch-scale", type=float, default=1.0, help="scale the mix's path counts (batch mode)")
+    ap.add_argument("--batch-sizes", default="",
+                    help="comma-separated grid sizes: keep only the mix's instances of these sizes (batch mode)")
     ap.add_argument("--requests", type=int, default=40, help="requests in serve mode")
     ap.add_argument("--rate", type=float, default=0.0,
                     help="arrival rate in req/s for serve mode (0: 0.7 x the measured capacity)")
@@ -298,6 +300,9 @@ def run_batch(args):
 
     M.load()
     insts = W.config4(count=args.batch_count)
+    if args.batch_sizes:
+        keep = {int(v) for v in args.batch_sizes.split(",")}
+        insts = [it for it in insts if it.n_xi in keep]
     if args.batch_scale != 1.0:
         for it in insts:
             it.n_paths = max(64, int(it.n_paths * args.batch_scale) // 64 * 64)
@@ -328,7 +333,8 @@ def run_batch(args):
     line = {"metric": "batched mix path-steps/s (one persistent launch)", "value": executed / wall,
             "unit": "path-steps/s", "kernel_ms": kernel_ms, "wall_s": wall, "executed_path_steps": executed,
             "nominal_path_steps": nominal, "instances": len(insts), "interface_nodes": sum(ms), "max_se": se,
-            "path_scale": args.batch_scale, "dtype": "f32 (paths) / f64 (sums)", "data": "synthetic",
+            "path_scale": args.batch_scale, "sizes": sorted({it.n_xi for it in insts}),
+            "dtype": "f32 (paths) / f64 (sums)", "data": "synthetic",
             "roofline_frac": W_SLOTS_PER_STEP * executed / (kernel_ms / 1e3) / 1e12 / VALU_PEAK_TOPS}
     print(json.dumps(line), flush=True)
     for h in hs:
