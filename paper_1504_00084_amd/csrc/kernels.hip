@@ -206,6 +206,7 @@ __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t w
     const uint32_t ci = (uint32_t)(cy * C.nx1 + cx);
     const GLOBAL f32x4 *cell = C.cells + 3u * ci;
     float r00, r10, r01, r11, g00, g10, g01, g11;
+    f32x4 G;   // dt rho_eta coefficients
     if (TAB == 2) {
         const float2 *t2 = (const float2 *)tab + (cy * C.n_xi + cx);
         const float2 c00 = t2[0], c10 = t2[1], c01 = t2[C.n_xi], c11 = t2[C.n_xi + 1];
@@ -218,10 +219,14 @@ __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t w
             const float2 c00 = t2[0], c10 = t2[1], c01 = t2[win.tw], c11 = t2[win.tw + 1];
             r00 = c00.x, r10 = c10.x, r01 = c01.x, r11 = c11.x;
             g00 = c00.y, g10 = c10.y, g01 = c01.y, g11 = c11.y;
+            G = C.coef_y[ci];
         } else {
+            // outside the window: the whole record, whose lines one lane then
+            // shares for its three gathers (the same coefficients as the plane)
             const f32x4 A = cell[0], B = cell[1];
             r00 = A.x, r10 = A.y, r01 = A.z, r11 = A.w;
             g00 = B.x, g10 = B.y, g01 = B.z, g11 = B.w;
+            G = cell[2];
         }
     } else {
         if (TAB == 1) {
@@ -234,10 +239,10 @@ __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t w
         const f32x4 B = cell[1];
         g00 = B.x, g10 = B.y, g01 = B.z, g11 = B.w;
     }
-    // the two-field table and window kernels read the coefficients from the
-    // compact plane (their only gather: better L1 reuse); the others from
-    // the record
-    const f32x4 G = TAB >= 2 ? C.coef_y[ci] : cell[2];
+    // the two-field table kernel reads the coefficients from the compact
+    // plane (its only gather: better L1 reuse), the window kernel too inside
+    // its window; the others from the record
+    if (TAB != 3) G = TAB == 2 ? C.coef_y[ci] : cell[2];
     const float rho = bilerp(tx, ty, r00, r10, r01, r11);
     const float gx = bilerp(tx, ty, g00, g10, g01, g11);
     const float gy = fmaf(ty, fmaf(G.w, tx, G.z), fmaf(G.y, tx, G.x));
