@@ -77,6 +77,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--paths", type=int, default=100_000)
+    ap.add_argument("--workload", default="rotbump129", choices=["rotbump129", "front257"],
+                    help="step mode: the rotating bump 129^2 4x4 (the metric's workload), or the periodic "
+                         "tanh front 257^2 8x8 (windowed kernel)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 plain comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving burst of the step mode")
@@ -141,7 +144,7 @@ def main():
     M.load()
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream(device=dev)
-    inst = W.config2(n_paths=args.paths)
+    inst = W.config2(n_paths=args.paths) if args.workload == "rotbump129" else W.config3(n_paths=args.paths)
     log("workload %s: grid %dx%d, %dx%d subdomains, N=%d, K=%d, tau=%g"
         % (inst.name, inst.n_xi, inst.n_eta, inst.sub_xi, inst.sub_eta, inst.n_paths, inst.K, inst.tau))
 
@@ -230,9 +233,12 @@ def main():
     per_launch = executed / args.steps
     achieved = W_SLOTS_PER_STEP * per_launch / kern_s / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 3), "unit": "TOP/s",
-                "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": recorded_traffic(),
-                "kernel": ("paths_fp32 (LDS table: %s; 1024 threads x 1 workgroup per CU)" % tables) if tables
-                else "paths_fp32", "kernel_ms": round(kern_s * 1e3, 3),
+                "frac": round(achieved / VALU_PEAK_TOPS, 4),
+                "traffic": recorded_traffic() if args.workload == "rotbump129" else None,
+                "kernel": {0: "paths_fp32 (cell records)",
+                           2: "paths_fp32 (LDS table: rho + dt rho_xi; 1024 threads x 1 workgroup per CU)",
+                           3: "paths_fp32_win (LDS windows of rho + dt rho_xi; 1024 threads x 1 workgroup per CU)"}[
+                               lo.table_level], "kernel_ms": round(kern_s * 1e3, 3),
                 "path_steps_per_launch": per_launch, "slots_per_path_step": W_SLOTS_PER_STEP}
 
     # p50 / p99 of a short FP32 serving burst (0.7 x capacity) beside the throughput
