@@ -179,9 +179,8 @@ struct Win {
 };
 
 // TAB: where the corner values of rho and dt rho_xi come from.  0: the cell
-// record; 1: rho from the LDS node table, dt rho_xi from the record; 2: both
-// from the LDS node table (rho, dt rho_xi interleaved); 3: both from the LDS
-// window when the cell lies inside it, else from the cell record.  The
+// record; 2: the LDS node table (rho, dt rho_xi interleaved); 3: the LDS
+// window when the cell lies inside it, else the cell record.  The
 // values are the same in every case, so the results are identical.
 template <int TAB>
 __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t wa, uint32_t wb, uint32_t wc,
@@ -229,14 +228,8 @@ __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t w
             G = cell[2];
         }
     } else {
-        if (TAB == 1) {
-            const float *t1 = tab + (cy * C.n_xi + cx);
-            r00 = t1[0], r10 = t1[1], r01 = t1[C.n_xi], r11 = t1[C.n_xi + 1];
-        } else {
-            const f32x4 A = cell[0];
-            r00 = A.x, r10 = A.y, r01 = A.z, r11 = A.w;
-        }
-        const f32x4 B = cell[1];
+        const f32x4 A = cell[0], B = cell[1];
+        r00 = A.x, r10 = A.y, r01 = A.z, r11 = A.w;
         g00 = B.x, g10 = B.y, g01 = B.z, g11 = B.w;
     }
     // the two-field table kernel reads the coefficients from the compact
@@ -399,13 +392,13 @@ __device__ __forceinline__ void path_value_f32(const InstView &I, const ConstF &
 
 // Advances one path by quarters of four substeps: each quarter draws its
 // three Philox blocks at once (words 3s..3s+2 for substep s of the quarter,
-// block 3 (k / 4) onwards).  The LDS-table kernels (TAB > 0, VALU-bound) run
-// up to 16 quarters and leave after a quarter once fewer than 56 of the
+// block 3 (k / 4) onwards).  The LDS table and window kernels (TAB 2, 3)
+// run up to 16 quarters and leave after a quarter once fewer than 56 of the
 // wave's 64 lanes still have a path in flight, so the caller's refill and
-// item bookkeeping runs only when lanes are idle.  The multi-instance kernel
-// (TAB 0) is bound by its cell-record gathers, where idle lanes cost more
-// than the bookkeeping: it runs one quarter per call, so ended lanes are
-// refilled at once.  The substeps and their random words do not depend on
+// item bookkeeping runs only when lanes are idle (measured: faster than 1 or
+// 4 quarters for both).  The cell-record kernel (TAB 0) is bound by its
+// gathers, where idle lanes cost more than the bookkeeping: it runs one
+// quarter per call, so ended lanes are refilled at once.  The substeps and their random words do not depend on
 // where the loop is left.  Returns the exit side or -1; `ended` is set when
 // the path exited or reached K.
 template <bool TRACE, int TAB>
@@ -770,13 +763,12 @@ __device__ __forceinline__ void item_loop(Src &src, uint32_t n_items, const Inst
 }
 
 // Queue-driven persistent kernel (one launch-wide queue of items).
-// TAB > 0: the launch holds one instance (the host guarantees it), whose
-// FP32 node table -- rho (TAB 1) or rho and dt rho_xi interleaved (TAB 2) --
-// the workgroup copies into LDS; the bilinear interpolation then reads those
-// corner values there instead of from the cell record (the same values, so
-// the results are identical).  Each moved field takes one of the three L1
-// gathers of a substep off the texture path, which bounds this kernel
-// together with VALU issue.  The table fills the LDS, so the waves keep the
+// TAB 2: the launch holds one instance (the host guarantees it), whose FP32
+// node tables of rho and dt rho_xi the workgroup copies into LDS,
+// interleaved; the bilinear interpolation then reads those corner values
+// there instead of from the cell record (the same values, so the results are
+// identical), which takes two of the three L1 gathers of a substep off the
+// texture path.  The table fills the LDS, so the waves keep the
 // end states of their items in `ends` (global memory, 6 * cap words per
 // wave, room for `end_waves` waves; read back by the same wave only).
 // PER >= 0 (single-instance launches): the instance's periodic flags as
@@ -800,13 +792,9 @@ __global__ __launch_bounds__(BLOCK) void paths_fp32(const InstView *__restrict__
         tab = lds;
         const int n = insts[0].n_xi * insts[0].n_eta;
         const GLOBAL float *src = gptr(insts[0].rho_f);
-        if (TAB == 2) {
-            const GLOBAL float *srx = gptr(insts[0].rhox_f);
-            float2 *t2 = (float2 *)tab;
-            for (int q = threadIdx.x; q < n; q += BLOCK) t2[q] = make_float2(src[q], srx[q]);
-        } else {
-            for (int q = threadIdx.x; q < n; q += BLOCK) tab[q] = src[q];
-        }
+        const GLOBAL float *srx = gptr(insts[0].rhox_f);
+        float2 *t2 = (float2 *)tab;
+        for (int q = threadIdx.x; q < n; q += BLOCK) t2[q] = make_float2(src[q], srx[q]);
         __syncthreads();
     }
 
@@ -1535,17 +1523,13 @@ hipError_t launch_paths_fp32_table(const InstView *insts, const WorkRange *range
     hipError_t e = launch_fill_u32(head, 0u, 1, s);
     if (e != hipSuccess) return e;
     if (n_items == 0) return hipSuccess;
-    if ((size_t)grid * (kTableBlock / 64) > end_waves || level < 1 || level > 2 || periodic < 0 || periodic > 3)
+    if ((size_t)grid * (kTableBlock / 64) > end_waves || level != 2 || periodic < 0 || periodic > 3)
         return hipErrorInvalidValue;
     const size_t lds = paths_fp32_table_lds_bytes(level, n_nodes);
-    switch (level * 4 + periodic) {
-    case 4: launch_table<1, 0>(grid, lds, s, insts, ranges, n_items, head, cap, ends, end_waves); break;
-    case 5: launch_table<1, 1>(grid, lds, s, insts, ranges, n_items, head, cap, ends, end_waves); break;
-    case 6: launch_table<1, 2>(grid, lds, s, insts, ranges, n_items, head, cap, ends, end_waves); break;
-    case 7: launch_table<1, 3>(grid, lds, s, insts, ranges, n_items, head, cap, ends, end_waves); break;
-    case 8: launch_table<2, 0>(grid, lds, s, insts, ranges, n_items, head, cap, ends, end_waves); break;
-    case 9: launch_table<2, 1>(grid, lds, s, insts, ranges, n_items, head, cap, ends, end_waves); break;
-    case 10: launch_table<2, 2>(grid, lds, s, insts, ranges, n_items, head, cap, ends, end_waves); break;
+    switch (periodic) {
+    case 0: launch_table<2, 0>(grid, lds, s, insts, ranges, n_items, head, cap, ends, end_waves); break;
+    case 1: launch_table<2, 1>(grid, lds, s, insts, ranges, n_items, head, cap, ends, end_waves); break;
+    case 2: launch_table<2, 2>(grid, lds, s, insts, ranges, n_items, head, cap, ends, end_waves); break;
     default: launch_table<2, 3>(grid, lds, s, insts, ranges, n_items, head, cap, ends, end_waves); break;
     }
     return hipGetLastError();
@@ -1556,10 +1540,9 @@ int paths_fp32_table_blocks_per_cu(int level, int n_nodes)
     // every periodicity instance has the same launch bounds and LDS use
     int n = 0;
     const size_t lds = paths_fp32_table_lds_bytes(level, n_nodes);
-    hipError_t e = level == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32<kTableBlock, 2, 0>,
-                                                                             kTableBlock, lds)
-                              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32<kTableBlock, 1, 0>,
-                                                                             kTableBlock, lds);
+    if (level != 2) return 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32<kTableBlock, 2, 0>, kTableBlock,
+                                                                      lds);
     return e == hipSuccess ? n : 0;
 }
 

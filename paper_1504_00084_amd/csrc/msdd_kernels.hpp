@@ -44,9 +44,9 @@ size_t paths_fp32_lds_bytes(int block, uint32_t cap);
 
 // The same kernel for a launch that holds ONE instance (n_ranges = 1): each
 // 1024-thread workgroup (16 waves, 4 per SIMD) copies that instance's FP32
-// node table into LDS -- rho (level 1) or rho and dt rho_xi interleaved
-// (level 2; n_nodes * 4 * level bytes) -- and reads those corner values
-// there instead of from the cell records; `ends` holds the waves' item end
+// node tables of rho and dt rho_xi into LDS, interleaved (level 2, the only
+// level; n_nodes * 8 bytes), and reads those corner values there instead of
+// from the cell records; `ends` holds the waves' item end
 // states (6 * cap floats per wave, room for `end_waves` >= grid * 16 waves).
 // Results are identical to launch_paths_fp32's.
 constexpr int kTableBlock = 1024;
