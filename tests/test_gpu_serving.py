@@ -293,3 +293,48 @@ def test_lds_and_l2_monitor_give_identical_results(M, ctx):
         say("LDS tables (levels %s) == L2 records (bitwise) on %s" % (levels, ", ".join(it.name for it in insts)))
     finally:
         H.close()
+
+
+def non_square(n_xi, n_eta, sub_xi, sub_eta, per_xi, Lx, Ly, instance_id):
+    x, y = W.uniform_mesh(n_xi, n_eta, Lx, Ly)
+    if per_xi:
+        ux, uy = W.tanh_front_grad(x, y, 0.0, 0.05 * Lx, Lx=Lx, phase=0.3 * Lx)
+    else:
+        ux, uy = W.gaussian_bump_grad(x, y, 0.4 * Lx, 0.6 * Ly, 0.02 * max(Lx, Ly) ** 2)
+    rho = W.arc_length_monitor(ux, uy, 1.0)
+    b = W.boundary_from_mesh(x, y)
+    return W.Instance("rect%dx%d" % (n_xi, n_eta), n_xi, n_eta, sub_xi, sub_eta, per_xi, 0, Lx, Ly, 0.02, 80, 3000,
+                      rho, x, y, b, b.copy(), seed=11, instance_id=instance_id)
+
+
+def test_windows_of_non_square_grids(M, ctx, oracle_lib):
+    """449 x 65 (xi periodic, Lx = 3, Ly = 0.5) and 65 x 449 (Dirichlet):
+    too large for the whole tables, so both run the windowed kernel with
+    301 x 65 and 65 x 301 windows over blocks of 211 nodes along the long
+    axis.  Alone, batched together, and from the cell records: bitwise
+    equal; sampled nodes of the periodic one against the oracle."""
+    from gpu_helpers import compare, oracle_solve
+    insts = [non_square(449, 65, 8, 2, 1, 3.0, 0.5, 41), non_square(65, 449, 2, 8, 0, 0.5, 3.0, 42)]
+    H = Handles(M, ctx, insts, M.FP32)
+    try:
+        assert [M.mesh_sdd_get_launch(h).table_level for h in H.h] == [3, 3]
+        alone = solve_alone(M, H, insts)
+        pairs = [M.host_result(m) for m in H.m]
+        M.mesh_sdd_solve_batch(H.h, steps_for(M, insts), [r for _, r in pairs])
+        batched = [M.result_dict(a, r, m) for (a, r), m in zip(pairs, H.m)]
+        M.mesh_sdd_set_launch(ctx, M.make_launch(monitor_table=1))
+        try:
+            l2 = solve_alone(M, H, insts)
+        finally:
+            M.mesh_sdd_set_launch(ctx, None)
+        for q, it in enumerate(insts):
+            assert same(alone[q], batched[q]), it.name
+            assert same(alone[q], l2[q]), it.name
+        nodes = np.unique(np.linspace(0, H.m[0] - 1, 5).astype(np.int32))
+        ora = oracle_solve(oracle_lib, insts[0], nodes=nodes)
+        s = compare(alone[0], ora, nodes=nodes, label="rect449x65 windowed vs oracle")
+        assert s["err"] <= 1e-5
+        say("non-square windows: alone == batched == cell records (bitwise) on %s"
+            % ", ".join(it.name for it in insts))
+    finally:
+        H.close()
