@@ -202,23 +202,29 @@ __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t w
     const int cy = min((int)(P.y * C.fny1), C.ny1 - 1);
     tx = P.x * C.fnx1 - (float)cx;
     ty = P.y * C.fny1 - (float)cy;
-    const uint32_t ci = (uint32_t)(cy * C.nx1 + cx);
-    const GLOBAL f32x4 *cell = C.cells + 3u * ci;
+    // 32-bit indices and byte offsets (grids hold far fewer than 2^24 nodes):
+    // each gather adds one lane offset to a scalar base, and the LDS address
+    // is one 24-bit multiply-add
+    const uint32_t ci = __umul24((uint32_t)cy, (uint32_t)C.nx1) + (uint32_t)cx;   // cell
+    const GLOBAL f32x4 *cell = (const GLOBAL f32x4 *)((const GLOBAL char *)C.cells + ci * 48u);
+    const GLOBAL f32x4 *coef = (const GLOBAL f32x4 *)((const GLOBAL char *)C.coef_y + (ci << 4));
     float r00, r10, r01, r11, g00, g10, g01, g11;
     f32x4 G;   // dt rho_eta coefficients
     if (TAB == 2) {
-        const float2 *t2 = (const float2 *)tab + (cy * C.n_xi + cx);
+        const uint32_t off = __umul24((uint32_t)cy, (uint32_t)C.n_xi << 3) + ((uint32_t)cx << 3);
+        const float2 *t2 = (const float2 *)((const char *)tab + off);
         const float2 c00 = t2[0], c10 = t2[1], c01 = t2[C.n_xi], c11 = t2[C.n_xi + 1];
         r00 = c00.x, r10 = c10.x, r01 = c01.x, r11 = c11.x;
         g00 = c00.y, g10 = c10.y, g01 = c01.y, g11 = c11.y;
     } else if (TAB == 3) {
         const int rx = cx - win.i0, ry = cy - win.j0;
         if ((uint32_t)rx < (uint32_t)win.w1 && (uint32_t)ry < (uint32_t)win.h1) {
-            const float2 *t2 = (const float2 *)tab + (ry * win.tw + rx);
+            const uint32_t off = __umul24((uint32_t)ry, (uint32_t)win.tw << 3) + ((uint32_t)rx << 3);
+            const float2 *t2 = (const float2 *)((const char *)tab + off);
             const float2 c00 = t2[0], c10 = t2[1], c01 = t2[win.tw], c11 = t2[win.tw + 1];
             r00 = c00.x, r10 = c10.x, r01 = c01.x, r11 = c11.x;
             g00 = c00.y, g10 = c10.y, g01 = c01.y, g11 = c11.y;
-            G = C.coef_y[ci];
+            G = *coef;
         } else {
             // outside the window: the whole record, whose lines one lane then
             // shares for its three gathers (the same coefficients as the plane)
@@ -235,7 +241,7 @@ __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t w
     // the two-field table kernel reads the coefficients from the compact
     // plane (its only gather: better L1 reuse), the window kernel too inside
     // its window; the others from the record
-    if (TAB != 3) G = TAB == 2 ? C.coef_y[ci] : cell[2];
+    if (TAB != 3) G = TAB == 2 ? *coef : cell[2];
     const float rho = bilerp(tx, ty, r00, r10, r01, r11);
     const float gx = bilerp(tx, ty, g00, g10, g01, g11);
     const float gy = fmaf(ty, fmaf(G.w, tx, G.z), fmaf(G.y, tx, G.x));
