@@ -224,6 +224,24 @@ int mesh_sdd_desc_check(const mesh_sdd_desc *desc);
  * rank order into caller arrays of length M. */
 int mesh_sdd_desc_interface_nodes(const mesh_sdd_desc *desc, int32_t *i, int32_t *j);
 
+/* Work order of the FP32 kernels for a descriptor and an interface stride
+ * (0 or 1: every interface node; else the sampling of section 3.6, with the
+ * same validation as mesh_sdd_step.interface_stride).  The nodes that run
+ * paths are stepped block by block: the grid is cut into blocks of 50 x 50
+ * nodes (an axis whose window fits whole is one block), blocks row-major,
+ * ranks ascending inside a block; each block has the window of the node
+ * tables that the windowed kernel stages in LDS (at most 140 x 140 nodes, the
+ * block plus 45 nodes on each side, clamped to the grid; the whole axis where
+ * it fits).  The order changes no result.  Returns the number of nodes Ms >= 0
+ * or a negative error.  When `ranks` is not NULL, writes the Ms interface
+ * ranks in work order (caller array of length Ms).  When `n_blocks` is not
+ * NULL, writes the block count there; when `blocks` is not NULL too, writes
+ * one record of six int32 per block -- first position, end position, window
+ * i0, j0, width, height -- into caller room for max_blocks records (E_INVAL
+ * if that is too small).  Host only: no device is touched. */
+int mesh_sdd_desc_work_order(const mesh_sdd_desc *desc, uint32_t interface_stride, int32_t *ranks, int32_t *blocks,
+                             int32_t max_blocks, int32_t *n_blocks);
+
 /* ---- instances ----------------------------------------------------------- */
 
 /* Validate the descriptor (n >= 4, (n-1) % sub == 0, sub >= 1, K >= 1,

@@ -165,6 +165,20 @@ int64_t resolve_paths(const mesh_sdd &inst, const mesh_sdd_step &s)
     return s.paths_per_node;
 }
 
+// Sampling stride along the interface lines (section 3.6): 0 or 1 for all
+// nodes; else it must divide both subdomain sizes and leave at least two
+// segments along every grid line.
+int check_stride(const mesh_sdd_desc &d, uint32_t st)
+{
+    if (st <= 1) return MESH_SDD_OK;
+    const uint32_t Px = (uint32_t)((d.n_xi - 1) / d.sub_xi), Py = (uint32_t)((d.n_eta - 1) / d.sub_eta);
+    if (Px % st || Py % st)
+        return fail(MESH_SDD_E_INVAL, "interface_stride %u does not divide the subdomain sizes %u x %u", st, Px, Py);
+    if ((uint32_t)(d.n_xi - 1) / st < 2 || (uint32_t)(d.n_eta - 1) / st < 2)
+        return fail(MESH_SDD_E_INVAL, "interface_stride %u leaves fewer than two segments along a grid line", st);
+    return MESH_SDD_OK;
+}
+
 int validate_step(const mesh_sdd &inst, const mesh_sdd_step *s, int64_t *N_out)
 {
     if (!s) return fail(MESH_SDD_E_INVAL, "step is NULL");
@@ -175,15 +189,8 @@ int validate_step(const mesh_sdd &inst, const mesh_sdd_step *s, int64_t *N_out)
     if (s->target_se < 0.0 || !std::isfinite(s->target_se)) return fail(MESH_SDD_E_INVAL, "target_se < 0");
     const int64_t N = resolve_paths(inst, *s);
     if (N < 1 || N > (int64_t)1 << 31) return fail(MESH_SDD_E_INVAL, "paths per node %lld outside [1, 2^31]", (long long)N);
-    if (s->interface_stride > 1) {
-        const mesh_sdd_desc &d = inst.d;
-        const uint32_t st = s->interface_stride;
-        const uint32_t Px = (uint32_t)((d.n_xi - 1) / d.sub_xi), Py = (uint32_t)((d.n_eta - 1) / d.sub_eta);
-        if (Px % st || Py % st)
-            return fail(MESH_SDD_E_INVAL, "interface_stride %u does not divide the subdomain sizes %u x %u", st, Px, Py);
-        if ((uint32_t)(d.n_xi - 1) / st < 2 || (uint32_t)(d.n_eta - 1) / st < 2)
-            return fail(MESH_SDD_E_INVAL, "interface_stride %u leaves fewer than two segments along a grid line", st);
-    }
+    const int rs = check_stride(inst.d, s->interface_stride);
+    if (rs != MESH_SDD_OK) return rs;
     *N_out = N;
     if (s->inputs_on_device) return MESH_SDD_OK;   // device inputs are not inspected
     const mesh_sdd_desc &d = inst.d;
@@ -1118,6 +1125,36 @@ int mesh_sdd_desc_interface_nodes(const mesh_sdd_desc *desc, int32_t *i, int32_t
         std::memcpy(j, nj.data(), nj.size() * 4);
     }
     return (int)ni.size();
+}
+
+int mesh_sdd_desc_work_order(const mesh_sdd_desc *desc, uint32_t interface_stride, int32_t *ranks, int32_t *blocks,
+                             int32_t max_blocks, int32_t *n_blocks)
+{
+    int rc = validate_desc(desc);
+    if (rc != MESH_SDD_OK) return rc;
+    rc = check_stride(*desc, interface_stride);
+    if (rc != MESH_SDD_OK) return rc;
+    if (blocks && (max_blocks < 0 || !n_blocks)) return fail(MESH_SDD_E_INVAL, "blocks given without room or count");
+    mesh_sdd tmp;   // host fields only: no device memory is touched
+    tmp.d = *desc;
+    enumerate_nodes(tmp.d, tmp.node_i, tmp.node_j);
+    if (tmp.node_i.size() > 0x7FFFFFFFu) return fail(MESH_SDD_E_INVAL, "too many interface nodes");
+    tmp.M = (int32_t)tmp.node_i.size();
+    std::vector<int32_t> order = sampled_ranks(tmp, interface_stride > 1 ? (int)interface_stride : 1);
+    std::vector<BlockRun> runs;
+    order_by_blocks(tmp, order, runs);
+    if (ranks && !order.empty()) std::memcpy(ranks, order.data(), order.size() * 4);
+    if (n_blocks) *n_blocks = (int32_t)runs.size();
+    if (blocks) {
+        if ((size_t)max_blocks < runs.size())
+            return fail(MESH_SDD_E_INVAL, "%zu blocks, room for %d", runs.size(), max_blocks);
+        for (size_t k = 0; k < runs.size(); ++k) {
+            const BlockRun &b = runs[k];
+            const int32_t rec[6] = {b.pos_begin, b.pos_end, b.i0, b.j0, b.tw, b.th};
+            std::memcpy(blocks + 6 * k, rec, sizeof rec);
+        }
+    }
+    return (int)order.size();
 }
 
 int mesh_sdd_create(mesh_sdd_ctx *ctx, const mesh_sdd_desc *desc, mesh_sdd **out)

@@ -32,7 +32,7 @@ EXPORTS = (
     "mesh_sdd_debug_paths", "mesh_sdd_last_error", "mesh_sdd_version", "mesh_sdd_desc_check",
     "mesh_sdd_desc_interface_nodes", "mesh_sdd_edge_generate", "mesh_sdd_subdomain_solve",
     "mesh_sdd_single_domain_solve", "mesh_sdd_mp_step", "mesh_sdd_set_monitor_arclength", "mesh_sdd_get_monitor",
-    "mesh_sdd_mesh_quality", "mesh_sdd_transfer_field",
+    "mesh_sdd_mesh_quality", "mesh_sdd_transfer_field", "mesh_sdd_desc_work_order",
 )
 
 
@@ -128,6 +128,7 @@ def load(path: str = LIB_PATH):
         "mesh_sdd_debug_paths": [vp, P(Step), i32, i64, i64, vp, vp, vp, vp, vp, vp],
         "mesh_sdd_desc_check": [P(Desc)],
         "mesh_sdd_desc_interface_nodes": [P(Desc), vp, vp],
+        "mesh_sdd_desc_work_order": [P(Desc), ctypes.c_uint32, vp, vp, ctypes.c_int32, P(ctypes.c_int32)],
         "mesh_sdd_last_error": [],
         "mesh_sdd_version": [],
         "mesh_sdd_edge_generate": [vp, vp, vp, P(MpOpts), ctypes.c_int],
@@ -238,6 +239,18 @@ def mesh_sdd_desc_interface_nodes(desc: Desc):
     j = np.empty(max(m, 1), dtype=np.int32)
     _check(load().mesh_sdd_desc_interface_nodes(ctypes.byref(desc), i.ctypes.data, j.ctypes.data))
     return i[:m], j[:m]
+
+
+def mesh_sdd_desc_work_order(desc: Desc, interface_stride: int = 0):
+    """(ranks in work order, blocks [n_blocks, 6]: first position, end
+    position, window i0, j0, width, height)."""
+    nb = ctypes.c_int32(0)
+    m = _check(load().mesh_sdd_desc_work_order(ctypes.byref(desc), interface_stride, None, None, 0, ctypes.byref(nb)))
+    ranks = np.empty(max(m, 1), dtype=np.int32)
+    blocks = np.empty((max(nb.value, 1), 6), dtype=np.int32)
+    _check(load().mesh_sdd_desc_work_order(ctypes.byref(desc), interface_stride, ranks.ctypes.data,
+                                           blocks.ctypes.data, nb.value, ctypes.byref(nb)))
+    return ranks[:m], blocks[:nb.value]
 
 
 def mesh_sdd_create(ctx, desc: Desc):

@@ -1,0 +1,89 @@
+"""Host logic of the FP32 work order (no GPU): the nodes that run paths are
+stepped grid block by grid block, and each block carries the window of node
+tables that the windowed kernel stages in LDS.  The order must be a
+permutation of the sampled interface ranks (section 3.6 sampling for a
+stride), the blocks must cover it in order with ranks ascending inside each
+block, and every window must lie in the grid, fit 140 x 140 nodes, and hold
+each of its nodes with 45 nodes of margin on every side (less only where the
+grid ends; the whole axis where it fits)."""
+import numpy as np
+import pytest
+
+from paper_1504_00084_amd import mesh_sdd as M
+
+WIN, MARGIN, CORE = 140, 45, 50
+
+CASES = [
+    # n_xi, n_eta, sub_xi, sub_eta, per_xi, per_eta, stride
+    (33, 33, 2, 2, 0, 0, 0),
+    (129, 129, 4, 4, 0, 0, 0),
+    (129, 129, 4, 4, 0, 0, 4),
+    (161, 161, 8, 8, 0, 0, 0),
+    (257, 257, 8, 8, 1, 0, 0),
+    (257, 257, 8, 8, 1, 0, 2),
+    (513, 513, 16, 16, 0, 0, 0),
+    (449, 65, 8, 2, 1, 0, 0),
+    (65, 449, 2, 8, 0, 0, 0),
+    (513, 5, 4, 2, 0, 1, 0),
+]
+
+
+def sampled(i, j, n_xi, n_eta, sub_xi, sub_eta, stride):
+    """Ranks whose nodes run paths: every interface node for stride <= 1,
+    else the nodes of the lines at multiples of the stride along each line
+    (a node on a vertical line i = k P_xi keeps j = 0 mod stride, on a
+    horizontal line j = k P_eta keeps i = 0 mod stride)."""
+    if stride <= 1:
+        return np.arange(len(i))
+    Px, Py = (n_xi - 1) // sub_xi, (n_eta - 1) // sub_eta
+    keep = ((i % Px == 0) & (j % stride == 0)) | ((j % Py == 0) & (i % stride == 0))
+    return np.nonzero(keep)[0]
+
+
+@pytest.mark.parametrize("case", CASES, ids=["x".join(map(str, c[:2])) + "_s%d" % c[6] for c in CASES])
+def test_work_order_is_a_blocked_permutation_with_windows(case):
+    n_xi, n_eta, sx, sy, px, py, stride = case
+    d = M.make_desc(n_xi, n_eta, sx, sy, px, py)
+    i, j = M.mesh_sdd_desc_interface_nodes(d)
+    ranks, blocks = M.mesh_sdd_desc_work_order(d, stride)
+    want = sampled(i, j, n_xi, n_eta, sx, sy, stride)
+    assert np.array_equal(np.sort(ranks), want)
+    # blocks cover [0, Ms) in order
+    assert blocks[0, 0] == 0 and blocks[-1, 1] == len(ranks)
+    assert np.all(blocks[1:, 0] == blocks[:-1, 1]) and np.all(blocks[:, 1] > blocks[:, 0])
+    fits_x, fits_y = n_xi <= WIN, n_eta <= WIN
+    seen = set()
+    for b0, b1, i0, j0, tw, th in blocks:
+        r = ranks[b0:b1]
+        assert np.all(np.diff(r) > 0)   # ranks ascending inside a block
+        assert 0 <= i0 and i0 + tw <= n_xi and 0 <= j0 and j0 + th <= n_eta
+        assert tw >= 2 and th >= 2 and tw * th <= WIN * WIN
+        ii, jj = i[r], j[r]
+        # one block of the grid per run, each block once
+        key = (int(ii[0]) // (n_xi if tw == n_xi else CORE), int(jj[0]) // (n_eta if th == n_eta else CORE))
+        assert key not in seen
+        seen.add(key)
+        for pos, lo, w, n in ((ii, i0, tw, n_xi), (jj, j0, th, n_eta)):
+            if w == n:   # the whole axis
+                continue
+            left, right = pos - lo, lo + w - 1 - pos
+            assert np.all(left >= np.minimum(MARGIN, pos)), (case, lo, w)
+            assert np.all(right >= np.minimum(MARGIN, n - 1 - pos)), (case, lo, w)
+        if fits_x and fits_y and n_xi * n_eta <= WIN * WIN:
+            assert (i0, j0, tw, th) == (0, 0, n_xi, n_eta) and len(blocks) == 1
+
+
+def test_non_square_windows_use_the_whole_short_axis():
+    d = M.make_desc(449, 65, 8, 2, 1, 0)
+    _, blocks = M.mesh_sdd_desc_work_order(d)
+    assert set(map(tuple, blocks[:, 4:6])) == {(301, 65)}   # 19600 // 65 = 301 along xi
+    d = M.make_desc(65, 449, 2, 8, 0, 0)
+    _, blocks = M.mesh_sdd_desc_work_order(d)
+    assert set(map(tuple, blocks[:, 4:6])) == {(65, 301)}
+
+
+def test_invalid_strides_are_rejected():
+    d = M.make_desc(129, 129, 4, 4)
+    for st in (3, 64):   # does not divide 32; leaves one segment along a line
+        with pytest.raises(M.MeshSddError):
+            M.mesh_sdd_desc_work_order(d, st)
