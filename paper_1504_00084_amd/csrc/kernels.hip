@@ -818,7 +818,7 @@ __global__ __launch_bounds__(BLOCK) void paths_fp32(const InstView *__restrict__
 // the job's items with the wave loop above; a lane whose path has left the
 // window reads the corner values from the cell record instead (TAB 3 in
 // substep_f32), so the results are those of every other kernel.  The waves
-// keep their items' end states in `ends` as the table kernels do.
+// keep their items' end states in `ends` as the table kernel does.
 // PER >= 0: every instance of the launch has that periodicity (compiled
 // in); a job of another kind is skipped, untouched.
 template <int PER>

@@ -81,10 +81,11 @@ struct InstView {
     // FP32 path: per-cell records of three float4, (n_xi-1)(n_eta-1) cells:
     // rho and dt rho_xi at the four corners (00, 10, 01, 11), then dt rho_eta
     // in coefficient form a + b tx + c ty + d tx ty; the same coefficients
-    // again as a compact plane (coef_y, read by the kernel that takes rho and
+    // again as a compact plane (coef_y, read by the kernels that take rho and
     // dt rho_xi from LDS); the FP32 node tables of rho and dt rho_xi
-    // [n_eta][n_xi] (the same corner values, staged in LDS by launches that
-    // hold this instance alone); padded mesh [n_eta+2][n_xi+2] with ghost /
+    // [n_eta][n_xi] (the same corner values, staged in LDS whole by launches
+    // that hold this instance alone when they fit, else in windows); padded
+    // mesh [n_eta+2][n_xi+2] with ghost /
     // wrapped values, origin at node (-1, -1); boundary arrays in the C-ABI
     // layout.
     const float4 *cells, *coef_y;

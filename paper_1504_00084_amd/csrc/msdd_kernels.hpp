@@ -66,7 +66,7 @@ int paths_fp32_table_blocks_per_cu(int level, int n_nodes);
 // window node, at most kWinNodes nodes) and runs its items; lanes outside the
 // window read the cell records.  `periodic` = per_xi + 2 per_eta shared by
 // every instance of the launch (compiled in), or -1 (read per instance).
-// `ends` as for the table kernels.  Results are identical to
+// `ends` as for the table kernel.  Results are identical to
 // launch_paths_fp32's.
 constexpr int kWinNodes = 19600;   // 140 x 140 nodes, 156800 bytes of LDS
 hipError_t launch_paths_fp32_window(const InstView *insts, const WorkRange *ranges, const WinJob *jobs,

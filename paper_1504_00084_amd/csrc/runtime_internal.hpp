@@ -191,8 +191,8 @@ struct mesh_sdd {
     // first use (under ctx->gpu_mu), and all live until destroy
     std::map<int, std::unique_ptr<SampleSet>> samples;
     DevBuf rho_in, rho, rho_xi, rho_eta;    // FP64 monitor staging and node tables
-    DevBuf rho_f, rhox_f;                   // FP32 node tables of rho and dt rho_xi (staged in LDS by
-                                            // single-instance launches)
+    DevBuf rho_f, rhox_f;                   // FP32 node tables of rho and dt rho_xi (staged in LDS whole
+                                            // or in windows)
     DevBuf cells;                           // FP32 per-cell records (rho and rho_xi corners, rho_eta coefficients)
     DevBuf coef_y;                          // FP32 rho_eta coefficients alone, one float4 per cell
     DevBuf node_rank;                       // [n_eta][n_xi] interface rank or -1
@@ -253,7 +253,7 @@ struct mesh_sdd_ctx {
     std::mutex gpu_mu;   // serialises use of the stream and the launch scratch below
     DevBuf head, views, ranges;
     DevBuf jobs;         // job list of windowed launches (grow-only)
-    DevBuf ends;         // item end states of single-instance launches (grow-only)
+    DevBuf ends;         // item end states of the LDS table and window launches (grow-only)
 
     std::mutex mu;       // guards everything below
     std::condition_variable cv, done_cv;
