@@ -90,3 +90,44 @@ def test_fullsize_fp64_plain_vs_oracle(M, ctx, oracle_lib):
     sub["paths_per_node"] = g["paths_per_node"]
     s = compare(sub, ora, label="rotbump129 fp64 sampled")
     assert s["err"] <= 1e-9
+
+
+def test_largest_mix_instance_windowed_vs_oracle(M, ctx, oracle_lib):
+    """The mix's largest instance (513^2, 16x16 subdomains, 15 105 nodes,
+    K = 500) at 2000 paths per node: alone it runs the windowed kernel
+    (a quarter of its path-steps outside their window); batched with two
+    smaller instances, the multi-instance windowed launch must give the same
+    bits; sampled nodes against the oracle."""
+    import dataclasses
+    insts = W.config4(count=64)
+    sizes = [len(M.mesh_sdd_desc_interface_nodes(M.desc_for(it))[0]) for it in insts]
+    big = dataclasses.replace(insts[int(np.argmax(sizes))], n_paths=2000)
+    others = [dataclasses.replace(it, n_paths=1024) for it in insts[:2]]
+    hs = [M.mesh_sdd_create(ctx, M.desc_for(it, M.FP32)) for it in [big] + others]
+    try:
+        for h, it in zip(hs, [big] + others):
+            M.mesh_sdd_set_monitor(h, it.rho)
+        assert M.mesh_sdd_get_launch(hs[0]).table_level == 3
+        m = M.mesh_sdd_num_interface_nodes(hs[0])
+        arrs, res = M.host_result(m)
+        step = M.make_step(big.x, big.y, big.bnd_t0, big.bnd_t1, paths_per_node=big.n_paths)
+        M.mesh_sdd_solve_interfaces(hs[0], step, res)
+        alone = M.result_dict(arrs, res, m)
+        say("%s: %d nodes, %.3e path-steps in %.1f ms (windowed)" % (big.name, m, alone["executed_path_steps"],
+                                                                   alone["device_ms"]))
+        check_all_nodes(alone, big, se_bound=1e-2)
+        pairs, steps = [], []
+        for h, it in zip(hs, [big] + others):
+            pairs.append(M.host_result(M.mesh_sdd_num_interface_nodes(h)))
+            steps.append(M.make_step(it.x, it.y, it.bnd_t0, it.bnd_t1, paths_per_node=it.n_paths))
+        M.mesh_sdd_solve_batch(hs, steps, [r for _, r in pairs])
+        batched = M.result_dict(pairs[0][0], pairs[0][1], m)
+        for k in ("mean_x", "mean_y", "se_x", "se_y", "exit_frac"):
+            assert np.array_equal(alone[k], batched[k]), k
+        nodes = sample_nodes(m)
+        ora = oracle_solve(oracle_lib, big, nodes=nodes)
+        s = compare(alone, ora, nodes=nodes, label=big.name + " windowed sampled")
+        assert s["err"] <= 1e-5
+    finally:
+        for h in hs:
+            M.mesh_sdd_destroy(h)
