@@ -149,9 +149,10 @@ size_t instance_bytes(const mesh_sdd_desc &d, int M)
 {
     const size_t n = (size_t)d.n_xi * d.n_eta;
     const size_t cells = (size_t)(d.n_xi - 1) * (d.n_eta - 1);
-    // monitor tables, FP32 rho and dt rho_xi, cell records, node-rank map, stride-1 node lists
+    // monitor tables, FP32 rho and dt rho_xi, cell records, node-rank map, interface nodes in rank order,
+    // stride-1 node lists (block order)
     return 4 * n * sizeof(double) + 2 * n * sizeof(float) + 4 * cells * sizeof(float4) + n * sizeof(int32_t) +
-           3 * (size_t)M * sizeof(int32_t);
+           2 * (size_t)M * sizeof(int32_t) + 3 * (size_t)M * sizeof(int32_t);
 }
 
 int64_t resolve_paths(const mesh_sdd &inst, const mesh_sdd_step &s)
@@ -690,7 +691,6 @@ int finalize_request(mesh_sdd_ctx *ctx, Request &r)
                                   (uint32_t)r.Ms, (uint64_t)r.N, o, o + M, o + 2 * (size_t)M, o + 3 * (size_t)M,
                                   o + 4 * (size_t)M, r.steps_total.as<unsigned long long>(), st));
     if (r.Ms < M) {
-        const SampleSet &all = *inst.samples.at(1);
         msdd::InterpArgs a{};
         a.n_xi = inst.d.n_xi;
         a.n_eta = inst.d.n_eta;
@@ -702,8 +702,8 @@ int finalize_request(mesh_sdd_ctx *ctx, Request &r)
         a.M = M;
         a.Lx = inst.d.Lx;
         a.Ly = inst.d.Ly;
-        a.node_i = all.node_i();
-        a.node_j = all.node_j();
+        a.node_i = inst.node_ij.as<int32_t>();   // rank order (the node lists are in block order)
+        a.node_j = inst.node_ij.as<int32_t>() + M;
         a.rank_of = inst.node_rank.as<int32_t>();
         a.bnd1 = r.b1.as<double>();
         a.mean_x = o;
@@ -1182,12 +1182,17 @@ int mesh_sdd_create(mesh_sdd_ctx *ctx, const mesh_sdd_desc *desc, mesh_sdd **out
     if (inst->rho_in.alloc(n * 8) || inst->rho.alloc(n * 8) || inst->rho_xi.alloc(n * 8) ||
         inst->rho_eta.alloc(n * 8) || inst->rho_f.alloc(n * 4) || inst->rhox_f.alloc(n * 4) ||
         inst->cells.alloc(cells * 3 * sizeof(float4)) || inst->coef_y.alloc(cells * sizeof(float4)) ||
-        inst->node_rank.alloc(n * 4))
+        inst->node_rank.alloc(n * 4) || inst->node_ij.alloc(std::max<size_t>(1, 2 * (size_t)inst->M) * 4))
         return fail(MESH_SDD_E_NOMEM, "device allocation for the instance tables failed");
     {
         std::vector<int32_t> rank(n, -1);
         for (int32_t r = 0; r < inst->M; ++r) rank[(size_t)inst->node_j[r] * desc->n_xi + inst->node_i[r]] = r;
         HIP_TRY(hipMemcpy(inst->node_rank.p, rank.data(), n * 4, hipMemcpyHostToDevice));
+        if (inst->M) {
+            HIP_TRY(hipMemcpy(inst->node_ij.p, inst->node_i.data(), (size_t)inst->M * 4, hipMemcpyHostToDevice));
+            HIP_TRY(hipMemcpy(inst->node_ij.as<int32_t>() + inst->M, inst->node_j.data(), (size_t)inst->M * 4,
+                              hipMemcpyHostToDevice));
+        }
     }
     const SampleSet *all = nullptr;
     rc = sample_set(*inst, 1, &all);

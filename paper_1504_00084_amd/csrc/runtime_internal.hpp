@@ -196,6 +196,7 @@ struct mesh_sdd {
     DevBuf cells;                           // FP32 per-cell records (rho and rho_xi corners, rho_eta coefficients)
     DevBuf coef_y;                          // FP32 rho_eta coefficients alone, one float4 per cell
     DevBuf node_rank;                       // [n_eta][n_xi] interface rank or -1
+    DevBuf node_ij;                         // interface nodes in rank order: i[M], then j[M]
     bool monitor_set = false;
     std::atomic<int> inflight{0};
     size_t resident_bytes = 0;

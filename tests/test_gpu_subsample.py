@@ -83,11 +83,13 @@ def check_against_full(P, full, sub, stride, bnd1, label):
 CASES = [((33, (2, 1), 0, 0), (2, 4, 16)),      # one vertical line; stride 16 leaves two segments
          ((33, (4, 4), 0, 0), (2, 4, 8)),
          ((33, (4, 4), 1, 0), (2, 8)),         # periodic xi: the seam column is a line too
-         ((33, (2, 2), 1, 1), (4, 8))]         # doubly periodic
+         ((33, (2, 2), 1, 1), (4, 8)),         # doubly periodic
+         ((257, (8, 8), 1, 0), (2, 4))]        # grid above 140^2: windowed kernel, sampled lists in block order
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-@pytest.mark.parametrize("case,strides", CASES, ids=["33_2x1", "33_4x4", "33_4x4_perxi", "33_2x2_perboth"])
+@pytest.mark.parametrize("case,strides", CASES,
+                         ids=["33_2x1", "33_4x4", "33_4x4_perxi", "33_2x2_perboth", "257_8x8_perxi"])
 def test_sampled_nodes_equal_full_run_and_rest_interpolated(M, ctx, case, strides, precision):
     n, sub, px, py = case
     inst = small_instance(n, sub, px, py)
