@@ -78,3 +78,38 @@ def test_solve_means_equal_debug_path_values(M, ctx, tau, monitor_table):
     assert level == (0 if monitor_table else 2)
     assert (wmax > 8192.0) == (tau > 1.0)
     assert worst <= 1e-12
+
+
+def test_debug_paths_address_ranks_on_a_blocked_grid(M, ctx):
+    """161 x 161, 4 x 4 subdomains: the node lists are stored block by
+    block, so positions differ from ranks; the debug entry point takes a
+    rank, and the mean of its per-path values must equal the solve's mean
+    at that rank."""
+    n, K, N = 161, 40, 256
+    x, y = W.uniform_mesh(n, n)
+    rho = 1.0 + 2.0 * np.exp(-((x - 0.3) ** 2 + (y - 0.7) ** 2) / 0.02)
+    b = W.boundary_from_mesh(x, y)
+    inst = W.Instance("blocked161", n, n, 4, 4, 0, 0, 1.0, 1.0, 0.01, K, N, rho, x, y, b, b.copy(), seed=5,
+                      instance_id=9)
+    h = M.mesh_sdd_create(ctx, M.desc_for(inst, M.FP32))
+    try:
+        M.mesh_sdd_set_monitor(h, rho)
+        m = M.mesh_sdd_num_interface_nodes(h)
+        ranks, blocks = M.mesh_sdd_desc_work_order(M.desc_for(inst, M.FP32))
+        assert len(blocks) > 1 and not np.array_equal(ranks, np.arange(m))
+        arrs, res = M.host_result(m)
+        st = M.make_step(x, y, b, b, paths_per_node=N)
+        M.mesh_sdd_solve_interfaces(h, st, res)
+        got = M.result_dict(arrs, res, m)
+        ni, nj = M.mesh_sdd_interface_nodes(h)
+        worst = 0.0
+        for r in (0, int(ranks[len(ranks) // 2]), m - 1):
+            d = M.mesh_sdd_debug_paths(h, st, r, 0, N, K)
+            i, j = int(ni[r]), int(nj[r])
+            for comp, ref in (("x", x[j, i]), ("y", y[j, i])):
+                dv = (d["v" + comp] - ref).astype(np.float32).astype(np.float64)
+                worst = max(worst, abs(ref + dv.sum() / N - got["mean_" + comp][r]))
+    finally:
+        M.mesh_sdd_destroy(h)
+    say("161x161 blocked lists: max |debug mean - solve mean| %.2e" % worst)
+    assert worst <= 1e-12
