@@ -168,7 +168,8 @@ typedef struct {
                                         dt rho_xi fit the LDS (8 B per node) stages
                                         them whole; any other launch (several
                                         instances, or a larger grid) stages
-                                        140 x 140-node windows of them around
+                                        windows of them (and, on most grids, of
+                                        the dt rho_eta cell coefficients) around
                                         blocks of interface nodes, and paths that
                                         leave a window read the cell records
                                         (1024-thread workgroups, item end states in
@@ -227,18 +228,22 @@ int mesh_sdd_desc_interface_nodes(const mesh_sdd_desc *desc, int32_t *i, int32_t
 /* Work order of the FP32 kernels for a descriptor and an interface stride
  * (0 or 1: every interface node; else the sampling of section 3.6, with the
  * same validation as mesh_sdd_step.interface_stride).  The nodes that run
- * paths are stepped block by block: the grid is cut into blocks of 50 x 50
- * nodes (an axis whose window fits whole is one block), blocks row-major,
- * ranks ascending inside a block; each block has the window of the node
- * tables that the windowed kernel stages in LDS (at most 140 x 140 nodes, the
- * block plus 45 nodes on each side, clamped to the grid; the whole axis where
- * it fits).  The order changes no result.  Returns the number of nodes Ms >= 0
- * or a negative error.  When `ranks` is not NULL, writes the Ms interface
- * ranks in work order (caller array of length Ms).  When `n_blocks` is not
- * NULL, writes the block count there; when `blocks` is not NULL too, writes
- * one record of six int32 per block -- first position, end position, window
- * i0, j0, width, height -- into caller room for max_blocks records (E_INVAL
- * if that is too small).  Host only: no device is touched. */
+ * paths are stepped block by block (blocks row-major, ranks ascending inside
+ * a block); each block has the window of the monitor tables that the
+ * windowed kernel stages in LDS around it, clamped to the grid, the whole
+ * axis where it fits.  Kind 0: windows of (rho, dt rho_xi) per node, at
+ * most 140 x 140 nodes, blocks of 50 nodes, 45 nodes of margin; kind 1:
+ * windows that also hold the dt rho_eta coefficients of their cells, 81 x 81
+ * nodes when square, blocks of 21 nodes, 30 nodes of margin.  Kind 1 where
+ * its window holds the whole grid, else kind 0 where that one does, else
+ * kind 1 for grids under 400 nodes per axis and kind 0 above.  The order changes no result.  Returns the
+ * number of nodes Ms >= 0 or a negative error.  When `ranks` is not NULL,
+ * writes the Ms interface ranks in work order (caller array of length Ms).
+ * When `n_blocks` is not NULL, writes the block count there; when `blocks`
+ * is not NULL too, writes one record of seven int32 per block -- first
+ * position, end position, window i0, j0, width, height, kind -- into caller
+ * room for max_blocks records (E_INVAL if that is too small).  Host only: no
+ * device is touched. */
 int mesh_sdd_desc_work_order(const mesh_sdd_desc *desc, uint32_t interface_stride, int32_t *ranks, int32_t *blocks,
                              int32_t max_blocks, int32_t *n_blocks);
 

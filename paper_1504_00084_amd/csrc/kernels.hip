@@ -173,14 +173,17 @@ __device__ __forceinline__ float bilerp(float tx, float ty, float f00, float f10
 
 // Window of the node tables held in LDS by the windowed kernel: nodes
 // [i0, i0 + tw) x [j0, j0 + th), (rho, dt rho_xi) interleaved, row stride tw;
-// w1 = tw - 1 and h1 = th - 1 cells.
+// w1 = tw - 1 and h1 = th - 1 cells.  Three-field windows (TAB 4) also hold
+// the dt rho_eta coefficients of their w1 x h1 cells, row stride w1, from
+// byte `coff` of the LDS on.
 struct Win {
-    int i0, j0, tw, w1, h1;
+    int i0, j0, tw, w1, h1, coff;
 };
 
 // TAB: where the corner values of rho and dt rho_xi come from.  0: the cell
 // record; 2: the LDS node table (rho, dt rho_xi interleaved); 3: the LDS
-// window when the cell lies inside it, else the cell record.  The
+// window when the cell lies inside it, else the cell record; 4: as 3, with
+// the dt rho_eta coefficients of the cells inside the window from LDS too.  The
 // values are the same in every case, so the results are identical.
 template <int TAB>
 __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t wa, uint32_t wb, uint32_t wc,
@@ -216,7 +219,7 @@ __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t w
         const float2 c00 = t2[0], c10 = t2[1], c01 = t2[C.n_xi], c11 = t2[C.n_xi + 1];
         r00 = c00.x, r10 = c10.x, r01 = c01.x, r11 = c11.x;
         g00 = c00.y, g10 = c10.y, g01 = c01.y, g11 = c11.y;
-    } else if (TAB == 3) {
+    } else if (TAB == 3 || TAB == 4) {
         const int rx = cx - win.i0, ry = cy - win.j0;
         if ((uint32_t)rx < (uint32_t)win.w1 && (uint32_t)ry < (uint32_t)win.h1) {
             const uint32_t off = __umul24((uint32_t)ry, (uint32_t)win.tw << 3) + ((uint32_t)rx << 3);
@@ -224,7 +227,13 @@ __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t w
             const float2 c00 = t2[0], c10 = t2[1], c01 = t2[win.tw], c11 = t2[win.tw + 1];
             r00 = c00.x, r10 = c10.x, r01 = c01.x, r11 = c11.x;
             g00 = c00.y, g10 = c10.y, g01 = c01.y, g11 = c11.y;
-            G = *coef;
+            if (TAB == 4) {
+                const uint32_t co = (uint32_t)win.coff + __umul24((uint32_t)ry, (uint32_t)win.w1 << 4) +
+                                    ((uint32_t)rx << 4);
+                G = *(const f32x4 *)((const char *)tab + co);
+            } else {
+                G = *coef;
+            }
         } else {
             // outside the window: the whole record, whose lines one lane then
             // shares for its three gathers (the same coefficients as the plane)
@@ -241,7 +250,7 @@ __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t w
     // the two-field table kernel reads the coefficients from the compact
     // plane (its only gather: better L1 reuse), the window kernel too inside
     // its window; the others from the record
-    if (TAB != 3) G = TAB == 2 ? *coef : cell[2];
+    if (TAB < 3) G = TAB == 2 ? *coef : cell[2];
     const float rho = bilerp(tx, ty, r00, r10, r01, r11);
     const float gx = bilerp(tx, ty, g00, g10, g01, g11);
     const float gy = fmaf(ty, fmaf(G.w, tx, G.z), fmaf(G.y, tx, G.x));
@@ -805,7 +814,7 @@ __global__ __launch_bounds__(BLOCK) void paths_fp32(const InstView *__restrict__
     }
 
     QueueSrc src{head, gptr(ranges), n_ranges};
-    const Win none{0, 0, 0, 0, 0};
+    const Win none{0, 0, 0, 0, 0, 0};
     item_loop<TAB, PER>(src, n_items, insts, buf, cap, tab, none, lane);
 }
 
@@ -829,8 +838,12 @@ __global__ __launch_bounds__(kTableBlock) void paths_fp32_win(const InstView *__
                                                             float *__restrict__ ends, uint32_t end_waves)
 {
     constexpr int BLOCK = kTableBlock;
+    // The only LDS of this kernel is the dynamic block (base 0): the job and
+    // item counters in its first 16 bytes, then the window, 16-byte aligned
+    // for the float4 cell coefficients of three-field windows.
     extern __shared__ float lds[];
-    __shared__ uint32_t s_job, s_next;
+    uint32_t *ctl = (uint32_t *)lds;   // [0]: current job, [1]: next item of the job
+    float *wtab = lds + 4;
     const int lane = threadIdx.x & 63;
     const uint32_t wave = blockIdx.x * (uint32_t)(BLOCK / 64) + (threadIdx.x >> 6);
     if ((blockIdx.x + 1u) * (uint32_t)(BLOCK / 64) > end_waves) return;   // whole block: no room
@@ -848,31 +861,44 @@ __global__ __launch_bounds__(kTableBlock) void paths_fp32_win(const InstView *__
                     break;
                 }
             }
-            s_job = j;
-            s_next = 0u;
+            ctl[0] = j;
+            ctl[1] = 0u;
         }
         __syncthreads();
-        const uint32_t job = s_job;
+        const uint32_t job = ctl[0];
         if (job >= n_jobs) break;   // the same for the whole workgroup
         const WinJob J = jobs[job];
         const WorkRange R = ranges[J.range];
         const InstView &I = insts[R.inst];
         const bool ok = PER < 0 || (I.per_xi == (PER & 1) && I.per_eta == (PER >> 1));
+        const int coff = (J.tw * J.th * 8 + 15) & ~15;   // three-field windows: cell coefficients from here
         {
             const GLOBAL float *src = gptr(I.rho_f);
             const GLOBAL float *srx = gptr(I.rhox_f);
-            float2 *t2 = (float2 *)lds;
+            float2 *t2 = (float2 *)wtab;
             const int n = J.tw * J.th;
             for (int q = threadIdx.x; q < n; q += BLOCK) {
                 const int r = q / J.tw, c = q - r * J.tw;
                 const uint32_t g = (uint32_t)((J.j0 + r) * I.n_xi + J.i0 + c);
                 t2[q] = make_float2(src[g], srx[g]);
             }
+            if (J.kind == 1) {
+                const GLOBAL f32x4 *cy = (const GLOBAL f32x4 *)I.coef_y;
+                f32x4 *t4 = (f32x4 *)((char *)wtab + coff);
+                const int w1 = J.tw - 1, nc = w1 * (J.th - 1);
+                for (int q = threadIdx.x; q < nc; q += BLOCK) {
+                    const int r = q / w1, c = q - r * w1;
+                    t4[q] = cy[(uint32_t)((J.j0 + r) * (I.n_xi - 1) + J.i0 + c)];
+                }
+            }
         }
         __syncthreads();
-        JobSrc js{&s_next, R, J.q0};
-        const Win win{J.i0, J.j0, J.tw, J.tw - 1, J.th - 1};
-        item_loop<3, PER>(js, ok ? J.count : 0u, insts, buf, cap, lds, win, lane);
+        JobSrc js{ctl + 1, R, J.q0};
+        const Win win{J.i0, J.j0, J.tw, J.tw - 1, J.th - 1, coff};
+        if (J.kind == 1)
+            item_loop<4, PER>(js, ok ? J.count : 0u, insts, buf, cap, wtab, win, lane);
+        else
+            item_loop<3, PER>(js, ok ? J.count : 0u, insts, buf, cap, wtab, win, lane);
         __syncthreads();   // every wave is done with the window
     }
 }
@@ -1415,7 +1441,7 @@ __global__ void debug_paths_kernel(const InstView *__restrict__ inst, int fp64, 
     int side = -1;
     bool ended = false;
     while (!ended) {
-        const Win none{0, 0, 0, 0, 0};
+        const Win none{0, 0, 0, 0, 0, 0};
         side = tr ? group_f32<true, 0>(P, C, path, I.node_r[node], I.ctr3, I.key0, I.key1, ended, tr, nullptr, none)
                   : group_f32<false, 0>(P, C, path, I.node_r[node], I.ctr3, I.key0, I.key1, ended, nullptr, nullptr,
                                         none);
@@ -1562,7 +1588,7 @@ static void launch_win(int grid, size_t lds, hipStream_t s, const InstView *inst
 }
 
 hipError_t launch_paths_fp32_window(const InstView *insts, const WorkRange *ranges, const WinJob *jobs,
-                                    const JobQueues &qs, uint32_t *head, uint32_t cap, int periodic, int win_nodes,
+                                    const JobQueues &qs, uint32_t *head, uint32_t cap, int periodic, size_t lds,
                                     int grid, float *ends, uint32_t end_waves, hipStream_t s)
 {
     hipError_t e = launch_fill_u32(head, 0u, kJobQueues, s);
@@ -1570,10 +1596,10 @@ hipError_t launch_paths_fp32_window(const InstView *insts, const WorkRange *rang
     if (qs.b[kJobQueues] == 0) return hipSuccess;
     for (int q = 0; q < kJobQueues; ++q)
         if (qs.b[q] > qs.b[q + 1]) return hipErrorInvalidValue;
-    if ((size_t)grid * (kTableBlock / 64) > end_waves || periodic < -1 || periodic > 3 || win_nodes < 4 ||
-        win_nodes > kWinNodes)
+    if ((size_t)grid * (kTableBlock / 64) > end_waves || periodic < -1 || periodic > 3 || lds < 32 ||
+        lds > kWinBytes)
         return hipErrorInvalidValue;
-    const size_t lds = (size_t)win_nodes * 2u * sizeof(float);
+    lds += 16;   // the job and item counters ahead of the window
     switch (periodic) {
     case 0: launch_win<0>(grid, lds, s, insts, ranges, jobs, qs, head, cap, ends, end_waves); break;
     case 1: launch_win<1>(grid, lds, s, insts, ranges, jobs, qs, head, cap, ends, end_waves); break;
@@ -1584,10 +1610,10 @@ hipError_t launch_paths_fp32_window(const InstView *insts, const WorkRange *rang
     return hipGetLastError();
 }
 
-int paths_fp32_window_blocks_per_cu(int win_nodes)
+int paths_fp32_window_blocks_per_cu(size_t lds)
 {
     int n = 0;
-    const size_t lds = (size_t)win_nodes * 2u * sizeof(float);
+    lds += 16;   // the job and item counters ahead of the window
     const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32_win<-1>, kTableBlock, lds);
     return e == hipSuccess ? n : 0;
 }

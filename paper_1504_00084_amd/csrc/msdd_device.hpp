@@ -28,13 +28,16 @@ struct WorkRange {
 // One job of the windowed kernel: the request-wide items [q0, q0 + count)
 // of range `range`, whose nodes all lie in one block of the grid, and the
 // window of the node tables that the workgroup stages in LDS for them:
-// nodes [i0, i0 + tw) x [j0, j0 + th), inside the grid.
+// nodes [i0, i0 + tw) x [j0, j0 + th), inside the grid.  kind 0: the window
+// holds (rho, dt rho_xi) per node (8 B); kind 1: also the dt rho_eta
+// coefficients of its (tw - 1)(th - 1) cells (16 B each, after the nodes,
+// 16-byte aligned).
 struct WinJob {
     uint32_t range;
     uint32_t q0;
     uint32_t count;
     int32_t i0, j0, tw, th;
-    uint32_t pad;
+    uint32_t kind;
 };
 
 // The job list of a windowed launch cut into kJobQueues contiguous queues:

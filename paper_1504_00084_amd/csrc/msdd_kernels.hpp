@@ -62,17 +62,19 @@ int paths_fp32_table_blocks_per_cu(int level, int n_nodes);
 // one range whose nodes lie in one grid block, and the node-table window
 // around that block), cut into kJobQueues queues; each 1024-thread workgroup
 // pops jobs from its queue and then the others (`head`: kJobQueues counters,
-// zeroed here), stages the job's window of (rho, dt rho_xi) in LDS (8 bytes per
-// window node, at most kWinNodes nodes) and runs its items; lanes outside the
-// window read the cell records.  `periodic` = per_xi + 2 per_eta shared by
-// every instance of the launch (compiled in), or -1 (read per instance).
-// `ends` as for the table kernel.  Results are identical to
-// launch_paths_fp32's.
-constexpr int kWinNodes = 19600;   // 140 x 140 nodes, 156800 bytes of LDS
+// zeroed here), stages the job's window in LDS -- (rho, dt rho_xi) per node,
+// 8 bytes, and for kind-1 jobs the dt rho_eta coefficients of the window's
+// cells too, 16 bytes each -- and runs its items; lanes outside the window
+// read the cell records.  `lds` = the largest window of the launch in bytes
+// (at most kWinBytes).  `periodic` = per_xi + 2 per_eta shared by every
+// instance of the launch (compiled in), or -1 (read per instance).  `ends`
+// as for the table kernel.  Results are identical to launch_paths_fp32's.
+constexpr size_t kWinBytes = 156800;   // LDS of one window (of the 160 KB of a CU)
+constexpr int kWinNodes = 19600;       // two-field windows: at most 140 x 140 nodes
 hipError_t launch_paths_fp32_window(const InstView *insts, const WorkRange *ranges, const WinJob *jobs,
-                                    const JobQueues &qs, uint32_t *head, uint32_t cap, int periodic, int win_nodes,
+                                    const JobQueues &qs, uint32_t *head, uint32_t cap, int periodic, size_t lds,
                                     int grid, float *ends, uint32_t end_waves, hipStream_t s);
-int paths_fp32_window_blocks_per_cu(int win_nodes);
+int paths_fp32_window_blocks_per_cu(size_t lds);
 
 // a2-a8, FP64 plain: one thread per path, one launch per instance; the
 // partial of (node, chunk) goes to partials[node * chunks + chunk].

@@ -257,7 +257,7 @@ int table_level(int n_nodes, int monitor_table, int *per_cu)
             return 2;
         }
     }
-    const int n = msdd::paths_fp32_window_blocks_per_cu(msdd::kWinNodes);
+    const int n = msdd::paths_fp32_window_blocks_per_cu(msdd::kWinBytes);
     if (n >= 1) {
         *per_cu = n;
         return 3;
@@ -327,23 +327,51 @@ std::shared_ptr<Request> make_request(mesh_sdd *inst, const mesh_sdd_step &s, in
     return r;
 }
 
-// Window of the windowed kernel along each axis: at most kWinNodes nodes
-// in all, the whole axis where it fits.
-void window_dims(int n_xi, int n_eta, int *wx, int *wy)
+// Windows of the windowed kernel.  Kind 0 holds (rho, dt rho_xi) per node (8
+// bytes, at most kWinNodes nodes); kind 1 also the dt rho_eta coefficients of
+// its cells (16 bytes each), so a lane inside it gathers nothing from memory,
+// at the price of a smaller window.  Chosen per grid, by measurement: kind 1
+// where it holds the whole grid (no gather at all); kind 0 where the two
+// fields of the whole grid fit (one well-cached gather per path-step beats
+// many small blocks and window refills); kind 1 below kWin1MaxN nodes per
+// axis; kind 0 above, where paths spread over more cells than a kind-1 window
+// holds around its block and the larger kind-0 window needs fewer record
+// gathers.
+constexpr int kWin1MaxN = 400;
+
+// LDS bytes of a window of tw x th nodes.
+size_t window_bytes(int kind, int tw, int th)
 {
-    const int side = 140;   // kWinNodes = 140 x 140
+    const size_t nodes = (size_t)tw * th * 8;
+    return kind ? ((nodes + 15) & ~(size_t)15) + (size_t)(tw - 1) * (th - 1) * 16 : nodes;
+}
+
+int window_kind(const mesh_sdd_desc &d)
+{
+    if (window_bytes(1, d.n_xi, d.n_eta) <= msdd::kWinBytes) return 1;
+    if (window_bytes(0, d.n_xi, d.n_eta) <= msdd::kWinBytes) return 0;
+    return std::max(d.n_xi, d.n_eta) < kWin1MaxN ? 1 : 0;
+}
+
+// Window extent along each axis: within kWinBytes of LDS, near square, the
+// whole axis where it fits.
+void window_dims(int kind, int n_xi, int n_eta, int *wx, int *wy)
+{
+    const int side = kind ? 81 : 140;   // the largest square of each kind within kWinBytes
     int y = std::min(n_eta, side);
-    const int x = std::min(n_xi, msdd::kWinNodes / y);
-    y = std::min(n_eta, msdd::kWinNodes / x);
+    int x = n_xi;
+    while (window_bytes(kind, x, y) > msdd::kWinBytes) --x;
+    while (y < n_eta && window_bytes(kind, x, y + 1) <= msdd::kWinBytes) ++y;
     *wx = x;
     *wy = y;
 }
 
-constexpr int kWinMargin = 45;   // window nodes beyond a block on each side (where the axis does not fit)
+// Window nodes beyond a block on each side, where the axis does not fit.
+int window_margin(int kind) { return kind ? 30 : 45; }
 
 // Block length along an axis of n nodes whose window is w nodes long, and
 // the window origin of block b (centred on the block, clamped to the grid).
-int block_len(int n, int w) { return n <= w ? n : w - 2 * kWinMargin; }
+int block_len(int kind, int n, int w) { return n <= w ? n : w - 2 * window_margin(kind); }
 int window_origin(int b, int len, int n, int w) { return n <= w ? 0 : std::clamp(b * len - (w - len) / 2, 0, n - w); }
 
 // Sorts `ranks` (ascending) into block order -- blocks row-major, ranks
@@ -352,9 +380,10 @@ int window_origin(int b, int len, int n, int w) { return n <= w ? 0 : std::clamp
 void order_by_blocks(const mesh_sdd &inst, std::vector<int32_t> &ranks, std::vector<BlockRun> &blocks)
 {
     const int n_xi = inst.d.n_xi, n_eta = inst.d.n_eta;
+    const int kind = window_kind(inst.d);
     int wx = 0, wy = 0;
-    window_dims(n_xi, n_eta, &wx, &wy);
-    const int lx = block_len(n_xi, wx), ly = block_len(n_eta, wy);
+    window_dims(kind, n_xi, n_eta, &wx, &wy);
+    const int lx = block_len(kind, n_xi, wx), ly = block_len(kind, n_eta, wy);
     const int nbx = (n_xi + lx - 1) / lx;
     auto block_of = [&](int32_t r) { return (inst.node_j[(size_t)r] / ly) * nbx + inst.node_i[(size_t)r] / lx; };
     std::stable_sort(ranks.begin(), ranks.end(), [&](int32_t a, int32_t b) { return block_of(a) < block_of(b); });
@@ -370,6 +399,7 @@ void order_by_blocks(const mesh_sdd &inst, std::vector<int32_t> &ranks, std::vec
         run.j0 = window_origin(b / nbx, ly, n_eta, wy);
         run.tw = wx;
         run.th = wy;
+        run.kind = kind;
         blocks.push_back(run);
         k = e;
     }
@@ -578,7 +608,8 @@ int run_fp32_launch(mesh_sdd_ctx *ctx, const std::vector<InstView> &views, const
     // order, cut into per-XCD queues of equal nominal work
     std::vector<msdd::WinJob> jobs;
     msdd::JobQueues qs{};
-    int win_nodes = 4, periodic = -2;
+    size_t win_lds = 32;
+    int periodic = -2;
     if (level == 3) {
         const size_t per = (size_t)ctx->cu_count * (size_t)per_cu * 32u;
         const size_t jmax = std::max<size_t>(64, (n_items + per - 1) / per);
@@ -593,8 +624,8 @@ int run_fp32_launch(mesh_sdd_ctx *ctx, const std::vector<InstView> &views, const
                 const size_t qb = std::min(hi, (size_t)b.pos_end * w.chunks);
                 for (size_t q = qa; q < qb; q += jmax)
                     jobs.push_back(msdd::WinJob{(uint32_t)ri, (uint32_t)q, (uint32_t)std::min(jmax, qb - q), b.i0,
-                                                b.j0, b.tw, b.th, 0u});
-                if (qa < qb) win_nodes = std::max(win_nodes, b.tw * b.th);
+                                                b.j0, b.tw, b.th, (uint32_t)b.kind});
+                if (qa < qb) win_lds = std::max(win_lds, window_bytes(b.kind, b.tw, b.th));
             }
         }
         std::vector<double> cum(jobs.size() + 1, 0.0);
@@ -620,7 +651,7 @@ int run_fp32_launch(mesh_sdd_ctx *ctx, const std::vector<InstView> &views, const
     hipError_t le =
         level == 3 ? msdd::launch_paths_fp32_window(ctx->views.as<InstView>(), ctx->ranges.as<WorkRange>(),
                                                     ctx->jobs.as<msdd::WinJob>(), qs, ctx->head.as<uint32_t>(),
-                                                    cap, periodic, win_nodes, table_grid,
+                                                    cap, periodic, win_lds, table_grid,
                                                     ctx->ends.as<float>(), end_waves, st)
         : level > 0 ? msdd::launch_paths_fp32_table(ctx->views.as<InstView>(), ctx->ranges.as<WorkRange>(),
                                                     (uint32_t)n_items, ctx->head.as<uint32_t>(), cap, level,
@@ -1150,8 +1181,8 @@ int mesh_sdd_desc_work_order(const mesh_sdd_desc *desc, uint32_t interface_strid
             return fail(MESH_SDD_E_INVAL, "%zu blocks, room for %d", runs.size(), max_blocks);
         for (size_t k = 0; k < runs.size(); ++k) {
             const BlockRun &b = runs[k];
-            const int32_t rec[6] = {b.pos_begin, b.pos_end, b.i0, b.j0, b.tw, b.th};
-            std::memcpy(blocks + 6 * k, rec, sizeof rec);
+            const int32_t rec[7] = {b.pos_begin, b.pos_end, b.i0, b.j0, b.tw, b.th, b.kind};
+            std::memcpy(blocks + 7 * k, rec, sizeof rec);
         }
     }
     return (int)order.size();

@@ -242,12 +242,12 @@ def mesh_sdd_desc_interface_nodes(desc: Desc):
 
 
 def mesh_sdd_desc_work_order(desc: Desc, interface_stride: int = 0):
-    """(ranks in work order, blocks [n_blocks, 6]: first position, end
-    position, window i0, j0, width, height)."""
+    """(ranks in work order, blocks [n_blocks, 7]: first position, end
+    position, window i0, j0, width, height, kind)."""
     nb = ctypes.c_int32(0)
     m = _check(load().mesh_sdd_desc_work_order(ctypes.byref(desc), interface_stride, None, None, 0, ctypes.byref(nb)))
     ranks = np.empty(max(m, 1), dtype=np.int32)
-    blocks = np.empty((max(nb.value, 1), 6), dtype=np.int32)
+    blocks = np.empty((max(nb.value, 1), 7), dtype=np.int32)
     _check(load().mesh_sdd_desc_work_order(ctypes.byref(desc), interface_stride, ranks.ctypes.data,
                                            blocks.ctypes.data, nb.value, ctypes.byref(nb)))
     return ranks[:m], blocks[:nb.value]

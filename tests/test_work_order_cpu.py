@@ -1,17 +1,27 @@
 """Host logic of the FP32 work order (no GPU): the nodes that run paths are
-stepped grid block by grid block, and each block carries the window of node
-tables that the windowed kernel stages in LDS.  The order must be a
+stepped grid block by grid block, and each block carries the window of
+monitor tables that the windowed kernel stages in LDS.  The order must be a
 permutation of the sampled interface ranks (section 3.6 sampling for a
 stride), the blocks must cover it in order with ranks ascending inside each
-block, and every window must lie in the grid, fit 140 x 140 nodes, and hold
-each of its nodes with 45 nodes of margin on every side (less only where the
-grid ends; the whole axis where it fits)."""
+block, and every window must lie in the grid, fit the LDS budget of its kind
+(kind 0: 8 B per node; kind 1: 8 B per node plus 16 B per cell; kind 1 where
+it holds the whole grid, else kind 0 where that does, else kind 1 below 400
+nodes per axis), and hold each of its nodes with the kind's margin on every
+side (45 or 30 nodes; less only where the grid ends; the whole axis where it
+fits)."""
 import numpy as np
 import pytest
 
 from paper_1504_00084_amd import mesh_sdd as M
 
-WIN, MARGIN, CORE = 140, 45, 50
+LDS = 156800
+MARGIN, CORE, SIDE = {0: 45, 1: 30}, {0: 50, 1: 21}, {0: 140, 1: 81}
+
+
+def window_bytes(kind, tw, th):
+    nodes = tw * th * 8
+    return ((nodes + 15) & ~15) + (tw - 1) * (th - 1) * 16 if kind else nodes
+
 
 CASES = [
     # n_xi, n_eta, sub_xi, sub_eta, per_xi, per_eta, stride
@@ -25,6 +35,10 @@ CASES = [
     (449, 65, 8, 2, 1, 0, 0),
     (65, 449, 2, 8, 0, 0, 0),
     (513, 5, 4, 2, 0, 1, 0),
+    (385, 49, 8, 2, 1, 0, 0),
+    (385, 65, 8, 2, 1, 0, 0),
+    (81, 81, 4, 4, 0, 0, 0),
+    (97, 97, 4, 4, 0, 0, 0),
 ]
 
 
@@ -51,35 +65,49 @@ def test_work_order_is_a_blocked_permutation_with_windows(case):
     # blocks cover [0, Ms) in order
     assert blocks[0, 0] == 0 and blocks[-1, 1] == len(ranks)
     assert np.all(blocks[1:, 0] == blocks[:-1, 1]) and np.all(blocks[:, 1] > blocks[:, 0])
-    fits_x, fits_y = n_xi <= WIN, n_eta <= WIN
+    if window_bytes(1, n_xi, n_eta) <= LDS:
+        kind = 1   # the whole grid in a three-field window
+    elif window_bytes(0, n_xi, n_eta) <= LDS:
+        kind = 0   # the whole grid in a two-field window
+    else:
+        kind = 1 if max(n_xi, n_eta) < 400 else 0
+    assert set(blocks[:, 6]) == {kind}
     seen = set()
-    for b0, b1, i0, j0, tw, th in blocks:
+    for b0, b1, i0, j0, tw, th, k in blocks:
         r = ranks[b0:b1]
         assert np.all(np.diff(r) > 0)   # ranks ascending inside a block
         assert 0 <= i0 and i0 + tw <= n_xi and 0 <= j0 and j0 + th <= n_eta
-        assert tw >= 2 and th >= 2 and tw * th <= WIN * WIN
+        assert tw >= 2 and th >= 2 and window_bytes(k, tw, th) <= LDS
         ii, jj = i[r], j[r]
         # one block of the grid per run, each block once
-        key = (int(ii[0]) // (n_xi if tw == n_xi else CORE), int(jj[0]) // (n_eta if th == n_eta else CORE))
+        key = (int(ii[0]) // (n_xi if tw == n_xi else CORE[k]), int(jj[0]) // (n_eta if th == n_eta else CORE[k]))
         assert key not in seen
         seen.add(key)
         for pos, lo, w, n in ((ii, i0, tw, n_xi), (jj, j0, th, n_eta)):
             if w == n:   # the whole axis
                 continue
             left, right = pos - lo, lo + w - 1 - pos
-            assert np.all(left >= np.minimum(MARGIN, pos)), (case, lo, w)
-            assert np.all(right >= np.minimum(MARGIN, n - 1 - pos)), (case, lo, w)
-        if fits_x and fits_y and n_xi * n_eta <= WIN * WIN:
+            assert np.all(left >= np.minimum(MARGIN[k], pos)), (case, lo, w)
+            assert np.all(right >= np.minimum(MARGIN[k], n - 1 - pos)), (case, lo, w)
+        if window_bytes(k, n_xi, n_eta) <= LDS:
             assert (i0, j0, tw, th) == (0, 0, n_xi, n_eta) and len(blocks) == 1
+        elif n_xi == n_eta:
+            assert tw == th == SIDE[k]
 
 
 def test_non_square_windows_use_the_whole_short_axis():
     d = M.make_desc(449, 65, 8, 2, 1, 0)
     _, blocks = M.mesh_sdd_desc_work_order(d)
-    assert set(map(tuple, blocks[:, 4:6])) == {(301, 65)}   # 19600 // 65 = 301 along xi
+    assert set(map(tuple, blocks[:, 4:7])) == {(301, 65, 0)}   # 19600 // 65 = 301 along xi
     d = M.make_desc(65, 449, 2, 8, 0, 0)
     _, blocks = M.mesh_sdd_desc_work_order(d)
-    assert set(map(tuple, blocks[:, 4:6])) == {(65, 301)}
+    assert set(map(tuple, blocks[:, 4:7])) == {(65, 301, 0)}
+    d = M.make_desc(385, 65, 8, 2, 1, 0)   # kind 1: 1544 w - 1024 <= 156800 along xi
+    _, blocks = M.mesh_sdd_desc_work_order(d)
+    assert set(map(tuple, blocks[:, 4:7])) == {(102, 65, 1)}
+    d = M.make_desc(385, 49, 8, 2, 1, 0)   # the whole grid in a two-field window (150 920 B)
+    _, blocks = M.mesh_sdd_desc_work_order(d)
+    assert set(map(tuple, blocks[:, 4:7])) == {(385, 49, 0)}
 
 
 def test_invalid_strides_are_rejected():
