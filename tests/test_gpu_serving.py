@@ -338,3 +338,41 @@ def test_windows_of_non_square_grids(M, ctx, oracle_lib):
             % ", ".join(it.name for it in insts))
     finally:
         H.close()
+
+
+def edge_instance(n, sub, per_xi, K, N, instance_id):
+    x, y = W.uniform_mesh(n, n)
+    ux, uy = W.gaussian_bump_grad(x, y, 0.45, 0.55, 0.05)
+    rho = W.arc_length_monitor(ux, uy, 2.0)
+    b = W.boundary_from_mesh(x, y)
+    return W.Instance("edge%d_%dx%d_K%d_N%d" % (n, sub[0], sub[1], K, N), n, n, sub[0], sub[1], per_xi, 0, 1.0, 1.0,
+                      0.01, K, N, rho, x, y, b, b.copy(), seed=3, instance_id=instance_id)
+
+
+def test_edge_instances_alone_batched_and_against_the_oracle(M, ctx, oracle_lib):
+    """Limits of the stepping loop and of the windows, in one batch and
+    alone: the smallest grid (4 x 4, every interior node an interface node)
+    with K = 1 and a single partial chunk (N = 65); a 5 x 5 grid periodic in
+    xi with K = 3 (less than one quarter of four substeps) and N = 129 (a full
+    chunk and one path); a 161^2 grid cut into window blocks with K = 7.
+    Alone and batched must agree bitwise; every node of the small grids and
+    sampled nodes of the large one against the oracle."""
+    from gpu_helpers import compare, oracle_solve
+    insts = [edge_instance(4, (3, 3), 0, 1, 65, 51), edge_instance(5, (4, 1), 1, 3, 129, 52),
+             edge_instance(161, (8, 8), 0, 7, 200, 53)]
+    H = Handles(M, ctx, insts, M.FP32)
+    try:
+        alone = solve_alone(M, H, insts)
+        pairs = [M.host_result(m) for m in H.m]
+        M.mesh_sdd_solve_batch(H.h, steps_for(M, insts), [r for _, r in pairs])
+        batched = [M.result_dict(a, r, m) for (a, r), m in zip(pairs, H.m)]
+        for q, it in enumerate(insts):
+            assert same(alone[q], batched[q]), it.name
+            nodes = None if H.m[q] < 100 else np.unique(np.linspace(0, H.m[q] - 1, 6).astype(np.int32))
+            ora = oracle_solve(oracle_lib, it, nodes=nodes)
+            s = compare(alone[q], ora, nodes=nodes, label=it.name)
+            assert s["err"] <= 1e-5 and s["flips"] == 0, it.name
+            steps = alone[q]["executed_path_steps"]
+            assert 0 < steps <= H.m[q] * it.n_paths * it.K
+    finally:
+        H.close()
