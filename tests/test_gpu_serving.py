@@ -376,3 +376,37 @@ def test_edge_instances_alone_batched_and_against_the_oracle(M, ctx, oracle_lib)
             assert 0 < steps <= H.m[q] * it.n_paths * it.K
     finally:
         H.close()
+
+
+def test_serving_blocked_grids_over_several_ticks(M):
+    """Served requests on grids cut into window blocks, each large enough
+    (~10^10 path-steps) to be split over several scheduler ticks, so the
+    windowed jobs of a tick cover partial runs of a block's items: the
+    results must equal the requests solved alone, bitwise."""
+    rng = np.random.default_rng(21)
+    insts = [W.random_instance(rng, 0, n_paths=20000, sizes=(257,), subs=(8,)),
+             W.random_instance(rng, 1, n_paths=20000, sizes=(161,), subs=(8,)),
+             W.random_instance(rng, 2, n_paths=3000, sizes=(65,))]
+    for q, it in enumerate(insts):
+        it.instance_id = 400 + q
+    c = M.mesh_sdd_ctx_create(0)
+    H = Handles(M, c, insts, M.FP32)
+    try:
+        assert [M.mesh_sdd_get_launch(h).table_level for h in H.h[:2]] == [3, 3]
+        alone = solve_alone(M, H, insts)
+        ticks0 = M.mesh_sdd_ctx_stats(c).ticks
+        tickets = [M.mesh_sdd_submit(h, s) for h, s in zip(H.h, steps_for(M, insts))]
+        outs = []
+        for q, t in enumerate(tickets):
+            arrs, res = M.host_result(H.m[q])
+            assert M.mesh_sdd_wait(c, t, res, 120_000)
+            outs.append(M.result_dict(arrs, res, H.m[q]))
+        ticks = M.mesh_sdd_ctx_stats(c).ticks - ticks0
+        work = [H.m[q] * it.n_paths * it.K for q, it in enumerate(insts)]
+        say("served %s over %d ticks (nominal %.2e path-steps)" % ([it.name for it in insts], ticks, sum(work)))
+        assert ticks >= 3
+        for q, it in enumerate(insts):
+            assert same(alone[q], outs[q]), it.name
+    finally:
+        H.close()
+        M.mesh_sdd_ctx_destroy(c)
