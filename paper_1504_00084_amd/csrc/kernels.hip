@@ -209,7 +209,7 @@ __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t w
     // each gather adds one lane offset to a scalar base, and the LDS address
     // is one 24-bit multiply-add
     const uint32_t ci = __umul24((uint32_t)cy, (uint32_t)C.nx1) + (uint32_t)cx;   // cell
-    const GLOBAL f32x4 *cell = (const GLOBAL f32x4 *)((const GLOBAL char *)C.cells + ci * 48u);
+    const GLOBAL f32x4 *cell = (const GLOBAL f32x4 *)((const GLOBAL char *)C.cells + __umul24(ci, 48u));
     const GLOBAL f32x4 *coef = (const GLOBAL f32x4 *)((const GLOBAL char *)C.coef_y + (ci << 4));
     float r00, r10, r01, r11, g00, g10, g01, g11;
     f32x4 G;   // dt rho_eta coefficients
@@ -220,8 +220,22 @@ __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t w
         r00 = c00.x, r10 = c10.x, r01 = c01.x, r11 = c11.x;
         g00 = c00.y, g10 = c10.y, g01 = c01.y, g11 = c11.y;
     } else if (TAB == 3 || TAB == 4) {
+        // Lanes outside the window read the cell record, which keeps its corner
+        // values in the window's order (rho, dt rho_xi per node, row by row):
+        // both branches load into the same registers, so neither waits for its
+        // loads before the join.  The LDS branch comes first, so a record load
+        // waits only for LDS reads before it overwrites their registers, never a
+        // gather for an LDS read.  The two-field window's coefficients come from
+        // the plane or the record through one gather issued ahead of both.
         const int rx = cx - win.i0, ry = cy - win.j0;
-        if ((uint32_t)rx < (uint32_t)win.w1 && (uint32_t)ry < (uint32_t)win.h1) {
+        const bool outside = ((uint32_t)rx >= (uint32_t)win.w1) | ((uint32_t)ry >= (uint32_t)win.h1);
+        if (TAB == 3) G = *(outside ? cell + 2 : coef);
+        if (outside) {
+            const f32x4 A = cell[0], B = cell[1];
+            r00 = A.x, g00 = A.y, r10 = A.z, g10 = A.w;
+            r01 = B.x, g01 = B.y, r11 = B.z, g11 = B.w;
+            if (TAB == 4) G = cell[2];
+        } else {
             const uint32_t off = __umul24((uint32_t)ry, (uint32_t)win.tw << 3) + ((uint32_t)rx << 3);
             const float2 *t2 = (const float2 *)((const char *)tab + off);
             const float2 c00 = t2[0], c10 = t2[1], c01 = t2[win.tw], c11 = t2[win.tw + 1];
@@ -231,21 +245,12 @@ __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t w
                 const uint32_t co = (uint32_t)win.coff + __umul24((uint32_t)ry, (uint32_t)win.w1 << 4) +
                                     ((uint32_t)rx << 4);
                 G = *(const f32x4 *)((const char *)tab + co);
-            } else {
-                G = *coef;
             }
-        } else {
-            // outside the window: the whole record, whose lines one lane then
-            // shares for its three gathers (the same coefficients as the plane)
-            const f32x4 A = cell[0], B = cell[1];
-            r00 = A.x, r10 = A.y, r01 = A.z, r11 = A.w;
-            g00 = B.x, g10 = B.y, g01 = B.z, g11 = B.w;
-            G = cell[2];
         }
     } else {
         const f32x4 A = cell[0], B = cell[1];
-        r00 = A.x, r10 = A.y, r01 = A.z, r11 = A.w;
-        g00 = B.x, g10 = B.y, g01 = B.z, g11 = B.w;
+        r00 = A.x, g00 = A.y, r10 = A.z, g10 = A.w;
+        r01 = B.x, g01 = B.y, r11 = B.z, g11 = B.w;
     }
     // the two-field table kernel reads the coefficients from the compact
     // plane (its only gather: better L1 reuse), the window kernel too inside
@@ -1213,10 +1218,12 @@ __global__ void prep_cells_kernel(const double *__restrict__ rho, const double *
     const int cx = idx % nx1, cy = idx / nx1;
     const size_t a = (size_t)cy * n_xi + cx, b = a + n_xi;
     const double *f[3] = {rho, rx, ry};
-    // rho and dt rho_xi: the four corner values, exactly the FP32 node tables'
-    cells[3 * (size_t)idx] = make_float4((float)rho[a], (float)rho[a + 1], (float)rho[b], (float)rho[b + 1]);
-    cells[3 * (size_t)idx + 1] = make_float4((float)(grad_scale * rx[a]), (float)(grad_scale * rx[a + 1]),
-                                             (float)(grad_scale * rx[b]), (float)(grad_scale * rx[b + 1]));
+    // rho and dt rho_xi at the four corners, exactly the FP32 node tables'
+    // values, in their order: (rho, dt rho_xi) of nodes 00, 10, then of 01, 11
+    cells[3 * (size_t)idx] = make_float4((float)rho[a], (float)(grad_scale * rx[a]), (float)rho[a + 1],
+                                         (float)(grad_scale * rx[a + 1]));
+    cells[3 * (size_t)idx + 1] = make_float4((float)rho[b], (float)(grad_scale * rx[b]), (float)rho[b + 1],
+                                             (float)(grad_scale * rx[b + 1]));
     {   // dt rho_eta in coefficient form a + b tx + c ty + d tx ty
         const double f00 = grad_scale * f[2][a], f10 = grad_scale * f[2][a + 1];
         const double f01 = grad_scale * f[2][b], f11 = grad_scale * f[2][b + 1];

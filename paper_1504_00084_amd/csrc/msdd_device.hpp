@@ -82,7 +82,7 @@ struct InstView {
     const uint32_t *node_r;
 
     // FP32 path: per-cell records of three float4, (n_xi-1)(n_eta-1) cells:
-    // rho and dt rho_xi at the four corners (00, 10, 01, 11), then dt rho_eta
+    // (rho, dt rho_xi) at the corners 00, 10, then 01, 11, then dt rho_eta
     // in coefficient form a + b tx + c ty + d tx ty; the same coefficients
     // again as a compact plane (coef_y, read by the kernels that take rho and
     // dt rho_xi from LDS); the FP32 node tables of rho and dt rho_xi

@@ -14,8 +14,8 @@ namespace msdd {
 hipError_t launch_prep_gradient(const double *rho_in, int n_xi, int n_eta, int per_xi, int per_eta,
                                 double *rho, double *rho_xi, double *rho_eta, hipStream_t s);
 
-// a0 (FP32 path): per-cell records of three float4: rho and s rho_xi at the
-// four corners, then s rho_eta in bilinear coefficient form, with s =
+// a0 (FP32 path): per-cell records of three float4: (rho, s rho_xi) at the
+// corners 00, 10, then 01, 11, then s rho_eta in bilinear coefficient form, with s =
 // grad_scale (the substep dt); coef_y gets the last float4 of every record
 // again, as a compact plane.
 hipError_t launch_prep_cells(const double *rho, const double *rho_xi, const double *rho_eta, int n_xi,
