@@ -103,7 +103,7 @@ struct ConstF {
     float c_rad;   // -4 ln2 dt, so that sqrt(c_rad log2 u) = sqrt(2 dt) sqrt(-2 ln u)
     float sq2dt;   // sqrt(2 dt) (diagnostics only)
     float delta;   // sqrt(18.5 dt): farther from every side, no bridge crossing can matter
-    const GLOBAL f32x4 *cells;   // per cell: rho corners, dt rho_xi corners, dt rho_eta coefficients
+    const GLOBAL f32x4 *cells;   // per cell: (rho, dt rho_xi) at corners 00, 10, 01, 11; dt rho_eta coefficients
     const GLOBAL f32x4 *coef_y;  // per cell: the dt rho_eta coefficients alone (compact)
 };
 
