@@ -228,7 +228,7 @@ int mesh_sdd_desc_interface_nodes(const mesh_sdd_desc *desc, int32_t *i, int32_t
 /* Work order of the FP32 kernels for a descriptor and an interface stride
  * (0 or 1: every interface node; else the sampling of section 3.6, with the
  * same validation as mesh_sdd_step.interface_stride).  The nodes that run
- * paths are stepped block by block (blocks row-major, ranks ascending inside
+ * paths are stepped block by block (blocks in Z order, ranks ascending inside
  * a block); each block has the window of the monitor tables that the
  * windowed kernel stages in LDS around it, clamped to the grid, the whole
  * axis where it fits.  Kind 0: windows of (rho, dt rho_xi) per node, at

