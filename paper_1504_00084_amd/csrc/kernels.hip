@@ -205,11 +205,14 @@ __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t w
     const int cy = min((int)(P.y * C.fny1), C.ny1 - 1);
     tx = P.x * C.fnx1 - (float)cx;
     ty = P.y * C.fny1 - (float)cy;
-    // 32-bit indices and byte offsets (grids hold far fewer than 2^24 nodes):
-    // each gather adds one lane offset to a scalar base, and the LDS address
-    // is one 24-bit multiply-add
+    // 32-bit indices and byte offsets (a grid has at most 8193^2 nodes, 2^26
+    // cells): each gather adds one lane offset to a scalar base, and the LDS
+    // address is one 24-bit multiply-add.  The record offset (48 B per cell,
+    // below 2^32) is the sum of two 24-bit products, each exact: the cell
+    // index itself can exceed 24 bits.
     const uint32_t ci = __umul24((uint32_t)cy, (uint32_t)C.nx1) + (uint32_t)cx;   // cell
-    const GLOBAL f32x4 *cell = (const GLOBAL f32x4 *)((const GLOBAL char *)C.cells + __umul24(ci, 48u));
+    const uint32_t rec = __umul24((uint32_t)cy, (uint32_t)C.nx1 * 48u) + __umul24((uint32_t)cx, 48u);
+    const GLOBAL f32x4 *cell = (const GLOBAL f32x4 *)((const GLOBAL char *)C.cells + rec);
     const GLOBAL f32x4 *coef = (const GLOBAL f32x4 *)((const GLOBAL char *)C.coef_y + (ci << 4));
     float r00, r10, r01, r11, g00, g10, g01, g11;
     f32x4 G;   // dt rho_eta coefficients

@@ -131,3 +131,46 @@ def test_largest_mix_instance_windowed_vs_oracle(M, ctx, oracle_lib):
     finally:
         for h in hs:
             M.mesh_sdd_destroy(h)
+
+
+def test_cell_indices_beyond_24_bits_vs_oracle(M, ctx, oracle_lib):
+    """A 4101^2 grid has 4100^2 = 16 810 000 cells, more than 2^24, so the
+    cell index of its top rows (cy >= 4092 on the interface column i = 2050)
+    needs more than 24 bits and the 48-B record offsets must not truncate
+    it.  rho = exp(8 eta^4) gives a drift rho_eta / rho = 32 eta^3: 32 at the
+    top rows against 0 at the bottom ones, so a record read from a wrong row
+    moves the estimate far beyond the tolerance.  The windowed kernel (lanes
+    outside the window read records) and the cell-record kernel
+    (monitor_table = 1, every substep reads a record) must both agree with
+    the oracle on nodes of the top rows and a few lower ones, and with each
+    other bitwise."""
+    n = 4101
+    x, y = W.uniform_mesh(n, n)
+    rho = np.exp(8.0 * y ** 4)   # y = eta on the uniform mesh
+    b = W.boundary_from_mesh(x, y)
+    inst = W.Instance("tall4101_2x1", n, n, 2, 1, 0, 0, 1.0, 1.0, 4e-4, 40, 256, rho, x, y, b, b.copy(), seed=5,
+                      instance_id=77)
+    h = M.mesh_sdd_create(ctx, M.desc_for(inst, M.FP32))
+    try:
+        M.mesh_sdd_set_monitor(h, inst.rho)
+        m = M.mesh_sdd_num_interface_nodes(h)
+        assert m == n - 2   # the column i = 2050, j = 1 .. 4099
+        assert M.mesh_sdd_get_launch(h).table_level == 3
+        step = M.make_step(inst.x, inst.y, inst.bnd_t0, inst.bnd_t1, paths_per_node=inst.n_paths)
+        out = []
+        for monitor_table in (0, 1):
+            M.mesh_sdd_set_launch(ctx, M.make_launch(monitor_table=monitor_table) if monitor_table else None)
+            try:
+                arrs, res = M.host_result(m)
+                M.mesh_sdd_solve_interfaces(h, step, res)
+                out.append(M.result_dict(arrs, res, m))
+            finally:
+                M.mesh_sdd_set_launch(ctx, None)
+    finally:
+        M.mesh_sdd_destroy(h)
+    for k in ("mean_x", "mean_y", "se_x", "se_y", "exit_frac"):
+        assert np.array_equal(out[0][k], out[1][k]), k
+    nodes = np.array([0, 2048, 3900, 4040, 4085, 4091, 4094, 4096, 4098], dtype=np.int32)   # rank = j - 1
+    ora = oracle_solve(oracle_lib, inst, nodes=nodes)
+    s = compare(out[0], ora, nodes=nodes, label=inst.name + " windowed and records, sampled")
+    assert s["err"] <= 1e-5 and s["flips"] <= 1
