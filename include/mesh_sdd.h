@@ -105,7 +105,7 @@ typedef struct {
     const double *x_cur, *y_cur;     /* mesh at t^n, [n_eta][n_xi]                   */
     const double *bnd_t0, *bnd_t1;   /* boundary arrays at t^n and t^{n+1}; pass the
                                         same pointer twice if only one level exists */
-    int64_t paths_per_node;          /* N >= 1; ignored when target_se > 0           */
+    int64_t paths_per_node;          /* 1 <= N <= 2^31; ignored when target_se > 0   */
     double target_se;                /* > 0: N = min(max_paths, ceil(2 tau L^2/se^2)) */
     int64_t max_paths;               /* cap for target_se (0: 1e6)                   */
     uint32_t mesh_step;              /* enters the RNG counter (low 16 bits)         */
@@ -275,14 +275,18 @@ int mesh_sdd_interface_nodes(const mesh_sdd *inst, int32_t *i, int32_t *j);
 /* ---- solving -------------------------------------------------------------- */
 
 /* Blocking solve of one mesh step.  E_STATE before set_monitor; E_INVAL on
- * a bad step (null pointers, N < 1, corner values of the boundary arrays
- * that disagree by more than 1e-12 (Lx + Ly), host inputs that are not
- * finite). */
+ * a bad step (null pointers, N outside [1, 2^31], corner values of the
+ * boundary arrays that disagree by more than 1e-12 (Lx + Ly), host inputs
+ * that are not finite) and on a request too large for 32-bit work-item
+ * numbers: FP32, more than 2^32 - 2^20 (node, path-chunk) items (nodes that
+ * run paths x ceil(N / chunk_paths)); FP64, 2^24 or more (node, 256-path
+ * block) pairs.  Nothing is allocated or launched for such a request. */
 int mesh_sdd_solve_interfaces(mesh_sdd *inst, const mesh_sdd_step *step, mesh_sdd_result *result);
 
 /* Blocking solve of `count` instances: all FP32 instances run in ONE
- * persistent launch over a shared (instance, node, path-chunk) work queue;
- * FP64 instances run one launch each.  Per-instance status codes go to
+ * persistent launch over a shared (instance, node, path-chunk) work queue
+ * (several launches, in order, where their items together exceed
+ * 2^32 - 2^20); FP64 instances run one launch each.  Per-instance status codes go to
  * status[] (may be NULL); the return value is the first error or OK. */
 int mesh_sdd_solve_batch(mesh_sdd *const *insts, const mesh_sdd_step *steps, mesh_sdd_result *results,
                          int32_t count, int32_t *status);

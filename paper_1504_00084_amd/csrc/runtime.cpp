@@ -455,6 +455,11 @@ int sample_set(mesh_sdd &inst, int stride, const SampleSet **out)
     return MESH_SDD_OK;
 }
 
+// Work items of one FP32 launch (and of one request) are numbered in 32 bits,
+// and the queue counters pass the last item by one pop per wave: 2^20 of
+// headroom below 2^32.
+constexpr uint32_t kMaxLaunchItems = 0xFFF00000u;
+
 // Allocate the request's device buffers, stage its inputs and run the prep
 // kernels; builds the work items.  Caller holds gpu_mu.
 int stage_request(Request &r, const mesh_sdd_step *dev_step)
@@ -479,6 +484,14 @@ int stage_request(Request &r, const mesh_sdd_step *dev_step)
         chunks = (uint32_t)((r.N + r.chunk_paths - 1) / r.chunk_paths);
     r.chunks_per_node = chunks;
     const size_t n_part = (size_t)Ms * chunks;
+    // the kernels number (node, chunk) items and partials in 32 bits; an FP64
+    // launch runs one 256-thread block per item, within HIP's 2^32 work-items
+    if (!fp64 && n_part > (size_t)kMaxLaunchItems)
+        return fail(MESH_SDD_E_INVAL, "%zu (node, chunk) work items, more than 2^32 - 2^20 (fewer paths per node or "
+                    "an interface stride)", n_part);
+    if (fp64 && n_part >= ((size_t)1 << 32) / msdd::kFp64Block)
+        return fail(MESH_SDD_E_INVAL, "FP64: %zu (node, block) pairs, at least 2^24 (fewer paths per node or an "
+                    "interface stride)", n_part);
 
     for (DevBuf *b : {&r.x64, &r.y64, &r.b0, &r.b1, &r.xpad, &r.ypad, &r.xpad_f, &r.ypad_f, &r.b0f, &r.b1f,
                       &r.view, &r.partials, &r.spans, &r.out, &r.steps_total})
@@ -803,6 +816,25 @@ int run_blocking(mesh_sdd_ctx *ctx, std::vector<std::shared_ptr<Request>> &reqs,
     size_t base = 0;
     mesh_sdd_launch l = default_launch();
     bool have_launch = false;
+    // one persistent launch over the FP32 requests gathered so far
+    auto launch_group = [&]() {
+        if (fp32_reqs.empty()) return;
+        double ms = 0.0;
+        int rc = run_fp32_launch(ctx, views, ranges, sets, l, &ms);
+        for (size_t q : fp32_reqs) {
+            Request &r = *reqs[q];
+            int rq = rc;
+            if (rq == MESH_SDD_OK) rq = finalize_request(ctx, r);
+            r.device_ms = ms;
+            status[q] = rq;
+            if (rq != MESH_SDD_OK) r.error = g_last_error;
+        }
+        views.clear();
+        ranges.clear();
+        sets.clear();
+        fp32_reqs.clear();
+        base = 0;
+    };
     for (size_t q = 0; q < reqs.size(); ++q) {
         Request &r = *reqs[q];
         int rc = stage_request(r, dev_steps[q]);
@@ -819,6 +851,10 @@ int run_blocking(mesh_sdd_ctx *ctx, std::vector<std::shared_ptr<Request>> &reqs,
             status[q] = rc;
             if (rc != MESH_SDD_OK) r.error = g_last_error;
         } else {
+            // a launch numbers its items in 32 bits: start another one first
+            // where this request's items would not fit (every request fits
+            // alone, stage_request checks it)
+            if (base + r.n_items > (size_t)kMaxLaunchItems) launch_group();
             const uint32_t slot = (uint32_t)views.size();
             views.push_back(r.v);
             sets.push_back(r.ss);
@@ -833,18 +869,7 @@ int run_blocking(mesh_sdd_ctx *ctx, std::vector<std::shared_ptr<Request>> &reqs,
             }
         }
     }
-    if (!fp32_reqs.empty()) {
-        double ms = 0.0;
-        int rc = run_fp32_launch(ctx, views, ranges, sets, l, &ms);
-        for (size_t q : fp32_reqs) {
-            Request &r = *reqs[q];
-            int rq = rc;
-            if (rq == MESH_SDD_OK) rq = finalize_request(ctx, r);
-            r.device_ms = ms;
-            status[q] = rq;
-            if (rq != MESH_SDD_OK) r.error = g_last_error;
-        }
-    }
+    launch_group();
     for (auto &r : reqs) release_request_buffers(*r);
     for (int s : status)
         if (s != MESH_SDD_OK) return s;

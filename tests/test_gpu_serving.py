@@ -196,6 +196,47 @@ def test_error_paths(M, ctx):
             M.mesh_sdd_destroy(h)
 
 
+def test_requests_beyond_32_bit_item_numbers_are_rejected(M, ctx):
+    """The kernels number (node, chunk) work items in 32 bits: a request with
+    more than 2^32 - 2^20 of them (FP32), or an FP64 request of 2^24 or more
+    256-path blocks, is refused with E_INVAL when it is staged, before any
+    allocation or launch.  Here 753 nodes at N = 2^31: 753 * 2^24 FP32 items,
+    753 * 2^23 FP64 blocks.  In a batch the other request is still solved,
+    with its results bitwise those of a solve alone; submitted for serving,
+    the request is refused too (its partials alone exceed the budget)."""
+    big, small = W.config2(1 << 31), W.config1(640)
+    big.K = small.K = 20
+    huge = {"paths_per_node": 1 << 31}
+    for prec in (M.FP32, M.FP64):
+        h = M.mesh_sdd_create(ctx, M.desc_for(big, prec))
+        try:
+            M.mesh_sdd_set_monitor(h, big.rho)
+            arrs, res = M.host_result(M.mesh_sdd_num_interface_nodes(h))
+            with pytest.raises(M.MeshSddError) as e:
+                M.mesh_sdd_solve_interfaces(h, M.make_step(big.x, big.y, big.bnd_t0, big.bnd_t1, **huge), res)
+            assert e.value.code == M.E_INVAL and ("work items" in str(e.value) or "FP64" in str(e.value)), str(e.value)
+        finally:
+            M.mesh_sdd_destroy(h)
+    H = Handles(M, ctx, [big, small], M.FP32)
+    try:
+        st_small = M.make_step(small.x, small.y, small.bnd_t0, small.bnd_t1, paths_per_node=small.n_paths)
+        a1, r1 = M.host_result(H.m[1])
+        M.mesh_sdd_solve_interfaces(H.h[1], st_small, r1)
+        alone = M.result_dict(a1, r1, H.m[1])
+        pairs = [M.host_result(m) for m in H.m]
+        st_big = M.make_step(big.x, big.y, big.bnd_t0, big.bnd_t1, **huge)
+        with pytest.raises(M.MeshSddError) as e:
+            M.mesh_sdd_solve_batch(H.h, [st_big, st_small], [r for _, r in pairs])
+        assert e.value.code == M.E_INVAL
+        assert same(alone, M.result_dict(pairs[1][0], pairs[1][1], H.m[1]))
+        with pytest.raises(M.MeshSddError) as e:
+            t = M.mesh_sdd_submit(H.h[0], st_big)
+            M.mesh_sdd_wait(ctx, t, pairs[0][1], 60_000)
+        assert e.value.code in (M.E_BUDGET, M.E_INVAL)
+    finally:
+        H.close()
+
+
 def test_degenerate_cases(M, ctx):
     # no interface node at all
     inst = W.constant_problem(9, 1, 0, 0, tau=0.01, K=10, n_paths=100)
