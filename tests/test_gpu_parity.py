@@ -75,8 +75,8 @@ SMALL_CASES = {
 }
 
 
-def small_instance(name):
-    n_xi, n_eta, sx, sy, px, py, K, N, tau, Lx, Ly, mon = SMALL_CASES[name]
+def small_instance(name, cases=None):
+    n_xi, n_eta, sx, sy, px, py, K, N, tau, Lx, Ly, mon = (cases or SMALL_CASES)[name]
     x, y = W.uniform_mesh(n_xi, n_eta, Lx, Ly)
     if mon == "bump":
         ux, uy = W.gaussian_bump_grad(x / Lx, y / Ly, 0.45, 0.55, 0.02)
@@ -112,6 +112,55 @@ def test_small_cases_both_precisions(M, ctx, oracle_lib, name):
     g32 = gpu_solve(M, ctx, inst, M.FP32)
     s32 = compare(g32, ora, label=name + " fp32")
     assert s32["err"] <= 1e-5 * max(inst.Lx, inst.Ly)
+
+
+WINDOW_CASES = {
+    # grids whose node tables do not fit the LDS whole, so a single-instance
+    # launch runs the windowed kernel with its periodicity compiled in
+    # (name: as above); tau = 0.05 spreads the paths (sqrt(2 tau) = 0.32)
+    # across the seams and out of their windows.  K = 400 keeps the substep
+    # short against the drift's variation across the front (dt |grad b|
+    # about 0.05): with K = 60 one substep can amplify a perturbation of the
+    # position by a third, and the FP32 paths drift apart from the FP64 ones
+    # by 1e-5 within 20 substeps (the FP64 kernel still matches to 1e-12)
+    "win161_pery_8x8": (161, 161, 8, 8, 0, 1, 400, 512, 0.05, 1.0, 1.5, "bump"),
+    "win161_perxy_8x8": (161, 161, 8, 8, 1, 1, 400, 512, 0.05, 1.0, 1.0, "front"),
+    "win417_pery_4x4": (417, 417, 4, 4, 0, 1, 400, 256, 0.05, 1.0, 1.0, "bump"),
+    "win417_perxy_8x4": (417, 417, 8, 4, 1, 1, 400, 256, 0.05, 2.0, 1.0, "front"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(WINDOW_CASES))
+def test_windowed_kernel_with_every_periodicity(M, ctx, oracle_lib, name):
+    """Windowed launches with eta periodic, alone or with xi: three-field
+    windows (161^2) and two-field ones (417^2), seam nodes included.  The
+    windowed kernel and the cell-record kernel (monitor_table = 1) must give
+    the same bits, and sampled nodes must match the oracle."""
+    inst = small_instance(name, WINDOW_CASES)
+    h = M.mesh_sdd_create(ctx, M.desc_for(inst, M.FP32))
+    try:
+        M.mesh_sdd_set_monitor(h, inst.rho)
+        assert M.mesh_sdd_get_launch(h).table_level == 3
+        m = M.mesh_sdd_num_interface_nodes(h)
+        st = M.make_step(inst.x, inst.y, inst.bnd_t0, inst.bnd_t1, paths_per_node=inst.n_paths,
+                         mesh_step=inst.mesh_step)
+        out = []
+        for monitor_table in (0, 1):
+            M.mesh_sdd_set_launch(ctx, M.make_launch(monitor_table=1) if monitor_table else None)
+            try:
+                arrs, res = M.host_result(m)
+                M.mesh_sdd_solve_interfaces(h, st, res)
+                out.append(M.result_dict(arrs, res, m))
+            finally:
+                M.mesh_sdd_set_launch(ctx, None)
+    finally:
+        M.mesh_sdd_destroy(h)
+    for k in ("mean_x", "mean_y", "se_x", "se_y", "exit_frac"):
+        assert np.array_equal(out[0][k], out[1][k]), k
+    nodes = np.unique(np.linspace(0, m - 1, 8).astype(np.int32))
+    ora = oracle_solve(oracle_lib, inst, nodes=nodes)
+    s = compare(out[0], ora, nodes=nodes, label=name + " windowed == records, sampled")
+    assert s["err"] <= 1e-5 * max(inst.Lx, inst.Ly)
 
 
 def test_trajectories_match_oracle(M, ctx, oracle_lib):
