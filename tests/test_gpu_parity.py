@@ -163,6 +163,38 @@ def test_windowed_kernel_with_every_periodicity(M, ctx, oracle_lib, name):
     assert s["err"] <= 1e-5 * max(inst.Lx, inst.Ly)
 
 
+def test_batch_of_every_periodicity_equals_alone(M, ctx):
+    """The four windowed cases above and a Dirichlet one in one batch: the
+    launch mixes periodicities, so its windowed kernel reads them per
+    instance at run time instead of having them compiled in; every result
+    must equal the instance's solve alone bitwise."""
+    insts = [small_instance(n, WINDOW_CASES) for n in sorted(WINDOW_CASES)] + [small_instance("bump17_dir_2x2")]
+    for q, it in enumerate(insts):
+        it.instance_id = 40 + q
+    hs = [M.mesh_sdd_create(ctx, M.desc_for(it, M.FP32)) for it in insts]
+    try:
+        steps, alone, pairs = [], [], []
+        for h, it in zip(hs, insts):
+            M.mesh_sdd_set_monitor(h, it.rho)
+            m = M.mesh_sdd_num_interface_nodes(h)
+            steps.append(M.make_step(it.x, it.y, it.bnd_t0, it.bnd_t1, paths_per_node=it.n_paths,
+                                     mesh_step=it.mesh_step))
+            arrs, res = M.host_result(m)
+            M.mesh_sdd_solve_interfaces(h, steps[-1], res)
+            alone.append(M.result_dict(arrs, res, m))
+            pairs.append(M.host_result(m))
+        M.mesh_sdd_solve_batch(hs, steps, [r for _, r in pairs])
+        for q, it in enumerate(insts):
+            b = M.result_dict(pairs[q][0], pairs[q][1], len(alone[q]["mean_x"]))
+            for k in ("mean_x", "mean_y", "se_x", "se_y", "exit_frac"):
+                assert np.array_equal(alone[q][k], b[k]), (it.name, k)
+            assert alone[q]["executed_path_steps"] == b["executed_path_steps"], it.name
+        say("batch of %s == alone (bitwise)" % ", ".join(it.name for it in insts))
+    finally:
+        for h in hs:
+            M.mesh_sdd_destroy(h)
+
+
 def test_trajectories_match_oracle(M, ctx, oracle_lib):
     """Tiny brute force: N = 4 paths, K = 5 substeps, per-substep positions
     and normals of the GPU debug kernel against the oracle's."""
