@@ -829,12 +829,14 @@ __global__ __launch_bounds__(BLOCK) void paths_fp32(const InstView *__restrict__
 // Windowed kernel for launches whose node tables do not fit the LDS whole:
 // several instances, or one large grid.  The host splits the launch into
 // jobs: the items of one range whose nodes lie in one block of the grid,
-// with a window of the node tables around that block (the block plus a
-// margin, clamped to the grid), in block order, cut into per-XCD queues
-// (JobQueues).  A workgroup (1024 threads, one per CU) pops a job, copies the window of (rho, dt rho_xi) into LDS, and its waves run
-// the job's items with the wave loop above; a lane whose path has left the
-// window reads the corner values from the cell record instead (TAB 3 in
-// substep_f32), so the results are those of every other kernel.  The waves
+// with a window of the monitor tables around that block (the block plus a
+// margin, clamped to the grid), blocks in Z order, cut into per-XCD queues
+// (JobQueues).  A workgroup (1024 threads, one per CU) pops a job and copies
+// its window into LDS: (rho, dt rho_xi) per node (kind 0), and also the dt
+// rho_eta coefficients of its cells (kind 1).  Its waves run the job's items
+// with the wave loop above; a lane whose path has left the window reads the
+// cell record instead (TAB 3 and 4 in substep_f32), so the results are those
+// of every other kernel.  The waves
 // keep their items' end states in `ends` as the table kernel does.
 // PER >= 0: every instance of the launch has that periodicity (compiled
 // in); a job of another kind is skipped, untouched.
