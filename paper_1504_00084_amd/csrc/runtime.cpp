@@ -631,8 +631,11 @@ int run_fp32_launch(mesh_sdd_ctx *ctx, const std::vector<InstView> &views, const
     if (level > 0 && ctx->ends.reserve((size_t)end_waves * 6u * cap * sizeof(float)))
         return fail(MESH_SDD_E_NOMEM, "device allocation of the end-state buffer failed");
     // windowed launch: one job per (range, grid block), split so that no job
-    // holds more than 1/32 of a workgroup's share of the items, in block
-    // order, cut into per-XCD queues of equal nominal work
+    // holds more than 1/32 of a workgroup's share of the items (1/256 in a
+    // block of a grid cut into two-field windows: measured on the batched
+    // mix, whose 513^2 grids then run 5 % faster; whole-grid windows are
+    // refilled for every job, and three-field windows lose with smaller
+    // jobs), in block order, cut into per-XCD queues of equal nominal work
     std::vector<msdd::WinJob> jobs;
     msdd::JobQueues qs{};
     size_t win_lds = 32;
@@ -640,6 +643,7 @@ int run_fp32_launch(mesh_sdd_ctx *ctx, const std::vector<InstView> &views, const
     if (level == 3) {
         const size_t per = (size_t)ctx->cu_count * (size_t)per_cu * 32u;
         const size_t jmax = std::max<size_t>(64, (n_items + per - 1) / per);
+        const size_t jmax0 = std::max<size_t>(64, (n_items + per * 8 - 1) / (per * 8));
         for (size_t ri = 0; ri < ranges.size(); ++ri) {
             const WorkRange &w = ranges[ri];
             const InstView &v = views[w.inst];
@@ -649,8 +653,10 @@ int run_fp32_launch(mesh_sdd_ctx *ctx, const std::vector<InstView> &views, const
             for (const BlockRun &b : sets[w.inst]->blocks) {
                 const size_t qa = std::max(lo, (size_t)b.pos_begin * w.chunks);
                 const size_t qb = std::min(hi, (size_t)b.pos_end * w.chunks);
-                for (size_t q = qa; q < qb; q += jmax)
-                    jobs.push_back(msdd::WinJob{(uint32_t)ri, (uint32_t)q, (uint32_t)std::min(jmax, qb - q), b.i0,
+                const bool blocked0 = b.kind == 0 && (b.tw < v.n_xi || b.th < v.n_eta);
+                const size_t jm = blocked0 ? jmax0 : jmax;
+                for (size_t q = qa; q < qb; q += jm)
+                    jobs.push_back(msdd::WinJob{(uint32_t)ri, (uint32_t)q, (uint32_t)std::min(jm, qb - q), b.i0,
                                                 b.j0, b.tw, b.th, (uint32_t)b.kind});
                 if (qa < qb) win_lds = std::max(win_lds, window_bytes(b.kind, b.tw, b.th));
             }
