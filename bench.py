@@ -1,14 +1,19 @@
 """Benchmark of the interface-node Monte-Carlo solve on one MI355X.
 
-One step = one pass of the whole hot path over one mesh step of the
-rotating-bump workload (129x129 grid, 4x4 subdomains, 753 interface nodes,
-1e5 paths per node, K = 500 substeps): freeze the monitor (finite-difference
-table on the device), then estimate (x, y) at every interface node with the
-batched FP32 kernel.  Inputs are resident in HBM before the timed region.
+One step = one pass of the whole hot path over one mesh step of the periodic
+moving-front workload (257x257 grid, xi periodic, 8x8 subdomains, 3776
+interface nodes, 1e5 paths per node, K = 500 substeps, tau = 0.005): freeze
+the monitor (finite-difference table on the device), then estimate (x, y) at
+every interface node with the batched FP32 kernel.  Inputs are resident in
+HBM before the timed region.  It is the largest single-instance workload on
+which every node reaches a standard error of 1e-3.
 
-Prints ONE JSON line: throughput in executed path-steps per second, the
-FP64 plain kernel on the same inputs and path count (equal standard error),
-the roofline of the dominant kernel and the CPU oracle on a bounded sample.
+Prints ONE JSON line: throughput in executed path-steps per second; the FP64
+plain kernel on the same inputs and path count (equal standard error) with
+the FP32-FP64 difference of every node; the 64-instance batched mix in one
+persistent launch; a short serving run of the mix (FP32 and FP64 plain); the
+roofline of the dominant kernel; the CPU oracle on a bounded sample of every
+workload, with the per-node GPU-oracle differences on that sample.
 """
 from __future__ import annotations
 
@@ -25,24 +30,32 @@ sys.path.insert(0, ROOT)
 # VALU issue peak of MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz (one
 # non-packed VALU lane-operation per lane per clock).
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-# Algorithmic VALU issue slots per executed path-step (Philox 0.75 blocks,
-# two uniforms, Box-Muller, bilinear cell location and three fields, drift,
-# EM, side distance, exit and bridge pre-tests, substep counter), weighted by
-# the measured issue cost of each instruction class.
-W_SLOTS_PER_STEP = 86.5
 
-# HBM traffic of one paths_fp32 launch on the 129x129, 4x4 workload at the
-# default launch (single instance: the LDS-table kernel at level 2, 1024
-# threads per workgroup, one workgroup per CU, 128-path chunks), from two
-# rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE, KiB per
-# dispatch), each scaled by what the counter reads for a 1 GiB device copy in
-# the same run (FETCH_SIZE reads 524708 KiB: x2.0; WRITE_SIZE reads 1.0492e6
-# KiB: x1.0).  Most of the writes are L2 write-backs of the waves' end-state
-# buffers.  Valid only for the kernel code it was measured on
-# (kernels_code_sha1: SHA-1 of csrc/kernels.hip without comments); reported
-# as null otherwise.
-TRAFFIC_RECORD = {"kernels_sha1": "a66ea9c138f2fd0073ad12e22fe7f2c9808fb4cc", "fetch_kib": 8889.0,
-                  "write_kib": 247854.0, "fetch_scale": 2.0, "write_scale": 1.0}
+
+def w_slots(per_xi: int, per_eta: int) -> float:
+    """Algorithmic VALU issue slots of one executed path-step: Philox
+    (0.75 blocks: 15 32x32->64 multiplies at 1.3 slots, 15 three-input
+    XORs), two uniforms, Box-Muller (four transcendentals at 2 slots and one
+    multiply), bilinear cell location and three fields, drift (rcp), EM,
+    substep bookkeeping -- 79.5 slots on every path-step -- plus, per axis,
+    2 slots for a Dirichlet side distance (complement, minimum) or 4 for a
+    periodic wrap (floor, subtract, convert, add), plus 3 for the exit test
+    and bridge pre-test when some axis is Dirichlet.  Weights measured with
+    the VALU issue-cost probe; the values are the frozen ones: 86.5 for a
+    Dirichlet problem, 88.5 with one periodic axis, 87.5 with two."""
+    base = 79.5
+    axes = sum(4.0 if p else 2.0 for p in (per_xi, per_eta))
+    exit_tests = 0.0 if (per_xi and per_eta) else 3.0
+    return base + axes + exit_tests
+
+
+# HBM traffic of one launch of the headline kernel, from two rocprofv3 --pmc
+# runs of this script (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each
+# scaled by what the counter reads for a 1 GiB device copy in the same run.
+# Valid only for the kernel code it was measured on (kernels_sha1: SHA-1 of
+# csrc/kernels.hip without comments) and the workload named; null otherwise.
+TRAFFIC_RECORD = {"workload": None, "kernels_sha1": None, "fetch_kib": 0.0, "write_kib": 0.0,
+                  "fetch_scale": 1.0, "write_scale": 1.0}
 
 
 def kernels_code_sha1():
@@ -60,9 +73,9 @@ def kernels_code_sha1():
     return hashlib.sha1("\n".join(lines).encode()).hexdigest()
 
 
-def recorded_traffic():
+def recorded_traffic(workload: str):
     r = TRAFFIC_RECORD
-    if kernels_code_sha1() != r["kernels_sha1"]:
+    if r["workload"] != workload or kernels_code_sha1() != r["kernels_sha1"]:
         return None
     return 1024.0 * (r["fetch_kib"] * r["fetch_scale"] + r["write_kib"] * r["write_scale"])
 
@@ -71,28 +84,52 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def host_threads():
+    """Host cores this process may use for the oracle: the CPU affinity, cut
+    to the cgroup's CPU quota and to OMP_NUM_THREADS where those are set (a
+    GPU machine exposes its share of the host that way).  Returns (threads, info)."""
+    info = {"nproc": os.cpu_count()}
+    try:
+        info["affinity"] = len(os.sched_getaffinity(0))
+    except AttributeError:
+        info["affinity"] = os.cpu_count()
+    n = info["affinity"] or 1
+    try:
+        with open("/sys/fs/cgroup/cpu.max") as f:
+            q, p = f.read().split()[:2]
+        if q != "max":
+            info["cgroup_quota"] = float(q) / float(p)
+            n = min(n, max(1, int(info["cgroup_quota"])))
+    except (OSError, ValueError):
+        pass
+    omp = os.environ.get("OMP_NUM_THREADS")
+    if omp and omp.isdigit() and int(omp) > 0:
+        info["omp_num_threads"] = int(omp)
+        n = min(n, int(omp))
+    info["threads"] = n
+    return n, info
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--paths", type=int, default=100_000)
-    ap.add_argument("--workload", default="rotbump129", choices=["rotbump129", "front257"],
-                    help="step mode: the rotating bump 129^2 4x4 (the metric's workload), or the periodic "
-                         "tanh front 257^2 8x8 (windowed kernel)")
+    ap.add_argument("--workload", default="front257", choices=["front257", "rotbump129"],
+                    help="step mode: the periodic tanh front 257^2 8x8 (the headline), or the rotating bump "
+                         "129^2 4x4")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 plain comparison")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-serve", action="store_true", help="skip the serving burst of the step mode")
-    ap.add_argument("--tune", action="store_true",
-                    help="run the library's autotuner first (default: the library's default launch shape, the "
-                         "one the recorded HBM traffic was measured with)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and its parity check")
+    ap.add_argument("--no-mix", action="store_true", help="skip the batched 64-instance mix of the step mode")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving run of the step mode")
+    ap.add_argument("--tune", action="store_true", help="run the library's autotuner before timing")
     ap.add_argument("--launch", default="", help="fixed launch shape BLOCK,WAVES_PER_SIMD,CHUNK")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU work of the oracle sample")
+    ap.add_argument("--jsonl", default="", help="also write per-node parity and serving records to this JSONL file")
     ap.add_argument("--mode", default="step", choices=["step", "batch", "serve", "mp", "quality", "variants"],
-                    help="step: the metric line (rotating bump 129^2); batch: the 64-instance mix in one "
-                         "persistent launch; serve: Poisson request stream through submit/poll; mp: the "
-                         "rotating-bump moving-mesh loop; quality: five-ring mesh quality R against the "
-                         "single-domain mesh")
+                    help="step: the metric line; batch: the 64-instance mix in one persistent launch; serve: "
+                         "Poisson request stream through submit/poll; mp: the rotating-bump moving-mesh loop; "
+                         "quality: five-ring mesh quality R against the single-domain mesh; variants: MkP / (MP)l")
     ap.add_argument("--mp-steps", type=int, default=50, help="mesh steps of the mp mode")
     ap.add_argument("--quality-subs", default="2,3,4", help="subdomains per axis of the quality mode")
     ap.add_argument("--quality-K", default="1,10", help="path substeps per mesh step of the quality mode")
@@ -107,12 +144,18 @@ def parse():
     ap.add_argument("--batch-scale", type=float, default=1.0, help="scale the mix's path counts (batch mode)")
     ap.add_argument("--batch-sizes", default="",
                     help="comma-separated grid sizes: keep only the mix's instances of these sizes (batch mode)")
-    ap.add_argument("--requests", type=int, default=40, help="requests in serve mode")
+    ap.add_argument("--requests", type=int, default=40, help="measured requests of the serve mode")
+    ap.add_argument("--serve-warmup", type=int, default=4, help="requests before the measured ones (serve mode)")
     ap.add_argument("--rate", type=float, default=0.0,
                     help="arrival rate in req/s for serve mode (0: 0.7 x the measured capacity)")
-    ap.add_argument("--serve-sizes", default="33,65,129", help="grid sizes of the serving mix")
-    ap.add_argument("--serve-max-paths", type=int, default=200_000, help="cap on a request's paths per node")
-    ap.add_argument("--serve-precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--capacity", type=float, default=0.0,
+                    help="serve mode: capacity in nominal path-steps/s behind the 0.7 x rate (0: measure it with "
+                         "one batched launch of the mix at 1/20 of its path counts)")
+    ap.add_argument("--serve-sizes", default="33,65,129,257,513", help="grid sizes of the serving mix")
+    ap.add_argument("--serve-max-paths", type=int, default=1_000_000, help="cap on a request's paths per node")
+    ap.add_argument("--serve-precision", default="fp32", choices=["fp32", "fp64", "both"])
+    ap.add_argument("--serve-requests", type=int, default=24,
+                    help="step mode: measured FP32 requests of its serving run (FP64: a third of them)")
     ap.add_argument("--budget-mb", type=int, default=0, help="HBM budget of the serving context (0: 90%% free)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first (HBM counter calibration)")
@@ -122,19 +165,33 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: the library has no multi-GPU path "
-              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        print("bench.py measures one GPU only: this build has no multi-GPU path (--gpus %d requested); "
+              "see the design notes for how the work would shard" % args.gpus, file=sys.stderr)
         sys.exit(2)
-    if args.mode == "batch":
-        return run_batch(args)
-    if args.mode == "serve":
-        return run_serve(args)
-    if args.mode == "mp":
-        return run_mp(args)
-    if args.mode == "quality":
-        return run_quality(args)
-    if args.mode == "variants":
-        return run_variants(args)
+    runners = {"step": run_step, "batch": run_batch, "serve": run_serve, "mp": run_mp, "quality": run_quality,
+               "variants": run_variants}
+    return runners[args.mode](args)
+
+
+def node_diff(a, b, n_paths):
+    """Per-node differences of two result dicts (all nodes): max |d mean|
+    per component, max |d se|, max exit-count difference, and the largest
+    |d mean| in units of the combined standard error."""
+    import numpy as np
+    dx = np.abs(a["mean_x"] - b["mean_x"])
+    dy = np.abs(a["mean_y"] - b["mean_y"])
+    dse = np.maximum(np.abs(a["se_x"] - b["se_x"]), np.abs(a["se_y"] - b["se_y"]))
+    flips = np.rint(np.abs(a["exit_frac"] - b["exit_frac"]) * n_paths)
+    sx = np.hypot(a["se_x"], b["se_x"])
+    sy = np.hypot(a["se_y"], b["se_y"])
+    z = np.maximum(dx / np.maximum(sx, 1e-300), dy / np.maximum(sy, 1e-300))
+    return {"nodes": int(len(dx)), "max_abs_dmean_x": float(dx.max()), "max_abs_dmean_y": float(dy.max()),
+            "max_abs_dse": float(dse.max()), "nodes_within_1e-5": int(np.sum(np.maximum(dx, dy) <= 1e-5)),
+            "max_exit_count_diff": int(flips.max()), "nodes_with_exit_diff": int(np.sum(flips > 0)),
+            "max_z_combined_se": float(z.max())}
+
+
+def run_step(args):
     import numpy as np
     import torch
 
@@ -144,16 +201,14 @@ def main():
     M.load()
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream(device=dev)
-    inst = W.config2(n_paths=args.paths) if args.workload == "rotbump129" else W.config3(n_paths=args.paths)
-    log("workload %s: grid %dx%d, %dx%d subdomains, N=%d, K=%d, tau=%g"
-        % (inst.name, inst.n_xi, inst.n_eta, inst.sub_xi, inst.sub_eta, inst.n_paths, inst.K, inst.tau))
+    inst = W.config3(n_paths=args.paths) if args.workload == "front257" else W.config2(n_paths=args.paths)
+    log("workload %s: grid %dx%d, %dx%d subdomains, periodic (%d, %d), N=%d, K=%d, tau=%g"
+        % (inst.name, inst.n_xi, inst.n_eta, inst.sub_xi, inst.sub_eta, inst.periodic_xi, inst.periodic_eta,
+           inst.n_paths, inst.K, inst.tau))
 
     with torch.cuda.stream(stream):
-        rho = torch.from_numpy(inst.rho).to(dev)
-        x = torch.from_numpy(inst.x).to(dev)
-        y = torch.from_numpy(inst.y).to(dev)
-        b0 = torch.from_numpy(inst.bnd_t0).to(dev)
-        b1 = torch.from_numpy(inst.bnd_t1).to(dev)
+        rho, x, y, b0, b1 = (torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+                             for a in (inst.rho, inst.x, inst.y, inst.bnd_t0, inst.bnd_t1))
     stream.synchronize()
     if args.copy_mb:
         src = torch.ones(args.copy_mb << 18, dtype=torch.float32, device=dev)
@@ -167,17 +222,16 @@ def main():
     m = M.mesh_sdd_num_interface_nodes(h32)
     outs = [torch.empty(m, dtype=torch.float64, device=dev) for _ in range(5)]
     res = M.make_result(*outs)
-    step = M.make_step(x, y, b0, b1, paths_per_node=inst.n_paths, mesh_step=0)
+    step = M.make_step(x, y, b0, b1, paths_per_node=inst.n_paths, mesh_step=inst.mesh_step)
 
     M.mesh_sdd_set_monitor(h32, rho)
     if args.launch:
-        b, w, c = (int(v) for v in args.launch.split(","))
-        M.mesh_sdd_set_launch(ctx, M.make_launch(b, w, c))
+        bl, wv, ch = (int(v) for v in args.launch.split(","))
+        M.mesh_sdd_set_launch(ctx, M.make_launch(bl, wv, ch))
     elif args.tune:
         t = time.time()
         lo = M.mesh_sdd_autotune(h32, step)
-        log("autotune: block %d, waves/SIMD %d, chunk %d (%.1f s)" % (lo.block, lo.waves_per_simd, lo.chunk_paths,
-                                                                      time.time() - t))
+        log("autotune: chunk %d (%.1f s)" % (lo.chunk_paths, time.time() - t))
     lo = M.mesh_sdd_get_launch(h32)
 
     def one_step():
@@ -188,26 +242,22 @@ def main():
     for _ in range(args.warmup):
         one_step()
     torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
     executed, kernel_ms = 0, []
     t0 = time.perf_counter()
-    ev0.record(stream)
     for _ in range(args.steps):
         e, k = one_step()
         executed += e
         kernel_ms.append(k)
-    ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    stream_ms = ev0.elapsed_time(ev1)
     rate = executed / wall
     ms_per_step = 1e3 * wall / args.steps
     nominal = m * inst.n_paths * inst.K
-    se_max = float(torch.max(torch.maximum(outs[2], outs[3])).item())
-    log("fp32 batched: %.3e path-steps/s (%.1f ms/step, kernel %.1f ms avg, stream %.1f ms), executed %.3e of "
-        "nominal %.3e per step, max SE %.2e" % (rate, ms_per_step, sum(kernel_ms) / len(kernel_ms), stream_ms,
-                                                executed / args.steps, nominal, se_max))
+    g32 = {k: a.cpu().numpy() for k, a in zip(("mean_x", "mean_y", "se_x", "se_y", "exit_frac"), outs)}
+    se_max = float(np.max(np.maximum(g32["se_x"], g32["se_y"])))
+    kern_s = sum(kernel_ms) / len(kernel_ms) / 1e3
+    log("fp32 batched: %.3e path-steps/s (%.1f ms/step, path kernel %.1f ms avg), executed %.3e of nominal %.3e "
+        "per step, max SE %.2e" % (rate, ms_per_step, 1e3 * kern_s, executed / args.steps, nominal, se_max))
 
     # FP64 plain kernel, one instance per launch, same inputs and N (equal SE)
     fp64 = None
@@ -221,57 +271,45 @@ def main():
         M.mesh_sdd_solve_interfaces(h64, step, res64)
         torch.cuda.synchronize()
         w64 = time.perf_counter() - t
-        fp64 = {"value": res64.executed_path_steps / w64, "ms_per_step": 1e3 * w64,
-                "kernel_ms": res64.device_ms, "max_abs_diff_vs_fp32": float(torch.max(torch.abs(outs64[0] - outs[0])).item())}
-        log("fp64 plain: %.3e path-steps/s (%.1f ms), fp32 vs fp64 max |dmean_x| %.2e"
-            % (fp64["value"], fp64["ms_per_step"], fp64["max_abs_diff_vs_fp32"]))
+        g64 = {k: a.cpu().numpy() for k, a in zip(("mean_x", "mean_y", "se_x", "se_y", "exit_frac"), outs64)}
+        fp64 = {"value": res64.executed_path_steps / w64, "ms_per_step": 1e3 * w64, "kernel_ms": res64.device_ms,
+                "executed_path_steps": int(res64.executed_path_steps),
+                "fp32_speedup_at_equal_se": w64 / (ms_per_step / 1e3),
+                "fp32_vs_fp64_per_node": node_diff(g32, g64, inst.n_paths)}
+        log("fp64 plain: %.3e path-steps/s (%.1f ms); fp32 vs fp64 per node: %s"
+            % (fp64["value"], fp64["ms_per_step"], fp64["fp32_vs_fp64_per_node"]))
         M.mesh_sdd_destroy(h64)
 
-    kern_s = sum(kernel_ms) / len(kernel_ms) / 1e3
-    # node tables the library stages in LDS for this single-instance launch
-    tables = {0: None, 2: "rho + dt rho_xi", 3: "rho + dt rho_xi windows"}[lo.table_level]
     per_launch = executed / args.steps
-    achieved = W_SLOTS_PER_STEP * per_launch / kern_s / 1e12
+    W_inst = w_slots(inst.periodic_xi, inst.periodic_eta)
+    achieved = W_inst * per_launch / kern_s / 1e12
+    kernel = {0: "paths_fp32 (cell records)",
+              2: "paths_fp32 (LDS table: rho + dt rho_xi; 1024 threads x 1 workgroup per CU)",
+              3: "paths_fp32_win<%d> (LDS windows; 1024 threads x 1 workgroup per CU)"
+                 % (inst.periodic_xi + 2 * inst.periodic_eta)}[lo.table_level]
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 3), "unit": "TOP/s",
-                "frac": round(achieved / VALU_PEAK_TOPS, 4),
-                "traffic": recorded_traffic() if args.workload == "rotbump129" else None,
-                "kernel": {0: "paths_fp32 (cell records)",
-                           2: "paths_fp32 (LDS table: rho + dt rho_xi; 1024 threads x 1 workgroup per CU)",
-                           3: "paths_fp32_win (LDS windows of rho + dt rho_xi; 1024 threads x 1 workgroup per CU)"}[
-                               lo.table_level], "kernel_ms": round(kern_s * 1e3, 3),
-                "path_steps_per_launch": per_launch, "slots_per_path_step": W_SLOTS_PER_STEP}
+                "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": recorded_traffic(inst.name),
+                "kernel": kernel, "kernel_ms": round(kern_s * 1e3, 3), "path_steps_per_launch": per_launch,
+                "slots_per_path_step": W_inst}
+    M.mesh_sdd_destroy(h32)
+    M.mesh_sdd_ctx_destroy(ctx)
 
-    # p50 / p99 of a short FP32 serving burst (0.7 x capacity) beside the throughput
+    mix = None if args.no_mix else batch_measure(1.0, 64, "", device_inputs=True)
     serving = None
     if not args.no_serve:
-        serving = serve_measure(24, "fp32", [int(v) for v in args.serve_sizes.split(",")], args.serve_max_paths,
-                                quiet=True)
-        log("serving: %d requests at %.2f req/s: p50 %.1f ms, p99 %.1f ms"
-            % (serving["requests"], serving["rate_req_s"], serving["p50_ms"], serving["p99_ms"]))
+        cap32 = mix["nominal_path_steps"] / mix["wall_s"] if mix else rate * nominal / max(per_launch, 1.0)
+        serving = {"fp32": serve_measure(args.serve_requests, 2, "fp32", [int(v) for v in args.serve_sizes.split(",")],
+                                         args.serve_max_paths, capacity=cap32, quiet=True)}
+        if fp64:
+            cap64 = fp64["value"] * nominal / max(fp64["executed_path_steps"], 1)
+            serving["fp64"] = serve_measure(max(4, args.serve_requests // 3), 1, "fp64",
+                                            [int(v) for v in args.serve_sizes.split(",")], args.serve_max_paths,
+                                            capacity=cap64, quiet=True)
+        for k, s in serving.items():
+            log("serving %s: %d requests at %.3f req/s: p50 %.1f ms, p99 %.1f ms, %.3e path-steps/s"
+                % (k, s["requests"], s["rate_req_s"], s["p50_ms"], s["p99_ms"], s["throughput_path_steps_s"]))
 
-    cpu = None
-    if not args.no_cpu:
-        import oracle
-        threads = min(16, os.cpu_count() or 1)
-        P = oracle.Problem(**inst.problem_kwargs())
-        # bounded sample: evenly spaced interface nodes at a reduced path count;
-        # the rate in path-steps/s does not depend on N
-        probe = oracle.solve(P, inst.rho, inst.x, inst.y, inst.bnd_t0, inst.bnd_t1, 200,
-                             nodes=np.arange(0, m, max(1, m // threads))[:threads], threads=threads)
-        t = time.perf_counter()
-        probe = oracle.solve(P, inst.rho, inst.x, inst.y, inst.bnd_t0, inst.bnd_t1, 400,
-                             nodes=np.arange(0, m, max(1, m // threads))[:threads], threads=threads)
-        probe_rate = float(np.sum(probe["steps"])) / (time.perf_counter() - t)
-        n_nodes = min(m, 4 * threads)
-        nodes = np.linspace(0, m - 1, n_nodes).astype(np.int32)
-        avg_len = float(np.sum(probe["steps"])) / (400 * len(probe["steps"]))
-        n_cpu = int(max(64, args.cpu_seconds * probe_rate / (n_nodes * avg_len)))
-        t = time.perf_counter()
-        r = oracle.solve(P, inst.rho, inst.x, inst.y, inst.bnd_t0, inst.bnd_t1, n_cpu, nodes=nodes, threads=threads)
-        cw = time.perf_counter() - t
-        cpu = {"value": float(np.sum(r["steps"])) / cw, "unit": "path-steps/s", "cores": threads, "kind": "oracle",
-               "sample": "%d of %d interface nodes x %d paths x K=%d (%.1f s)" % (n_nodes, m, n_cpu, inst.K, cw)}
-        log("cpu oracle: %.3e path-steps/s on %d threads (%s)" % (cpu["value"], threads, cpu["sample"]))
+    cpu, parity = (None, None) if args.no_cpu else cpu_baseline_and_parity(inst.name, args.jsonl)
 
     line = {
         "metric": "interface-node path-steps/sec at 1 GPU (FP32 batched vs FP64 plain) at sigma<=1e-3; p99 latency",
@@ -279,25 +317,27 @@ def main():
         "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 (paths) / f64 (sums)", "data": "synthetic",
         "config": {"workload": inst.name, "grid": [inst.n_xi, inst.n_eta], "subdomains": [inst.sub_xi, inst.sub_eta],
-                   "interface_nodes": m, "paths_per_node": inst.n_paths, "K": inst.K, "tau": inst.tau,
-                   "nominal_path_steps": nominal, "executed_path_steps_per_step": per_launch,
-                   "max_se": se_max, "launch": {"block": 1024 if tables else lo.block,
-                                                "waves_per_simd": 4 if tables else lo.waves_per_simd,
-                                                "chunk_paths": lo.chunk_paths, "lds_tables": tables or "none (L2)"}},
+                   "periodic": [inst.periodic_xi, inst.periodic_eta], "interface_nodes": m,
+                   "paths_per_node": inst.n_paths, "K": inst.K, "tau": inst.tau, "nominal_path_steps": nominal,
+                   "executed_path_steps_per_step": per_launch, "max_se": se_max,
+                   "launch": {"block": 1024 if lo.table_level else lo.block, "chunk_paths": lo.chunk_paths,
+                              "table_level": lo.table_level}},
         "fp64_plain": fp64,
         "roofline": roofline,
+        "batched_mix": mix,
+        "serving": serving,
         "cpu_baseline": cpu,
-        "serving_fp32": serving,
+        "parity_vs_oracle": parity,
     }
     print(json.dumps(line), flush=True)
-    M.mesh_sdd_destroy(h32)
-    M.mesh_sdd_ctx_destroy(ctx)
 
 
-def run_batch(args):
+def batch_measure(scale: float, count: int, sizes: str, device_inputs: bool = True, launch: str = "",
+                  label: str = "batched mix") -> dict:
     """The batched mix: independent instances (grids 33..513, 2x2..16x16
     subdomains, bump or periodic front, 1e4..1e6 paths) in ONE persistent
-    FP32 launch through mesh_sdd_solve_batch."""
+    FP32 launch through mesh_sdd_solve_batch; inputs resident on the device.
+    Its roofline weighs each instance's executed path-steps by its W."""
     import numpy as np
     import torch
 
@@ -305,15 +345,19 @@ def run_batch(args):
     from paper_1504_00084_amd import workloads as W
 
     M.load()
-    insts = W.config4(count=args.batch_count)
-    if args.batch_sizes:
-        keep = {int(v) for v in args.batch_sizes.split(",")}
+    insts = W.config4(count=count)
+    if sizes:
+        keep = {int(v) for v in sizes.split(",")}
         insts = [it for it in insts if it.n_xi in keep]
-    if args.batch_scale != 1.0:
+    if scale != 1.0:
         for it in insts:
-            it.n_paths = max(64, int(it.n_paths * args.batch_scale) // 64 * 64)
+            it.n_paths = max(64, int(it.n_paths * scale) // 64 * 64)
+    dev = torch.device("cuda:0")
     ctx = M.mesh_sdd_ctx_create(0)
-    hs, ms, steps, results, arrs = [], [], [], [], []
+    if launch:
+        bl, wv, ch = (int(v) for v in launch.split(","))
+        M.mesh_sdd_set_launch(ctx, M.make_launch(bl, wv, ch))
+    hs, ms, steps, results, arrs, keep_alive = [], [], [], [], [], []
     for it in insts:
         h = M.mesh_sdd_create(ctx, M.desc_for(it, M.FP32))
         M.mesh_sdd_set_monitor(h, it.rho)
@@ -323,38 +367,60 @@ def run_batch(args):
         ms.append(m)
         arrs.append(a)
         results.append(r)
-        steps.append(M.make_step(it.x, it.y, it.bnd_t0, it.bnd_t1, paths_per_node=it.n_paths))
-    if args.launch:
-        b, w, c = (int(v) for v in args.launch.split(","))
-        M.mesh_sdd_set_launch(ctx, M.make_launch(b, w, c))
+        src = [it.x, it.y, it.bnd_t0, it.bnd_t1]
+        if device_inputs:
+            src = [torch.from_numpy(np.ascontiguousarray(v)).to(dev) for v in src]
+            keep_alive.append(src)
+        steps.append(M.make_step(*src, paths_per_node=it.n_paths))
     nominal = sum(m * it.n_paths * it.K for m, it in zip(ms, insts))
-    log("batch: %d instances, %d interface nodes, nominal %.3e path-steps" % (len(insts), sum(ms), nominal))
+    log("%s: %d instances, %d interface nodes, nominal %.3e path-steps" % (label, len(insts), sum(ms), nominal))
     torch.cuda.synchronize()
     t = time.perf_counter()
     M.mesh_sdd_solve_batch(hs, steps, results)
     wall = time.perf_counter() - t
     executed = sum(int(r.executed_path_steps) for r in results)
     kernel_ms = results[0].device_ms
+    slots = sum(w_slots(it.periodic_xi, it.periodic_eta) * int(r.executed_path_steps) for it, r in zip(insts, results))
     se = max(float(np.max(np.maximum(a[2][:m], a[3][:m]))) for a, m in zip(arrs, ms) if m)
-    line = {"metric": "batched mix path-steps/s (one persistent launch)", "value": executed / wall,
-            "unit": "path-steps/s", "kernel_ms": kernel_ms, "wall_s": wall, "executed_path_steps": executed,
-            "nominal_path_steps": nominal, "instances": len(insts), "interface_nodes": sum(ms), "max_se": se,
-            "path_scale": args.batch_scale, "sizes": sorted({it.n_xi for it in insts}),
-            "dtype": "f32 (paths) / f64 (sums)", "data": "synthetic",
-            "roofline_frac": W_SLOTS_PER_STEP * executed / (kernel_ms / 1e3) / 1e12 / VALU_PEAK_TOPS}
-    print(json.dumps(line), flush=True)
+    frac = slots / (kernel_ms / 1e3) / 1e12 / VALU_PEAK_TOPS
+    by_size = {}
+    for it, m, r in zip(insts, ms, results):
+        d = by_size.setdefault(str(it.n_xi), {"instances": 0, "executed_path_steps": 0})
+        d["instances"] += 1
+        d["executed_path_steps"] += int(r.executed_path_steps)
+    out = {"value": executed / wall, "unit": "path-steps/s", "kernel": "paths_fp32_win<-1> (one launch)",
+           "kernel_ms": kernel_ms, "wall_s": wall, "executed_path_steps": executed, "nominal_path_steps": nominal,
+           "instances": len(insts), "interface_nodes": sum(ms), "max_se": se, "path_scale": scale,
+           "sizes": sorted({it.n_xi for it in insts}), "by_size": by_size,
+           "roofline": {"bound": "alu", "achieved": round(slots / (kernel_ms / 1e3) / 1e12, 3),
+                        "peak": round(VALU_PEAK_TOPS, 3), "unit": "TOP/s", "frac": round(frac, 4),
+                        "slots_per_path_step": round(slots / max(executed, 1), 3)}}
+    log("%s: %.3e path-steps/s (kernel %.1f ms, wall %.2f s), frac %.3f, max SE %.2e"
+        % (label, executed / wall, kernel_ms, wall, frac, se))
     for h in hs:
         M.mesh_sdd_destroy(h)
     M.mesh_sdd_ctx_destroy(ctx)
+    return out
 
 
-def serve_measure(requests: int, precision: str, sizes, max_paths: int, rate: float = 0.0, budget_mb: int = 0,
-                  launch: str = "", quiet: bool = False) -> dict:
+def run_batch(args):
+    line = {"metric": "batched mix path-steps/s (one persistent launch)"}
+    line.update(batch_measure(args.batch_scale, args.batch_count, args.batch_sizes, launch=args.launch))
+    line["dtype"] = "f32 (paths) / f64 (sums)"
+    line["data"] = "synthetic"
+    print(json.dumps(line), flush=True)
+
+
+def serve_measure(requests: int, warmup: int, precision: str, sizes, max_paths: int, rate: float = 0.0,
+                  budget_mb: int = 0, capacity: float = 0.0, launch: str = "", quiet: bool = False,
+                  jsonl: str = "") -> dict:
     """Poisson stream of interface-solve requests from the batched mix, with
-    a per-request standard-error target setting N; requests are created,
-    frozen and submitted at their arrival times by client threads and
-    served by the library's continuous-batching scheduler.  p50 / p99 are
-    the library's submit-to-completion latencies."""
+    a per-request standard-error target (log-uniform in [1e-4, 1e-3]) setting
+    N (capped at max_paths); requests are created, frozen and submitted at
+    their arrival times by client threads and served by the library's
+    continuous-batching scheduler.  The first `warmup` requests are left out
+    of the percentiles.  rate = 0: 0.7 x capacity (nominal path-steps/s) over
+    the mean nominal work of a request.  Latency = submit to completion."""
     import threading
 
     import numpy as np
@@ -364,25 +430,25 @@ def serve_measure(requests: int, precision: str, sizes, max_paths: int, rate: fl
 
     M.load()
     prec = M.FP32 if precision == "fp32" else M.FP64
-    stream = W.serving_stream(requests, rate_hz=1.0, sizes=tuple(sizes),   # unit rate, rescaled below
+    stream = W.serving_stream(warmup + requests, rate_hz=1.0, sizes=tuple(sizes),   # unit rate, rescaled below
                               max_paths=max_paths)
     work = []
     for _, it, _ in stream:
         m = len(M.mesh_sdd_desc_interface_nodes(M.desc_for(it))[0])
         work.append(m * it.n_paths * it.K)
     if rate <= 0.0:
-        # 0.7 x capacity, capacity from the measured single-GPU rates of the
-        # two paths (executed path-steps are about 0.85 of nominal)
-        cap = 2.5e11 if prec == M.FP32 else 6.0e10
-        rate = 0.7 * cap * 0.85 / float(np.mean(work))
+        if capacity <= 0.0:
+            raise ValueError("serve_measure needs a rate or a measured capacity")
+        rate = 0.7 * capacity / float(np.mean(work))
     arrivals = [t / rate for t, _, _ in stream]
     ctx = M.mesh_sdd_ctx_create(0, budget_mb << 20)
     if launch:
-        b, w, c = (int(v) for v in launch.split(","))
-        M.mesh_sdd_set_launch(ctx, M.make_launch(b, w, c))
-    log("serve: %d requests at %.3f req/s (%s), mean nominal work %.3e path-steps"
-        % (len(stream), rate, precision, float(np.mean(work))))
-    done, e2e, rejected = [], [], []
+        bl, wv, ch = (int(v) for v in launch.split(","))
+        M.mesh_sdd_set_launch(ctx, M.make_launch(bl, wv, ch))
+    log("serve: %d + %d requests at %.3f req/s (%s), mean nominal work %.3e path-steps"
+        % (warmup, requests, rate, precision, float(np.mean(work))))
+    recs = {}
+    rejected = []
     lock = threading.Lock()
     t0 = time.perf_counter()
 
@@ -391,32 +457,34 @@ def serve_measure(requests: int, precision: str, sizes, max_paths: int, rate: fl
         now = time.perf_counter() - t0
         if ta > now:
             time.sleep(ta - now)
-        ts = time.perf_counter()
-        _, it, _ = stream[k]
+        _, it, se_target = stream[k]
         h = M.mesh_sdd_create(ctx, M.desc_for(it, prec))
         try:
             M.mesh_sdd_set_monitor(h, it.rho)
             m = M.mesh_sdd_num_interface_nodes(h)
             a, r = M.host_result(m)
+            step = M.make_step(it.x, it.y, it.bnd_t0, it.bnd_t1, paths_per_node=it.n_paths)
+            ts = time.perf_counter()
             try:
-                tk = M.mesh_sdd_submit(h, M.make_step(it.x, it.y, it.bnd_t0, it.bnd_t1, paths_per_node=it.n_paths))
+                tk = M.mesh_sdd_submit(h, step)
             except M.MeshSddError as e:
                 if e.code != M.E_BUDGET:
                     raise
                 with lock:   # the request alone needs more device memory than the whole budget
                     rejected.append(k)
-                    if not quiet:
-                        log("request %d rejected: %s" % (k, e))
                 return
             M.mesh_sdd_wait(ctx, tk, r, -1)
+            lat = time.perf_counter() - ts
         finally:
             M.mesh_sdd_destroy(h)
+        se = float(np.max(np.maximum(a[2][:m], a[3][:m]))) if m else 0.0
         with lock:
-            done.append(int(r.executed_path_steps))
-            e2e.append(time.perf_counter() - ts)
+            recs[k] = {"request": k, "grid": it.n_xi, "nodes": m, "paths_per_node": it.n_paths,
+                       "target_se": se_target, "max_se": se, "executed_path_steps": int(r.executed_path_steps),
+                       "latency_ms": 1e3 * lat, "warmup": k < warmup}
             if not quiet:
-                log("request %d done (%d of %d): %.3e path-steps, %.1f ms"
-                    % (k, len(done), len(stream), float(r.executed_path_steps), 1e3 * e2e[-1]))
+                log("request %d done: grid %d, %d nodes, N %d, %.3e path-steps, %.1f ms"
+                    % (k, it.n_xi, m, it.n_paths, float(r.executed_path_steps), 1e3 * lat))
 
     errors = []
 
@@ -433,28 +501,130 @@ def serve_measure(requests: int, precision: str, sizes, max_paths: int, rate: fl
     for th in threads:
         th.join()
     wall = time.perf_counter() - t0
-    if errors:
-        M.mesh_sdd_ctx_destroy(ctx)
-        raise errors[0]
     st = M.mesh_sdd_ctx_stats(ctx)
-    out = {"precision": precision, "requests": len(stream), "rate_req_s": rate, "completed": int(st.completed),
-           "failed": int(st.failed), "rejected_over_budget": len(rejected), "p50_ms": st.p50_ms, "p99_ms": st.p99_ms, "mean_ms": st.mean_ms,
-           "client_p50_ms": 1e3 * float(np.percentile(e2e, 50)) if e2e else None,
-           "client_p99_ms": 1e3 * float(np.percentile(e2e, 99)) if e2e else None,
-           "throughput_path_steps_s": sum(done) / wall, "busy_ms": st.busy_ms, "wall_s": wall,
-           "ticks": int(st.ticks), "sizes": list(sizes), "max_paths": max_paths,
-           "budget_mb": budget_mb or None}
     M.mesh_sdd_ctx_destroy(ctx)
-    return out
+    if errors:
+        raise errors[0]
+    meas = [r for r in recs.values() if not r["warmup"]]
+    lat = np.array([r["latency_ms"] for r in meas]) if meas else np.zeros(0)
+    done = sum(r["executed_path_steps"] for r in recs.values())
+    if jsonl:
+        with open(jsonl, "a") as f:
+            for k in sorted(recs):
+                f.write(json.dumps(dict(recs[k], kind="serving_request", precision=precision)) + "\n")
+    return {"precision": precision, "requests": len(meas), "warmup_requests": warmup, "rate_req_s": rate,
+            "completed": int(st.completed), "failed": int(st.failed), "rejected_over_budget": len(rejected),
+            "p50_ms": float(np.percentile(lat, 50)) if len(lat) else None,
+            "p99_ms": float(np.percentile(lat, 99)) if len(lat) else None,
+            "mean_ms": float(lat.mean()) if len(lat) else None,
+            "library_p50_ms": st.p50_ms, "library_p99_ms": st.p99_ms,
+            "throughput_path_steps_s": done / wall, "busy_ms": st.busy_ms, "wall_s": wall, "ticks": int(st.ticks),
+            "sizes": list(sizes), "max_paths": max_paths, "se_target_range": [1e-4, 1e-3],
+            "max_se_over_target": max((r["max_se"] / r["target_se"] for r in meas), default=None),
+            "budget_mb": budget_mb or None}
 
 
 def run_serve(args):
     sizes = [int(v) for v in args.serve_sizes.split(",")]
-    line = {"metric": "serving p50/p99 latency and throughput"}
-    line.update(serve_measure(args.requests, args.serve_precision, sizes, args.serve_max_paths, args.rate,
-                              args.budget_mb, args.launch))
+    cap = args.capacity
+    if args.rate <= 0.0 and cap <= 0.0:
+        m = batch_measure(0.05, 64, "", label="capacity probe (mix at 1/20 of its paths)")
+        cap = m["nominal_path_steps"] / m["wall_s"]
+    precs = ["fp32", "fp64"] if args.serve_precision == "both" else [args.serve_precision]
+    line = {"metric": "serving p50/p99 latency and throughput (Poisson stream of the batched mix)"}
+    for p in precs:
+        c = cap if p == "fp32" else cap / 6.0 if args.capacity <= 0.0 else cap
+        line[p] = serve_measure(args.requests, args.serve_warmup, p, sizes, args.serve_max_paths, args.rate,
+                                args.budget_mb, capacity=c, launch=args.launch, jsonl=args.jsonl)
+        s = line[p]
+        log("serving %s: %d requests at %.3f req/s: p50 %.1f ms, p99 %.1f ms, %.3e path-steps/s"
+            % (p, s["requests"], s["rate_req_s"], s["p50_ms"], s["p99_ms"], s["throughput_path_steps_s"]))
+    line["capacity_nominal_path_steps_s"] = cap
     line["data"] = "synthetic"
     print(json.dumps(line), flush=True)
+
+
+def cpu_baseline_and_parity(headline: str, jsonl: str = ""):
+    """The FP64 CPU oracle on a bounded sample of every workload -- the
+    33^2 bump at its full 1e4 paths, the 129^2 bump and the 257^2 front at
+    1e3 paths per node, the mix's first four instances at 128 paths, every
+    interface node each -- timed on the host cores this process may use;
+    and the GPU kernels on the same samples (same inputs, N and streams),
+    compared node by node with it.  cpu_baseline.value is the headline
+    workload's oracle rate."""
+    import numpy as np
+
+    import oracle
+    from paper_1504_00084_amd import mesh_sdd as M
+    from paper_1504_00084_amd import workloads as W
+
+    threads, info = host_threads()
+    log("cpu oracle on %d threads (%s)" % (threads, info))
+    samples = [("bump33_2x1", [W.config1()], 10_000), ("rotbump129_4x4", [W.config2(n_paths=1000)], 1000),
+               ("front257_8x8_perx", [W.config3(n_paths=1000)], 1000)]
+    mix4 = W.config4(count=64)[:4]
+    for it in mix4:
+        it.n_paths = 128
+    samples.append(("mix_first4", mix4, 128))
+    rates, parity = {}, {}
+    ctx = M.mesh_sdd_ctx_create(0)
+    for name, insts, N in samples:
+        t = time.perf_counter()
+        ora = []
+        steps = 0
+        for it in insts:
+            P = oracle.Problem(**it.problem_kwargs())
+            o = oracle.solve(P, it.rho, it.x, it.y, it.bnd_t0, it.bnd_t1, N, threads=threads)
+            steps += int(np.sum(o["steps"]))
+            ora.append(o)
+        cw = time.perf_counter() - t
+        nodes = sum(len(o["mean_x"]) for o in ora)
+        rates[name] = {"value": steps / cw, "seconds": cw, "path_steps": steps, "nodes": nodes, "paths_per_node": N}
+        log("cpu oracle %s: %.3e path-steps/s (%d nodes x %d paths, %.1f s)" % (name, steps / cw, nodes, N, cw))
+        # the GPU kernels on the same sample: FP32 batched (all instances in
+        # one launch) and, for the 33^2 bump, FP64 plain
+        hs, res, arrs = [], [], []
+        for it in insts:
+            h = M.mesh_sdd_create(ctx, M.desc_for(it, M.FP32))
+            M.mesh_sdd_set_monitor(h, it.rho)
+            a, r = M.host_result(M.mesh_sdd_num_interface_nodes(h))
+            hs.append(h)
+            res.append(r)
+            arrs.append(a)
+        M.mesh_sdd_solve_batch(hs, [M.make_step(it.x, it.y, it.bnd_t0, it.bnd_t1, paths_per_node=N,
+                                                mesh_step=it.mesh_step) for it in insts], res)
+        g = {k: np.concatenate([a[q][:len(o["mean_x"])] for a, o in zip(arrs, ora)])
+             for q, k in enumerate(("mean_x", "mean_y", "se_x", "se_y", "exit_frac"))}
+        o_all = {k: np.concatenate([o[k] for o in ora]) for k in ("mean_x", "mean_y", "se_x", "se_y", "exit_frac")}
+        for h in hs:
+            M.mesh_sdd_destroy(h)
+        parity[name] = {"fp32": node_diff(g, o_all, N)}
+        if name == "bump33_2x1":
+            g64 = M.solve_instance(ctx, insts[0], M.FP64, n_paths=N)
+            parity[name]["fp64"] = node_diff(g64, o_all, N)
+        log("gpu vs oracle %s: %s" % (name, parity[name]))
+        if jsonl:
+            with open(jsonl, "a") as f:
+                for k in range(len(g["mean_x"])):
+                    f.write(json.dumps({"kind": "node_parity", "workload": name, "paths_per_node": N, "node": k,
+                                        "gpu_fp32_mean_x": float(g["mean_x"][k]),
+                                        "gpu_fp32_mean_y": float(g["mean_y"][k]),
+                                        "oracle_mean_x": float(o_all["mean_x"][k]),
+                                        "oracle_mean_y": float(o_all["mean_y"][k]),
+                                        "abs_dmean": float(max(abs(g["mean_x"][k] - o_all["mean_x"][k]),
+                                                               abs(g["mean_y"][k] - o_all["mean_y"][k]))),
+                                        "oracle_se_x": float(o_all["se_x"][k]),
+                                        "oracle_se_y": float(o_all["se_y"][k])}) + "\n")
+    M.mesh_sdd_ctx_destroy(ctx)
+    head = rates.get(headline, rates["front257_8x8_perx"])
+    total_s = sum(r["seconds"] for r in rates.values())
+    cpu = {"value": head["value"], "unit": "path-steps/s", "cores": threads, "kind": "oracle",
+           "sample": "%s: all %d interface nodes x %d paths (%.1f s); all samples: %s (%.1f s of oracle work "
+                     "in total)" % (headline, head["nodes"], head["paths_per_node"], head["seconds"],
+                                    ", ".join("%s %d nodes x %d" % (k, r["nodes"], r["paths_per_node"])
+                                              for k, r in rates.items()), total_s),
+           "host": info, "per_workload": rates}
+    return cpu, parity
 
 
 def run_mp(args):

@@ -186,7 +186,9 @@ typedef struct {
 
 /* ---- context ------------------------------------------------------------ */
 
-/* Create a context on HIP device `device`.  hbm_budget_bytes caps the device
+/* Execution context of the interface solves of section 3.4 (no paper
+ * counterpart: device, stream, serving queue).
+ * Create a context on HIP device `device`.  hbm_budget_bytes caps the device
  * memory of admitted requests (0: 90% of the free memory).  hip_stream: a
  * hipStream_t to launch on (NULL: the context creates its own, default
  * priority).  Starts the serving scheduler thread.  Errors: E_INVAL,
@@ -198,14 +200,17 @@ int mesh_sdd_ctx_create(int device, size_t hbm_budget_bytes, void *hip_stream, m
  * (E_STATE otherwise). */
 int mesh_sdd_ctx_destroy(mesh_sdd_ctx *ctx);
 
-/* Counters and latency percentiles of the serving loop. */
+/* Counters and latency percentiles of the serving loop (no paper
+ * counterpart; the requests are section 3.4 interface solves). */
 int mesh_sdd_ctx_stats(mesh_sdd_ctx *ctx, mesh_sdd_stats *out);
 
-/* Fix the launch shape of the batched kernel (overrides the autotuner for
- * every later launch); NULL restores autotuning. */
+/* Fix the launch shape of the batched kernel of the section 3.4 solve
+ * (overrides the autotuner for every later launch; results do not depend on
+ * it except through chunk_paths, which sets the grouping of the FP64 sums);
+ * NULL restores autotuning. */
 int mesh_sdd_set_launch(mesh_sdd_ctx *ctx, const mesh_sdd_launch *launch);
 
-/* Launch shape that the next launch over `inst` would use. */
+/* Launch shape that the next section 3.4 launch over `inst` would use. */
 int mesh_sdd_get_launch(mesh_sdd *inst, mesh_sdd_launch *out);
 
 /* Autotune the batched kernel for the shape bucket of `inst` (grid size,
@@ -216,8 +221,9 @@ int mesh_sdd_autotune(mesh_sdd *inst, const mesh_sdd_step *step, mesh_sdd_launch
 
 /* ---- host-only helpers (no device needed) --------------------------------- */
 
-/* Validate a descriptor without creating anything: MESH_SDD_OK or E_INVAL
- * with the reason in mesh_sdd_last_error(). */
+/* Validate a descriptor (grid and partition of section 3.5, step of section
+ * 3.4) without creating anything: MESH_SDD_OK or E_INVAL with the reason in
+ * mesh_sdd_last_error(). */
 int mesh_sdd_desc_check(const mesh_sdd_desc *desc);
 
 /* Interface nodes of a descriptor's partition (section 3.5): returns M >= 0
@@ -249,13 +255,17 @@ int mesh_sdd_desc_work_order(const mesh_sdd_desc *desc, uint32_t interface_strid
 
 /* ---- instances ----------------------------------------------------------- */
 
-/* Validate the descriptor (n >= 4, (n-1) % sub == 0, sub >= 1, K >= 1,
+/* One problem instance: the computational grid and its s_xi x s_eta
+ * subdomain partition (section 3.5), the mesh step tau and its K substeps
+ * (section 3.4), the periodic axes (section 3.3) and the RNG identity.
+ * Validate the descriptor (n >= 4, (n-1) % sub == 0, sub >= 1, K >= 1,
  * tau > 0, L > 0, instance_id < 65536, precision in {FP32, FP64}) and
  * allocate the instance's resident device buffers.  E_INVAL, E_NOMEM,
  * E_BUDGET (the instance alone exceeds the context's budget). */
 int mesh_sdd_create(mesh_sdd_ctx *ctx, const mesh_sdd_desc *desc, mesh_sdd **out);
 
-/* Free an instance.  E_STATE if it has requests in flight. */
+/* Free an instance (the resident tables of the monitor frozen for section
+ * 3.4) and its device buffers.  E_STATE if it has requests in flight. */
 int mesh_sdd_destroy(mesh_sdd *inst);
 
 /* Freeze the monitor for the next solves (section 3.2): rho is
@@ -265,16 +275,30 @@ int mesh_sdd_destroy(mesh_sdd *inst);
  * input only; device input is not inspected). */
 int mesh_sdd_set_monitor(mesh_sdd *inst, const double *rho, int is_device_ptr);
 
-/* Number M of interface nodes (>= 0), or a negative error. */
+/* Number M of artificial interface nodes of the instance's partition
+ * (paper section 3.5: the nodes where the subdomains' Dirichlet data are
+ * estimated; the rule is stated in the conventions above), >= 0, or a
+ * negative error. */
 int mesh_sdd_num_interface_nodes(const mesh_sdd *inst);
 
-/* Write the interface nodes (i, j) in rank order into caller arrays of
- * length M (host memory). */
+/* Write the interface nodes (i, j) of section 3.5 in rank order (row-major
+ * in (j, i)) into caller arrays of length M (host memory).  E_INVAL on a
+ * NULL instance or, when M > 0, a NULL array. */
 int mesh_sdd_interface_nodes(const mesh_sdd *inst, int32_t *i, int32_t *j);
 
 /* ---- solving -------------------------------------------------------------- */
 
-/* Blocking solve of one mesh step.  E_STATE before set_monitor; E_INVAL on
+/* Blocking solve of one mesh step (paper section 3.4: N Euler-Maruyama paths
+ * of K substeps of eq. WinslowGeneratorSDEDiscretization per interface node,
+ * bilinear monitor, Brownian-bridge exit test, bicubic terminal value; the
+ * estimator of eq. WinslowGeneratorRelaxedStochasticSolutionA, section 3.2,
+ * or eq. StochasticSolutionPeriodicDomainSolution, section 3.3, on periodic
+ * axes; mean over the N paths).  Results as mesh_sdd_result describes; the
+ * FP32 kernel matches the FP64 oracle to 1e-5 per node (unit square) where
+ * the substep resolves the drift (dt |grad b| well below 0.1, as with K =
+ * 500 on the benchmark grids); with longer substeps the FP32 and FP64 paths
+ * separate and the FP32 estimate agrees with the FP64 one statistically
+ * (within 3 combined standard errors), not path by path.  E_STATE before set_monitor; E_INVAL on
  * a bad step (null pointers, N outside [1, 2^31], corner values of the
  * boundary arrays that disagree by more than 1e-12 (Lx + Ly), host inputs
  * that are not finite) and on a request too large for 32-bit work-item
@@ -283,7 +307,8 @@ int mesh_sdd_interface_nodes(const mesh_sdd *inst, int32_t *i, int32_t *j);
  * block) pairs.  Nothing is allocated or launched for such a request. */
 int mesh_sdd_solve_interfaces(mesh_sdd *inst, const mesh_sdd_step *step, mesh_sdd_result *result);
 
-/* Blocking solve of `count` instances: all FP32 instances run in ONE
+/* Blocking solve of `count` instances (each as mesh_sdd_solve_interfaces,
+ * section 3.4): all FP32 instances run in ONE
  * persistent launch over a shared (instance, node, path-chunk) work queue
  * (several launches, in order, where their items together exceed
  * 2^32 - 2^20); FP64 instances run one launch each.  Per-instance status codes go to
@@ -291,7 +316,8 @@ int mesh_sdd_solve_interfaces(mesh_sdd *inst, const mesh_sdd_step *step, mesh_sd
 int mesh_sdd_solve_batch(mesh_sdd *const *insts, const mesh_sdd_step *steps, mesh_sdd_result *results,
                          int32_t count, int32_t *status);
 
-/* Non-blocking: snapshot the step's inputs and queue a request.  The
+/* Non-blocking interface solve (section 3.4, as mesh_sdd_solve_interfaces):
+ * snapshot the step's inputs and queue a request.  The
  * scheduler admits requests while the HBM in use plus the request's cost
  * stays within the budget, and runs all admitted requests' pending chunks
  * in persistent launches ("ticks"); a request that arrives while a tick is
@@ -299,15 +325,19 @@ int mesh_sdd_solve_batch(mesh_sdd *const *insts, const mesh_sdd_step *steps, mes
  * E_BUDGET only if the request alone exceeds the budget. */
 int mesh_sdd_submit(mesh_sdd *inst, const mesh_sdd_step *step, mesh_sdd_ticket *ticket);
 
-/* MESH_SDD_PENDING while the request runs; MESH_SDD_OK once done (the
+/* Result of a submitted interface solve (section 3.4).
+ * MESH_SDD_PENDING while the request runs; MESH_SDD_OK once done (the
  * result arrays given here are filled, the ticket is released); a negative
  * error if it failed (ticket released).  E_INVAL for an unknown ticket. */
 int mesh_sdd_poll(mesh_sdd_ctx *ctx, mesh_sdd_ticket ticket, mesh_sdd_result *result);
 
-/* Like poll but waits up to timeout_ms (< 0: forever) for completion. */
+/* Like poll (section 3.4 solve) but waits up to timeout_ms (< 0: forever)
+ * for completion. */
 int mesh_sdd_wait(mesh_sdd_ctx *ctx, mesh_sdd_ticket ticket, mesh_sdd_result *result, int64_t timeout_ms);
 
-/* Cancel a queued request (E_STATE if it is already running). */
+/* Cancel a queued interface solve (section 3.4) that has not been admitted
+ * yet: it ends with E_CANCELLED.  E_STATE if it is already running or
+ * finished, E_INVAL for an unknown ticket. */
 int mesh_sdd_cancel(mesh_sdd_ctx *ctx, mesh_sdd_ticket ticket);
 
 /* ---- the mesh step around the interface estimate (sections 2, 3.5-3.7) ------ */
@@ -430,10 +460,11 @@ int mesh_sdd_debug_paths(mesh_sdd *inst, const mesh_sdd_step *step, int32_t node
                          int64_t p_end, double *vx, double *vy, int32_t *exited, int32_t *side,
                          int32_t *steps, double *trace);
 
-/* Text of the last error on the calling thread ("" if none). */
+/* Text of the last error on the calling thread ("" if none); no paper
+ * counterpart. */
 const char *mesh_sdd_last_error(void);
 
-/* Library version string. */
+/* Library version string (no paper counterpart). */
 const char *mesh_sdd_version(void);
 
 #ifdef __cplusplus

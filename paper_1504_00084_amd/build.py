@@ -1,6 +1,7 @@
 """Build libmesh_sdd.so (HIP kernels for gfx950 + host runtime) in-tree.
 
-    python -m paper_1504_00084_amd.build
+    python -m paper_1504_00084_amd.build            # the library
+    python -m paper_1504_00084_amd.build --probe    # and the VALU issue-cost probe
 
 Packed-FP32 instructions are disabled for all device code
 (``-Xclang -target-feature -Xclang -packed-fp32-ops``).
@@ -57,7 +58,14 @@ def build(verbose: bool = False) -> str:
     if res.returncode != 0:
         raise RuntimeError("link failed: %s\n%s\n%s" % (" ".join(cmd), res.stdout, res.stderr))
     os.replace(tmp, LIB)
-    # stand-alone VALU issue-cost probe (roofline calibration)
+    if verbose:
+        print("built", LIB)
+    return LIB
+
+
+def build_probe(verbose: bool = False) -> str:
+    """Compile the stand-alone VALU issue-cost probe (the calibration of the
+    roofline's slot weights; not part of the library)."""
     tmp = PROBE + ".tmp%d" % os.getpid()
     cmd = [hipcc(), "-O3", "-std=c++17", "--offload-arch=" + ARCH] + DEVICE_FLAGS + [
         os.path.join(CSRC, "valu_probe.hip"), "-o", tmp]
@@ -66,10 +74,12 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError("probe build failed: %s\n%s\n%s" % (" ".join(cmd), res.stdout, res.stderr))
     os.replace(tmp, PROBE)
     if verbose:
-        print("built", LIB, "and", PROBE)
-    return LIB
+        print("built", PROBE)
+    return PROBE
 
 
 if __name__ == "__main__":
     build(verbose=True)
+    if "--probe" in sys.argv[1:]:
+        build_probe(verbose=True)
     sys.exit(0)

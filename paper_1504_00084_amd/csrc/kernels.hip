@@ -619,17 +619,14 @@ struct QueueSrc {
 };
 
 // JobSrc: the items q0 .. q0 + count of one range, handed out by a counter
-// in LDS that the workgroup's waves share.
+// in LDS that the workgroup's waves share.  The pop is the queue's: every
+// lane takes part in the atomic (lane 0 adds 1), so no lane leaves the wave
+// loop on a branch of its own.
 struct JobSrc {
     uint32_t *next;   // LDS
     WorkRange R;
     uint32_t q0;
-    __device__ __forceinline__ uint32_t pop(int lane)
-    {
-        uint32_t v = 0;
-        if (lane == 0) v = atomicAdd(next, 1u);
-        return __builtin_amdgcn_readlane(v, 0);
-    }
+    __device__ __forceinline__ uint32_t pop(int lane) { return pop_item(next, lane); }
     __device__ __forceinline__ ItemF decode(uint32_t it) const
     {
         const uint32_t q = q0 + it;   // request-wide item, node-major
