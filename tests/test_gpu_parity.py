@@ -112,6 +112,7 @@ def test_small_cases_both_precisions(M, ctx, oracle_lib, name):
     g32 = gpu_solve(M, ctx, inst, M.FP32)
     s32 = compare(g32, ora, label=name + " fp32")
     assert s32["err"] <= 1e-5 * max(inst.Lx, inst.Ly)
+    assert s32["flips"] <= 2   # exit decisions that FP32 rounding moved, per node
 
 
 WINDOW_CASES = {
@@ -230,3 +231,28 @@ def test_trajectories_match_oracle(M, ctx, oracle_lib):
             assert np.array_equal(o["side"], g["side"])
         finally:
             M.mesh_sdd_destroy(h)
+
+
+def test_under_resolved_substeps_agree_statistically(M, ctx, oracle_lib):
+    """Outside the regime where the FP32 paths shadow the FP64 ones: the
+    161^2 doubly periodic front of width 0.05 with tau = 0.05 and only
+    K = 60 substeps (dt |grad b| up to about a third).  One substep then
+    multiplies a perturbation of the position by up to 1.3, so the FP32
+    paths separate from the oracle's within ~20 substeps and the per-node
+    1e-5 bar does not apply; the two estimates are the same estimator on
+    other sample paths and must agree within 3 combined standard errors at
+    every node (the benchmark spec's statistical bar).  The FP64 kernel, whose
+    paths stay on the oracle's, must still match it to 1e-9 at every node."""
+    cases = {"under161_perxy_8x8": (161, 161, 8, 8, 1, 1, 60, 2048, 0.05, 1.0, 1.0, "front")}
+    inst = small_instance("under161_perxy_8x8", cases)
+    ora = oracle_solve(oracle_lib, inst)
+    g32 = gpu_solve(M, ctx, inst, M.FP32)
+    g64 = gpu_solve(M, ctx, inst, M.FP64)
+    s64 = compare(g64, ora, label="K=60 fp64")
+    assert s64["err"] <= 1e-9
+    dx = np.abs(g32["mean_x"] - ora["mean_x"])
+    dy = np.abs(g32["mean_y"] - ora["mean_y"])
+    z = np.maximum(dx / np.hypot(g32["se_x"], ora["se_x"]), dy / np.hypot(g32["se_y"], ora["se_y"]))
+    say("K=60 fp32 vs oracle: %d nodes, max |dmean| %.2e (%d nodes beyond 1e-5), max z %.3f, median z %.3f"
+        % (len(z), max(dx.max(), dy.max()), int(np.sum(np.maximum(dx, dy) > 1e-5)), z.max(), np.median(z)))
+    assert np.max(z) <= 3.0

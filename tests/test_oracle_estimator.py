@@ -289,3 +289,71 @@ def test_single_path_and_determinism(oracle_lib):
     assert r2["mean_x"][0] == r["mean_x"][1]        # per-node result does not depend on the node set
     p = oracle_lib.paths(problem(oracle_lib, inst), inst.rho, inst.x, inst.y, inst.bnd_t0, inst.bnd_t1, 5, 0, 1)
     assert p["vx"][0] == r["mean_x"][1]
+
+
+def test_harmonic_data_exit_location(oracle_lib):
+    """Tangential exit point and boundary interpolation (section 3.2, eq.
+    WinslowGeneratorRelaxedStochasticSolutionA; section 3.4, exit point on
+    the side): with rho constant, any harmonic function is a steady
+    solution of (Gen).  Taking the mesh AND the boundary data from
+    f1 = xi^2 - eta^2 (x component) and f2 = xi eta (y component), the
+    estimate must return f1, f2 at the start node whatever the split into
+    survivors (Keys bicubic of the mesh: exact for quadratics) and exits
+    (boundary arrays, linear between nodes: O(h^2) = 2.4e-4 for f1 on a
+    33^2 grid, exact for f2), provided the exit value is read at the right
+    point along the right side.  tau = 0.05 with 100 substeps makes most
+    paths from these nodes exit; a value read at the start node's
+    tangential coordinate, with the tangential coordinate of the other axis,
+    or from the other side's array misses by many standard errors (planted
+    in a scratch copy of the oracle: each fails this pin)."""
+    n = 33
+    xi = np.arange(n) / (n - 1.0)
+    XI, ETA = np.meshgrid(xi, xi)
+    f1 = XI ** 2 - ETA ** 2
+    f2 = XI * ETA
+    b = W.boundary_from_mesh(f1, f2)
+    rho = np.ones((n, n))
+    inst = W.Instance("harmonic33", n, n, 2, 2, 0, 0, 1.0, 1.0, 0.05, 100, 20_000, rho, f1, f2, b, b.copy())
+    P = problem(oracle_lib, inst)
+    i, j = oracle_lib.interface_nodes(P)
+    # nodes near the sides, where most paths exit, and the centre
+    pick = [k for k in range(len(i)) if (i[k], j[k]) in {(16, 2), (16, 30), (2, 16), (30, 16), (16, 8), (16, 16),
+                                                          (8, 16), (16, 24)}]
+    assert len(pick) == 8
+    r = solve(oracle_lib, inst, nodes=pick)
+    a, e = xi[i[pick]], xi[j[pick]]
+    exact_x, exact_y = a ** 2 - e ** 2, a * e
+    zx = (r["mean_x"] - exact_x) / np.sqrt(r["se_x"] ** 2 + (2.5e-4) ** 2)
+    zy = (r["mean_y"] - exact_y) / r["se_y"]
+    assert np.max(np.abs(zx)) < 4.0, zx
+    assert np.max(np.abs(zy)) < 4.0, zy
+    assert np.min(r["exit_frac"][:4]) > 0.5   # the near-side nodes mostly exit
+
+
+def test_fd_single_domain_reference_sharp_bump(oracle_lib):
+    """The non-constant-monitor pin at the 33^2 workload's own monitor: the
+    Gaussian bump of width 0.01 with alpha = 10 (rho up to 27), tau = 0.05,
+    K = 500 (section 3.4), against the deterministic single-domain solve of
+    (Gen) with the same coefficient field (centred differences + forward
+    Euler, section 3.5) on the grid refined 4 times, its discretisation
+    error estimated by the refine-2 solve.  A 2x2 partition puts interface
+    nodes on the row through the bump too, where the drift moves x (the
+    column through it moves only y, by symmetry): the nodes move up to 0.16,
+    about 60 standard errors, so a dropped or reversed drift fails."""
+    from oracle import fd_reference
+    inst = W.config1(6000)
+    inst.sub_eta = 2
+    assert inst.rho.max() > 25.0
+    r = solve(oracle_lib, inst)
+    i, j = oracle_lib.interface_nodes(problem(oracle_lib, inst))
+    x4, y4 = fd_reference.solve(inst.rho, inst.x, inst.y, inst.bnd_t0, inst.bnd_t1, inst.tau, refine=4)
+    x2, y2 = fd_reference.solve(inst.rho, inst.x, inst.y, inst.bnd_t0, inst.bnd_t1, inst.tau, refine=2)
+    fx, fy = x4[j, i], y4[j, i]
+    ex, ey = np.abs(x4 - x2)[j, i], np.abs(y4 - y2)[j, i]
+    assert np.max(np.abs(fx - i / 32.0)) > 40 * np.max(r["se_x"])
+    assert np.max(np.abs(fy - j / 32.0)) > 40 * np.max(r["se_y"])
+    zx = (r["mean_x"] - fx) / np.sqrt(r["se_x"] ** 2 + ex ** 2)
+    zy = (r["mean_y"] - fy) / np.sqrt(r["se_y"] ** 2 + ey ** 2)
+    z = np.concatenate([zx, zy])
+    assert np.max(np.abs(z)) < 4.0, np.max(np.abs(z))
+    assert np.mean(z ** 2) < 1.6, np.mean(z ** 2)
