@@ -434,6 +434,7 @@ typedef struct {
     monitor_table T;
     mesh_field X, Y;
     const double *bnd_t0, *bnd_t1;
+    int32_t round_f32;   /* sensitivity probe only: see oracle_paths_rounded */
 } solve_context;
 
 /* trace (optional): per substep, 4 doubles (xi, eta after the step, before
@@ -455,6 +456,10 @@ static path_outcome run_path(const solve_context *C, int32_t node, int32_t i0, i
         bilinear3(&C->T, xi, eta, &r, &rx, &ry);
         double nxi = xi + (rx / r) * dt + sq * n1;
         double neta = eta + (ry / r) * dt + sq * n2;
+        if (C->round_f32) {   /* the probe's perturbation: positions rounded as binary32 */
+            nxi = (double)(float)nxi;
+            neta = (double)(float)neta;
+        }
 
         if (P->periodic_xi) {
             double m = floor(nxi);
@@ -615,6 +620,7 @@ static void build_context(const oracle_problem *P, const double *rho, double *rh
     C->Y.f = y_cur; C->Y.off_xi = 0.0; C->Y.off_eta = P->Ly;
     C->bnd_t0 = bnd_t0;
     C->bnd_t1 = bnd_t1;
+    C->round_f32 = 0;
 }
 
 /*
@@ -689,10 +695,10 @@ done:
  * position after wrapping and the two normals, 4 doubles per substep, K
  * substeps per path (unused entries after an exit are left untouched).
  */
-int32_t oracle_paths(const oracle_problem *P, const double *rho, const double *x_cur, const double *y_cur,
-                     const double *bnd_t0, const double *bnd_t1, int32_t node_rank,
-                     int64_t p_begin, int64_t p_end, double *vx, double *vy, int32_t *exited,
-                     int32_t *side, int32_t *steps, double *trace)
+static int32_t paths_impl(const oracle_problem *P, const double *rho, const double *x_cur, const double *y_cur,
+                          const double *bnd_t0, const double *bnd_t1, int32_t node_rank,
+                          int64_t p_begin, int64_t p_end, double *vx, double *vy, int32_t *exited,
+                          int32_t *side, int32_t *steps, double *trace, int32_t round_f32)
 {
     if (!P || P->n_xi < 4 || P->n_eta < 4 || P->K < 1 || P->tau <= 0.0) return -1;
     int32_t total = oracle_interface_nodes(P, NULL, NULL);
@@ -708,6 +714,7 @@ int32_t oracle_paths(const oracle_problem *P, const double *rho, const double *x
     oracle_interface_nodes(P, all_i, all_j);
     solve_context C;
     build_context(P, rho, rho_xi, rho_eta, x_cur, y_cur, bnd_t0, bnd_t1, &C);
+    C.round_f32 = round_f32;
     for (int64_t p = p_begin; p < p_end; ++p) {
         int64_t q = p - p_begin;
         path_outcome o = run_path(&C, node_rank, all_i[node_rank], all_j[node_rank], p,
@@ -720,4 +727,29 @@ int32_t oracle_paths(const oracle_problem *P, const double *rho, const double *x
     }
     free(all_i); free(all_j); free(rho_xi); free(rho_eta);
     return 0;
+}
+
+int32_t oracle_paths(const oracle_problem *P, const double *rho, const double *x_cur, const double *y_cur,
+                     const double *bnd_t0, const double *bnd_t1, int32_t node_rank,
+                     int64_t p_begin, int64_t p_end, double *vx, double *vy, int32_t *exited,
+                     int32_t *side, int32_t *steps, double *trace)
+{
+    return paths_impl(P, rho, x_cur, y_cur, bnd_t0, bnd_t1, node_rank, p_begin, p_end, vx, vy, exited, side,
+                      steps, trace, 0);
+}
+
+/*
+ * Sensitivity probe, not an estimate: the same paths with each substep's new
+ * position rounded to the nearest binary32 value (a perturbation of the size
+ * a single-precision path suffers at every substep).  A path whose outcome
+ * this moves far is one along which the drift amplifies rounding; the tests
+ * use it to tell such paths from arithmetic mistakes.
+ */
+int32_t oracle_paths_rounded(const oracle_problem *P, const double *rho, const double *x_cur, const double *y_cur,
+                             const double *bnd_t0, const double *bnd_t1, int32_t node_rank,
+                             int64_t p_begin, int64_t p_end, double *vx, double *vy, int32_t *exited,
+                             int32_t *side, int32_t *steps)
+{
+    return paths_impl(P, rho, x_cur, y_cur, bnd_t0, bnd_t1, node_rank, p_begin, p_end, vx, vy, exited, side,
+                      steps, NULL, 1);
 }

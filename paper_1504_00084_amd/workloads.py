@@ -291,14 +291,23 @@ def rotating_bump_loop(n_paths: int = 100_000, steps: int = 50) -> MeshLoop:
                     x, y, lambda xx, yy, t: rotating_bump_u(xx, yy, t))
 
 
-def five_ring_loop(sub: int, n: int = 41, n_paths: int = 10_000, steps: int = 100, K: int = 1) -> MeshLoop:
+def five_ring_loop(sub: int, n: int = 41, n_paths: int = 10_000, steps: int = 100, K: int = 1,
+                   comp_side: float = 2.0) -> MeshLoop:
     """The five-ring periodic mesh test (section 4.2): [-1, 1[^2 periodic in
     both axes, n x n nodes (node n-1 is the image of node 0), sub x sub
-    subdomains, R = 30, alpha = 0.2, dt = 5e-4 with K substeps (the paper
-    uses one), 1e4 paths, 100 steps to t = 0.05."""
+    subdomains, R = 30, alpha = 0.2, time step 5e-4 with K substeps (the
+    paper uses one), 1e4 paths, 100 steps to t = 0.05.
+
+    The computational coordinates span a square of side `comp_side` (2: the
+    same [-1, 1[^2 as the physical domain).  The generator's operator scales
+    as 1 / side^2 under a change of that side, so a step of 5e-4 there is a
+    step of 5e-4 / side^2 in the unit-square coordinates every solver here
+    works in (comp_side = 1 reads the step in unit-square time instead)."""
     x, y = uniform_mesh(n, n, 2.0, 2.0)
-    return MeshLoop("five_ring%d_%dx%d_K%d" % (n, sub, sub, K), n, n, sub, sub, 1, 1, 2.0, 2.0, 5e-4, K, n_paths,
-                    steps, 0.2, False, x - 1.0, y - 1.0, lambda xx, yy, t: five_ring_u(xx, yy))
+    tau = 5e-4 / (comp_side * comp_side)
+    return MeshLoop("five_ring%d_%dx%d_K%d" % (n, sub, sub, K) + ("" if comp_side == 2.0 else "_side%g" % comp_side),
+                    n, n, sub, sub, 1, 1, 2.0, 2.0, tau, K, n_paths, steps, 0.2, False, x - 1.0, y - 1.0,
+                    lambda xx, yy, t: five_ring_u(xx, yy))
 
 
 # --------------------------------------------------------------------------

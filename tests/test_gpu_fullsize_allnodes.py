@@ -12,14 +12,20 @@ within FP32 rounding of the boundary (or of the bridge uniform) can exit in
 one precision and not in the other, which at a reduced N moves that node's
 mean by (v32 - v64) / N; so every node beyond 1e-5 is audited path by path
 (mesh_sdd_debug_paths runs the production arithmetic one path per lane, the
-oracle gives the same paths): a "flip" node has a few paths whose side or
-step count differ, every other path agreeing to 1e-4 and the mean without
-the differing paths to 1e-5.  Where the substep does not resolve the drift
+oracle gives the same paths): an "explained" node has at most max(4, N/64)
+paths with a different exit side or step count (a flip); every path with
+the same decisions but an end point more than 1e-4 away (a separated path)
+is one whose FP64 end point itself moves by 2e-6 or more under the oracle's
+sensitivity probe (its position rounded to binary32 after every substep;
+without drift the probe moves a path by at most 1.2e-6),
+i.e. a path along which the drift amplifies rounding where it crosses a
+steep part of the monitor; and over the paths that do shadow the oracle's
+(same decisions, values within 1e-4) the mean agrees to 1e-5.  Where the substep does not resolve the drift
 -- monitors with a front or bump only one or two cells wide, grid maximum
 of dt |grad b| above 1 -- FP32 rounding is amplified along the paths, which
 then separate from the oracle's; there the bar is statistical: within 3
-combined standard errors at every node (a "separated" node).  Instances
-below that indicator may have flip nodes but no separated ones."""
+combined standard errors at every node (a "statistical" node).  Instances
+below that indicator may have explained nodes but no statistical ones."""
 import dataclasses
 
 import numpy as np
@@ -73,17 +79,43 @@ def solve_many(M, ctx, insts, precision):
 
 def audit_node(M, oracle_lib, h, step, inst, node):
     """Path-by-path comparison of one node: FP32 production arithmetic
-    against the oracle.  Returns (paths with another discrete outcome,
-    max |dv| over the others, |dmean| without the differing paths)."""
+    against the oracle.  A path "shadows" the oracle's when it has the same
+    exit side and step count and its value agrees to 1e-4; the others either
+    took another discrete decision (a flip) or, same decisions, ended
+    elsewhere (a separated path).  A separated path must be one that FP64
+    itself cannot hold steady: the oracle's sensitivity probe (the same path
+    with its position rounded to binary32 after every substep, the size of
+    the FP32 path's own rounding) must move that path's end by at least
+    2e-6 or change its decisions.  Without drift the probe moves a path by
+    at most 1.2e-6 (3072 paths of a constant monitor at K = 500, 33^2 to
+    513^2), and an FP32 path then stays within about as much of the
+    oracle's, far from the 1e-4 of a separated path; along a path the drift
+    amplifies, the two perturbations grow by the same factor but land on
+    the growing direction differently, so their sizes can differ by one or
+    two orders.  Returns (flips, separated paths, separated paths the probe
+    keeps within 2e-6, the larger of |dmean| and |dse| over the shadowing
+    paths)."""
     N = inst.n_paths
     g = M.mesh_sdd_debug_paths(h, step, int(node), 0, N, inst.K)
     P = oracle_lib.Problem(**inst.problem_kwargs())
     o = oracle_lib.paths(P, inst.rho, inst.x, inst.y, inst.bnd_t0, inst.bnd_t1, int(node), 0, N)
     same = (g["side"] == o["side"]) & (g["steps"] == o["steps"])
     dv = np.maximum(np.abs(g["vx"] - o["vx"]), np.abs(g["vy"] - o["vy"]))
-    keep = np.flatnonzero(same)
+    shadow = same & (dv <= 1e-4)
+    sep = np.flatnonzero(same & ~shadow)
+    steady = 0
+    if len(sep):
+        q = oracle_lib.paths(P, inst.rho, inst.x, inst.y, inst.bnd_t0, inst.bnd_t1, int(node), 0, N,
+                             round_f32=True)
+        moved = np.maximum(np.abs(q["vx"] - o["vx"]), np.abs(q["vy"] - o["vy"]))
+        sensitive = (q["side"] != o["side"]) | (q["steps"] != o["steps"]) | (moved >= 2e-6)
+        steady = int(np.sum(~sensitive[sep]))
+    keep = np.flatnonzero(shadow)
     dmean = max(abs(np.sum(g["vx"][keep] - o["vx"][keep])), abs(np.sum(g["vy"][keep] - o["vy"][keep]))) / N
-    return int(np.sum(~same)), float(dv[keep].max()) if len(keep) else 0.0, dmean
+    if len(keep) > 1:   # the standard error of the shadowing paths, on both sides
+        se = lambda v: np.std(v[keep], ddof=1) / np.sqrt(len(keep))
+        dmean = max(dmean, abs(se(g["vx"]) - se(o["vx"])), abs(se(g["vy"]) - se(o["vy"])))
+    return int(np.sum(~same)), len(sep), steady, dmean
 
 
 def drift_indicator(inst):
@@ -97,25 +129,35 @@ def drift_indicator(inst):
     return inst.tau / inst.K * float(np.max(np.sqrt(gxx ** 2 + gxy ** 2 + gyx ** 2 + gyy ** 2)))
 
 
+def zscore(diff, se_a, se_b):
+    """|diff| in units of the combined standard error: 0 where the two
+    agree exactly (also a coordinate every path leaves unchanged, standard
+    error 0 on both sides), infinite where they differ with no spread."""
+    diff, sd = np.abs(diff), np.hypot(se_a, se_b)
+    z = np.full(diff.shape, np.inf)
+    np.divide(diff, sd, out=z, where=sd > 0)
+    z[diff == 0] = 0.0
+    return z
+
+
 def check_fp32(M, oracle_lib, label, parts, allow_separated=False, max_audits=200):
     """parts: list of (handle, step, instance, gpu result, oracle result).
     Nodes within 1e-5 pass; the others are audited (all of them, or an
     evenly spaced `max_audits` per instance where separation is allowed,
     the rest checked statistically)."""
-    totals = {"nodes": 0, "within": 0, "flip": 0, "separated": 0, "flipped_paths": 0}
+    totals = {"nodes": 0, "within": 0, "flip": 0, "separated": 0, "flipped_paths": 0, "separated_paths": 0}
     worst = 0.0
     for h, step, inst, g, o in parts:
         N = inst.n_paths
         d = np.maximum(np.abs(g["mean_x"] - o["mean_x"]), np.abs(g["mean_y"] - o["mean_y"]))
         dse = np.maximum(np.abs(g["se_x"] - o["se_x"]), np.abs(g["se_y"] - o["se_y"]))
-        z = np.maximum(np.abs(g["mean_x"] - o["mean_x"]) / np.hypot(g["se_x"], o["se_x"]),
-                       np.abs(g["mean_y"] - o["mean_y"]) / np.hypot(g["se_y"], o["se_y"]))
-        within = d <= 1e-5
+        z = np.maximum(zscore(g["mean_x"] - o["mean_x"], g["se_x"], o["se_x"]),
+                       zscore(g["mean_y"] - o["mean_y"], g["se_y"], o["se_y"]))
+        within = (d <= 1e-5) & (dse <= 1e-5)   # mean and standard error
         totals["nodes"] += len(d)
         totals["within"] += int(np.sum(within))
         if np.any(within):
             worst = max(worst, float(d[within].max()))
-            assert np.all(dse[within] <= 1e-5), (label, inst.name, float(dse[within].max()))
         out = np.flatnonzero(~within)
         resolved = drift_indicator(inst) < 1.0
         if len(out) and allow_separated and not resolved:
@@ -124,27 +166,27 @@ def check_fp32(M, oracle_lib, label, parts, allow_separated=False, max_audits=20
             out[np.unique(np.linspace(0, len(out) - 1, max_audits).astype(int))]
         flips = seps = 0
         for node in audit:
-            n_diff, dv_max, dmean = audit_node(M, oracle_lib, h, step, inst, node)
-            flip = 1 <= n_diff <= max(2, N // 200) and dv_max <= 1e-4 and dmean <= 1e-5
-            if flip:
+            n_flip, n_sep, steady, dmean = audit_node(M, oracle_lib, h, step, inst, node)
+            if 1 <= n_flip + n_sep and n_flip <= max(4, N // 64) and steady == 0 and dmean <= 1e-5:
                 flips += 1
-                totals["flipped_paths"] += n_diff
+                totals["flipped_paths"] += n_flip
+                totals["separated_paths"] += n_sep
                 continue
             seps += 1
-            msg = ("%s %s node %d: |dmean| %.2e, z %.2f, %d of %d paths with another exit outcome, max |dv| of the "
-                   "others %.2e, |dmean| without them %.2e" % (label, inst.name, node, d[node], z[node], n_diff, N,
-                                                               dv_max, dmean))
+            msg = ("%s %s node %d: |dmean| %.2e, z %.2f, of %d paths %d flipped and %d separated (%d of them steady "
+                   "under the rounding probe), |dmean| over the others %.2e"
+                   % (label, inst.name, node, d[node], z[node], N, n_flip, n_sep, steady, dmean))
             assert allow_separated and not resolved, msg
             assert z[node] <= 3.0, msg
         totals["flip"] += flips
         totals["separated"] += seps + (len(out) - len(audit))
         if len(out):
-            say("  %s (dt|grad b| %.2f): %d nodes, %d within 1e-5, %d audited: %d flips, %d separated (max z %.2f)"
+            say("  %s (dt|grad b| %.2f): %d nodes, %d within 1e-5, %d audited: %d explained, %d statistical (max z %.2f)"
                 % (inst.name, drift_indicator(inst), len(d), int(np.sum(within)), len(audit), flips, seps,
                    float(z[out].max())))
-    say("%s: %d nodes: %d within 1e-5 (max %.2e), %d explained by exit decisions (%d paths), %d separated (within "
-        "3 sigma)" % (label, totals["nodes"], totals["within"], worst, totals["flip"], totals["flipped_paths"],
-                      totals["separated"]))
+    say("%s: %d nodes: %d within 1e-5 (max %.2e), %d explained by a few paths (%d flipped, %d separated), %d "
+        "statistical (within 3 sigma)" % (label, totals["nodes"], totals["within"], worst, totals["flip"],
+                                          totals["flipped_paths"], totals["separated_paths"], totals["separated"]))
     return totals
 
 

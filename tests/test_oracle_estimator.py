@@ -357,3 +357,42 @@ def test_fd_single_domain_reference_sharp_bump(oracle_lib):
     z = np.concatenate([zx, zy])
     assert np.max(np.abs(z)) < 4.0, np.max(np.abs(z))
     assert np.mean(z ** 2) < 1.6, np.mean(z ** 2)
+
+
+def test_rounding_probe_is_a_rounding_sized_perturbation(oracle_lib):
+    """The sensitivity probe used by the GPU audits (each substep's position
+    rounded to binary32) must perturb a path by rounding and nothing else:
+    with a constant monitor there is no drift to amplify it, so every path
+    keeps its exit decisions (bar one whose exit test sits within rounding
+    of the side) and its end moves by at most K half-ulps of positions
+    below 1 (2^-25 each) times the mesh's slope (a uniform mesh on
+    [0, 2] x [0, 3] here), and at K = 500 on 33^2 to 513^2 by less than
+    1.5e-6; on the sharp 257^2 front the same probe moves a path crossing
+    the front by orders of magnitude more."""
+    inst = W.constant_problem(33, 2, 0, 0, tau=0.05, K=200, n_paths=512, Lx=2.0, Ly=3.0)
+    P = oracle_lib.Problem(**inst.problem_kwargs())
+    args = (P, inst.rho, inst.x, inst.y, inst.bnd_t0, inst.bnd_t1)
+    worst, flips = 0.0, 0
+    for node in (0, 17, 40):
+        o = oracle_lib.paths(*args, node, 0, inst.n_paths)
+        q = oracle_lib.paths(*args, node, 0, inst.n_paths, round_f32=True)
+        same = (o["side"] == q["side"]) & (o["steps"] == q["steps"])
+        flips += int(np.sum(~same))
+        worst = max(worst, float(np.max(np.maximum(np.abs(o["vx"] - q["vx"]), np.abs(o["vy"] - q["vy"]))[same])))
+    assert flips <= 1 and 0.0 < worst <= inst.K * 2.0 ** -25 * 3.0, (flips, worst)
+    # the GPU audits call a path sensitive when the probe moves it by 2e-6: without drift, at the
+    # workloads' K = 500 and grid sizes, no path comes near that
+    for n in (33, 257, 513):
+        flat = W.constant_problem(n, 2, 1, 0, tau=0.01, K=500, n_paths=1024)
+        P = oracle_lib.Problem(**flat.problem_kwargs())
+        args = (P, flat.rho, flat.x, flat.y, flat.bnd_t0, flat.bnd_t1, 3, 0, 1024)
+        o, q = oracle_lib.paths(*args), oracle_lib.paths(*args, round_f32=True)
+        same = o["steps"] == q["steps"]
+        moved = np.maximum(np.abs(o["vx"] - q["vx"]), np.abs(o["vy"] - q["vy"]))[same]
+        assert float(np.max(moved)) < 1.5e-6, (n, float(np.max(moved)))
+    front = W.config3(n_paths=1024)
+    P = oracle_lib.Problem(**front.problem_kwargs())
+    args = (P, front.rho, front.x, front.y, front.bnd_t0, front.bnd_t1, 2208, 0, 1024)
+    o, q = oracle_lib.paths(*args), oracle_lib.paths(*args, round_f32=True)
+    moved = np.maximum(np.abs(o["vx"] - q["vx"]), np.abs(o["vy"] - q["vy"]))
+    assert float(np.max(moved)) > 1e-2 and float(np.median(moved)) < 1e-6

@@ -279,3 +279,35 @@ def test_quality_closed_forms():
     assert np.max(np.abs(q - want)) < 1e-13
     r, rmax, rmean = mp.quality_ratio(a * x, b * y, a * x, b * y)
     assert rmax == 1.0 and rmean == 1.0
+
+
+# ---------------------------------------------------------------------------
+# the five-ring test of section 4.2, as the paper runs it (one substep)
+# ---------------------------------------------------------------------------
+@pytest.mark.slow
+def test_five_ring_one_substep_matches_single_domain():
+    """Section 4.2 reports single-domain and decomposed meshes of equal
+    quality on the five-ring monitor with one path substep per mesh step.
+    Read with the computational square the same [-1, 1[^2 as the physical
+    domain (a step of 5e-4 there is 1.25e-4 in unit-square time), the
+    decomposed 2x2 mesh after all 100 steps has R = Q_SD / Q_SDD within a
+    few percent of 1 in every cell; read in unit-square time the single
+    Euler-Maruyama substep crosses the steep rings in one jump and the
+    decomposed mesh folds."""
+    def run(comp_side):
+        L = W.five_ring_loop(2, n_paths=2000, comp_side=comp_side)
+        out = []
+        for decomposed in (False, True):
+            x, y, _ = mp.mp_loop(L.u, L.x0, L.y0, L.steps, L.tau, L.K, L.n_paths, L.sub_xi, L.sub_eta,
+                                 L.periodic_xi, L.periodic_eta, L.Lx, L.Ly, L.alpha, L.normalize,
+                                 decomposed=decomposed, threads=8)
+            out.append((x, y))
+        return out
+
+    (xs, ys), (xd, yd) = run(2.0)
+    r, rmax, rmean = mp.quality_ratio(xs, ys, xd, yd)
+    assert float(r.min()) > 0.9 and rmax < 1.1 and abs(rmean - 1.0) < 0.005, (float(r.min()), rmax, rmean)
+    (xs, ys), (xd, yd) = run(1.0)
+    dx_xi, dy_xi = np.diff(xd, axis=1)[:-1], np.diff(yd, axis=1)[:-1]
+    dx_eta, dy_eta = np.diff(xd, axis=0)[:, :-1], np.diff(yd, axis=0)[:, :-1]
+    assert float(np.min(dx_xi * dy_eta - dx_eta * dy_xi)) < 0.0   # a folded cell: negative orientation
