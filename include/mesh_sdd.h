@@ -307,6 +307,29 @@ int mesh_sdd_interface_nodes(const mesh_sdd *inst, int32_t *i, int32_t *j);
  * block) pairs.  Nothing is allocated or launched for such a request. */
 int mesh_sdd_solve_interfaces(mesh_sdd *inst, const mesh_sdd_step *step, mesh_sdd_result *result);
 
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: the same
+ * solve as mesh_sdd_solve_interfaces (same kernels, same chunk plan, so the
+ * same result bits), but every per-call device buffer (staged mesh and
+ * boundary copies, padded meshes, partial sums, queue counters, job list,
+ * end-state buffer, results before their copy-out) is carved from one static
+ * device array of the library, 64 MiB per device, instead of being
+ * allocated.  The call makes no hipMalloc / hipFree and uses no allocating
+ * library routine; the instance's tables (mesh_sdd_create, set_monitor) are
+ * its inputs.  Inputs and outputs must be device pointers
+ * (step->inputs_on_device = 1, result->outputs_on_device = 1; E_INVAL
+ * otherwise).  A solve that needs more than 64 MiB of scratch is refused
+ * with E_INVAL before any work (e.g. 129^2 with 4x4 subdomains fits up to
+ * about 1.9e5 paths per node at the default chunk of 128 paths); an interface
+ * stride > 1 must have been used by an allocating solve of the instance
+ * first (its node lists are built then; E_STATE otherwise).  Every call on
+ * a device shares that device's array, which keeps the last call's contents
+ * (whatever must start at zero is cleared by a fill kernel each call); calls
+ * on one device are serialised by a process-wide lock, and a call blocks
+ * until its results are in the output arrays.  Errors otherwise as
+ * mesh_sdd_solve_interfaces. */
+int mesh_sdd_solve_interfaces_noalloc(mesh_sdd *inst, const mesh_sdd_step *step, mesh_sdd_result *result);
+
 /* Blocking solve of `count` instances (each as mesh_sdd_solve_interfaces,
  * section 3.4): all FP32 instances run in ONE
  * persistent launch over a shared (instance, node, path-chunk) work queue

@@ -29,6 +29,7 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", "-I" + INCLUDE, "-I" + CSRC, "-Wall", "-
 SOURCES = [
     ("kernels.hip", ["--offload-arch=" + ARCH] + DEVICE_FLAGS),
     ("mesh_step.hip", ["--offload-arch=" + ARCH] + DEVICE_FLAGS),
+    ("noalloc.hip", ["--offload-arch=" + ARCH] + DEVICE_FLAGS),
     ("runtime.cpp", []),
     ("mesh_step.cpp", []),
 ]

@@ -461,8 +461,9 @@ int sample_set(mesh_sdd &inst, int stride, const SampleSet **out)
 constexpr uint32_t kMaxLaunchItems = 0xFFF00000u;
 
 // Allocate the request's device buffers, stage its inputs and run the prep
-// kernels; builds the work items.  Caller holds gpu_mu.
-int stage_request(Request &r, const mesh_sdd_step *dev_step)
+// kernels; builds the work items.  With an arena the buffers are carved from
+// it instead of allocated (the no-allocation solve).  Caller holds gpu_mu.
+int stage_request(Request &r, const mesh_sdd_step *dev_step, Arena *arena = nullptr)
 {
     mesh_sdd &inst = *r.inst;
     mesh_sdd_ctx *ctx = inst.ctx;
@@ -494,8 +495,10 @@ int stage_request(Request &r, const mesh_sdd_step *dev_step)
                     "interface stride)", n_part);
 
     for (DevBuf *b : {&r.x64, &r.y64, &r.b0, &r.b1, &r.xpad, &r.ypad, &r.xpad_f, &r.ypad_f, &r.b0f, &r.b1f,
-                      &r.view, &r.partials, &r.spans, &r.out, &r.steps_total})
+                      &r.view, &r.partials, &r.spans, &r.out, &r.steps_total}) {
         b->pool = &ctx->pool;
+        b->arena = arena;
+    }
     if (r.x64.alloc(n * 8) || r.y64.alloc(n * 8) || r.b0.alloc(nb * 8) || r.b1.alloc(nb * 8) ||
         r.xpad.alloc(np * 8) || r.ypad.alloc(np * 8) || r.xpad_f.alloc(np * 4) || r.ypad_f.alloc(np * 4) ||
         r.b0f.alloc(nb * 4) || r.b1f.alloc(nb * 4) || r.view.alloc(sizeof(InstView)) ||
@@ -600,9 +603,16 @@ void release_request_buffers(Request &r)
 // inst fields index `views`).  Caller holds gpu_mu.  Returns the device time
 // in ms via *ms.
 int run_fp32_launch(mesh_sdd_ctx *ctx, const std::vector<InstView> &views, const std::vector<WorkRange> &ranges,
-                    const std::vector<const SampleSet *> &sets, const mesh_sdd_launch &l, double *ms)
+                    const std::vector<const SampleSet *> &sets, const mesh_sdd_launch &l, double *ms,
+                    Arena *arena = nullptr)
 {
     hipStream_t st = ctx->stream;
+    // launch scratch: the context's grow-only buffers, or pieces of the arena
+    DevBuf a_views, a_ranges, a_head, a_jobs, a_ends;
+    for (DevBuf *b : {&a_views, &a_ranges, &a_head, &a_jobs, &a_ends}) b->arena = arena;
+    DevBuf &views_b = arena ? a_views : ctx->views, &ranges_b = arena ? a_ranges : ctx->ranges;
+    DevBuf &head_b = arena ? a_head : ctx->head, &jobs_b = arena ? a_jobs : ctx->jobs;
+    DevBuf &ends_b = arena ? a_ends : ctx->ends;
     size_t n_items = 0;
     for (const WorkRange &w : ranges) n_items += w.count;
     if (n_items == 0) {
@@ -613,11 +623,11 @@ int run_fp32_launch(mesh_sdd_ctx *ctx, const std::vector<InstView> &views, const
     uint32_t cap = 64;   // LDS slots per item: the largest chunk of the launch
     for (const WorkRange &w : ranges) cap = std::max(cap, w.chunk_paths);
     cap = (cap + 63u) / 64u * 64u;
-    if (ctx->views.reserve(views.size() * sizeof(InstView)) ||
-        ctx->ranges.reserve(ranges.size() * sizeof(WorkRange)) || ctx->head.reserve(64))
+    if (views_b.reserve(views.size() * sizeof(InstView)) ||
+        ranges_b.reserve(ranges.size() * sizeof(WorkRange)) || head_b.reserve(64))
         return fail(MESH_SDD_E_NOMEM, "device allocation for the work queue failed");
-    HIP_TRY(hipMemcpyAsync(ctx->views.p, views.data(), views.size() * sizeof(InstView), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(ctx->ranges.p, ranges.data(), ranges.size() * sizeof(WorkRange), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(views_b.p, views.data(), views.size() * sizeof(InstView), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(ranges_b.p, ranges.data(), ranges.size() * sizeof(WorkRange), hipMemcpyHostToDevice, st));
     // A launch that holds one instance whose node tables of rho and dt rho_xi
     // fit the LDS stages them whole (1024-thread workgroups); any other
     // launch stages windows of them, job by job; the waves then keep their
@@ -628,7 +638,7 @@ int run_fp32_launch(mesh_sdd_ctx *ctx, const std::vector<InstView> &views, const
     const int level = table_level(n_nodes, l.monitor_table, &per_cu);
     const int table_grid = ctx->cu_count * per_cu;
     const uint32_t end_waves = (uint32_t)table_grid * (uint32_t)(msdd::kTableBlock / 64);
-    if (level > 0 && ctx->ends.reserve((size_t)end_waves * 6u * cap * sizeof(float)))
+    if (level > 0 && ends_b.reserve((size_t)end_waves * 6u * cap * sizeof(float)))
         return fail(MESH_SDD_E_NOMEM, "device allocation of the end-state buffer failed");
     // windowed launch: one job per (range, grid block), split so that no job
     // holds more than 1/32 of a workgroup's share of the items (1/256 in a
@@ -671,10 +681,10 @@ int run_fp32_launch(mesh_sdd_ctx *ctx, const std::vector<InstView> &views, const
             while (q == msdd::kJobQueues ? k < (int)jobs.size() : (k < (int)jobs.size() && cum[k] < goal)) ++k;
             qs.b[q] = (uint32_t)k;
         }
-        if (ctx->jobs.reserve(std::max<size_t>(1, jobs.size()) * sizeof(msdd::WinJob)))
+        if (jobs_b.reserve(std::max<size_t>(1, jobs.size()) * sizeof(msdd::WinJob)))
             return fail(MESH_SDD_E_NOMEM, "device allocation of the job list failed");
         if (!jobs.empty())
-            HIP_TRY(hipMemcpyAsync(ctx->jobs.p, jobs.data(), jobs.size() * sizeof(msdd::WinJob),
+            HIP_TRY(hipMemcpyAsync(jobs_b.p, jobs.data(), jobs.size() * sizeof(msdd::WinJob),
                                    hipMemcpyHostToDevice, st));
     }
     hipEvent_t e0, e1;
@@ -682,17 +692,17 @@ int run_fp32_launch(mesh_sdd_ctx *ctx, const std::vector<InstView> &views, const
     HIP_TRY(hipEventCreate(&e1));
     HIP_TRY(hipEventRecord(e0, st));
     hipError_t le =
-        level == 3 ? msdd::launch_paths_fp32_window(ctx->views.as<InstView>(), ctx->ranges.as<WorkRange>(),
-                                                    ctx->jobs.as<msdd::WinJob>(), qs, ctx->head.as<uint32_t>(),
+        level == 3 ? msdd::launch_paths_fp32_window(views_b.as<InstView>(), ranges_b.as<WorkRange>(),
+                                                    jobs_b.as<msdd::WinJob>(), qs, head_b.as<uint32_t>(),
                                                     cap, periodic, win_lds, table_grid,
-                                                    ctx->ends.as<float>(), end_waves, st)
-        : level > 0 ? msdd::launch_paths_fp32_table(ctx->views.as<InstView>(), ctx->ranges.as<WorkRange>(),
-                                                    (uint32_t)n_items, ctx->head.as<uint32_t>(), cap, level,
+                                                    ends_b.as<float>(), end_waves, st)
+        : level > 0 ? msdd::launch_paths_fp32_table(views_b.as<InstView>(), ranges_b.as<WorkRange>(),
+                                                    (uint32_t)n_items, head_b.as<uint32_t>(), cap, level,
                                                     views[0].per_xi + 2 * views[0].per_eta, n_nodes, table_grid,
-                                                    ctx->ends.as<float>(), end_waves, st)
-                    : msdd::launch_paths_fp32(ctx->views.as<InstView>(), ctx->ranges.as<WorkRange>(),
+                                                    ends_b.as<float>(), end_waves, st)
+                    : msdd::launch_paths_fp32(views_b.as<InstView>(), ranges_b.as<WorkRange>(),
                                                       (uint32_t)ranges.size(), (uint32_t)n_items,
-                                                      ctx->head.as<uint32_t>(), cap, grid_for(ctx, l, cap), l.block,
+                                                      head_b.as<uint32_t>(), cap, grid_for(ctx, l, cap), l.block,
                                                       st);
     HIP_TRY(hipEventRecord(e1, st));
     hipError_t se = hipEventSynchronize(e1);
@@ -744,8 +754,9 @@ int run_fp64_launch(mesh_sdd_ctx *ctx, Request &r, double *ms)
 }
 
 // Finalize (a9) into the request's output buffer, interpolate the nodes
-// that ran no paths (a10), and copy the results to the host.
-int finalize_request(mesh_sdd_ctx *ctx, Request &r)
+// that ran no paths (a10), and copy the results to the host -- or, when
+// `dev_out` is given, straight into its device arrays.
+int finalize_request(mesh_sdd_ctx *ctx, Request &r, const mesh_sdd_result *dev_out = nullptr)
 {
     hipStream_t st = ctx->stream;
     const mesh_sdd &inst = *r.inst;
@@ -777,9 +788,17 @@ int finalize_request(mesh_sdd_ctx *ctx, Request &r)
         a.exit_frac = o + 4 * (size_t)M;
         HIP_TRY(msdd::launch_interpolate(a, st));
     }
-    r.host_out.resize((size_t)5 * M);
     unsigned long long steps = 0;
-    if (M) HIP_TRY(hipMemcpyAsync(r.host_out.data(), o, r.host_out.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    if (dev_out) {
+        double *dst[5] = {dev_out->mean_x, dev_out->mean_y, dev_out->se_x, dev_out->se_y, dev_out->exit_frac};
+        for (int k = 0; k < 5; ++k)
+            if (dst[k] && M)
+                HIP_TRY(hipMemcpyAsync(dst[k], o + (size_t)k * M, (size_t)M * sizeof(double), hipMemcpyDeviceToDevice,
+                                       st));
+    } else {
+        r.host_out.resize((size_t)5 * M);
+        if (M) HIP_TRY(hipMemcpyAsync(r.host_out.data(), o, r.host_out.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    }
     HIP_TRY(hipMemcpyAsync(&steps, r.steps_total.p, sizeof steps, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     r.executed_steps = steps;
@@ -1069,6 +1088,10 @@ int mesh_sdd_ctx_create(int device, size_t hbm_budget_bytes, void *hip_stream, m
     hipDeviceProp_t prop;
     HIP_TRY(hipGetDeviceProperties(&prop, device));
     ctx->cu_count = prop.multiProcessorCount;
+    // the no-allocation solve's scratch array: its address on this device,
+    // looked up once with the device current (a failure is reported by that
+    // solve, not here)
+    (void)msdd_rt::scratch_resolve(device);
     if (hip_stream) {
         ctx->stream = static_cast<hipStream_t>(hip_stream);
     } else {
@@ -1402,6 +1425,83 @@ int mesh_sdd_solve_interfaces(mesh_sdd *inst, const mesh_sdd_step *step, mesh_sd
     int32_t st = 0;
     mesh_sdd *one[1] = {inst};
     return mesh_sdd_solve_batch(one, step, result, 1, &st);
+}
+
+int mesh_sdd_solve_interfaces_noalloc(mesh_sdd *inst, const mesh_sdd_step *step, mesh_sdd_result *result)
+{
+    if (!inst || !step || !result) return fail(MESH_SDD_E_INVAL, "NULL argument");
+    if (!inst->monitor_set) return fail(MESH_SDD_E_STATE, "set_monitor not called");
+    if (result->struct_size != sizeof(mesh_sdd_result))
+        return fail(MESH_SDD_E_INVAL, "result.struct_size %u != %zu", result->struct_size, sizeof(mesh_sdd_result));
+    int64_t N = 0;
+    int rc = validate_step(*inst, step, &N);
+    if (rc != MESH_SDD_OK) return rc;
+    if (!step->inputs_on_device) return fail(MESH_SDD_E_INVAL, "the no-allocation solve takes device inputs");
+    if (!result->outputs_on_device) return fail(MESH_SDD_E_INVAL, "the no-allocation solve takes device outputs");
+    mesh_sdd_ctx *ctx = inst->ctx;
+    const mesh_sdd_desc &d = inst->d;
+    auto r = make_request(inst, *step, N);
+    void *base = nullptr;
+    std::mutex *use = nullptr;
+    rc = msdd_rt::scratch_region(ctx->device, &base, &use);
+    if (rc != MESH_SDD_OK) return rc;
+    std::lock_guard<std::mutex> su(*use);   // one user of the device's array at a time
+    std::lock_guard<std::mutex> g(ctx->gpu_mu);
+    auto set = inst->samples.find(r->stride);
+    if (set == inst->samples.end())
+        return fail(MESH_SDD_E_STATE, "interface stride %d: its node lists are built by the first allocating solve "
+                    "with that stride", r->stride);
+    // the scratch this call carves, counted as stage_request and the launch
+    // carve it (each piece rounded to 256 bytes); the job list by its bound
+    // of one job per 64 items plus one per grid block
+    const bool fp64 = d.precision == MESH_SDD_FP64;
+    const size_t n = (size_t)d.n_xi * d.n_eta, np = (size_t)(d.n_xi + 2) * (d.n_eta + 2);
+    const size_t nb = 4 * (size_t)d.n_eta + 4 * (size_t)d.n_xi;
+    const size_t chunks = fp64 ? (size_t)((N + msdd::kFp64Block - 1) / msdd::kFp64Block)
+                               : (size_t)((N + r->chunk_paths - 1) / r->chunk_paths);
+    const size_t n_items = (size_t)r->Ms * chunks;
+    auto piece = [](size_t b) { return b == 0 ? (size_t)256 : round_up(b, 256); };
+    size_t need = 2 * piece(n * 8) + 2 * piece(nb * 8) + 2 * piece(np * 8) + 2 * piece(np * 4) + 2 * piece(nb * 4) +
+                  piece(sizeof(InstView)) + piece(n_items * sizeof(Partial)) +
+                  piece((size_t)r->Ms * sizeof(NodeSpan)) + piece((size_t)5 * inst->M * sizeof(double)) + piece(8);
+    if (!fp64) {
+        const mesh_sdd_launch l = launch_for(ctx, d);
+        int per_cu = 0;
+        const int level = table_level((int)n, l.monitor_table, &per_cu);
+        const size_t cap = (size_t)(r->chunk_paths + 63) / 64 * 64;
+        need += piece(sizeof(InstView)) + piece(sizeof(WorkRange)) + piece(64);
+        if (level > 0) need += piece((size_t)ctx->cu_count * per_cu * (msdd::kTableBlock / 64) * 6 * cap * 4);
+        if (level == 3) need += piece((n_items / 64 + set->second->blocks.size() + 1) * sizeof(msdd::WinJob));
+    }
+    if (need > msdd_rt::scratch_capacity())
+        return fail(MESH_SDD_E_INVAL, "the solve needs %zu bytes of scratch, more than the %zu of the no-allocation "
+                    "solve (fewer paths per node, a smaller grid or an interface stride)", need,
+                    msdd_rt::scratch_capacity());
+    Arena arena;
+    arena.base = static_cast<char *>(base);
+    arena.size = msdd_rt::scratch_capacity();
+    inst->inflight.fetch_add(1);
+    rc = stage_request(*r, step, &arena);
+    double ms = 0.0;
+    if (rc == MESH_SDD_OK) {
+        if (fp64) {
+            rc = run_fp64_launch(ctx, *r, &ms);
+        } else {
+            std::vector<InstView> views{r->v};
+            std::vector<WorkRange> ranges;
+            std::vector<const SampleSet *> sets{r->ss};
+            if (r->n_items) ranges.push_back(range_of(*r, 0, 0, 0, r->n_items));
+            rc = run_fp32_launch(ctx, views, ranges, sets, launch_for(ctx, d), &ms, &arena);
+        }
+    }
+    if (rc == MESH_SDD_OK) rc = finalize_request(ctx, *r, result);
+    release_request_buffers(*r);   // frees nothing: every piece is the arena's
+    inst->inflight.fetch_sub(1);
+    if (rc != MESH_SDD_OK) return rc;
+    result->executed_path_steps = r->executed_steps;
+    result->paths_per_node = r->N;
+    result->device_ms = ms;
+    return MESH_SDD_OK;
 }
 
 int mesh_sdd_submit(mesh_sdd *inst, const mesh_sdd_step *step, mesh_sdd_ticket *ticket)

@@ -95,18 +95,37 @@ struct DevPool {
     }
 };
 
-// Device allocation owned by one object (from a pool when one is given).
+// A fixed region of device memory handed out front to back in 256-byte
+// aligned pieces (the no-allocation solve carves its buffers from the
+// library's static scratch array this way).  Nothing is ever freed.
+struct Arena {
+    char *base = nullptr;
+    size_t size = 0;
+    size_t used = 0;
+    void *take(size_t n)
+    {
+        n = n == 0 ? 256 : (n + 255) / 256 * 256;
+        if (!base || used + n > size) return nullptr;
+        void *p = base + used;
+        used += n;
+        return p;
+    }
+};
+
+// Device allocation owned by one object (from a pool when one is given), or
+// a piece of an Arena that it only borrows (never freed by it).
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
     DevPool *pool = nullptr;
+    Arena *arena = nullptr;   // set: alloc takes from the arena, release frees nothing
     DevBuf() = default;
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
     ~DevBuf() { release(); }
     void release()
     {
-        if (p) {
+        if (p && !arena) {
             if (pool)
                 pool->put(p, bytes);
             else
@@ -119,6 +138,12 @@ struct DevBuf {
     {
         release();
         n = n == 0 ? 256 : (n + 255) / 256 * 256;
+        if (arena) {
+            p = arena->take(n);
+            if (!p) return hipErrorOutOfMemory;
+            bytes = n;
+            return hipSuccess;
+        }
         if (pool) {
             p = pool->get(n);
             if (!p) return hipErrorOutOfMemory;
@@ -281,6 +306,13 @@ struct mesh_sdd_ctx {
 
 namespace msdd_rt {
 int install_monitor(mesh_sdd *inst, hipStream_t st);
+
+// The static device scratch of the no-allocation solve (noalloc.hip): its
+// size, the one-time lookup of its address on a device (the caller has made
+// that device current), and that address with the lock its users hold.
+size_t scratch_capacity();
+hipError_t scratch_resolve(int device);
+int scratch_region(int device, void **base, std::mutex **use);
 
 // Ranks of the interface nodes that run paths under `stride` (0 or 1: all),
 // in rank order.  The stride must have passed the step validation.

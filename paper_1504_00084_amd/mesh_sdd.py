@@ -33,6 +33,7 @@ EXPORTS = (
     "mesh_sdd_desc_interface_nodes", "mesh_sdd_edge_generate", "mesh_sdd_subdomain_solve",
     "mesh_sdd_single_domain_solve", "mesh_sdd_mp_step", "mesh_sdd_set_monitor_arclength", "mesh_sdd_get_monitor",
     "mesh_sdd_mesh_quality", "mesh_sdd_transfer_field", "mesh_sdd_desc_work_order",
+    "mesh_sdd_solve_interfaces_noalloc",
 )
 
 
@@ -120,6 +121,7 @@ def load(path: str = LIB_PATH):
         "mesh_sdd_num_interface_nodes": [vp],
         "mesh_sdd_interface_nodes": [vp, vp, vp],
         "mesh_sdd_solve_interfaces": [vp, P(Step), P(Result)],
+        "mesh_sdd_solve_interfaces_noalloc": [vp, P(Step), P(Result)],
         "mesh_sdd_solve_batch": [P(vp), P(Step), P(Result), i32, P(i32)],
         "mesh_sdd_submit": [vp, P(Step), P(ctypes.c_uint64)],
         "mesh_sdd_poll": [vp, ctypes.c_uint64, P(Result)],
@@ -309,6 +311,13 @@ def make_result(mean_x, mean_y, se_x, se_y, exit_frac) -> Result:
 
 def mesh_sdd_solve_interfaces(inst, step: Step, result: Result) -> Result:
     _check(load().mesh_sdd_solve_interfaces(inst, ctypes.byref(step), ctypes.byref(result)))
+    return result
+
+
+def mesh_sdd_solve_interfaces_noalloc(inst, step: Step, result: Result) -> Result:
+    """The solve with every per-call buffer in the library's static device
+    scratch (device inputs and outputs only)."""
+    _check(load().mesh_sdd_solve_interfaces_noalloc(inst, ctypes.byref(step), ctypes.byref(result)))
     return result
 
 
