@@ -84,6 +84,22 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# Launch shapes found by the library's autotuner on an MI355X (per grid
+# bucket and for multi-instance launches), loaded into every context the
+# benchmark creates when the file exists.
+TUNE_CACHE = os.path.join(ROOT, "paper_1504_00084_amd", "tune_cache.txt")
+
+
+def new_ctx(M, budget_bytes=0, stream=None, tune_cache=None):
+    """A library context with the tuned shapes of `tune_cache` (default: the
+    committed cache, if present)."""
+    ctx = M.mesh_sdd_ctx_create(0, budget_bytes, stream)
+    path = TUNE_CACHE if tune_cache is None else tune_cache
+    if path and os.path.exists(path):
+        M.mesh_sdd_tune_load(ctx, path)
+    return ctx
+
+
 def host_threads():
     """Host cores this process may use for the oracle: the CPU affinity, cut
     to the cgroup's CPU quota and to OMP_NUM_THREADS where those are set (a
@@ -123,7 +139,12 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and its parity check")
     ap.add_argument("--no-mix", action="store_true", help="skip the batched 64-instance mix of the step mode")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run of the step mode")
-    ap.add_argument("--tune", action="store_true", help="run the library's autotuner before timing")
+    ap.add_argument("--tune", action="store_true",
+                    help="step mode: autotune the headline's bucket before timing; batch mode: time the mix with "
+                         "the default shapes, autotune the batch, time it again")
+    ap.add_argument("--tune-cache", default=None,
+                    help="tuned shapes to load (default: paper_1504_00084_amd/tune_cache.txt if present; '' for none)")
+    ap.add_argument("--tune-save", default="", help="batch mode with --tune: write the tuned shapes here")
     ap.add_argument("--launch", default="", help="fixed launch shape BLOCK,WAVES_PER_SIMD,CHUNK")
     ap.add_argument("--jsonl", default="", help="also write per-node parity and serving records to this JSONL file")
     ap.add_argument("--mode", default="step", choices=["step", "batch", "serve", "mp", "quality", "variants"],
@@ -132,7 +153,7 @@ def parse():
                          "quality: five-ring mesh quality R against the single-domain mesh; variants: MkP / (MP)l")
     ap.add_argument("--mp-steps", type=int, default=50, help="mesh steps of the mp mode")
     ap.add_argument("--quality-subs", default="2,3,4", help="subdomains per axis of the quality mode")
-    ap.add_argument("--quality-K", default="1,10", help="path substeps per mesh step of the quality mode")
+    ap.add_argument("--quality-K", default="1", help="path substeps per mesh step of the quality mode")
     ap.add_argument("--quality-stride", default="1,2",
                     help="interface sampling strides of the quality mode (skipped where a stride does not divide "
                          "the subdomain size)")
@@ -217,7 +238,7 @@ def run_step(args):
         torch.cuda.synchronize()
         log("plain copy: %d MiB read, %d MiB written" % (args.copy_mb, args.copy_mb))
         del src, dst
-    ctx = M.mesh_sdd_ctx_create(0, 0, stream.cuda_stream)
+    ctx = new_ctx(M, 0, stream.cuda_stream, args.tune_cache)
     h32 = M.mesh_sdd_create(ctx, M.desc_for(inst, M.FP32))
     m = M.mesh_sdd_num_interface_nodes(h32)
     outs = [torch.empty(m, dtype=torch.float64, device=dev) for _ in range(5)]
@@ -231,8 +252,9 @@ def run_step(args):
     elif args.tune:
         t = time.time()
         lo = M.mesh_sdd_autotune(h32, step)
-        log("autotune: chunk %d (%.1f s)" % (lo.chunk_paths, time.time() - t))
+        log("autotune: %s (%.1f s)" % (lo.as_dict(), time.time() - t))
     lo = M.mesh_sdd_get_launch(h32)
+    log("launch shape: %s" % lo.as_dict())
 
     def one_step():
         M.mesh_sdd_set_monitor(h32, rho)        # a0: table of the frozen monitor
@@ -294,7 +316,7 @@ def run_step(args):
     M.mesh_sdd_destroy(h32)
     M.mesh_sdd_ctx_destroy(ctx)
 
-    mix = None if args.no_mix else batch_measure(1.0, 64, "", device_inputs=True)
+    mix = None if args.no_mix else batch_measure(1.0, 64, "", device_inputs=True, tune_cache=args.tune_cache)
     serving = None
     if not args.no_serve:
         cap32 = mix["nominal_path_steps"] / mix["wall_s"] if mix else rate * nominal / max(per_launch, 1.0)
@@ -320,8 +342,7 @@ def run_step(args):
                    "periodic": [inst.periodic_xi, inst.periodic_eta], "interface_nodes": m,
                    "paths_per_node": inst.n_paths, "K": inst.K, "tau": inst.tau, "nominal_path_steps": nominal,
                    "executed_path_steps_per_step": per_launch, "max_se": se_max,
-                   "launch": {"block": 1024 if lo.table_level else lo.block, "chunk_paths": lo.chunk_paths,
-                              "table_level": lo.table_level}},
+                   "launch": dict(lo.as_dict(), tune_source=tune_source(args.tune_cache, args.tune))},
         "fp64_plain": fp64,
         "roofline": roofline,
         "batched_mix": mix,
@@ -332,8 +353,15 @@ def run_step(args):
     print(json.dumps(line), flush=True)
 
 
+def tune_source(tune_cache, tuned_now=False):
+    if tuned_now:
+        return "autotuned in this run"
+    path = TUNE_CACHE if tune_cache is None else tune_cache
+    return os.path.relpath(path, ROOT) if path and os.path.exists(path) else "library defaults"
+
+
 def batch_measure(scale: float, count: int, sizes: str, device_inputs: bool = True, launch: str = "",
-                  label: str = "batched mix") -> dict:
+                  label: str = "batched mix", tune_cache=None, tune: bool = False, tune_save: str = "") -> dict:
     """The batched mix: independent instances (grids 33..513, 2x2..16x16
     subdomains, bump or periodic front, 1e4..1e6 paths) in ONE persistent
     FP32 launch through mesh_sdd_solve_batch; inputs resident on the device.
@@ -353,7 +381,7 @@ def batch_measure(scale: float, count: int, sizes: str, device_inputs: bool = Tr
         for it in insts:
             it.n_paths = max(64, int(it.n_paths * scale) // 64 * 64)
     dev = torch.device("cuda:0")
-    ctx = M.mesh_sdd_ctx_create(0)
+    ctx = new_ctx(M, 0, None, "" if tune else tune_cache)
     if launch:
         bl, wv, ch = (int(v) for v in launch.split(","))
         M.mesh_sdd_set_launch(ctx, M.make_launch(bl, wv, ch))
@@ -374,6 +402,27 @@ def batch_measure(scale: float, count: int, sizes: str, device_inputs: bool = Tr
         steps.append(M.make_step(*src, paths_per_node=it.n_paths))
     nominal = sum(m * it.n_paths * it.K for m, it in zip(ms, insts))
     log("%s: %d instances, %d interface nodes, nominal %.3e path-steps" % (label, len(insts), sum(ms), nominal))
+    untuned = None
+    if tune:
+        # the library's default shapes first, then the autotuned ones
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        M.mesh_sdd_solve_batch(hs, steps, results)
+        w0 = time.perf_counter() - t
+        untuned = {"kernel_ms": results[0].device_ms, "wall_s": w0,
+                   "executed_path_steps": sum(int(r.executed_path_steps) for r in results)}
+        log("%s, default shapes: kernel %.1f ms" % (label, untuned["kernel_ms"]))
+        t = time.perf_counter()
+        lo = M.mesh_sdd_autotune_batch(hs, steps, scale_down=50)
+        untuned["tuning_s"] = time.perf_counter() - t
+        log("autotuned batch (%.1f s): %s" % (untuned["tuning_s"], lo.as_dict()))
+        if tune_save:
+            M.mesh_sdd_tune_save(ctx, tune_save)
+    shapes = {}
+    for it, h in zip(insts, hs):
+        key = "%d%s" % (it.n_xi, "p" if it.periodic_xi else "")
+        if key not in shapes:
+            shapes[key] = M.mesh_sdd_get_launch(h).as_dict()
     torch.cuda.synchronize()
     t = time.perf_counter()
     M.mesh_sdd_solve_batch(hs, steps, results)
@@ -394,7 +443,11 @@ def batch_measure(scale: float, count: int, sizes: str, device_inputs: bool = Tr
            "sizes": sorted({it.n_xi for it in insts}), "by_size": by_size,
            "roofline": {"bound": "alu", "achieved": round(slots / (kernel_ms / 1e3) / 1e12, 3),
                         "peak": round(VALU_PEAK_TOPS, 3), "unit": "TOP/s", "frac": round(frac, 4),
-                        "slots_per_path_step": round(slots / max(executed, 1), 3)}}
+                        "slots_per_path_step": round(slots / max(executed, 1), 3)},
+           "launch_shapes": {"tune_source": tune_source(tune_cache, tune), "per_grid": shapes}}
+    if untuned:
+        untuned["frac"] = round(frac * kernel_ms / untuned["kernel_ms"], 4)
+        out["default_shapes"] = untuned
     log("%s: %.3e path-steps/s (kernel %.1f ms, wall %.2f s), frac %.3f, max SE %.2e"
         % (label, executed / wall, kernel_ms, wall, frac, se))
     for h in hs:
@@ -405,7 +458,8 @@ def batch_measure(scale: float, count: int, sizes: str, device_inputs: bool = Tr
 
 def run_batch(args):
     line = {"metric": "batched mix path-steps/s (one persistent launch)"}
-    line.update(batch_measure(args.batch_scale, args.batch_count, args.batch_sizes, launch=args.launch))
+    line.update(batch_measure(args.batch_scale, args.batch_count, args.batch_sizes, launch=args.launch,
+                              tune_cache=args.tune_cache, tune=args.tune, tune_save=args.tune_save))
     line["dtype"] = "f32 (paths) / f64 (sums)"
     line["data"] = "synthetic"
     print(json.dumps(line), flush=True)
@@ -441,7 +495,7 @@ def serve_measure(requests: int, warmup: int, precision: str, sizes, max_paths: 
             raise ValueError("serve_measure needs a rate or a measured capacity")
         rate = 0.7 * capacity / float(np.mean(work))
     arrivals = [t / rate for t, _, _ in stream]
-    ctx = M.mesh_sdd_ctx_create(0, budget_mb << 20)
+    ctx = new_ctx(M, budget_mb << 20)
     if launch:
         bl, wv, ch = (int(v) for v in launch.split(","))
         M.mesh_sdd_set_launch(ctx, M.make_launch(bl, wv, ch))
@@ -763,10 +817,11 @@ def run_variants(args):
 
 def run_quality(args):
     """Five-ring periodic mesh test: 100 steps of dt = 5e-4 (K = 1), 1e4 paths,
-    alpha = 0.2, R = 30, on [-1, 1[^2; the decomposed mesh against the
-    single-domain mesh, R_max and R_mean of R = Q_SD / Q_SDD.  41 nodes per
-    axis (40 distinct) for 2x2 and 4x4; 43 for 3x3 (40 is not a multiple
-    of 3)."""
+    alpha = 0.2, R = 30, on [-1, 1[^2 (the computational square the same
+    [-1, 1[^2, so 1.25e-4 per step in unit-square time); the decomposed mesh
+    against the single-domain mesh, R_max and R_mean of R = Q_SD / Q_SDD.
+    41 nodes per axis (40 distinct) for 2x2 and 4x4; 43 for 3x3 (40 is not a
+    multiple of 3)."""
     from paper_1504_00084_amd import mesh_sdd as M
     from paper_1504_00084_amd import mp_loop
     from paper_1504_00084_amd import workloads as W

@@ -157,12 +157,17 @@ typedef struct {
     uint64_t executed_path_steps;    /* summed over completed requests               */
 } mesh_sdd_stats;
 
-/* Launch shape of the batched FP32 kernel (chosen by the autotuner or set). */
+/* Launch shape of the batched FP32 kernels of the section 3.4 solve (chosen
+ * by the autotuner or set).  Only chunk_paths changes results (it sets how
+ * the paths of a node are grouped into FP64 partial sums); every other
+ * field changes speed only.  0 in an int field below means its default. */
 typedef struct {
     uint32_t struct_size;
-    int32_t block;                   /* threads per workgroup (64, 128, 256, 512)    */
-    int32_t waves_per_simd;          /* persistent residency target (1..8)           */
-    int32_t chunk_paths;             /* paths per work item (multiple of 64)         */
+    int32_t block;                   /* cell-record kernel (monitor_table = 1) only:
+                                        threads per workgroup (64, 128, 256, 512)    */
+    int32_t waves_per_simd;          /* cell-record kernel only: residency (1..8)    */
+    int32_t chunk_paths;             /* paths per work item (multiple of 64, 64..2048;
+                                        default 128)                                 */
     int32_t monitor_table;           /* 0: automatic -- a launch that holds one
                                         instance whose FP32 node tables of rho and
                                         dt rho_xi fit the LDS (8 B per node) stages
@@ -174,14 +179,35 @@ typedef struct {
                                         leave a window read the cell records
                                         (1024-thread workgroups, item end states in
                                         a context buffer; identical results); 1:
-                                        always from the cell records in L2;
-                                        block / waves_per_simd apply to that kernel
-                                        only                                         */
+                                        always from the cell records in L2          */
     int32_t table_level;             /* out (mesh_sdd_get_launch): how a launch
                                         holding this instance alone reads the
                                         tables: 0 cell records, 2 whole node tables
                                         in LDS, 3 windows in LDS.  Ignored by
                                         mesh_sdd_set_launch.                         */
+    int32_t refill_lanes;            /* LDS kernels: a wave leaves its stepping loop
+                                        for the lane refill once fewer than this
+                                        many of its 64 lanes have a path in flight
+                                        (1..64; default 56)                          */
+    int32_t max_quarters;            /* LDS kernels: ... or after this many groups
+                                        of four substeps (1..64; default 16)         */
+    int32_t window_kind;             /* windowed kernel, grids whose tables the LDS
+                                        cannot hold whole: 1 two-field windows (rho,
+                                        dt rho_xi per node, up to 140 x 140 nodes),
+                                        2 three-field windows (also the dt rho_eta
+                                        coefficients of their cells, up to 81 x 81);
+                                        default: three-field below 400 nodes per
+                                        axis, two-field above.  A window that holds
+                                        the whole grid is always used.               */
+    int32_t window_margin;           /* window nodes beyond a block on each side
+                                        (default 45 two-field, 30 three-field); the
+                                        block is the window less twice the margin
+                                        (at least 1 node): a wider margin keeps more
+                                        paths inside, at more window refills         */
+    int32_t job_split;               /* windowed kernel: a job holds at most 1/job_split
+                                        of a workgroup's share of the launch's items
+                                        (1..4096; default 32, and 256 on grids cut
+                                        into several two-field windows)              */
 } mesh_sdd_launch;
 
 /* ---- context ------------------------------------------------------------ */
@@ -207,17 +233,41 @@ int mesh_sdd_ctx_stats(mesh_sdd_ctx *ctx, mesh_sdd_stats *out);
 /* Fix the launch shape of the batched kernel of the section 3.4 solve
  * (overrides the autotuner for every later launch; results do not depend on
  * it except through chunk_paths, which sets the grouping of the FP64 sums);
- * NULL restores autotuning. */
+ * NULL restores the tuned or default shapes.  E_INVAL on a field outside
+ * its range. */
 int mesh_sdd_set_launch(mesh_sdd_ctx *ctx, const mesh_sdd_launch *launch);
 
-/* Launch shape that the next section 3.4 launch over `inst` would use. */
+/* Launch shape that the next section 3.4 launch over `inst` alone would use
+ * (defaults filled in). */
 int mesh_sdd_get_launch(mesh_sdd *inst, mesh_sdd_launch *out);
 
-/* Autotune the batched kernel for the shape bucket of `inst` (grid size,
- * periodicity) by timing candidate shapes on a reduced path count of
- * `step`; the result is cached in the context for later launches of that
- * bucket.  Writes the winner to *out if non-NULL. */
+/* Autotune the FP32 kernels for the shape bucket of `inst` (grid size and
+ * periodicity): times launches of `inst` alone on a reduced path count of
+ * `step` (about 6e9 path-steps each) and searches, one knob at a time, over
+ * chunk_paths {64, 128, 256}, window_kind and window_margin (windowed grids
+ * only), job_split {8, 32, 128, 256, 1024}, refill_lanes {48, 56, 60} and
+ * max_quarters {8, 16, 32}.  The winner is kept in the context for every
+ * later launch of that bucket alone (and for the per-instance knobs,
+ * chunk_paths, window_kind and window_margin, inside batches and serving
+ * ticks too).  Writes it to *out if non-NULL. */
 int mesh_sdd_autotune(mesh_sdd *inst, const mesh_sdd_step *step, mesh_sdd_launch *out);
+
+/* Autotune for a batch: first each distinct shape bucket of `insts` (as
+ * mesh_sdd_autotune, on the first instance of the bucket), then the
+ * launch-wide knobs of a multi-instance launch (job_split, refill_lanes,
+ * max_quarters) by timing the whole batch at 1/scale_down of every step's
+ * path count (at least 64 paths).  The launch-wide winner is kept for every
+ * later launch of several instances (mesh_sdd_solve_batch, serving ticks)
+ * and written to *out if non-NULL.  All FP32. */
+int mesh_sdd_autotune_batch(mesh_sdd *const *insts, const mesh_sdd_step *steps, int32_t count, int32_t scale_down,
+                            mesh_sdd_launch *out);
+
+/* Write the context's tuned shapes (per bucket and for multi-instance
+ * launches) to a text file, one line each; mesh_sdd_tune_load reads such a
+ * file back into a context (replacing its entries of the same keys).
+ * E_INVAL on a file that cannot be written or parsed. */
+int mesh_sdd_tune_save(mesh_sdd_ctx *ctx, const char *path);
+int mesh_sdd_tune_load(mesh_sdd_ctx *ctx, const char *path);
 
 /* ---- host-only helpers (no device needed) --------------------------------- */
 

@@ -115,9 +115,8 @@ def _load():
     lib.oracle_paths.argtypes = [P(_Problem), pd, pd, pd, pd, pd, i32, i64, i64,
                                  pd, pd, pi32, pi32, pi32, pd]
     lib.oracle_paths.restype = i32
-    lib.oracle_paths_rounded.argtypes = [P(_Problem), pd, pd, pd, pd, pd, i32, i64, i64,
-                                         pd, pd, pi32, pi32, pi32]
-    lib.oracle_paths_rounded.restype = i32
+    lib.oracle_path_amplification.argtypes = [P(_Problem), pd, pd, pd, pd, pd, i32, i64, i64, pd]
+    lib.oracle_path_amplification.restype = i32
     _lib = lib
     return lib
 
@@ -250,12 +249,30 @@ def solve(prob: Problem, rho, x_cur, y_cur, bnd_t0, bnd_t1, n_paths: int,
     return res
 
 
+def path_amplification(prob: Problem, rho, x_cur, y_cur, bnd_t0, bnd_t1, node: int, p_begin: int,
+                       p_end: int):
+    """Per path, how much it amplifies rounding (linearised, not an
+    estimate): the standard deviation of its end point in (xi, eta) per unit
+    standard deviation of independent perturbations of each coordinate
+    after every substep; sqrt(substeps) where there is no drift."""
+    lib = _load()
+    pc = prob.c()
+    rho, x_cur, y_cur = _f64(rho), _f64(x_cur), _f64(y_cur)
+    bnd_t0, bnd_t1 = _f64(bnd_t0), _f64(bnd_t1)
+    n = p_end - p_begin
+    amp = np.empty(max(n, 1))
+    rc = lib.oracle_path_amplification(ctypes.byref(pc), _ptr(rho, ctypes.c_double), _ptr(x_cur, ctypes.c_double),
+                                       _ptr(y_cur, ctypes.c_double), _ptr(bnd_t0, ctypes.c_double),
+                                       _ptr(bnd_t1, ctypes.c_double), node, p_begin, p_end,
+                                       _ptr(amp, ctypes.c_double))
+    if rc != 0:
+        raise ValueError("oracle_path_amplification rejected its arguments")
+    return amp[:n]
+
+
 def paths(prob: Problem, rho, x_cur, y_cur, bnd_t0, bnd_t1, node: int, p_begin: int, p_end: int,
-          trace: bool = False, round_f32: bool = False) -> dict:
-    """Per-path outcomes of one node (values, exit flag/side, steps, trace).
-    round_f32: the sensitivity probe (no trace): every substep's position
-    rounded to binary32, the size of a single-precision path's own rounding;
-    not an estimate of anything."""
+          trace: bool = False) -> dict:
+    """Per-path outcomes of one node (values, exit flag/side, steps, trace)."""
     lib = _load()
     pc = prob.c()
     rho, x_cur, y_cur = _f64(rho), _f64(x_cur), _f64(y_cur)
@@ -264,16 +281,12 @@ def paths(prob: Problem, rho, x_cur, y_cur, bnd_t0, bnd_t1, node: int, p_begin: 
     vx, vy = np.empty(max(n, 1)), np.empty(max(n, 1))
     ex, sd, st = (np.empty(max(n, 1), dtype=np.int32) for _ in range(3))
     tr = np.full((max(n, 1), prob.K, 4), np.nan) if trace else None
-    args = (ctypes.byref(pc), _ptr(rho, ctypes.c_double), _ptr(x_cur, ctypes.c_double),
-            _ptr(y_cur, ctypes.c_double), _ptr(bnd_t0, ctypes.c_double), _ptr(bnd_t1, ctypes.c_double), node,
-            p_begin, p_end, _ptr(vx, ctypes.c_double), _ptr(vy, ctypes.c_double), _ptr(ex, ctypes.c_int32),
-            _ptr(sd, ctypes.c_int32), _ptr(st, ctypes.c_int32))
-    if round_f32:
-        if trace:
-            raise ValueError("the rounded probe keeps no trace")
-        rc = lib.oracle_paths_rounded(*args)
-    else:
-        rc = lib.oracle_paths(*args, _ptr(tr, ctypes.c_double) if trace else None)
+    rc = lib.oracle_paths(ctypes.byref(pc), _ptr(rho, ctypes.c_double), _ptr(x_cur, ctypes.c_double),
+                          _ptr(y_cur, ctypes.c_double), _ptr(bnd_t0, ctypes.c_double),
+                          _ptr(bnd_t1, ctypes.c_double), node, p_begin, p_end,
+                          _ptr(vx, ctypes.c_double), _ptr(vy, ctypes.c_double),
+                          _ptr(ex, ctypes.c_int32), _ptr(sd, ctypes.c_int32), _ptr(st, ctypes.c_int32),
+                          _ptr(tr, ctypes.c_double) if trace else None)
     if rc != 0:
         raise ValueError("oracle_paths rejected its arguments")
     out = {"vx": vx[:n], "vy": vy[:n], "exited": ex[:n], "side": sd[:n], "steps": st[:n]}

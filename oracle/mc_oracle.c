@@ -290,6 +290,39 @@ static void bilinear3(const monitor_table *T, double xi, double eta, double *r, 
     *ry = bilinear_field(T->rho_eta, T, ci, cj, tx, ty);
 }
 
+/* Partial derivatives in (xi, eta) of the bilinear interpolant inside cell
+ * (ci, cj) at local coordinates (tx, ty). */
+static void bilinear_field_grad(const double *f, const monitor_table *T, int ci, int cj, double tx, double ty,
+                                double *f_xi, double *f_eta)
+{
+    double f00 = table_node(f, T, ci, cj), f10 = table_node(f, T, ci + 1, cj);
+    double f01 = table_node(f, T, ci, cj + 1), f11 = table_node(f, T, ci + 1, cj + 1);
+    *f_xi = (double)(T->n_xi - 1) * ((1.0 - ty) * (f10 - f00) + ty * (f11 - f01));
+    *f_eta = (double)(T->n_eta - 1) * ((1.0 - tx) * (f01 - f00) + tx * (f11 - f10));
+}
+
+/* Jacobian of one Euler-Maruyama substep's deterministic part,
+ * I + dt grad(b), b = (rho_xi / rho, rho_eta / rho) interpolated as in
+ * bilinear3, at (xi, eta): row-major a[4]. */
+static void substep_jacobian(const monitor_table *T, double xi, double eta, double dt, double a[4])
+{
+    int ci, cj;
+    double tx, ty, r, gx, gy, r_xi, r_eta, gx_xi, gx_eta, gy_xi, gy_eta;
+    locate(xi, T->n_xi, T->per_xi, &ci, &tx);
+    locate(eta, T->n_eta, T->per_eta, &cj, &ty);
+    r = bilinear_field(T->rho, T, ci, cj, tx, ty);
+    gx = bilinear_field(T->rho_xi, T, ci, cj, tx, ty);
+    gy = bilinear_field(T->rho_eta, T, ci, cj, tx, ty);
+    bilinear_field_grad(T->rho, T, ci, cj, tx, ty, &r_xi, &r_eta);
+    bilinear_field_grad(T->rho_xi, T, ci, cj, tx, ty, &gx_xi, &gx_eta);
+    bilinear_field_grad(T->rho_eta, T, ci, cj, tx, ty, &gy_xi, &gy_eta);
+    /* d(g / r) = (dg r - g dr) / r^2 */
+    a[0] = 1.0 + dt * (gx_xi * r - gx * r_xi) / (r * r);
+    a[1] = dt * (gx_eta * r - gx * r_eta) / (r * r);
+    a[2] = dt * (gy_xi * r - gy * r_xi) / (r * r);
+    a[3] = 1.0 + dt * (gy_eta * r - gy * r_eta) / (r * r);
+}
+
 void oracle_bilinear(int32_t n_xi, int32_t n_eta, int32_t per_xi, int32_t per_eta,
                      const double *rho, const double *rho_xi, const double *rho_eta,
                      double xi, double eta, double out[3])
@@ -434,12 +467,13 @@ typedef struct {
     monitor_table T;
     mesh_field X, Y;
     const double *bnd_t0, *bnd_t1;
-    int32_t round_f32;   /* sensitivity probe only: see oracle_paths_rounded */
+    int32_t track;       /* sensitivity only (oracle_path_amplification): when set, */
+    double amp;          /* run_path leaves the path's rounding amplification here */
 } solve_context;
 
 /* trace (optional): per substep, 4 doubles (xi, eta after the step, before
  * any exit projection) -- used by the tiny brute-force comparison. */
-static path_outcome run_path(const solve_context *C, int32_t node, int32_t i0, int32_t j0, int64_t path,
+static path_outcome run_path(solve_context *C, int32_t node, int32_t i0, int32_t j0, int64_t path,
                              double *trace)
 {
     const oracle_problem *P = C->P;
@@ -449,17 +483,26 @@ static path_outcome run_path(const solve_context *C, int32_t node, int32_t i0, i
     double eta = (double)j0 / (double)(P->n_eta - 1);
     long w_xi = 0, w_eta = 0;
     path_outcome out = {0.0, 0.0, 0, -1, 0};
+    double S[3] = {0.0, 0.0, 0.0};   /* sensitivity only: symmetric 2x2 (xx, xy, yy) */
+    if (C->track) C->amp = 0.0;       /* (the estimate's threads share C and never write it) */
 
     for (int k = 0; k < P->K; ++k) {
         double n1, n2, r, rx, ry;
         oracle_normals(P, node, path, k, &n1, &n2);
+        if (C->track) {   /* S <- A S A^T + I, A the Jacobian of this substep */
+            double a[4];
+            substep_jacobian(&C->T, xi, eta, dt, a);
+            double t0 = a[0] * S[0] + a[1] * S[1], t1 = a[0] * S[1] + a[1] * S[2];
+            double t2 = a[2] * S[0] + a[3] * S[1], t3 = a[2] * S[1] + a[3] * S[2];
+            S[0] = t0 * a[0] + t1 * a[1] + 1.0;
+            S[1] = t0 * a[2] + t1 * a[3];
+            S[2] = t2 * a[2] + t3 * a[3] + 1.0;
+            double amp = sqrt(0.5 * (S[0] + S[2]));
+            if (amp > C->amp) C->amp = amp;
+        }
         bilinear3(&C->T, xi, eta, &r, &rx, &ry);
         double nxi = xi + (rx / r) * dt + sq * n1;
         double neta = eta + (ry / r) * dt + sq * n2;
-        if (C->round_f32) {   /* the probe's perturbation: positions rounded as binary32 */
-            nxi = (double)(float)nxi;
-            neta = (double)(float)neta;
-        }
 
         if (P->periodic_xi) {
             double m = floor(nxi);
@@ -620,7 +663,8 @@ static void build_context(const oracle_problem *P, const double *rho, double *rh
     C->Y.f = y_cur; C->Y.off_xi = 0.0; C->Y.off_eta = P->Ly;
     C->bnd_t0 = bnd_t0;
     C->bnd_t1 = bnd_t1;
-    C->round_f32 = 0;
+    C->track = 0;
+    C->amp = 0.0;
 }
 
 /*
@@ -695,10 +739,10 @@ done:
  * position after wrapping and the two normals, 4 doubles per substep, K
  * substeps per path (unused entries after an exit are left untouched).
  */
-static int32_t paths_impl(const oracle_problem *P, const double *rho, const double *x_cur, const double *y_cur,
-                          const double *bnd_t0, const double *bnd_t1, int32_t node_rank,
-                          int64_t p_begin, int64_t p_end, double *vx, double *vy, int32_t *exited,
-                          int32_t *side, int32_t *steps, double *trace, int32_t round_f32)
+int32_t oracle_paths(const oracle_problem *P, const double *rho, const double *x_cur, const double *y_cur,
+                     const double *bnd_t0, const double *bnd_t1, int32_t node_rank,
+                     int64_t p_begin, int64_t p_end, double *vx, double *vy, int32_t *exited,
+                     int32_t *side, int32_t *steps, double *trace)
 {
     if (!P || P->n_xi < 4 || P->n_eta < 4 || P->K < 1 || P->tau <= 0.0) return -1;
     int32_t total = oracle_interface_nodes(P, NULL, NULL);
@@ -714,7 +758,6 @@ static int32_t paths_impl(const oracle_problem *P, const double *rho, const doub
     oracle_interface_nodes(P, all_i, all_j);
     solve_context C;
     build_context(P, rho, rho_xi, rho_eta, x_cur, y_cur, bnd_t0, bnd_t1, &C);
-    C.round_f32 = round_f32;
     for (int64_t p = p_begin; p < p_end; ++p) {
         int64_t q = p - p_begin;
         path_outcome o = run_path(&C, node_rank, all_i[node_rank], all_j[node_rank], p,
@@ -729,27 +772,42 @@ static int32_t paths_impl(const oracle_problem *P, const double *rho, const doub
     return 0;
 }
 
-int32_t oracle_paths(const oracle_problem *P, const double *rho, const double *x_cur, const double *y_cur,
-                     const double *bnd_t0, const double *bnd_t1, int32_t node_rank,
-                     int64_t p_begin, int64_t p_end, double *vx, double *vy, int32_t *exited,
-                     int32_t *side, int32_t *steps, double *trace)
-{
-    return paths_impl(P, rho, x_cur, y_cur, bnd_t0, bnd_t1, node_rank, p_begin, p_end, vx, vy, exited, side,
-                      steps, trace, 0);
-}
-
 /*
- * Sensitivity probe, not an estimate: the same paths with each substep's new
- * position rounded to the nearest binary32 value (a perturbation of the size
- * a single-precision path suffers at every substep).  A path whose outcome
- * this moves far is one along which the drift amplifies rounding; the tests
- * use it to tell such paths from arithmetic mistakes.
+ * Sensitivity of each path to rounding, not an estimate.  A perturbation
+ * e_k of the position after substep k (k = 1..s, s the substeps the path
+ * ran), independent between substeps with unit variance per coordinate,
+ * reaches the position after substep k as a deviation of covariance S_k:
+ * S_1 = I, S_{k+1} = A_k S_k A_k^T + I with A_k = I + dt grad b the
+ * Jacobian of substep k at the position before it (linearised).
+ * amp[q] = max over k of sqrt(trace(S_k) / 2): the largest standard
+ * deviation the path reaches per unit per-substep perturbation, sqrt(s)
+ * where there is no drift.  The maximum over time, not the end value: a
+ * deviation grown large in a steep stretch leaves the linear regime and
+ * need not shrink again where the linearisation would contract it.
  */
-int32_t oracle_paths_rounded(const oracle_problem *P, const double *rho, const double *x_cur, const double *y_cur,
-                             const double *bnd_t0, const double *bnd_t1, int32_t node_rank,
-                             int64_t p_begin, int64_t p_end, double *vx, double *vy, int32_t *exited,
-                             int32_t *side, int32_t *steps)
+int32_t oracle_path_amplification(const oracle_problem *P, const double *rho, const double *x_cur,
+                                  const double *y_cur, const double *bnd_t0, const double *bnd_t1,
+                                  int32_t node_rank, int64_t p_begin, int64_t p_end, double *amp)
 {
-    return paths_impl(P, rho, x_cur, y_cur, bnd_t0, bnd_t1, node_rank, p_begin, p_end, vx, vy, exited, side,
-                      steps, NULL, 1);
+    if (!P || P->n_xi < 4 || P->n_eta < 4 || P->K < 1 || P->tau <= 0.0) return -1;
+    int32_t total = oracle_interface_nodes(P, NULL, NULL);
+    if (node_rank < 0 || node_rank >= total) return -1;
+    int32_t *all_i = (int32_t *)malloc(sizeof(int32_t) * (size_t)total);
+    int32_t *all_j = (int32_t *)malloc(sizeof(int32_t) * (size_t)total);
+    double *rho_xi = (double *)malloc(sizeof(double) * (size_t)P->n_xi * P->n_eta);
+    double *rho_eta = (double *)malloc(sizeof(double) * (size_t)P->n_xi * P->n_eta);
+    if (!all_i || !all_j || !rho_xi || !rho_eta) {
+        free(all_i); free(all_j); free(rho_xi); free(rho_eta);
+        return -1;
+    }
+    oracle_interface_nodes(P, all_i, all_j);
+    solve_context C;
+    build_context(P, rho, rho_xi, rho_eta, x_cur, y_cur, bnd_t0, bnd_t1, &C);
+    C.track = 1;
+    for (int64_t p = p_begin; p < p_end; ++p) {
+        run_path(&C, node_rank, all_i[node_rank], all_j[node_rank], p, NULL);
+        amp[p - p_begin] = C.amp;
+    }
+    free(all_i); free(all_j); free(rho_xi); free(rho_eta);
+    return 0;
 }

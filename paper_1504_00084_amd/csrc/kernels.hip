@@ -103,8 +103,13 @@ struct ConstF {
     float c_rad;   // -4 ln2 dt, so that sqrt(c_rad log2 u) = sqrt(2 dt) sqrt(-2 ln u)
     float sq2dt;   // sqrt(2 dt) (diagnostics only)
     float delta;   // sqrt(18.5 dt): farther from every side, no bridge crossing can matter
-    const GLOBAL f32x4 *cells;   // per cell: (rho, dt rho_xi) at corners 00, 10, 01, 11; dt rho_eta coefficients
-    const GLOBAL f32x4 *coef_y;  // per cell: the dt rho_eta coefficients alone (compact)
+    // The instance's cell data, one allocation: first the compact plane of
+    // the dt rho_eta coefficients (16 B per cell), then from byte `rec0` the
+    // 48-B cell records ((rho, dt rho_xi) at corners 00, 10, 01, 11; the dt
+    // rho_eta coefficients again).  Every gather is this scalar base plus a
+    // 32-bit lane offset (the two parts together stay below 2^32 bytes).
+    const GLOBAL char *cdata;
+    uint32_t rec0;
 };
 
 // PER >= 0: the periodic flags are the compile-time constants PER & 1 (xi)
@@ -132,8 +137,8 @@ __device__ __forceinline__ ConstF load_const_f(const InstView &I)
     c.c_rad = I.c_rad_f;
     c.sq2dt = I.sq2dt_f;
     c.delta = I.delta_f;
-    c.cells = (const GLOBAL f32x4 *)I.cells;
-    c.coef_y = (const GLOBAL f32x4 *)I.coef_y;
+    c.cdata = (const GLOBAL char *)I.coef_y;
+    c.rec0 = I.rec0;
     return c;
 }
 
@@ -177,7 +182,7 @@ __device__ __forceinline__ float bilerp(float tx, float ty, float f00, float f10
 // the dt rho_eta coefficients of their w1 x h1 cells, row stride w1, from
 // byte `coff` of the LDS on.
 struct Win {
-    int i0, j0, tw, w1, h1, coff;
+    int i0, j0, tw, w1, h1, coff, tw8;   // tw8 = 8 tw: bytes per window row
 };
 
 // TAB: where the corner values of rho and dt rho_xi come from.  0: the cell
@@ -206,14 +211,14 @@ __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t w
     tx = P.x * C.fnx1 - (float)cx;
     ty = P.y * C.fny1 - (float)cy;
     // 32-bit indices and byte offsets (a grid has at most 8193^2 nodes, 2^26
-    // cells): each gather adds one lane offset to a scalar base, and the LDS
-    // address is one 24-bit multiply-add.  The record offset (48 B per cell,
-    // below 2^32) is the sum of two 24-bit products, each exact: the cell
-    // index itself can exceed 24 bits.
+    // cells): each gather adds one lane offset to the scalar base of the cell
+    // data, and the LDS address is one 24-bit multiply-add.  The record
+    // offset (rec0 + 48 B per cell, below 2^32) is a sum of 24-bit products,
+    // each exact: the cell index itself can exceed 24 bits.
     const uint32_t ci = __umul24((uint32_t)cy, (uint32_t)C.nx1) + (uint32_t)cx;   // cell
-    const uint32_t rec = __umul24((uint32_t)cy, (uint32_t)C.nx1 * 48u) + __umul24((uint32_t)cx, 48u);
-    const GLOBAL f32x4 *cell = (const GLOBAL f32x4 *)((const GLOBAL char *)C.cells + rec);
-    const GLOBAL f32x4 *coef = (const GLOBAL f32x4 *)((const GLOBAL char *)C.coef_y + (ci << 4));
+    const uint32_t rec = C.rec0 + __umul24((uint32_t)cy, (uint32_t)C.nx1 * 48u) + __umul24((uint32_t)cx, 48u);
+    const GLOBAL f32x4 *cell = (const GLOBAL f32x4 *)(C.cdata + rec);
+    const GLOBAL f32x4 *coef = (const GLOBAL f32x4 *)(C.cdata + (ci << 4));
     float r00, r10, r01, r11, g00, g10, g01, g11;
     f32x4 G;   // dt rho_eta coefficients
     if (TAB == 2) {
@@ -232,16 +237,18 @@ __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t w
         // the plane or the record through one gather issued ahead of both.
         const int rx = cx - win.i0, ry = cy - win.j0;
         const bool outside = ((uint32_t)rx >= (uint32_t)win.w1) | ((uint32_t)ry >= (uint32_t)win.h1);
-        if (TAB == 3) G = *(outside ? cell + 2 : coef);
+        // one base, a selected 32-bit offset: the record's coefficients or the plane's
+        if (TAB == 3) G = *(const GLOBAL f32x4 *)(C.cdata + (outside ? rec + 32u : ci << 4));
         if (outside) {
             const f32x4 A = cell[0], B = cell[1];
             r00 = A.x, g00 = A.y, r10 = A.z, g10 = A.w;
             r01 = B.x, g01 = B.y, r11 = B.z, g11 = B.w;
             if (TAB == 4) G = cell[2];
         } else {
-            const uint32_t off = __umul24((uint32_t)ry, (uint32_t)win.tw << 3) + ((uint32_t)rx << 3);
+            const uint32_t off = __umul24((uint32_t)ry, (uint32_t)win.tw8) + ((uint32_t)rx << 3);
             const float2 *t2 = (const float2 *)((const char *)tab + off);
-            const float2 c00 = t2[0], c10 = t2[1], c01 = t2[win.tw], c11 = t2[win.tw + 1];
+            const float2 *u2 = (const float2 *)((const char *)tab + off + (uint32_t)win.tw8);
+            const float2 c00 = t2[0], c10 = t2[1], c01 = u2[0], c11 = u2[1];
             r00 = c00.x, r10 = c10.x, r01 = c01.x, r11 = c11.x;
             g00 = c00.y, g10 = c10.y, g01 = c01.y, g11 = c11.y;
             if (TAB == 4) {
@@ -268,24 +275,15 @@ __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t w
     float nx = fmaf(rad, cs, fmaf(gx, inv_rho, P.x));
     float ny = fmaf(rad, sn, fmaf(gy, inv_rho, P.y));
 
-    // a6: periodic wrap with winding.
+    // a6: periodic wrap with winding: x - floor(x) by v_fract, which also
+    // keeps the rare tiny negative x (where x + 1 rounds to 1) below 1.
     if (C.per_xi) {
-        const float f = floorf(nx);
-        nx -= f;
-        P.wx += (int)f;
-        if (nx >= 1.0f) {
-            nx -= 1.0f;
-            P.wx += 1;
-        }
+        P.wx += (int)floorf(nx);
+        nx = __builtin_amdgcn_fractf(nx);
     }
     if (C.per_eta) {
-        const float f = floorf(ny);
-        ny -= f;
-        P.wy += (int)f;
-        if (ny >= 1.0f) {
-            ny -= 1.0f;
-            P.wy += 1;
-        }
+        P.wy += (int)floorf(ny);
+        ny = __builtin_amdgcn_fractf(ny);
     }
     if (trace4) {   // diagnostics: position after the wrap, before any exit projection
         trace4[0] = nx;
@@ -318,7 +316,10 @@ __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t w
                 ny = 1.0f;
             }
         }
-    } else if (C.bridge && fminf(P.m, m) < C.delta) {
+    } else if (C.bridge && min(__float_as_int(P.m), __float_as_int(m)) < __float_as_int(C.delta)) {
+        // (the minimum of the two distances below delta; on the signed-integer
+        // bit patterns, which order non-NaN floats as their values for a
+        // positive delta, -0 included, with no NaN quieting of a float min)
         // Brownian bridge between the two inside points: crossing probability
         // exp(-d0 d1 / dt) per side; d0 d1 / dt > 18.5 gives < 2^-26.6, below
         // the smallest uniform even summed over four sides.
@@ -413,28 +414,36 @@ __device__ __forceinline__ void path_value_f32(const InstView &I, const ConstF &
     if (C.per_eta) vy = fmaf((float)P.wy, C.Ly, vy);
 }
 
+// When a wave leaves its stepping loop for the refill and item bookkeeping
+// (LDS table and window kernels): once fewer than `lanes` of its 64 lanes
+// still have a path in flight, or after `quarters` groups of four substeps
+// (the launch's tuned values; 56 and 16 by default).
+struct Refill {
+    uint32_t lanes, quarters;
+};
+
 // Advances one path by quarters of four substeps: each quarter draws its
 // three Philox blocks at once (words 3s..3s+2 for substep s of the quarter,
-// block 3 (k / 4) onwards).  The LDS table and window kernels (TAB 2, 3)
-// run up to 16 quarters and leave after a quarter once fewer than 56 of the
-// wave's 64 lanes still have a path in flight, so the caller's refill and
-// item bookkeeping runs only when lanes are idle (measured: faster than 1 or
-// 4 quarters for both).  The cell-record kernel (TAB 0) is bound by its
-// gathers, where idle lanes cost more than the bookkeeping: it runs one
-// quarter per call, so ended lanes are refilled at once.  The substeps and their random words do not depend on
+// block 3 (k / 4) onwards).  The LDS table and window kernels (TAB 2, 3, 4)
+// run up to rf.quarters quarters and leave after a quarter once fewer than
+// rf.lanes of the wave's 64 lanes still have a path in flight, so the
+// caller's refill and item bookkeeping runs only when lanes are idle.  The
+// cell-record kernel (TAB 0) is bound by its gathers, where idle lanes cost
+// more than the bookkeeping: it runs one quarter per call, so ended lanes are
+// refilled at once.  The substeps and their random words do not depend on
 // where the loop is left.  Returns the exit side or -1; `ended` is set when
 // the path exited or reached K.
 template <bool TRACE, int TAB>
 __device__ __forceinline__ int group_f32(PathF &P, const ConstF &C, uint32_t path, uint32_t node, uint32_t ctr3,
                                          uint32_t key0, uint32_t key1, bool &ended, double *trace,
-                                         const float *tab, const Win &win)
+                                         const float *tab, const Win &win, const Refill rf)
 {
     int side = -1;
     ended = false;
-    constexpr int QUARTERS = TAB > 0 ? 16 : 1;
+    const uint32_t quarters = TAB > 0 ? rf.quarters : 1u;
 #pragma unroll 1
-    for (int q = 0; q < QUARTERS; ++q) {
-        if (q > 0 && (uint32_t)__popcll(__ballot(!ended && P.k < C.K)) < 56u) break;
+    for (uint32_t q = 0; q < quarters; ++q) {
+        if (q > 0 && (uint32_t)__popcll(__ballot(!ended && P.k < C.K)) < rf.lanes) break;
         const uint32_t blk = 3u * ((uint32_t)P.k >> 2);
         const Words4 A = philox4x32_10(blk, path, node, ctr3, key0, key1);
         const Words4 B = philox4x32_10(blk + 1u, path, node, ctr3, key0, key1);
@@ -656,7 +665,7 @@ struct JobSrc {
 // has no item left and both slots have drained.
 template <int TAB, int PER, class Src>
 __device__ __forceinline__ void item_loop(Src &src, uint32_t n_items, const InstView *__restrict__ insts, float *buf,
-                                          uint32_t cap, const float *tab, const Win &win, int lane)
+                                          uint32_t cap, const float *tab, const Win &win, int lane, const Refill rf)
 {
     // wave-uniform state
     uint32_t next = src.pop(lane);
@@ -748,7 +757,7 @@ __device__ __forceinline__ void item_loop(Src &src, uint32_t n_items, const Inst
         // advance every path until the wave has lanes to refill
         bool ended = false;
         if (has) {
-            const int side = group_f32<false, TAB>(P, C, path, node, ctr3, key0, key1, ended, nullptr, tab, win);
+            const int side = group_f32<false, TAB>(P, C, path, node, ctr3, key0, key1, ended, nullptr, tab, win, rf);
             if (ended) {
                 store_end(buf + (size_t)which * 3u * cap, cap, slot, *Ip, C, P, side);
                 const uint32_t e = side >= 0 ? 1u : 0u;
@@ -782,6 +791,20 @@ __device__ __forceinline__ void item_loop(Src &src, uint32_t n_items, const Inst
     }
 }
 
+// The wave loop compiled for the periodicity `per` (per_xi + 2 per_eta).
+template <int TAB, class Src>
+__device__ __forceinline__ void item_loop_per(int per, Src &src, uint32_t n_items, const InstView *__restrict__ insts,
+                                              float *buf, uint32_t cap, const float *tab, const Win &win, int lane,
+                                              const Refill rf)
+{
+    switch (per) {
+    case 0: item_loop<TAB, 0>(src, n_items, insts, buf, cap, tab, win, lane, rf); break;
+    case 1: item_loop<TAB, 1>(src, n_items, insts, buf, cap, tab, win, lane, rf); break;
+    case 2: item_loop<TAB, 2>(src, n_items, insts, buf, cap, tab, win, lane, rf); break;
+    default: item_loop<TAB, 3>(src, n_items, insts, buf, cap, tab, win, lane, rf); break;
+    }
+}
+
 // Queue-driven persistent kernel (one launch-wide queue of items).
 // TAB 2: the launch holds one instance (the host guarantees it), whose FP32
 // node tables of rho and dt rho_xi the workgroup copies into LDS,
@@ -798,7 +821,7 @@ template <int BLOCK, int TAB, int PER>
 __global__ __launch_bounds__(BLOCK) void paths_fp32(const InstView *__restrict__ insts,
                                                     const WorkRange *__restrict__ ranges, uint32_t n_ranges,
                                                     uint32_t n_items, uint32_t *__restrict__ head, uint32_t cap,
-                                                    float *__restrict__ ends, uint32_t end_waves)
+                                                    float *__restrict__ ends, uint32_t end_waves, Refill rf)
 {
     extern __shared__ float lds[];
     if (PER >= 0 && (insts[0].per_xi != (PER & 1) || insts[0].per_eta != (PER >> 1))) return;
@@ -819,8 +842,8 @@ __global__ __launch_bounds__(BLOCK) void paths_fp32(const InstView *__restrict__
     }
 
     QueueSrc src{head, gptr(ranges), n_ranges};
-    const Win none{0, 0, 0, 0, 0, 0};
-    item_loop<TAB, PER>(src, n_items, insts, buf, cap, tab, none, lane);
+    const Win none{0, 0, 0, 0, 0, 0, 0};
+    item_loop<TAB, PER>(src, n_items, insts, buf, cap, tab, none, lane, rf);
 }
 
 // Windowed kernel for launches whose node tables do not fit the LDS whole:
@@ -842,7 +865,7 @@ __global__ __launch_bounds__(kTableBlock) void paths_fp32_win(const InstView *__
                                                             const WorkRange *__restrict__ ranges,
                                                             const WinJob *__restrict__ jobs, JobQueues qs,
                                                             uint32_t *__restrict__ head, uint32_t cap,
-                                                            float *__restrict__ ends, uint32_t end_waves)
+                                                            float *__restrict__ ends, uint32_t end_waves, Refill rf)
 {
     constexpr int BLOCK = kTableBlock;
     // The only LDS of this kernel is the dynamic block (base 0): the job and
@@ -901,11 +924,23 @@ __global__ __launch_bounds__(kTableBlock) void paths_fp32_win(const InstView *__
         }
         __syncthreads();
         JobSrc js{ctl + 1, R, J.q0};
-        const Win win{J.i0, J.j0, J.tw, J.tw - 1, J.th - 1, coff};
-        if (J.kind == 1)
-            item_loop<4, PER>(js, ok ? J.count : 0u, insts, buf, cap, wtab, win, lane);
-        else
-            item_loop<3, PER>(js, ok ? J.count : 0u, insts, buf, cap, wtab, win, lane);
+        const Win win{J.i0, J.j0, J.tw, J.tw - 1, J.th - 1, coff, J.tw * 8};
+        const uint32_t count = ok ? J.count : 0u;
+        if (PER >= 0) {
+            if (J.kind == 1)
+                item_loop<4, PER>(js, count, insts, buf, cap, wtab, win, lane, rf);
+            else
+                item_loop<3, PER>(js, count, insts, buf, cap, wtab, win, lane, rf);
+        } else {
+            // a launch of mixed periodicity: a job holds one instance, so its
+            // periodic flags are uniform over the workgroup; each kind runs the
+            // wave loop compiled for it
+            const int per = I.per_xi + 2 * I.per_eta;
+            if (J.kind == 1)
+                item_loop_per<4>(per, js, count, insts, buf, cap, wtab, win, lane, rf);
+            else
+                item_loop_per<3>(per, js, count, insts, buf, cap, wtab, win, lane, rf);
+        }
         __syncthreads();   // every wave is done with the window
     }
 }
@@ -1450,10 +1485,11 @@ __global__ void debug_paths_kernel(const InstView *__restrict__ inst, int fp64, 
     int side = -1;
     bool ended = false;
     while (!ended) {
-        const Win none{0, 0, 0, 0, 0, 0};
-        side = tr ? group_f32<true, 0>(P, C, path, I.node_r[node], I.ctr3, I.key0, I.key1, ended, tr, nullptr, none)
+        const Win none{0, 0, 0, 0, 0, 0, 0};
+        side = tr ? group_f32<true, 0>(P, C, path, I.node_r[node], I.ctr3, I.key0, I.key1, ended, tr, nullptr, none,
+                                       Refill{64u, 1u})
                   : group_f32<false, 0>(P, C, path, I.node_r[node], I.ctr3, I.key0, I.key1, ended, nullptr, nullptr,
-                                        none);
+                                        none, Refill{64u, 1u});
     }
     float fx, fy;
     path_value_f32(I, C, P, side, fx, fy);
@@ -1527,19 +1563,19 @@ hipError_t launch_paths_fp32(const InstView *insts, const WorkRange *ranges, uin
     switch (block) {
     case 64:
         hipLaunchKernelGGL((paths_fp32<64, 0, -1>), dim3(grid), dim3(64), lds, s, insts, ranges, n_ranges, n_items, head,
-                           cap, nullptr, 0u);
+                           cap, nullptr, 0u, Refill{64u, 1u});
         break;
     case 128:
         hipLaunchKernelGGL((paths_fp32<128, 0, -1>), dim3(grid), dim3(128), lds, s, insts, ranges, n_ranges, n_items,
-                           head, cap, nullptr, 0u);
+                           head, cap, nullptr, 0u, Refill{64u, 1u});
         break;
     case 256:
         hipLaunchKernelGGL((paths_fp32<256, 0, -1>), dim3(grid), dim3(256), lds, s, insts, ranges, n_ranges, n_items,
-                           head, cap, nullptr, 0u);
+                           head, cap, nullptr, 0u, Refill{64u, 1u});
         break;
     case 512:
         hipLaunchKernelGGL((paths_fp32<512, 0, -1>), dim3(grid), dim3(512), lds, s, insts, ranges, n_ranges, n_items,
-                           head, cap, nullptr, 0u);
+                           head, cap, nullptr, 0u, Refill{64u, 1u});
         break;
     default:
         return hipErrorInvalidValue;
@@ -1551,27 +1587,29 @@ size_t paths_fp32_table_lds_bytes(int level, int n_nodes) { return (size_t)n_nod
 
 template <int TAB, int PER>
 static void launch_table(int grid, size_t lds, hipStream_t s, const InstView *insts, const WorkRange *ranges,
-                         uint32_t n_items, uint32_t *head, uint32_t cap, float *ends, uint32_t end_waves)
+                         uint32_t n_items, uint32_t *head, uint32_t cap, float *ends, uint32_t end_waves, Refill rf)
 {
     hipLaunchKernelGGL((paths_fp32<kTableBlock, TAB, PER>), dim3(grid), dim3(kTableBlock), lds, s, insts, ranges, 1u,
-                       n_items, head, cap, ends, end_waves);
+                       n_items, head, cap, ends, end_waves, rf);
 }
 
 hipError_t launch_paths_fp32_table(const InstView *insts, const WorkRange *ranges, uint32_t n_items, uint32_t *head,
                                    uint32_t cap, int level, int periodic, int n_nodes, int grid, float *ends,
-                                   uint32_t end_waves, hipStream_t s)
+                                   uint32_t end_waves, uint32_t refill_lanes, uint32_t max_quarters, hipStream_t s)
 {
     hipError_t e = launch_fill_u32(head, 0u, 1, s);
     if (e != hipSuccess) return e;
     if (n_items == 0) return hipSuccess;
-    if ((size_t)grid * (kTableBlock / 64) > end_waves || level != 2 || periodic < 0 || periodic > 3)
+    if ((size_t)grid * (kTableBlock / 64) > end_waves || level != 2 || periodic < 0 || periodic > 3 ||
+        refill_lanes < 1 || refill_lanes > 64 || max_quarters < 1 || max_quarters > 64)
         return hipErrorInvalidValue;
     const size_t lds = paths_fp32_table_lds_bytes(level, n_nodes);
+    const Refill rf{refill_lanes, max_quarters};
     switch (periodic) {
-    case 0: launch_table<2, 0>(grid, lds, s, insts, ranges, n_items, head, cap, ends, end_waves); break;
-    case 1: launch_table<2, 1>(grid, lds, s, insts, ranges, n_items, head, cap, ends, end_waves); break;
-    case 2: launch_table<2, 2>(grid, lds, s, insts, ranges, n_items, head, cap, ends, end_waves); break;
-    default: launch_table<2, 3>(grid, lds, s, insts, ranges, n_items, head, cap, ends, end_waves); break;
+    case 0: launch_table<2, 0>(grid, lds, s, insts, ranges, n_items, head, cap, ends, end_waves, rf); break;
+    case 1: launch_table<2, 1>(grid, lds, s, insts, ranges, n_items, head, cap, ends, end_waves, rf); break;
+    case 2: launch_table<2, 2>(grid, lds, s, insts, ranges, n_items, head, cap, ends, end_waves, rf); break;
+    default: launch_table<2, 3>(grid, lds, s, insts, ranges, n_items, head, cap, ends, end_waves, rf); break;
     }
     return hipGetLastError();
 }
@@ -1590,15 +1628,16 @@ int paths_fp32_table_blocks_per_cu(int level, int n_nodes)
 template <int PER>
 static void launch_win(int grid, size_t lds, hipStream_t s, const InstView *insts, const WorkRange *ranges,
                        const WinJob *jobs, const JobQueues &qs, uint32_t *head, uint32_t cap, float *ends,
-                       uint32_t end_waves)
+                       uint32_t end_waves, Refill rf)
 {
     hipLaunchKernelGGL((paths_fp32_win<PER>), dim3(grid), dim3(kTableBlock), lds, s, insts, ranges, jobs, qs, head,
-                       cap, ends, end_waves);
+                       cap, ends, end_waves, rf);
 }
 
 hipError_t launch_paths_fp32_window(const InstView *insts, const WorkRange *ranges, const WinJob *jobs,
                                     const JobQueues &qs, uint32_t *head, uint32_t cap, int periodic, size_t lds,
-                                    int grid, float *ends, uint32_t end_waves, hipStream_t s)
+                                    int grid, float *ends, uint32_t end_waves, uint32_t refill_lanes,
+                                    uint32_t max_quarters, hipStream_t s)
 {
     hipError_t e = launch_fill_u32(head, 0u, kJobQueues, s);
     if (e != hipSuccess) return e;
@@ -1606,15 +1645,16 @@ hipError_t launch_paths_fp32_window(const InstView *insts, const WorkRange *rang
     for (int q = 0; q < kJobQueues; ++q)
         if (qs.b[q] > qs.b[q + 1]) return hipErrorInvalidValue;
     if ((size_t)grid * (kTableBlock / 64) > end_waves || periodic < -1 || periodic > 3 || lds < 32 ||
-        lds > kWinBytes)
+        lds > kWinBytes || refill_lanes < 1 || refill_lanes > 64 || max_quarters < 1 || max_quarters > 64)
         return hipErrorInvalidValue;
     lds += 16;   // the job and item counters ahead of the window
+    const Refill rf{refill_lanes, max_quarters};
     switch (periodic) {
-    case 0: launch_win<0>(grid, lds, s, insts, ranges, jobs, qs, head, cap, ends, end_waves); break;
-    case 1: launch_win<1>(grid, lds, s, insts, ranges, jobs, qs, head, cap, ends, end_waves); break;
-    case 2: launch_win<2>(grid, lds, s, insts, ranges, jobs, qs, head, cap, ends, end_waves); break;
-    case 3: launch_win<3>(grid, lds, s, insts, ranges, jobs, qs, head, cap, ends, end_waves); break;
-    default: launch_win<-1>(grid, lds, s, insts, ranges, jobs, qs, head, cap, ends, end_waves); break;
+    case 0: launch_win<0>(grid, lds, s, insts, ranges, jobs, qs, head, cap, ends, end_waves, rf); break;
+    case 1: launch_win<1>(grid, lds, s, insts, ranges, jobs, qs, head, cap, ends, end_waves, rf); break;
+    case 2: launch_win<2>(grid, lds, s, insts, ranges, jobs, qs, head, cap, ends, end_waves, rf); break;
+    case 3: launch_win<3>(grid, lds, s, insts, ranges, jobs, qs, head, cap, ends, end_waves, rf); break;
+    default: launch_win<-1>(grid, lds, s, insts, ranges, jobs, qs, head, cap, ends, end_waves, rf); break;
     }
     return hipGetLastError();
 }

@@ -227,7 +227,7 @@ extern "C" {
 
 int mesh_sdd_edge_generate(mesh_sdd *inst, const double *bnd_cur, double *bnd_new, const mesh_sdd_mp_opts *opts,
                            int pointers_on_device)
-{
+try {
     int rc = check_ready(inst);
     if (rc != MESH_SDD_OK) return rc;
     if (!bnd_cur || !bnd_new) return fail(MESH_SDD_E_INVAL, "NULL boundary array");
@@ -248,6 +248,8 @@ int mesh_sdd_edge_generate(mesh_sdd *inst, const double *bnd_cur, double *bnd_ne
     if ((rc = finish(out, st)) != MESH_SDD_OK) return rc;
     HIP_TRY(hipStreamSynchronize(st));
     return MESH_SDD_OK;
+} catch (...) {
+    return abi_exception();
 }
 
 static int solve_common(mesh_sdd *inst, const double *x_cur, const double *y_cur, const double *bnd_new,
@@ -290,19 +292,23 @@ static int solve_common(mesh_sdd *inst, const double *x_cur, const double *y_cur
 int mesh_sdd_subdomain_solve(mesh_sdd *inst, const double *x_cur, const double *y_cur, const double *bnd_new,
                              const double *iface_x, const double *iface_y, double *x_new, double *y_new,
                              const mesh_sdd_mp_opts *opts, int pointers_on_device)
-{
+try {
     return solve_common(inst, x_cur, y_cur, bnd_new, iface_x, iface_y, x_new, y_new, opts, pointers_on_device, true);
+} catch (...) {
+    return abi_exception();
 }
 
 int mesh_sdd_single_domain_solve(mesh_sdd *inst, const double *x_cur, const double *y_cur, const double *bnd_new,
                                  double *x_new, double *y_new, const mesh_sdd_mp_opts *opts, int pointers_on_device)
-{
+try {
     return solve_common(inst, x_cur, y_cur, bnd_new, nullptr, nullptr, x_new, y_new, opts, pointers_on_device, false);
+} catch (...) {
+    return abi_exception();
 }
 
 int mesh_sdd_mp_step(mesh_sdd *inst, const mesh_sdd_step *step, const mesh_sdd_mp_opts *opts, double *x_new,
                      double *y_new, double *bnd_new, mesh_sdd_result *result)
-{
+try {
     int rc = check_ready(inst);
     if (rc != MESH_SDD_OK) return rc;
     if (!step || !result || !x_new || !y_new || !bnd_new) return fail(MESH_SDD_E_INVAL, "NULL argument");
@@ -320,7 +326,7 @@ int mesh_sdd_mp_step(mesh_sdd *inst, const mesh_sdd_step *step, const mesh_sdd_m
     DevOut bo, xo, yo;
     DevOut rs[5];
     SyncOnExit sync{ctx->stream};
-    hipEvent_t e0 = nullptr, e1 = nullptr;
+    TimerEvents ev;
     {
         std::lock_guard<std::mutex> g(ctx->gpu_mu);
         HIP_TRY(hipSetDevice(ctx->device));
@@ -336,9 +342,8 @@ int mesh_sdd_mp_step(mesh_sdd *inst, const mesh_sdd_step *step, const mesh_sdd_m
             if (!dst[k] && M > 0) return fail(MESH_SDD_E_INVAL, "NULL result array");
             if ((rc = stage_out(ctx, dst[k], M, out_dev, rs[k])) != MESH_SDD_OK) return rc;
         }
-        HIP_TRY(hipEventCreate(&e0));
-        HIP_TRY(hipEventCreate(&e1));
-        HIP_TRY(hipEventRecord(e0, st));
+        HIP_TRY(ev.create());
+        HIP_TRY(hipEventRecord(ev.e0, st));
         // boundary arrays at t^{n+1}
         if (o.edge_gen) {
             HIP_TRY(hipMemcpyAsync(bo.p, b0.p, nb * 8, hipMemcpyDeviceToDevice, st));
@@ -365,11 +370,7 @@ int mesh_sdd_mp_step(mesh_sdd *inst, const mesh_sdd_step *step, const mesh_sdd_m
     r2.se_y = rs[3].p;
     r2.exit_frac = rs[4].p;
     rc = mesh_sdd_solve_interfaces(inst, &s2, &r2);
-    if (rc != MESH_SDD_OK) {
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        return rc;
-    }
+    if (rc != MESH_SDD_OK) return rc;
     std::lock_guard<std::mutex> g(ctx->gpu_mu);
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t st = ctx->stream;
@@ -378,23 +379,23 @@ int mesh_sdd_mp_step(mesh_sdd *inst, const mesh_sdd_step *step, const mesh_sdd_m
         for (DevOut *p : {&bo, &xo, &yo, &rs[0], &rs[1], &rs[2], &rs[3], &rs[4]})
             if ((rc = finish(*p, st)) != MESH_SDD_OK) break;
     }
-    if (rc == MESH_SDD_OK) rc = hipEventRecord(e1, st) == hipSuccess ? MESH_SDD_OK : fail(MESH_SDD_E_DEVICE, "event record failed");
+    if (rc == MESH_SDD_OK) rc = hipEventRecord(ev.e1, st) == hipSuccess ? MESH_SDD_OK : fail(MESH_SDD_E_DEVICE, "event record failed");
     hipError_t se = hipStreamSynchronize(st);
     float ms = 0.0f;
-    if (rc == MESH_SDD_OK && se == hipSuccess) (void)hipEventElapsedTime(&ms, e0, e1);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    if (rc == MESH_SDD_OK && se == hipSuccess) (void)hipEventElapsedTime(&ms, ev.e0, ev.e1);
     if (rc != MESH_SDD_OK) return rc;
     if (se != hipSuccess) return fail(MESH_SDD_E_DEVICE, "mesh step failed: %s", hipGetErrorString(se));
     result->executed_path_steps = r2.executed_path_steps;
     result->paths_per_node = r2.paths_per_node;
     result->device_ms = ms;
     return MESH_SDD_OK;
+} catch (...) {
+    return abi_exception();
 }
 
 int mesh_sdd_transfer_field(mesh_sdd *inst, const double *x_old, const double *y_old, const double *f_old,
                             const double *x_new, const double *y_new, double *f_new, int pointers_on_device)
-{
+try {
     if (!inst) return fail(MESH_SDD_E_INVAL, "instance is NULL");
     if (!x_old || !y_old || !f_old || !x_new || !y_new || !f_new) return fail(MESH_SDD_E_INVAL, "NULL array");
     mesh_sdd_ctx *ctx = inst->ctx;
@@ -437,11 +438,13 @@ int mesh_sdd_transfer_field(mesh_sdd *inst, const double *x_old, const double *y
     if ((rc = finish(out, st)) != MESH_SDD_OK) return rc;
     HIP_TRY(hipStreamSynchronize(st));
     return MESH_SDD_OK;
+} catch (...) {
+    return abi_exception();
 }
 
 int mesh_sdd_set_monitor_arclength(mesh_sdd *inst, const double *u, const double *x, const double *y, double alpha,
                                    int normalize, int pointers_on_device)
-{
+try {
     if (!inst || !u || !x || !y) return fail(MESH_SDD_E_INVAL, "NULL argument");
     if (!(alpha >= 0.0) || !std::isfinite(alpha)) return fail(MESH_SDD_E_INVAL, "alpha must be finite and >= 0");
     if (inst->inflight.load() > 0) return fail(MESH_SDD_E_STATE, "instance has requests in flight");
@@ -473,10 +476,12 @@ int mesh_sdd_set_monitor_arclength(mesh_sdd *inst, const double *u, const double
         return fail(MESH_SDD_E_INVAL, "|grad u| is not finite somewhere (degenerate mesh or bad input)");
     }
     return install_monitor(inst, st);
+} catch (...) {
+    return abi_exception();
 }
 
 int mesh_sdd_get_monitor(mesh_sdd *inst, double *rho_out, int pointer_on_device)
-{
+try {
     int rc = check_ready(inst);
     if (rc != MESH_SDD_OK) return rc;
     if (!rho_out) return fail(MESH_SDD_E_INVAL, "NULL argument");
@@ -487,11 +492,13 @@ int mesh_sdd_get_monitor(mesh_sdd *inst, double *rho_out, int pointer_on_device)
                            pointer_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     return MESH_SDD_OK;
+} catch (...) {
+    return abi_exception();
 }
 
 int mesh_sdd_mesh_quality(mesh_sdd *inst, const double *x_sd, const double *y_sd, const double *x_dd,
                           const double *y_dd, double *r_cells, double *r_max, double *r_mean, int pointers_on_device)
-{
+try {
     if (!inst || !x_sd || !y_sd || !x_dd || !y_dd || !r_max || !r_mean) return fail(MESH_SDD_E_INVAL, "NULL argument");
     mesh_sdd_ctx *ctx = inst->ctx;
     const mesh_sdd_desc &d = inst->d;
@@ -523,6 +530,8 @@ int mesh_sdd_mesh_quality(mesh_sdd *inst, const double *x_sd, const double *y_sd
     *r_max = h2[0];
     *r_mean = h2[1];
     return MESH_SDD_OK;
+} catch (...) {
+    return abi_exception();
 }
 
 }  // extern "C"

@@ -68,7 +68,7 @@ struct InstView {
     int32_t pad0;
     uint32_t key0, key1;          // Philox key (seed low / high word)
     uint32_t ctr3;                // instance_id << 16 | mesh_step & 0xffff
-    uint32_t pad1;
+    uint32_t rec0;                // byte offset of `cells` from `coef_y` (one allocation)
     double Lx, Ly, tau, dt;       // extents, mesh step, substep
     float Lx_f, Ly_f, dt_f, sq2dt_f, inv_dt_f, inv_tau_f;
     float c_rad_f;                // -4 ln2 dt
@@ -85,7 +85,8 @@ struct InstView {
     // (rho, dt rho_xi) at the corners 00, 10, then 01, 11, then dt rho_eta
     // in coefficient form a + b tx + c ty + d tx ty; the same coefficients
     // again as a compact plane (coef_y, read by the kernels that take rho and
-    // dt rho_xi from LDS); the FP32 node tables of rho and dt rho_xi
+    // dt rho_xi from LDS), in the same allocation ahead of the records
+    // (cells = coef_y + rec0 bytes); the FP32 node tables of rho and dt rho_xi
     // [n_eta][n_xi] (the same corner values, staged in LDS whole by launches
     // that hold this instance alone when they fit, else in windows); padded
     // mesh [n_eta+2][n_xi+2] with ghost /

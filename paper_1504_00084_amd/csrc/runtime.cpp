@@ -48,8 +48,30 @@ int fail(int code, const char *fmt, ...)
     va_start(ap, fmt);
     std::vsnprintf(buf, sizeof buf, fmt, ap);
     va_end(ap);
-    g_last_error = buf;
+    try {
+        g_last_error = buf;
+    } catch (...) {   // no memory left even for the message: keep the status
+    }
     return code;
+}
+
+int abi_exception() noexcept
+{
+    try {
+        throw;
+    } catch (const std::bad_alloc &) {
+        return fail(MESH_SDD_E_NOMEM, "host memory allocation failed");
+    } catch (const std::exception &e) {
+        return fail(MESH_SDD_E_NOMEM, "host resources exhausted: %s", e.what());
+    } catch (...) {
+        return fail(MESH_SDD_E_NOMEM, "host resources exhausted");
+    }
+}
+
+// The 48-B cell records, behind the coefficient plane in inst.cells.
+float4 *cell_records(const mesh_sdd &inst)
+{
+    return inst.cells.as<float4>() + (size_t)(inst.d.n_xi - 1) * (inst.d.n_eta - 1);
 }
 
 // Build the monitor's node tables and FP32 cell table from inst->rho_in on
@@ -61,8 +83,8 @@ int install_monitor(mesh_sdd *inst, hipStream_t st)
     HIP_TRY(msdd::launch_prep_gradient(inst->rho_in.as<double>(), d.n_xi, d.n_eta, d.periodic_xi, d.periodic_eta,
                                        inst->rho.as<double>(), inst->rho_xi.as<double>(), inst->rho_eta.as<double>(), st));
     HIP_TRY(msdd::launch_prep_cells(inst->rho.as<double>(), inst->rho_xi.as<double>(), inst->rho_eta.as<double>(),
-                                    d.n_xi, d.n_eta, d.tau / (double)d.K, inst->cells.as<float4>(),
-                                    inst->coef_y.as<float4>(), st));
+                                    d.n_xi, d.n_eta, d.tau / (double)d.K, cell_records(*inst),
+                                    inst->cells.as<float4>(), st));
     HIP_TRY(msdd::launch_to_f32(inst->rho.as<double>(), inst->rho_f.as<float>(), (size_t)d.n_xi * d.n_eta, st));
     HIP_TRY(msdd::launch_scaled_to_f32(inst->rho_xi.as<double>(), d.tau / (double)d.K, inst->rhox_f.as<float>(),
                                        (size_t)d.n_xi * d.n_eta, st));
@@ -238,6 +260,26 @@ mesh_sdd_launch default_launch()
     l.chunk_paths = 128;   // small enough that the LDS variant's wave buffers leave room for a 129x129 rho table
     l.monitor_table = 0;
     l.table_level = 0;
+    // leave the stepping loop once fewer than 56 lanes are busy, or after 16
+    // quarters (measured on the 129^2 workload: 16 beats 2, 32 and 64; 56
+    // beats 48 and 60)
+    l.refill_lanes = 56;
+    l.max_quarters = 16;
+    l.window_kind = 0;     // automatic: see window_kind()
+    l.window_margin = 0;   // the kind's default margin
+    l.job_split = 0;       // 32, and 256 in grids cut into several two-field windows
+    return l;
+}
+
+// A shape with every 0 ("default") field replaced by its default.
+mesh_sdd_launch with_defaults(mesh_sdd_launch l)
+{
+    const mesh_sdd_launch d = default_launch();
+    l.struct_size = sizeof(mesh_sdd_launch);
+    if (l.block == 0) l.block = d.block;
+    if (l.chunk_paths == 0) l.chunk_paths = d.chunk_paths;
+    if (l.refill_lanes == 0) l.refill_lanes = d.refill_lanes;
+    if (l.max_quarters == 0) l.max_quarters = d.max_quarters;
     return l;
 }
 
@@ -265,12 +307,27 @@ int table_level(int n_nodes, int monitor_table, int *per_cu)
     return 0;
 }
 
+// Shape of a launch over `d` alone: the override, else the bucket's tuned
+// shape, else the default.  Its per-instance knobs (chunk_paths, window kind
+// and margin) apply to `d` in every launch.
 mesh_sdd_launch launch_for(mesh_sdd_ctx *ctx, const mesh_sdd_desc &d)
 {
     std::lock_guard<std::mutex> g(ctx->mu);
-    if (ctx->has_override) return ctx->override_launch;
+    if (ctx->has_override) return with_defaults(ctx->override_launch);
     auto it = ctx->tuned.find(TuneKey{d.n_xi, d.n_eta, d.periodic_xi, d.periodic_eta});
-    if (it != ctx->tuned.end()) return it->second;
+    if (it != ctx->tuned.end()) return with_defaults(it->second);
+    return default_launch();
+}
+
+// Launch-wide knobs of a launch over several instances: the override, else
+// the tuned multi-instance shape, else the default.  `one`: the launch holds
+// that single instance (its bucket's shape then).
+mesh_sdd_launch launch_for_group(mesh_sdd_ctx *ctx, const mesh_sdd_desc *one)
+{
+    if (one) return launch_for(ctx, *one);
+    std::lock_guard<std::mutex> g(ctx->mu);
+    if (ctx->has_override) return with_defaults(ctx->override_launch);
+    if (ctx->has_batch_tuned) return with_defaults(ctx->batch_tuned);
     return default_launch();
 }
 
@@ -346,10 +403,14 @@ size_t window_bytes(int kind, int tw, int th)
     return kind ? ((nodes + 15) & ~(size_t)15) + (size_t)(tw - 1) * (th - 1) * 16 : nodes;
 }
 
-int window_kind(const mesh_sdd_desc &d)
+// want: 0 automatic, 1 two-field (kind 0), 2 three-field (kind 1); a
+// window that holds the whole grid is always taken.
+int window_kind(const mesh_sdd_desc &d, int want = 0)
 {
     if (window_bytes(1, d.n_xi, d.n_eta) <= msdd::kWinBytes) return 1;
     if (window_bytes(0, d.n_xi, d.n_eta) <= msdd::kWinBytes) return 0;
+    if (want == 1) return 0;
+    if (want == 2) return 1;
     return std::max(d.n_xi, d.n_eta) < kWin1MaxN ? 1 : 0;
 }
 
@@ -366,12 +427,25 @@ void window_dims(int kind, int n_xi, int n_eta, int *wx, int *wy)
     *wy = y;
 }
 
-// Window nodes beyond a block on each side, where the axis does not fit.
-int window_margin(int kind) { return kind ? 30 : 45; }
+// Window nodes beyond a block on each side, where the axis does not fit
+// (`want` > 0: the tuned margin).
+int window_margin(int kind, int want = 0) { return want > 0 ? want : (kind ? 30 : 45); }
 
-// Block length along an axis of n nodes whose window is w nodes long, and
-// the window origin of block b (centred on the block, clamped to the grid).
-int block_len(int kind, int n, int w) { return n <= w ? n : w - 2 * window_margin(kind); }
+// Block layout of an instance's windowed launches: window kind and margin.
+struct Layout {
+    int kind, margin;
+};
+
+Layout layout_of(const mesh_sdd_desc &d, const mesh_sdd_launch &l)
+{
+    const int kind = window_kind(d, l.window_kind);
+    return Layout{kind, window_margin(kind, l.window_margin)};
+}
+
+// Block length along an axis of n nodes whose window is w nodes long (at
+// least one node), and the window origin of block b (centred on the block,
+// clamped to the grid).
+int block_len(int margin, int n, int w) { return n <= w ? n : std::max(1, w - 2 * margin); }
 int window_origin(int b, int len, int n, int w) { return n <= w ? 0 : std::clamp(b * len - (w - len) / 2, 0, n - w); }
 
 // Z (Morton) order of block (bx, by): consecutive blocks form compact
@@ -389,13 +463,14 @@ uint32_t z_order(uint32_t bx, uint32_t by)
 // Sorts `ranks` (ascending) into block order -- blocks in Z order, ranks
 // ascending inside a block -- and lists the runs of positions per block
 // with their windows.
-void order_by_blocks(const mesh_sdd &inst, std::vector<int32_t> &ranks, std::vector<BlockRun> &blocks)
+void order_by_blocks(const mesh_sdd &inst, const Layout &lay, std::vector<int32_t> &ranks,
+                     std::vector<BlockRun> &blocks)
 {
     const int n_xi = inst.d.n_xi, n_eta = inst.d.n_eta;
-    const int kind = window_kind(inst.d);
+    const int kind = lay.kind;
     int wx = 0, wy = 0;
     window_dims(kind, n_xi, n_eta, &wx, &wy);
-    const int lx = block_len(kind, n_xi, wx), ly = block_len(kind, n_eta, wy);
+    const int lx = block_len(lay.margin, n_xi, wx), ly = block_len(lay.margin, n_eta, wy);
     const int nbx = (n_xi + lx - 1) / lx;
     auto block_of = [&](int32_t r) { return (inst.node_j[(size_t)r] / ly) * nbx + inst.node_i[(size_t)r] / lx; };
     auto z_of = [&](int b) { return z_order((uint32_t)(b % nbx), (uint32_t)(b / nbx)); };
@@ -419,11 +494,12 @@ void order_by_blocks(const mesh_sdd &inst, std::vector<int32_t> &ranks, std::vec
     }
 }
 
-// Node lists of `stride` (built on first use and kept by the instance).
-// Caller holds gpu_mu.
-int sample_set(mesh_sdd &inst, int stride, const SampleSet **out)
+// Node lists of `stride` in the block order of `lay` (built on first use
+// and kept by the instance).  Caller holds gpu_mu.
+int sample_set(mesh_sdd &inst, int stride, const Layout &lay, const SampleSet **out)
 {
-    auto it = inst.samples.find(stride);
+    const auto key = std::make_tuple(stride, lay.kind, lay.margin);
+    auto it = inst.samples.find(key);
     if (it != inst.samples.end()) {
         *out = it->second.get();
         return MESH_SDD_OK;
@@ -431,7 +507,9 @@ int sample_set(mesh_sdd &inst, int stride, const SampleSet **out)
     std::vector<int32_t> ranks = sampled_ranks(inst, stride);
     const size_t Ms = ranks.size();
     auto set = std::make_unique<SampleSet>();
-    order_by_blocks(inst, ranks, set->blocks);
+    set->kind = lay.kind;
+    set->margin = lay.margin;
+    order_by_blocks(inst, lay, ranks, set->blocks);
     set->pos_of_rank.assign((size_t)inst.M, -1);
     for (size_t k = 0; k < Ms; ++k) set->pos_of_rank[(size_t)ranks[k]] = (int32_t)k;
     std::vector<int32_t> host(3 * Ms);
@@ -445,13 +523,13 @@ int sample_set(mesh_sdd &inst, int stride, const SampleSet **out)
     if (set->lists.alloc(host.size() * sizeof(int32_t)) != hipSuccess)
         return fail(MESH_SDD_E_NOMEM, "device allocation of the sampled node lists failed");
     if (Ms) HIP_TRY(hipMemcpy(set->lists.p, host.data(), host.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    if (stride > 1) {
+    if (!inst.samples.empty()) {   // every set after the first counts against the budget
         std::lock_guard<std::mutex> lk(inst.ctx->mu);
         inst.resident_bytes += set->lists.bytes;
         inst.ctx->in_use += set->lists.bytes;
     }
     *out = set.get();
-    inst.samples.emplace(stride, std::move(set));
+    inst.samples.emplace(key, std::move(set));
     return MESH_SDD_OK;
 }
 
@@ -474,8 +552,23 @@ int stage_request(Request &r, const mesh_sdd_step *dev_step, Arena *arena = null
     const size_t nb = 4 * (size_t)d.n_eta + 4 * (size_t)d.n_xi;
     const int M = inst.M;
     const bool fp64 = d.precision == MESH_SDD_FP64;
-    int rc = sample_set(inst, r.stride, &r.ss);
-    if (rc != MESH_SDD_OK) return rc;
+    int rc = MESH_SDD_OK;
+    if (arena) {
+        // no allocation: the set of the instance's current layout if built,
+        // else any set of the stride (the layout orders the work only)
+        const Layout lay = layout_of(d, launch_for(ctx, d));
+        auto it = inst.samples.find(std::make_tuple(r.stride, lay.kind, lay.margin));
+        if (it == inst.samples.end())
+            for (auto s = inst.samples.begin(); s != inst.samples.end(); ++s)
+                if (std::get<0>(s->first) == r.stride) it = s;
+        if (it == inst.samples.end())
+            return fail(MESH_SDD_E_STATE, "interface stride %d: its node lists are built by the first allocating "
+                        "solve with that stride", r.stride);
+        r.ss = it->second.get();
+    } else {
+        rc = sample_set(inst, r.stride, layout_of(d, launch_for(ctx, d)), &r.ss);
+        if (rc != MESH_SDD_OK) return rc;
+    }
     const int Ms = r.ss->Ms;
 
     uint32_t chunks;
@@ -551,8 +644,9 @@ int stage_request(Request &r, const mesh_sdd_step *dev_step, Arena *arena = null
     v.node_i = r.ss->node_i();
     v.node_j = r.ss->node_j();
     v.node_r = r.ss->node_r();
-    v.cells = inst.cells.as<float4>();
-    v.coef_y = inst.coef_y.as<float4>();
+    v.coef_y = inst.cells.as<float4>();
+    v.cells = cell_records(inst);
+    v.rec0 = (uint32_t)((size_t)(d.n_xi - 1) * (d.n_eta - 1) * sizeof(float4));
     v.rho_f = inst.rho_f.as<float>();
     v.rhox_f = inst.rhox_f.as<float>();
     v.xpad_f = r.xpad_f.as<float>();
@@ -641,19 +735,22 @@ int run_fp32_launch(mesh_sdd_ctx *ctx, const std::vector<InstView> &views, const
     if (level > 0 && ends_b.reserve((size_t)end_waves * 6u * cap * sizeof(float)))
         return fail(MESH_SDD_E_NOMEM, "device allocation of the end-state buffer failed");
     // windowed launch: one job per (range, grid block), split so that no job
-    // holds more than 1/32 of a workgroup's share of the items (1/256 in a
-    // block of a grid cut into two-field windows: measured on the batched
-    // mix, whose 513^2 grids then run 5 % faster; whole-grid windows are
-    // refilled for every job, and three-field windows lose with smaller
-    // jobs), in block order, cut into per-XCD queues of equal nominal work
+    // holds more than 1/job_split of a workgroup's share of the items (by
+    // default 1/32, and 1/256 in a block of a grid cut into two-field
+    // windows: measured on the batched mix, whose 513^2 grids then run 5 %
+    // faster; whole-grid windows are refilled for every job, and three-field
+    // windows lose with smaller jobs), in block order, cut into per-XCD
+    // queues of equal nominal work
     std::vector<msdd::WinJob> jobs;
     msdd::JobQueues qs{};
     size_t win_lds = 32;
     int periodic = -2;
     if (level == 3) {
-        const size_t per = (size_t)ctx->cu_count * (size_t)per_cu * 32u;
-        const size_t jmax = std::max<size_t>(64, (n_items + per - 1) / per);
-        const size_t jmax0 = std::max<size_t>(64, (n_items + per * 8 - 1) / (per * 8));
+        const size_t share = ((size_t)ctx->cu_count * (size_t)per_cu);
+        const size_t split = l.job_split > 0 ? (size_t)l.job_split : 32u;
+        const size_t split0 = l.job_split > 0 ? (size_t)l.job_split : 256u;
+        const size_t jmax = std::max<size_t>(64, (n_items + share * split - 1) / (share * split));
+        const size_t jmax0 = std::max<size_t>(64, (n_items + share * split0 - 1) / (share * split0));
         for (size_t ri = 0; ri < ranges.size(); ++ri) {
             const WorkRange &w = ranges[ri];
             const InstView &v = views[w.inst];
@@ -687,29 +784,28 @@ int run_fp32_launch(mesh_sdd_ctx *ctx, const std::vector<InstView> &views, const
             HIP_TRY(hipMemcpyAsync(jobs_b.p, jobs.data(), jobs.size() * sizeof(msdd::WinJob),
                                    hipMemcpyHostToDevice, st));
     }
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
-    HIP_TRY(hipEventRecord(e0, st));
+    TimerEvents ev;
+    HIP_TRY(ev.create());
+    HIP_TRY(hipEventRecord(ev.e0, st));
     hipError_t le =
         level == 3 ? msdd::launch_paths_fp32_window(views_b.as<InstView>(), ranges_b.as<WorkRange>(),
                                                     jobs_b.as<msdd::WinJob>(), qs, head_b.as<uint32_t>(),
                                                     cap, periodic, win_lds, table_grid,
-                                                    ends_b.as<float>(), end_waves, st)
+                                                    ends_b.as<float>(), end_waves, (uint32_t)l.refill_lanes,
+                                                    (uint32_t)l.max_quarters, st)
         : level > 0 ? msdd::launch_paths_fp32_table(views_b.as<InstView>(), ranges_b.as<WorkRange>(),
                                                     (uint32_t)n_items, head_b.as<uint32_t>(), cap, level,
                                                     views[0].per_xi + 2 * views[0].per_eta, n_nodes, table_grid,
-                                                    ends_b.as<float>(), end_waves, st)
+                                                    ends_b.as<float>(), end_waves, (uint32_t)l.refill_lanes,
+                                                    (uint32_t)l.max_quarters, st)
                     : msdd::launch_paths_fp32(views_b.as<InstView>(), ranges_b.as<WorkRange>(),
                                                       (uint32_t)ranges.size(), (uint32_t)n_items,
                                                       head_b.as<uint32_t>(), cap, grid_for(ctx, l, cap), l.block,
                                                       st);
-    HIP_TRY(hipEventRecord(e1, st));
-    hipError_t se = hipEventSynchronize(e1);
+    HIP_TRY(hipEventRecord(ev.e1, st));
+    hipError_t se = hipEventSynchronize(ev.e1);
     float t = 0.0f;
-    (void)hipEventElapsedTime(&t, e0, e1);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    (void)hipEventElapsedTime(&t, ev.e0, ev.e1);
     if (le != hipSuccess) return fail(MESH_SDD_E_DEVICE, "path kernel launch failed: %s", hipGetErrorString(le));
     if (se != hipSuccess) return fail(MESH_SDD_E_DEVICE, "path kernel failed: %s", hipGetErrorString(se));
     *ms = t;
@@ -735,18 +831,15 @@ WorkRange range_of(const Request &r, uint32_t slot, size_t base, size_t first, s
 int run_fp64_launch(mesh_sdd_ctx *ctx, Request &r, double *ms)
 {
     hipStream_t st = ctx->stream;
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
-    HIP_TRY(hipEventRecord(e0, st));
+    TimerEvents ev;
+    HIP_TRY(ev.create());
+    HIP_TRY(hipEventRecord(ev.e0, st));
     hipError_t le = msdd::launch_paths_fp64(r.view.as<InstView>(), (uint32_t)r.Ms, (uint32_t)r.N,
                                             r.chunks_per_node, r.partials.as<Partial>(), st);
-    HIP_TRY(hipEventRecord(e1, st));
-    hipError_t se = hipEventSynchronize(e1);
+    HIP_TRY(hipEventRecord(ev.e1, st));
+    hipError_t se = hipEventSynchronize(ev.e1);
     float t = 0.0f;
-    (void)hipEventElapsedTime(&t, e0, e1);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    (void)hipEventElapsedTime(&t, ev.e0, ev.e1);
     if (le != hipSuccess) return fail(MESH_SDD_E_DEVICE, "FP64 path kernel launch failed: %s", hipGetErrorString(le));
     if (se != hipSuccess) return fail(MESH_SDD_E_DEVICE, "FP64 path kernel failed: %s", hipGetErrorString(se));
     *ms = t;
@@ -839,12 +932,13 @@ int run_blocking(mesh_sdd_ctx *ctx, std::vector<std::shared_ptr<Request>> &reqs,
     std::vector<const SampleSet *> sets;
     std::vector<size_t> fp32_reqs;
     size_t base = 0;
-    mesh_sdd_launch l = default_launch();
-    bool have_launch = false;
-    // one persistent launch over the FP32 requests gathered so far
+    // one persistent launch over the FP32 requests gathered so far: the
+    // bucket's shape for a launch of one instance, the multi-instance shape
+    // otherwise
     auto launch_group = [&]() {
         if (fp32_reqs.empty()) return;
         double ms = 0.0;
+        const mesh_sdd_launch l = launch_for_group(ctx, fp32_reqs.size() == 1 ? &reqs[fp32_reqs[0]]->inst->d : nullptr);
         int rc = run_fp32_launch(ctx, views, ranges, sets, l, &ms);
         for (size_t q : fp32_reqs) {
             Request &r = *reqs[q];
@@ -888,10 +982,6 @@ int run_blocking(mesh_sdd_ctx *ctx, std::vector<std::shared_ptr<Request>> &reqs,
                 base += r.n_items;
             }
             fp32_reqs.push_back(q);
-            if (!have_launch) {
-                l = launch_for(ctx, r.inst->d);
-                have_launch = true;
-            }
         }
     }
     launch_group();
@@ -901,16 +991,140 @@ int run_blocking(mesh_sdd_ctx *ctx, std::vector<std::shared_ptr<Request>> &reqs,
     return MESH_SDD_OK;
 }
 
+// Autotuning: a candidate wins only if it is this much faster per path-step
+// (timings of one launch repeat to a few tenths of a percent).
+constexpr double kTuneMargin = 0.005;
+
+// Tune the bucket of `inst` (grid size, periodicity) by timing launches of
+// `inst` alone at a reduced path count, one knob at a time; the winner goes
+// to ctx->tuned.  The context's override is used for the timings and then
+// restored.
+int tune_bucket(mesh_sdd *inst, const mesh_sdd_step &step, int64_t N, mesh_sdd_launch *out)
+{
+    mesh_sdd_ctx *ctx = inst->ctx;
+    const mesh_sdd_desc &d = inst->d;
+    const TuneKey key{d.n_xi, d.n_eta, d.periodic_xi, d.periodic_eta};
+    // about 6e9 nominal path-steps per timing (~20 ms of kernel)
+    const int32_t Ms = step.interface_stride > 1 ? (int32_t)sampled_ranks(*inst, (int)step.interface_stride).size()
+                                                 : inst->M;
+    int64_t Nt = (int64_t)(6.0e9 / std::max(1.0, (double)Ms * d.K));
+    Nt = std::min<int64_t>(N, std::max<int64_t>(256, (Nt + 63) / 64 * 64));
+    mesh_sdd_step s = step;
+    s.target_se = 0.0;
+    s.paths_per_node = Nt;
+    bool saved_override;
+    mesh_sdd_launch saved_l;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        saved_override = ctx->has_override;
+        saved_l = ctx->override_launch;
+    }
+    auto timeit = [&](const mesh_sdd_launch &l, double *ms_per_step) -> int {
+        {
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            ctx->override_launch = l;
+            ctx->has_override = true;
+        }
+        std::vector<std::shared_ptr<Request>> reqs{make_request(inst, s, Nt)};
+        std::vector<const mesh_sdd_step *> ds{s.inputs_on_device ? &s : nullptr};
+        std::vector<int> st;
+        InflightHold hold;
+        hold.add(inst);
+        const int rc = run_blocking(ctx, reqs, ds, st);
+        if (rc == MESH_SDD_OK)
+            *ms_per_step = reqs[0]->device_ms / std::max<double>(1.0, (double)reqs[0]->executed_steps);
+        return rc;
+    };
+    mesh_sdd_launch best = launch_for(ctx, d);
+    best.monitor_table = 0;
+    double best_t = 0.0, t = 0.0;
+    int rc = timeit(best, &t);   // warm-up: the first launch of a shape also builds its node lists
+    if (rc == MESH_SDD_OK) rc = timeit(best, &best_t);
+    // knobs that matter for this bucket
+    int per_cu = 0;
+    const int level = table_level(d.n_xi * d.n_eta, 0, &per_cu);
+    std::vector<std::pair<int32_t mesh_sdd_launch::*, std::vector<int32_t>>> knobs;
+    knobs.push_back({&mesh_sdd_launch::chunk_paths, {64, 128, 256}});
+    if (level == 3) {
+        const bool whole = window_bytes(0, d.n_xi, d.n_eta) <= msdd::kWinBytes;
+        if (!whole) {
+            knobs.push_back({&mesh_sdd_launch::window_kind, {1, 2}});
+            knobs.push_back({&mesh_sdd_launch::window_margin, {0, 20, 30, 38, 45, 55}});
+        }
+        knobs.push_back({&mesh_sdd_launch::job_split, {8, 32, 128, 256, 1024}});
+    }
+    knobs.push_back({&mesh_sdd_launch::refill_lanes, {48, 56, 60}});
+    knobs.push_back({&mesh_sdd_launch::max_quarters, {8, 16, 32}});
+    for (size_t k = 0; k < knobs.size() && rc == MESH_SDD_OK; ++k)
+        for (int32_t v : knobs[k].second) {
+            if (best.*(knobs[k].first) == v) continue;
+            mesh_sdd_launch c = best;
+            c.*(knobs[k].first) = v;
+            if (knobs[k].first == &mesh_sdd_launch::window_kind) c.window_margin = 0;   // the kind's own default
+            if (knobs[k].first == &mesh_sdd_launch::window_margin) {
+                // margins that leave a block of at least 8 nodes in the window
+                const Layout lay = layout_of(d, c);
+                int wx = 0, wy = 0;
+                window_dims(lay.kind, d.n_xi, d.n_eta, &wx, &wy);
+                if (std::min(wx, wy) - 2 * lay.margin < 8) continue;
+            }
+            rc = timeit(c, &t);
+            if (rc != MESH_SDD_OK) break;
+            if (t < best_t * (1.0 - kTuneMargin)) {
+                best = c;
+                best_t = t;
+            }
+        }
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->has_override = saved_override;
+        ctx->override_launch = saved_l;
+        if (rc == MESH_SDD_OK) ctx->tuned[key] = best;
+    }
+    if (rc != MESH_SDD_OK) return rc;
+    *out = best;
+    return MESH_SDD_OK;
+}
+
+// Range checks of a launch shape given by a caller (0 = default allowed).
+int check_launch(const mesh_sdd_launch *l)
+{
+    if (l->struct_size != sizeof(mesh_sdd_launch))
+        return fail(MESH_SDD_E_INVAL, "launch.struct_size %u != %zu", l->struct_size, sizeof(mesh_sdd_launch));
+    if (l->block != 0 && l->block != 64 && l->block != 128 && l->block != 256 && l->block != 512)
+        return fail(MESH_SDD_E_INVAL, "block must be 64, 128, 256 or 512");
+    if (l->waves_per_simd < 0 || l->waves_per_simd > 8)
+        return fail(MESH_SDD_E_INVAL, "waves_per_simd must be in [0, 8]");
+    const int chunk = l->chunk_paths ? l->chunk_paths : 128;
+    if (chunk < 64 || chunk % 64 || chunk > 2048 ||
+        msdd::paths_fp32_lds_bytes(l->block ? l->block : 256, (uint32_t)chunk) > kLdsBytes)
+        return fail(MESH_SDD_E_INVAL, "chunk_paths must be a multiple of 64 in [64, 2048] and fit in LDS");
+    if (l->monitor_table != 0 && l->monitor_table != 1)
+        return fail(MESH_SDD_E_INVAL, "launch.monitor_table must be 0 or 1");
+    if (l->refill_lanes < 0 || l->refill_lanes > 64) return fail(MESH_SDD_E_INVAL, "refill_lanes must be in [0, 64]");
+    if (l->max_quarters < 0 || l->max_quarters > 64) return fail(MESH_SDD_E_INVAL, "max_quarters must be in [0, 64]");
+    if (l->window_kind < 0 || l->window_kind > 2) return fail(MESH_SDD_E_INVAL, "window_kind must be 0, 1 or 2");
+    if (l->window_margin < 0 || l->window_margin > 64)
+        return fail(MESH_SDD_E_INVAL, "window_margin must be in [0, 64]");
+    if (l->job_split < 0 || l->job_split > 4096) return fail(MESH_SDD_E_INVAL, "job_split must be in [0, 4096]");
+    return MESH_SDD_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Serving scheduler: admission by HBM budget, chunk-granularity ticks.
 // ---------------------------------------------------------------------------
 constexpr double kTickPathSteps = 6.0e9;   // work per tick, ~tens of ms at full rate
 
-void finish_request(mesh_sdd_ctx *ctx, const std::shared_ptr<Request> &r, int status, const std::string &err)
+// Ends a request (ctx->mu held by the caller).  Never throws: a request that
+// left the running list must end, or its waiters and its instance's
+// destroy would wait for ever.
+void finish_request(mesh_sdd_ctx *ctx, const std::shared_ptr<Request> &r, int status, const std::string &err) noexcept
 {
-    // ctx->mu held by caller
     r->status = status;
-    r->error = err;
+    try {
+        r->error = err;
+    } catch (...) {   // the status alone then tells the caller
+    }
     r->finished = true;
     r->t_done = Clock::now();
     if (r->admitted) ctx->in_use -= std::min(ctx->in_use, r->cost_bytes);
@@ -918,7 +1132,10 @@ void finish_request(mesh_sdd_ctx *ctx, const std::shared_ptr<Request> &r, int st
     if (status == MESH_SDD_OK) {
         ++ctx->completed;
         ctx->executed += r->executed_steps;
-        ctx->latencies.push_back(std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count());
+        try {
+            ctx->latencies.push_back(std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count());
+        } catch (...) {   // the latency is left out of the percentiles
+        }
     } else if (status == MESH_SDD_E_CANCELLED) {
         ++ctx->cancelled;
     } else {
@@ -931,121 +1148,137 @@ void scheduler_loop(mesh_sdd_ctx *ctx)
 {
     (void)hipSetDevice(ctx->device);
     for (;;) {
-        std::vector<std::shared_ptr<Request>> to_admit;
-        {
-            std::unique_lock<std::mutex> lk(ctx->mu);
-            ctx->cv.wait(lk, [&] { return ctx->stop || !ctx->queue.empty() || !ctx->running.empty(); });
-            if (ctx->stop) break;
-            // admission in arrival order while the budget allows
-            while (!ctx->queue.empty()) {
-                auto &r = ctx->queue.front();
-                if (ctx->in_use + r->cost_bytes > ctx->budget && !ctx->running.empty()) break;
-                ctx->in_use += r->cost_bytes;
-                r->admitted = true;
-                to_admit.push_back(r);
-                ctx->running.push_back(r);
-                ctx->queue.pop_front();
-                if (ctx->in_use > ctx->budget) break;   // a lone request over budget never reaches here
-            }
-        }
-        // stage newly admitted requests (FP64 ones run whole, here)
-        for (auto &r : to_admit) {
-            int rc;
-            double ms = 0.0;
+        try {
+            std::vector<std::shared_ptr<Request>> to_admit;
             {
-                std::lock_guard<std::mutex> g(ctx->gpu_mu);
-                rc = stage_request(*r, nullptr);
-                if (rc == MESH_SDD_OK && r->inst->d.precision == MESH_SDD_FP64) {
-                    rc = run_fp64_launch(ctx, *r, &ms);
-                    if (rc == MESH_SDD_OK) rc = finalize_request(ctx, *r);
-                    r->device_ms = ms;
-                    release_request_buffers(*r);
+                std::unique_lock<std::mutex> lk(ctx->mu);
+                ctx->cv.wait(lk, [&] { return ctx->stop || !ctx->queue.empty() || !ctx->running.empty(); });
+                if (ctx->stop) break;
+                // admission in arrival order while the budget allows
+                while (!ctx->queue.empty()) {
+                    auto &r = ctx->queue.front();
+                    if (ctx->in_use + r->cost_bytes > ctx->budget && !ctx->running.empty()) break;
+                    to_admit.reserve(to_admit.size() + 1);   // the only allocations, before any state changes
+                    ctx->running.reserve(ctx->running.size() + 1);
+                    ctx->in_use += r->cost_bytes;
+                    r->admitted = true;
+                    to_admit.push_back(r);
+                    ctx->running.push_back(r);
+                    ctx->queue.pop_front();
+                    if (ctx->in_use > ctx->budget) break;   // a lone request over budget never reaches here
                 }
             }
-            // FP32 requests without work (no interface node) finish at once
-            const bool empty_fp32 = rc == MESH_SDD_OK && r->inst->d.precision == MESH_SDD_FP32 && r->n_items == 0;
-            if (empty_fp32) {
-                std::lock_guard<std::mutex> g(ctx->gpu_mu);
-                rc = finalize_request(ctx, *r);
-                release_request_buffers(*r);
+            // stage newly admitted requests (FP64 ones run whole, here)
+            for (auto &r : to_admit) {
+                int rc;
+                double ms = 0.0;
+                {
+                    std::lock_guard<std::mutex> g(ctx->gpu_mu);
+                    rc = stage_request(*r, nullptr);
+                    if (rc == MESH_SDD_OK && r->inst->d.precision == MESH_SDD_FP64) {
+                        rc = run_fp64_launch(ctx, *r, &ms);
+                        if (rc == MESH_SDD_OK) rc = finalize_request(ctx, *r);
+                        r->device_ms = ms;
+                        release_request_buffers(*r);
+                    }
+                }
+                // FP32 requests without work (no interface node) finish at once
+                const bool empty_fp32 = rc == MESH_SDD_OK && r->inst->d.precision == MESH_SDD_FP32 && r->n_items == 0;
+                if (empty_fp32) {
+                    std::lock_guard<std::mutex> g(ctx->gpu_mu);
+                    rc = finalize_request(ctx, *r);
+                    release_request_buffers(*r);
+                }
+                std::lock_guard<std::mutex> lk(ctx->mu);
+                ctx->busy_ms += ms;
+                if (rc != MESH_SDD_OK || r->inst->d.precision == MESH_SDD_FP64 || empty_fp32) {
+                    const std::string msg = rc == MESH_SDD_OK ? std::string() : g_last_error;   // may throw: first
+                    ctx->running.erase(std::find(ctx->running.begin(), ctx->running.end(), r));
+                    if (rc != MESH_SDD_OK) release_request_buffers(*r);
+                    finish_request(ctx, r, rc, msg);
+                }
             }
-            std::lock_guard<std::mutex> lk(ctx->mu);
-            ctx->busy_ms += ms;
-            if (rc != MESH_SDD_OK || r->inst->d.precision == MESH_SDD_FP64 || empty_fp32) {
-                ctx->running.erase(std::find(ctx->running.begin(), ctx->running.end(), r));
-                if (rc != MESH_SDD_OK) release_request_buffers(*r);
-                finish_request(ctx, r, rc, rc == MESH_SDD_OK ? std::string() : g_last_error);
+            // build one tick over the running FP32 requests: a fair share of the
+            // tick's work for each, at least one item each
+            std::vector<InstView> views;
+            std::vector<WorkRange> ranges;
+            std::vector<const SampleSet *> sets;
+            std::vector<std::pair<std::shared_ptr<Request>, size_t>> taken;
+            mesh_sdd_launch l = default_launch();
+            {
+                std::lock_guard<std::mutex> lk(ctx->mu);
+                size_t active = 0;
+                for (auto &r : ctx->running)
+                    if (r->next_item < r->n_items) ++active;
+                if (active == 0) continue;
+                const double share = kTickPathSteps / (double)active;
+                size_t base = 0;
+                for (auto &r : ctx->running) {
+                    if (r->next_item >= r->n_items) continue;
+                    const double per_item = (double)r->chunk_paths * (double)r->inst->d.K;
+                    size_t take = (size_t)std::max(1.0, share / per_item);
+                    take = std::min(take, r->n_items - r->next_item);
+                    const uint32_t slot = (uint32_t)views.size();
+                    views.push_back(r->v);
+                    sets.push_back(r->ss);
+                    ranges.push_back(range_of(*r, slot, base, r->next_item, take));
+                    base += take;
+                    r->next_item += take;
+                    taken.emplace_back(r, take);
+                }
+                ++ctx->ticks;
             }
-        }
-        // build one tick over the running FP32 requests: a fair share of the
-        // tick's work for each, at least one item each
-        std::vector<InstView> views;
-        std::vector<WorkRange> ranges;
-        std::vector<const SampleSet *> sets;
-        std::vector<std::pair<std::shared_ptr<Request>, size_t>> taken;
-        mesh_sdd_launch l = default_launch();
-        {
-            std::lock_guard<std::mutex> lk(ctx->mu);
-            size_t active = 0;
-            for (auto &r : ctx->running)
-                if (r->next_item < r->n_items) ++active;
-            if (active == 0) continue;
-            const double share = kTickPathSteps / (double)active;
-            size_t base = 0;
-            for (auto &r : ctx->running) {
-                if (r->next_item >= r->n_items) continue;
-                const double per_item = (double)r->chunk_paths * (double)r->inst->d.K;
-                size_t take = (size_t)std::max(1.0, share / per_item);
-                take = std::min(take, r->n_items - r->next_item);
-                const uint32_t slot = (uint32_t)views.size();
-                views.push_back(r->v);
-                sets.push_back(r->ss);
-                ranges.push_back(range_of(*r, slot, base, r->next_item, take));
-                base += take;
-                r->next_item += take;
-                taken.emplace_back(r, take);
-            }
-            ++ctx->ticks;
-            if (ctx->has_override)
-                l = ctx->override_launch;
-            else {
-                auto it = ctx->tuned.find(TuneKey{taken.front().first->inst->d.n_xi, taken.front().first->inst->d.n_eta,
-                                                  taken.front().first->inst->d.periodic_xi,
-                                                  taken.front().first->inst->d.periodic_eta});
-                if (it != ctx->tuned.end()) l = it->second;
-            }
-        }
-        double ms = 0.0;
-        int rc;
-        {
-            std::lock_guard<std::mutex> g(ctx->gpu_mu);
-            rc = run_fp32_launch(ctx, views, ranges, sets, l, &ms);
-        }
-        std::string err = rc == MESH_SDD_OK ? std::string() : g_last_error;
-        std::vector<std::shared_ptr<Request>> complete;
-        {
-            std::lock_guard<std::mutex> lk(ctx->mu);
-            ctx->busy_ms += ms;
-            for (auto &t : taken) {
-                t.first->done_items += t.second;
-                t.first->device_ms += ms;
-                if (rc != MESH_SDD_OK || t.first->done_items == t.first->n_items) complete.push_back(t.first);
-            }
-        }
-        for (auto &r : complete) {
-            int fr = rc;
-            if (fr == MESH_SDD_OK) {
-                std::lock_guard<std::mutex> g(ctx->gpu_mu);
-                fr = finalize_request(ctx, *r);
-            }
-            std::string e2 = fr == MESH_SDD_OK ? std::string() : (rc != MESH_SDD_OK ? err : g_last_error);
+            // a tick of one request takes its bucket's shape, else the
+            // multi-instance shape (launch_for_group takes ctx->mu itself)
+            l = launch_for_group(ctx, taken.size() == 1 ? &taken.front().first->inst->d : nullptr);
+            double ms = 0.0;
+            int rc;
             {
                 std::lock_guard<std::mutex> g(ctx->gpu_mu);
-                release_request_buffers(*r);
+                rc = run_fp32_launch(ctx, views, ranges, sets, l, &ms);
+            }
+            std::string err = rc == MESH_SDD_OK ? std::string() : g_last_error;
+            std::vector<std::shared_ptr<Request>> complete;
+            {
+                std::lock_guard<std::mutex> lk(ctx->mu);
+                ctx->busy_ms += ms;
+                for (auto &t : taken) {
+                    t.first->done_items += t.second;
+                    t.first->device_ms += ms;
+                    if (rc != MESH_SDD_OK || t.first->done_items == t.first->n_items) complete.push_back(t.first);
+                }
+            }
+            for (auto &r : complete) {
+                int fr = rc;
+                if (fr == MESH_SDD_OK) {
+                    std::lock_guard<std::mutex> g(ctx->gpu_mu);
+                    fr = finalize_request(ctx, *r);
+                }
+                std::string e2 = fr == MESH_SDD_OK ? std::string() : (rc != MESH_SDD_OK ? err : g_last_error);
+                {
+                    std::lock_guard<std::mutex> g(ctx->gpu_mu);
+                    release_request_buffers(*r);
+                }
+                std::lock_guard<std::mutex> lk(ctx->mu);
+                ctx->running.erase(std::find(ctx->running.begin(), ctx->running.end(), r));
+                finish_request(ctx, r, fr, e2);
+            }
+        } catch (...) {
+            // a host resource ran out inside the tick: the requests that were
+            // running end with the error; queued ones wait for the next tick
+            (void)abi_exception();
+            const std::string err = g_last_error;
+            std::vector<std::shared_ptr<Request>> left;
+            {
+                std::lock_guard<std::mutex> lk(ctx->mu);
+                left.swap(ctx->running);
+            }
+            {
+                std::lock_guard<std::mutex> g(ctx->gpu_mu);
+                for (auto &r : left) release_request_buffers(*r);
             }
             std::lock_guard<std::mutex> lk(ctx->mu);
-            ctx->running.erase(std::find(ctx->running.begin(), ctx->running.end(), r));
-            finish_request(ctx, r, fr, e2);
+            for (auto &r : left) finish_request(ctx, r, MESH_SDD_E_NOMEM, err);
         }
     }
     // cancel whatever is left (buffers are freed without holding ctx->mu)
@@ -1076,7 +1309,7 @@ const char *mesh_sdd_last_error(void) { return g_last_error.c_str(); }
 const char *mesh_sdd_version(void) { return "mesh_sdd 0.1 (gfx950)"; }
 
 int mesh_sdd_ctx_create(int device, size_t hbm_budget_bytes, void *hip_stream, mesh_sdd_ctx **out)
-{
+try {
     if (!out) return fail(MESH_SDD_E_INVAL, "out is NULL");
     *out = nullptr;
     int count = 0;
@@ -1113,10 +1346,12 @@ int mesh_sdd_ctx_create(int device, size_t hbm_budget_bytes, void *hip_stream, m
     }
     *out = ctx.release();
     return MESH_SDD_OK;
+} catch (...) {
+    return abi_exception();
 }
 
 int mesh_sdd_ctx_destroy(mesh_sdd_ctx *ctx)
-{
+try {
     if (!ctx) return fail(MESH_SDD_E_INVAL, "ctx is NULL");
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
@@ -1134,10 +1369,12 @@ int mesh_sdd_ctx_destroy(mesh_sdd_ctx *ctx)
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
     return MESH_SDD_OK;
+} catch (...) {
+    return abi_exception();
 }
 
 int mesh_sdd_ctx_stats(mesh_sdd_ctx *ctx, mesh_sdd_stats *out)
-{
+try {
     if (!ctx || !out) return fail(MESH_SDD_E_INVAL, "NULL argument");
     if (out->struct_size != sizeof(mesh_sdd_stats))
         return fail(MESH_SDD_E_INVAL, "stats.struct_size %u != %zu", out->struct_size, sizeof(mesh_sdd_stats));
@@ -1171,34 +1408,30 @@ int mesh_sdd_ctx_stats(mesh_sdd_ctx *ctx, mesh_sdd_stats *out)
         out->mean_ms = s / (double)lat.size();
     }
     return MESH_SDD_OK;
+} catch (...) {
+    return abi_exception();
 }
 
 int mesh_sdd_set_launch(mesh_sdd_ctx *ctx, const mesh_sdd_launch *launch)
-{
+try {
     if (!ctx) return fail(MESH_SDD_E_INVAL, "ctx is NULL");
-    std::lock_guard<std::mutex> lk(ctx->mu);
     if (!launch) {
+        std::lock_guard<std::mutex> lk(ctx->mu);
         ctx->has_override = false;
         return MESH_SDD_OK;
     }
-    if (launch->struct_size != sizeof(mesh_sdd_launch))
-        return fail(MESH_SDD_E_INVAL, "launch.struct_size %u != %zu", launch->struct_size, sizeof(mesh_sdd_launch));
-    if (launch->block != 64 && launch->block != 128 && launch->block != 256 && launch->block != 512)
-        return fail(MESH_SDD_E_INVAL, "block must be 64, 128, 256 or 512");
-    if (launch->waves_per_simd < 0 || launch->waves_per_simd > 8)
-        return fail(MESH_SDD_E_INVAL, "waves_per_simd must be in [0, 8]");
-    if (launch->chunk_paths < 64 || launch->chunk_paths % 64 || launch->chunk_paths > 2048 ||
-        msdd::paths_fp32_lds_bytes(launch->block, (uint32_t)launch->chunk_paths) > kLdsBytes)
-        return fail(MESH_SDD_E_INVAL, "chunk_paths must be a multiple of 64 in [64, 2048] and fit in LDS");
-    if (launch->monitor_table != 0 && launch->monitor_table != 1)
-        return fail(MESH_SDD_E_INVAL, "launch.monitor_table must be 0 or 1");
-    ctx->override_launch = *launch;
+    int rc = check_launch(launch);
+    if (rc != MESH_SDD_OK) return rc;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->override_launch = with_defaults(*launch);
     ctx->has_override = true;
     return MESH_SDD_OK;
+} catch (...) {
+    return abi_exception();
 }
 
 int mesh_sdd_get_launch(mesh_sdd *inst, mesh_sdd_launch *out)
-{
+try {
     if (!inst || !out) return fail(MESH_SDD_E_INVAL, "NULL argument");
     *out = launch_for(inst->ctx, inst->d);
     if (out->waves_per_simd == 0) {
@@ -1207,13 +1440,23 @@ int mesh_sdd_get_launch(mesh_sdd *inst, mesh_sdd_launch *out)
     }
     int per_cu = 0;
     out->table_level = table_level(inst->d.n_xi * inst->d.n_eta, out->monitor_table, &per_cu);
+    const Layout lay = layout_of(inst->d, *out);
+    out->window_kind = lay.kind ? 2 : 1;
+    out->window_margin = lay.margin;
+    if (out->job_split == 0) {
+        int wx = 0, wy = 0;
+        window_dims(lay.kind, inst->d.n_xi, inst->d.n_eta, &wx, &wy);
+        out->job_split = lay.kind == 0 && (wx < inst->d.n_xi || wy < inst->d.n_eta) ? 256 : 32;
+    }
     return MESH_SDD_OK;
+} catch (...) {
+    return abi_exception();
 }
 
 int mesh_sdd_desc_check(const mesh_sdd_desc *desc) { return validate_desc(desc); }
 
 int mesh_sdd_desc_interface_nodes(const mesh_sdd_desc *desc, int32_t *i, int32_t *j)
-{
+try {
     int rc = validate_desc(desc);
     if (rc != MESH_SDD_OK) return rc;
     std::vector<int32_t> ni, nj;
@@ -1224,11 +1467,13 @@ int mesh_sdd_desc_interface_nodes(const mesh_sdd_desc *desc, int32_t *i, int32_t
         std::memcpy(j, nj.data(), nj.size() * 4);
     }
     return (int)ni.size();
+} catch (...) {
+    return abi_exception();
 }
 
 int mesh_sdd_desc_work_order(const mesh_sdd_desc *desc, uint32_t interface_stride, int32_t *ranks, int32_t *blocks,
                              int32_t max_blocks, int32_t *n_blocks)
-{
+try {
     int rc = validate_desc(desc);
     if (rc != MESH_SDD_OK) return rc;
     rc = check_stride(*desc, interface_stride);
@@ -1241,7 +1486,7 @@ int mesh_sdd_desc_work_order(const mesh_sdd_desc *desc, uint32_t interface_strid
     tmp.M = (int32_t)tmp.node_i.size();
     std::vector<int32_t> order = sampled_ranks(tmp, interface_stride > 1 ? (int)interface_stride : 1);
     std::vector<BlockRun> runs;
-    order_by_blocks(tmp, order, runs);
+    order_by_blocks(tmp, layout_of(*desc, default_launch()), order, runs);
     if (ranks && !order.empty()) std::memcpy(ranks, order.data(), order.size() * 4);
     if (n_blocks) *n_blocks = (int32_t)runs.size();
     if (blocks) {
@@ -1254,10 +1499,12 @@ int mesh_sdd_desc_work_order(const mesh_sdd_desc *desc, uint32_t interface_strid
         }
     }
     return (int)order.size();
+} catch (...) {
+    return abi_exception();
 }
 
 int mesh_sdd_create(mesh_sdd_ctx *ctx, const mesh_sdd_desc *desc, mesh_sdd **out)
-{
+try {
     if (!ctx || !out) return fail(MESH_SDD_E_INVAL, "NULL argument");
     *out = nullptr;
     int rc = validate_desc(desc);
@@ -1280,7 +1527,7 @@ int mesh_sdd_create(mesh_sdd_ctx *ctx, const mesh_sdd_desc *desc, mesh_sdd **out
     HIP_TRY(hipSetDevice(ctx->device));
     if (inst->rho_in.alloc(n * 8) || inst->rho.alloc(n * 8) || inst->rho_xi.alloc(n * 8) ||
         inst->rho_eta.alloc(n * 8) || inst->rho_f.alloc(n * 4) || inst->rhox_f.alloc(n * 4) ||
-        inst->cells.alloc(cells * 3 * sizeof(float4)) || inst->coef_y.alloc(cells * sizeof(float4)) ||
+        inst->cells.alloc(cells * 4 * sizeof(float4)) ||
         inst->node_rank.alloc(n * 4) || inst->node_ij.alloc(std::max<size_t>(1, 2 * (size_t)inst->M) * 4))
         return fail(MESH_SDD_E_NOMEM, "device allocation for the instance tables failed");
     {
@@ -1294,7 +1541,7 @@ int mesh_sdd_create(mesh_sdd_ctx *ctx, const mesh_sdd_desc *desc, mesh_sdd **out
         }
     }
     const SampleSet *all = nullptr;
-    rc = sample_set(*inst, 1, &all);
+    rc = sample_set(*inst, 1, layout_of(inst->d, launch_for(ctx, inst->d)), &all);
     if (rc != MESH_SDD_OK) return rc;
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
@@ -1303,10 +1550,12 @@ int mesh_sdd_create(mesh_sdd_ctx *ctx, const mesh_sdd_desc *desc, mesh_sdd **out
     }
     *out = inst.release();
     return MESH_SDD_OK;
+} catch (...) {
+    return abi_exception();
 }
 
 int mesh_sdd_destroy(mesh_sdd *inst)
-{
+try {
     if (!inst) return fail(MESH_SDD_E_INVAL, "instance is NULL");
     if (inst->inflight.load() > 0) return fail(MESH_SDD_E_STATE, "instance has requests in flight");
     mesh_sdd_ctx *ctx = inst->ctx;
@@ -1320,10 +1569,12 @@ int mesh_sdd_destroy(mesh_sdd *inst)
     ctx->in_use -= std::min(ctx->in_use, bytes);
     --ctx->n_instances;
     return MESH_SDD_OK;
+} catch (...) {
+    return abi_exception();
 }
 
 int mesh_sdd_set_monitor(mesh_sdd *inst, const double *rho, int is_device_ptr)
-{
+try {
     if (!inst || !rho) return fail(MESH_SDD_E_INVAL, "NULL argument");
     const mesh_sdd_desc &d = inst->d;
     const size_t n = (size_t)d.n_xi * d.n_eta;
@@ -1338,16 +1589,20 @@ int mesh_sdd_set_monitor(mesh_sdd *inst, const double *rho, int is_device_ptr)
     hipStream_t st = ctx->stream;
     HIP_TRY(hipMemcpyAsync(inst->rho_in.p, rho, n * 8, is_device_ptr ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
     return msdd_rt::install_monitor(inst, st);
+} catch (...) {
+    return abi_exception();
 }
 
 int mesh_sdd_num_interface_nodes(const mesh_sdd *inst)
-{
+try {
     if (!inst) return fail(MESH_SDD_E_INVAL, "instance is NULL");
     return inst->M;
+} catch (...) {
+    return abi_exception();
 }
 
 int mesh_sdd_interface_nodes(const mesh_sdd *inst, int32_t *i, int32_t *j)
-{
+try {
     if (!inst) return fail(MESH_SDD_E_INVAL, "instance is NULL");
     if (inst->M && (!i || !j)) return fail(MESH_SDD_E_INVAL, "output array is NULL");
     if (inst->M) {
@@ -1355,11 +1610,13 @@ int mesh_sdd_interface_nodes(const mesh_sdd *inst, int32_t *i, int32_t *j)
         std::memcpy(j, inst->node_j.data(), (size_t)inst->M * 4);
     }
     return MESH_SDD_OK;
+} catch (...) {
+    return abi_exception();
 }
 
 int mesh_sdd_solve_batch(mesh_sdd *const *insts, const mesh_sdd_step *steps, mesh_sdd_result *results,
                          int32_t count, int32_t *status)
-{
+try {
     if (count < 0 || (count > 0 && (!insts || !steps || !results))) return fail(MESH_SDD_E_INVAL, "bad batch arguments");
     if (count == 0) return MESH_SDD_OK;
     mesh_sdd_ctx *ctx = insts[0] ? insts[0]->ctx : nullptr;
@@ -1370,6 +1627,7 @@ int mesh_sdd_solve_batch(mesh_sdd *const *insts, const mesh_sdd_step *steps, mes
     int first_err = MESH_SDD_OK;
     std::string first_msg;
     std::vector<int> idx;
+    InflightHold hold;
     for (int32_t q = 0; q < count; ++q) {
         mesh_sdd *inst = insts[q];
         int rc = MESH_SDD_OK;
@@ -1387,7 +1645,7 @@ int mesh_sdd_solve_batch(mesh_sdd *const *insts, const mesh_sdd_step *steps, mes
             }
             continue;
         }
-        inst->inflight.fetch_add(1);
+        hold.add(inst);
         reqs.push_back(make_request(inst, steps[q], N));
         dev_steps.push_back(steps[q].inputs_on_device ? &steps[q] : nullptr);
         idx.push_back(q);
@@ -1411,24 +1669,27 @@ int mesh_sdd_solve_batch(mesh_sdd *const *insts, const mesh_sdd_step *steps, mes
                 }
             }
         }
-        reqs[k]->inst->inflight.fetch_sub(1);
     }
     if (status)
         for (int32_t q = 0; q < count; ++q) status[q] = st[q];
     if (first_err != MESH_SDD_OK) g_last_error = first_msg;
     return first_err;
+} catch (...) {
+    return abi_exception();
 }
 
 int mesh_sdd_solve_interfaces(mesh_sdd *inst, const mesh_sdd_step *step, mesh_sdd_result *result)
-{
+try {
     if (!inst || !result) return fail(MESH_SDD_E_INVAL, "NULL argument");
     int32_t st = 0;
     mesh_sdd *one[1] = {inst};
     return mesh_sdd_solve_batch(one, step, result, 1, &st);
+} catch (...) {
+    return abi_exception();
 }
 
 int mesh_sdd_solve_interfaces_noalloc(mesh_sdd *inst, const mesh_sdd_step *step, mesh_sdd_result *result)
-{
+try {
     if (!inst || !step || !result) return fail(MESH_SDD_E_INVAL, "NULL argument");
     if (!inst->monitor_set) return fail(MESH_SDD_E_STATE, "set_monitor not called");
     if (result->struct_size != sizeof(mesh_sdd_result))
@@ -1447,7 +1708,9 @@ int mesh_sdd_solve_interfaces_noalloc(mesh_sdd *inst, const mesh_sdd_step *step,
     if (rc != MESH_SDD_OK) return rc;
     std::lock_guard<std::mutex> su(*use);   // one user of the device's array at a time
     std::lock_guard<std::mutex> g(ctx->gpu_mu);
-    auto set = inst->samples.find(r->stride);
+    auto set = inst->samples.end();
+    for (auto s = inst->samples.begin(); s != inst->samples.end(); ++s)
+        if (std::get<0>(s->first) == r->stride) set = s;
     if (set == inst->samples.end())
         return fail(MESH_SDD_E_STATE, "interface stride %d: its node lists are built by the first allocating solve "
                     "with that stride", r->stride);
@@ -1471,7 +1734,10 @@ int mesh_sdd_solve_interfaces_noalloc(mesh_sdd *inst, const mesh_sdd_step *step,
         const size_t cap = (size_t)(r->chunk_paths + 63) / 64 * 64;
         need += piece(sizeof(InstView)) + piece(sizeof(WorkRange)) + piece(64);
         if (level > 0) need += piece((size_t)ctx->cu_count * per_cu * (msdd::kTableBlock / 64) * 6 * cap * 4);
-        if (level == 3) need += piece((n_items / 64 + set->second->blocks.size() + 1) * sizeof(msdd::WinJob));
+        size_t nb_max = 0;   // the most blocks of any layout of the stride
+        for (auto s = inst->samples.begin(); s != inst->samples.end(); ++s)
+            if (std::get<0>(s->first) == r->stride) nb_max = std::max(nb_max, s->second->blocks.size());
+        if (level == 3) need += piece((n_items / 64 + nb_max + 1) * sizeof(msdd::WinJob));
     }
     if (need > msdd_rt::scratch_capacity())
         return fail(MESH_SDD_E_INVAL, "the solve needs %zu bytes of scratch, more than the %zu of the no-allocation "
@@ -1480,7 +1746,8 @@ int mesh_sdd_solve_interfaces_noalloc(mesh_sdd *inst, const mesh_sdd_step *step,
     Arena arena;
     arena.base = static_cast<char *>(base);
     arena.size = msdd_rt::scratch_capacity();
-    inst->inflight.fetch_add(1);
+    InflightHold hold;
+    hold.add(inst);
     rc = stage_request(*r, step, &arena);
     double ms = 0.0;
     if (rc == MESH_SDD_OK) {
@@ -1496,16 +1763,17 @@ int mesh_sdd_solve_interfaces_noalloc(mesh_sdd *inst, const mesh_sdd_step *step,
     }
     if (rc == MESH_SDD_OK) rc = finalize_request(ctx, *r, result);
     release_request_buffers(*r);   // frees nothing: every piece is the arena's
-    inst->inflight.fetch_sub(1);
     if (rc != MESH_SDD_OK) return rc;
     result->executed_path_steps = r->executed_steps;
     result->paths_per_node = r->N;
     result->device_ms = ms;
     return MESH_SDD_OK;
+} catch (...) {
+    return abi_exception();
 }
 
 int mesh_sdd_submit(mesh_sdd *inst, const mesh_sdd_step *step, mesh_sdd_ticket *ticket)
-{
+try {
     if (!inst || !ticket) return fail(MESH_SDD_E_INVAL, "NULL argument");
     if (!inst->monitor_set) return fail(MESH_SDD_E_STATE, "set_monitor not called");
     int64_t N = 0;
@@ -1534,14 +1802,21 @@ int mesh_sdd_submit(mesh_sdd *inst, const mesh_sdd_step *step, mesh_sdd_ticket *
             return fail(MESH_SDD_E_BUDGET, "request needs %zu B, budget is %zu B", r->cost_bytes, ctx->budget);
         r->ticket = ctx->next_ticket++;
         r->t_submit = Clock::now();
-        inst->inflight.fetch_add(1);
         ctx->tickets[r->ticket] = r;
-        ctx->queue.push_back(r);
+        try {
+            ctx->queue.push_back(r);
+        } catch (...) {
+            ctx->tickets.erase(r->ticket);
+            throw;
+        }
+        inst->inflight.fetch_add(1);   // released by finish_request
         ++ctx->submitted;
         *ticket = r->ticket;
     }
     ctx->cv.notify_all();
     return MESH_SDD_OK;
+} catch (...) {
+    return abi_exception();
 }
 
 static int poll_impl(mesh_sdd_ctx *ctx, mesh_sdd_ticket ticket, mesh_sdd_result *result, int64_t timeout_ms)
@@ -1568,17 +1843,21 @@ static int poll_impl(mesh_sdd_ctx *ctx, mesh_sdd_ticket ticket, mesh_sdd_result 
 }
 
 int mesh_sdd_poll(mesh_sdd_ctx *ctx, mesh_sdd_ticket ticket, mesh_sdd_result *result)
-{
+try {
     return poll_impl(ctx, ticket, result, 0);
+} catch (...) {
+    return abi_exception();
 }
 
 int mesh_sdd_wait(mesh_sdd_ctx *ctx, mesh_sdd_ticket ticket, mesh_sdd_result *result, int64_t timeout_ms)
-{
+try {
     return poll_impl(ctx, ticket, result, timeout_ms);
+} catch (...) {
+    return abi_exception();
 }
 
 int mesh_sdd_cancel(mesh_sdd_ctx *ctx, mesh_sdd_ticket ticket)
-{
+try {
     if (!ctx) return fail(MESH_SDD_E_INVAL, "ctx is NULL");
     std::lock_guard<std::mutex> lk(ctx->mu);
     auto it = ctx->tickets.find(ticket);
@@ -1590,75 +1869,216 @@ int mesh_sdd_cancel(mesh_sdd_ctx *ctx, mesh_sdd_ticket ticket)
     ctx->queue.erase(q);
     finish_request(ctx, r, MESH_SDD_E_CANCELLED, "cancelled");
     return MESH_SDD_OK;
+} catch (...) {
+    return abi_exception();
 }
 
 int mesh_sdd_autotune(mesh_sdd *inst, const mesh_sdd_step *step, mesh_sdd_launch *out)
-{
+try {
     if (!inst || !step) return fail(MESH_SDD_E_INVAL, "NULL argument");
     if (!inst->monitor_set) return fail(MESH_SDD_E_STATE, "set_monitor not called");
-    if (inst->d.precision != MESH_SDD_FP32) return fail(MESH_SDD_E_INVAL, "autotuning applies to the FP32 kernel");
+    if (inst->d.precision != MESH_SDD_FP32) return fail(MESH_SDD_E_INVAL, "autotuning applies to the FP32 kernels");
     int64_t N = 0;
     int rc = validate_step(*inst, step, &N);
     if (rc != MESH_SDD_OK) return rc;
-    mesh_sdd_ctx *ctx = inst->ctx;
-    // candidates: residency x chunk size, timed on a reduced path count
-    const int blocks[] = {256};
-    const int chunks[] = {128, 256, 512, 1024};
-    std::vector<int> waves = {2, 3, 4, 5, 6, 8};
-    mesh_sdd_step s = *step;
-    s.target_se = 0.0;
-    s.paths_per_node = std::min<int64_t>(N, std::max<int64_t>(4096, 2000000 / std::max(1, inst->M)));
-    double best = 1e300;
-    mesh_sdd_launch best_l = default_launch();
-    bool saved_override;
-    mesh_sdd_launch saved_l;
-    {
-        std::lock_guard<std::mutex> lk(ctx->mu);
-        saved_override = ctx->has_override;
-        saved_l = ctx->override_launch;
+    mesh_sdd_launch best{};
+    rc = tune_bucket(inst, *step, N, &best);
+    if (rc != MESH_SDD_OK) return rc;
+    if (out) *out = best;
+    return MESH_SDD_OK;
+} catch (...) {
+    return abi_exception();
+}
+
+int mesh_sdd_autotune_batch(mesh_sdd *const *insts, const mesh_sdd_step *steps, int32_t count, int32_t scale_down,
+                            mesh_sdd_launch *out)
+try {
+    if (count <= 0 || !insts || !steps || scale_down < 1) return fail(MESH_SDD_E_INVAL, "bad batch arguments");
+    mesh_sdd_ctx *ctx = insts[0] ? insts[0]->ctx : nullptr;
+    if (!ctx) return fail(MESH_SDD_E_INVAL, "instance is NULL");
+    std::vector<int64_t> Ns((size_t)count);
+    for (int32_t q = 0; q < count; ++q) {
+        mesh_sdd *inst = insts[q];
+        if (!inst || inst->ctx != ctx) return fail(MESH_SDD_E_INVAL, "instance %d is NULL or of another context", q);
+        if (!inst->monitor_set) return fail(MESH_SDD_E_STATE, "set_monitor not called on instance %d", q);
+        if (inst->d.precision != MESH_SDD_FP32) return fail(MESH_SDD_E_INVAL, "instance %d is not FP32", q);
+        int rc = validate_step(*inst, &steps[q], &Ns[(size_t)q]);
+        if (rc != MESH_SDD_OK) return rc;
     }
-    for (int b : blocks)
-        for (int c : chunks)
-            for (int w : waves) {
-                mesh_sdd_launch l = default_launch();
-                l.block = b;
-                l.chunk_paths = c;
-                l.waves_per_simd = w;
-                // skip shapes whose registers or LDS do not allow w waves per SIMD
-                if (msdd::paths_fp32_blocks_per_cu(b, (uint32_t)c) * (b / 64) < w * 4) continue;
-                {
-                    std::lock_guard<std::mutex> lk(ctx->mu);
-                    ctx->override_launch = l;
-                    ctx->has_override = true;
-                }
-                std::vector<std::shared_ptr<Request>> reqs{make_request(inst, s, s.paths_per_node)};
-                std::vector<const mesh_sdd_step *> ds{s.inputs_on_device ? &s : nullptr};
-                std::vector<int> st;
-                inst->inflight.fetch_add(1);
-                rc = run_blocking(ctx, reqs, ds, st);
-                inst->inflight.fetch_sub(1);
-                if (rc != MESH_SDD_OK) break;
-                const double rate_ms = reqs[0]->device_ms / std::max<double>(1.0, (double)reqs[0]->executed_steps);
-                if (rate_ms < best) {
-                    best = rate_ms;
-                    best_l = l;
-                }
-            }
+    // 1. each bucket on its first instance
+    std::map<TuneKey, int32_t> first;
+    for (int32_t q = 0; q < count; ++q) {
+        const mesh_sdd_desc &d = insts[q]->d;
+        first.emplace(TuneKey{d.n_xi, d.n_eta, d.periodic_xi, d.periodic_eta}, q);
+    }
+    for (auto &kv : first) {
+        mesh_sdd_launch b{};
+        int rc = tune_bucket(insts[kv.second], steps[kv.second], Ns[(size_t)kv.second], &b);
+        if (rc != MESH_SDD_OK) return rc;
+    }
+    // 2. the launch-wide knobs on the whole batch at reduced path counts
+    std::vector<mesh_sdd_step> small(steps, steps + count);
+    for (int32_t q = 0; q < count; ++q) {
+        small[(size_t)q].target_se = 0.0;
+        small[(size_t)q].paths_per_node = std::max<int64_t>(64, Ns[(size_t)q] / scale_down / 64 * 64);
+    }
+    bool saved_has;
+    mesh_sdd_launch saved;
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
-        ctx->has_override = saved_override;
-        ctx->override_launch = saved_l;
-        if (rc == MESH_SDD_OK)
-            ctx->tuned[TuneKey{inst->d.n_xi, inst->d.n_eta, inst->d.periodic_xi, inst->d.periodic_eta}] = best_l;
+        saved_has = ctx->has_batch_tuned;
+        saved = ctx->batch_tuned;
+    }
+    auto time_batch = [&](const mesh_sdd_launch &l, double *ms_per_step) -> int {
+        {
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            ctx->batch_tuned = l;
+            ctx->has_batch_tuned = true;
+        }
+        std::vector<std::shared_ptr<Request>> reqs;
+        std::vector<const mesh_sdd_step *> ds;
+        InflightHold hold;
+        for (int32_t q = 0; q < count; ++q) {
+            reqs.push_back(make_request(insts[q], small[(size_t)q], small[(size_t)q].paths_per_node));
+            ds.push_back(small[(size_t)q].inputs_on_device ? &small[(size_t)q] : nullptr);
+            hold.add(insts[q]);
+        }
+        std::vector<int> st;
+        const int rc = run_blocking(ctx, reqs, ds, st);
+        if (rc != MESH_SDD_OK) return rc;
+        double ms = 0.0, steps_done = 0.0;
+        for (auto &r : reqs) steps_done += (double)r->executed_steps;
+        ms = reqs.empty() ? 0.0 : reqs[0]->device_ms;   // one launch: the same device time for each
+        *ms_per_step = ms / std::max(1.0, steps_done);
+        return MESH_SDD_OK;
+    };
+    mesh_sdd_launch best = saved_has ? with_defaults(saved) : default_launch();
+    double best_t = 0.0, t = 0.0;
+    int rc = time_batch(best, &t);   // warm-up
+    if (rc == MESH_SDD_OK) rc = time_batch(best, &best_t);
+    const std::vector<std::pair<int32_t mesh_sdd_launch::*, std::vector<int32_t>>> knobs = {
+        {&mesh_sdd_launch::job_split, {8, 32, 128, 256, 1024}},
+        {&mesh_sdd_launch::refill_lanes, {48, 56, 60}},
+        {&mesh_sdd_launch::max_quarters, {8, 16, 32}},
+    };
+    for (size_t k = 0; k < knobs.size() && rc == MESH_SDD_OK; ++k)
+        for (int32_t v : knobs[k].second) {
+            if (best.*(knobs[k].first) == v) continue;
+            mesh_sdd_launch c = best;
+            c.*(knobs[k].first) = v;
+            rc = time_batch(c, &t);
+            if (rc != MESH_SDD_OK) break;
+            if (t < best_t * (1.0 - kTuneMargin)) {
+                best = c;
+                best_t = t;
+            }
+        }
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        if (rc == MESH_SDD_OK) {
+            ctx->batch_tuned = best;
+            ctx->has_batch_tuned = true;
+        } else {
+            ctx->batch_tuned = saved;
+            ctx->has_batch_tuned = saved_has;
+        }
     }
     if (rc != MESH_SDD_OK) return rc;
-    if (out) *out = best_l;
+    if (out) *out = best;
     return MESH_SDD_OK;
+} catch (...) {
+    return abi_exception();
+}
+
+int mesh_sdd_tune_save(mesh_sdd_ctx *ctx, const char *path)
+try {
+    if (!ctx || !path) return fail(MESH_SDD_E_INVAL, "NULL argument");
+    std::string text = "# mesh_sdd tuned launch shapes: key n_xi n_eta per_xi per_eta chunk_paths refill_lanes "
+                       "max_quarters window_kind window_margin job_split\n";
+    char line[256];
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        for (auto &kv : ctx->tuned) {
+            const mesh_sdd_launch &l = kv.second;
+            std::snprintf(line, sizeof line, "bucket %d %d %d %d %d %d %d %d %d %d\n", kv.first.n_xi, kv.first.n_eta,
+                          kv.first.per_xi, kv.first.per_eta, l.chunk_paths, l.refill_lanes, l.max_quarters,
+                          l.window_kind, l.window_margin, l.job_split);
+            text += line;
+        }
+        if (ctx->has_batch_tuned) {
+            const mesh_sdd_launch &l = ctx->batch_tuned;
+            std::snprintf(line, sizeof line, "batch 0 0 0 0 %d %d %d %d %d %d\n", l.chunk_paths, l.refill_lanes,
+                          l.max_quarters, l.window_kind, l.window_margin, l.job_split);
+            text += line;
+        }
+    }
+    FILE *f = std::fopen(path, "w");
+    if (!f) return fail(MESH_SDD_E_INVAL, "cannot write %s", path);
+    const bool ok = std::fwrite(text.data(), 1, text.size(), f) == text.size();
+    if (std::fclose(f) != 0 || !ok) return fail(MESH_SDD_E_INVAL, "cannot write %s", path);
+    return MESH_SDD_OK;
+} catch (...) {
+    return abi_exception();
+}
+
+int mesh_sdd_tune_load(mesh_sdd_ctx *ctx, const char *path)
+try {
+    if (!ctx || !path) return fail(MESH_SDD_E_INVAL, "NULL argument");
+    FILE *f = std::fopen(path, "r");
+    if (!f) return fail(MESH_SDD_E_INVAL, "cannot read %s", path);
+    std::vector<std::pair<TuneKey, mesh_sdd_launch>> buckets;
+    bool have_batch = false;
+    mesh_sdd_launch batch{};
+    char buf[512];
+    int lineno = 0, rc = MESH_SDD_OK;
+    while (std::fgets(buf, sizeof buf, f)) {
+        ++lineno;
+        if (buf[0] == '#' || buf[0] == '\n') continue;
+        char key[16];
+        int v[10];
+        if (std::sscanf(buf, "%15s %d %d %d %d %d %d %d %d %d %d", key, &v[0], &v[1], &v[2], &v[3], &v[4], &v[5],
+                        &v[6], &v[7], &v[8], &v[9]) != 11) {
+            rc = fail(MESH_SDD_E_INVAL, "%s:%d: expected a key and ten integers", path, lineno);
+            break;
+        }
+        mesh_sdd_launch l = default_launch();
+        l.chunk_paths = v[4];
+        l.refill_lanes = v[5];
+        l.max_quarters = v[6];
+        l.window_kind = v[7];
+        l.window_margin = v[8];
+        l.job_split = v[9];
+        rc = check_launch(&l);
+        if (rc != MESH_SDD_OK) {
+            rc = fail(MESH_SDD_E_INVAL, "%s:%d: %s", path, lineno, g_last_error.c_str());
+            break;
+        }
+        if (std::strcmp(key, "bucket") == 0) {
+            buckets.emplace_back(TuneKey{v[0], v[1], v[2], v[3]}, with_defaults(l));
+        } else if (std::strcmp(key, "batch") == 0) {
+            have_batch = true;
+            batch = with_defaults(l);
+        } else {
+            rc = fail(MESH_SDD_E_INVAL, "%s:%d: unknown key '%s'", path, lineno, key);
+            break;
+        }
+    }
+    std::fclose(f);
+    if (rc != MESH_SDD_OK) return rc;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    for (auto &b : buckets) ctx->tuned[b.first] = b.second;
+    if (have_batch) {
+        ctx->batch_tuned = batch;
+        ctx->has_batch_tuned = true;
+    }
+    return MESH_SDD_OK;
+} catch (...) {
+    return abi_exception();
 }
 
 int mesh_sdd_debug_paths(mesh_sdd *inst, const mesh_sdd_step *step, int32_t node_rank, int64_t p_begin, int64_t p_end,
                          double *vx, double *vy, int32_t *exited, int32_t *side, int32_t *steps, double *trace)
-{
+try {
     if (!inst || !step || !vx || !vy || !exited || !side || !steps) return fail(MESH_SDD_E_INVAL, "NULL argument");
     if (!inst->monitor_set) return fail(MESH_SDD_E_STATE, "set_monitor not called");
     if (node_rank < 0 || node_rank >= inst->M) return fail(MESH_SDD_E_INVAL, "node rank %d outside [0, %d)", node_rank, inst->M);
@@ -1673,7 +2093,8 @@ int mesh_sdd_debug_paths(mesh_sdd *inst, const mesh_sdd_step *step, int32_t node
     full.interface_stride = 0;   // node_rank indexes the full node lists
     auto r = make_request(inst, full, std::max<int64_t>(1, count));
     std::lock_guard<std::mutex> g(ctx->gpu_mu);
-    inst->inflight.fetch_add(1);
+    InflightHold hold;
+    hold.add(inst);
     rc = stage_request(*r, step->inputs_on_device ? step : nullptr);
     DevBuf dvx, dvy, dex, dsd, dst, dtr;
     if (rc == MESH_SDD_OK && count) {
@@ -1702,8 +2123,9 @@ int mesh_sdd_debug_paths(mesh_sdd *inst, const mesh_sdd_step *step, int32_t node
         }
     }
     release_request_buffers(*r);
-    inst->inflight.fetch_sub(1);
     return rc;
+} catch (...) {
+    return abi_exception();
 }
 
 }  // extern "C"

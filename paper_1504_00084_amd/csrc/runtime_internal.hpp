@@ -30,6 +30,12 @@ namespace msdd_rt {
 // returns `code`.
 int fail(int code, const char *fmt, ...);
 
+// Status of an exception caught at the C-ABI (called inside a catch block):
+// E_NOMEM for a failed host allocation (std::bad_alloc) or any other
+// exhausted host resource (e.g. a thread that cannot be started).  No
+// exception crosses the ABI.
+int abi_exception() noexcept;
+
 #define HIP_TRY(expr)                                                                                     \
     do {                                                                                                  \
         hipError_t e_ = (expr);                                                                           \
@@ -71,10 +77,15 @@ struct DevPool {
         }
         return p;
     }
-    void put(void *p, size_t n)
+    void put(void *p, size_t n) noexcept   // called from destructors: never throws
     {
         std::lock_guard<std::mutex> g(mu);
-        free_blocks.emplace(n, p);
+        try {
+            free_blocks.emplace(n, p);
+        } catch (...) {   // no host memory for the pool's bookkeeping: free the block
+            (void)hipFree(p);
+            return;
+        }
         pooled += n;
         while (pooled > cap && !free_blocks.empty()) {
             auto it = free_blocks.begin();
@@ -168,6 +179,30 @@ struct DevBuf {
 
 inline size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// The two timing events of a launch, destroyed on every way out of the scope.
+struct TimerEvents {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    TimerEvents() = default;
+    TimerEvents(const TimerEvents &) = delete;
+    TimerEvents &operator=(const TimerEvents &) = delete;
+    hipError_t create()
+    {
+        hipError_t e = hipEventCreate(&e0);
+        if (e != hipSuccess) {
+            e0 = nullptr;
+            return e;
+        }
+        e = hipEventCreate(&e1);
+        if (e != hipSuccess) e1 = nullptr;
+        return e;
+    }
+    ~TimerEvents()
+    {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    }
+};
+
 }  // namespace msdd_rt
 
 using msdd_rt::Clock;
@@ -199,6 +234,7 @@ struct BlockRun {
 // stream and result slot, so the order does not change any result.
 struct SampleSet {
     int stride = 1;
+    int kind = 0, margin = 0;            // block layout: window kind and margin (see BlockRun)
     int32_t Ms = 0;
     DevBuf lists;
     std::vector<BlockRun> blocks;        // covers positions [0, Ms) in order
@@ -213,14 +249,17 @@ struct mesh_sdd {
     mesh_sdd_desc d{};
     int32_t M = 0;
     std::vector<int32_t> node_i, node_j;
-    // sample sets by stride; stride 1 is built at create, the others on
-    // first use (under ctx->gpu_mu), and all live until destroy
-    std::map<int, std::unique_ptr<SampleSet>> samples;
+    // sample sets by (stride, window kind, window margin): the stride-1 set
+    // of the default layout is built at create, the others on first use
+    // (under ctx->gpu_mu), and all live until destroy -- a staged request
+    // keeps a pointer to its set, so a set is never rebuilt in place
+    std::map<std::tuple<int, int, int>, std::unique_ptr<SampleSet>> samples;
     DevBuf rho_in, rho, rho_xi, rho_eta;    // FP64 monitor staging and node tables
     DevBuf rho_f, rhox_f;                   // FP32 node tables of rho and dt rho_xi (staged in LDS whole
                                             // or in windows)
-    DevBuf cells;                           // FP32 per-cell records (rho and rho_xi corners, rho_eta coefficients)
-    DevBuf coef_y;                          // FP32 rho_eta coefficients alone, one float4 per cell
+    DevBuf cells;                           // FP32 cell data: the dt rho_eta coefficients alone (one float4 per
+                                            // cell), then the 48-B records (rho and dt rho_xi corners, the
+                                            // coefficients again); one allocation, below 2^32 bytes
     DevBuf node_rank;                       // [n_eta][n_xi] interface rank or -1
     DevBuf node_ij;                         // interface nodes in rank order: i[M], then j[M]
     bool monitor_set = false;
@@ -261,6 +300,22 @@ struct Request {
     bool cancelled = false;
 };
 
+// Holds one in-flight count on each instance added, for the duration of a
+// blocking call: released when the hold goes out of scope, also when the call
+// leaves by an exception (the count never leaks, so destroy never blocks).
+struct InflightHold {
+    std::vector<mesh_sdd *> held;
+    void add(mesh_sdd *i)
+    {
+        held.push_back(i);   // may throw: then nothing was counted
+        i->inflight.fetch_add(1);
+    }
+    ~InflightHold()
+    {
+        for (mesh_sdd *i : held) i->inflight.fetch_sub(1);
+    }
+};
+
 struct TuneKey {
     int n_xi, n_eta, per_xi, per_eta;
     bool operator<(const TuneKey &o) const
@@ -298,10 +353,14 @@ struct mesh_sdd_ctx {
     double busy_ms = 0.0;
     std::vector<double> latencies;
 
-    // launch shapes
+    // launch shapes: a fixed override, the tuned shape per bucket (launches of
+    // one instance, and the per-instance knobs everywhere), and the tuned
+    // launch-wide knobs of multi-instance launches
     bool has_override = false;
     mesh_sdd_launch override_launch{};
     std::map<TuneKey, mesh_sdd_launch> tuned;
+    bool has_batch_tuned = false;
+    mesh_sdd_launch batch_tuned{};
 };
 
 namespace msdd_rt {

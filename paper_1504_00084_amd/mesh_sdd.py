@@ -33,7 +33,7 @@ EXPORTS = (
     "mesh_sdd_desc_interface_nodes", "mesh_sdd_edge_generate", "mesh_sdd_subdomain_solve",
     "mesh_sdd_single_domain_solve", "mesh_sdd_mp_step", "mesh_sdd_set_monitor_arclength", "mesh_sdd_get_monitor",
     "mesh_sdd_mesh_quality", "mesh_sdd_transfer_field", "mesh_sdd_desc_work_order",
-    "mesh_sdd_solve_interfaces_noalloc",
+    "mesh_sdd_solve_interfaces_noalloc", "mesh_sdd_autotune_batch", "mesh_sdd_tune_save", "mesh_sdd_tune_load",
 )
 
 
@@ -85,7 +85,12 @@ class Stats(ctypes.Structure):
 
 class Launch(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("block", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32),
-                ("chunk_paths", ctypes.c_int32), ("monitor_table", ctypes.c_int32), ("table_level", ctypes.c_int32)]
+                ("chunk_paths", ctypes.c_int32), ("monitor_table", ctypes.c_int32), ("table_level", ctypes.c_int32),
+                ("refill_lanes", ctypes.c_int32), ("max_quarters", ctypes.c_int32), ("window_kind", ctypes.c_int32),
+                ("window_margin", ctypes.c_int32), ("job_split", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {k: int(getattr(self, k)) for k, _ in self._fields_ if k != "struct_size"}
 
 
 _lib = None
@@ -115,6 +120,9 @@ def load(path: str = LIB_PATH):
         "mesh_sdd_set_launch": [vp, P(Launch)],
         "mesh_sdd_get_launch": [vp, P(Launch)],
         "mesh_sdd_autotune": [vp, P(Step), P(Launch)],
+        "mesh_sdd_autotune_batch": [P(vp), P(Step), i32, i32, P(Launch)],
+        "mesh_sdd_tune_save": [vp, ctypes.c_char_p],
+        "mesh_sdd_tune_load": [vp, ctypes.c_char_p],
         "mesh_sdd_create": [vp, P(Desc), P(vp)],
         "mesh_sdd_destroy": [vp],
         "mesh_sdd_set_monitor": [vp, vp, ctypes.c_int],
@@ -215,14 +223,34 @@ def mesh_sdd_get_launch(inst) -> Launch:
     return lo
 
 
-def make_launch(block=256, waves_per_simd=3, chunk_paths=128, monitor_table=0) -> Launch:
-    return Launch(ctypes.sizeof(Launch), block, waves_per_simd, chunk_paths, monitor_table, 0)
+def make_launch(block=256, waves_per_simd=3, chunk_paths=128, monitor_table=0, refill_lanes=0, max_quarters=0,
+                window_kind=0, window_margin=0, job_split=0) -> Launch:
+    """Launch shape; 0 in the last five fields means the library's default."""
+    return Launch(ctypes.sizeof(Launch), block, waves_per_simd, chunk_paths, monitor_table, 0, refill_lanes,
+                  max_quarters, window_kind, window_margin, job_split)
 
 
 def mesh_sdd_autotune(inst, step: Step) -> Launch:
     lo = Launch(struct_size=ctypes.sizeof(Launch))
     _check(load().mesh_sdd_autotune(inst, ctypes.byref(step), ctypes.byref(lo)))
     return lo
+
+
+def mesh_sdd_autotune_batch(insts, steps, scale_down: int = 50) -> Launch:
+    n = len(insts)
+    arr_i = (ctypes.c_void_p * n)(*insts)
+    arr_s = (Step * n)(*steps)
+    lo = Launch(struct_size=ctypes.sizeof(Launch))
+    _check(load().mesh_sdd_autotune_batch(arr_i, arr_s, n, int(scale_down), ctypes.byref(lo)))
+    return lo
+
+
+def mesh_sdd_tune_save(ctx, path: str) -> None:
+    _check(load().mesh_sdd_tune_save(ctx, os.fsencode(path)))
+
+
+def mesh_sdd_tune_load(ctx, path: str) -> None:
+    _check(load().mesh_sdd_tune_load(ctx, os.fsencode(path)))
 
 
 def make_desc(n_xi, n_eta, sub_xi, sub_eta, periodic_xi=0, periodic_eta=0, K=500, Lx=1.0, Ly=1.0, tau=0.01,

@@ -39,7 +39,7 @@ def run_full(M, ctx, inst, precision, tune=True):
                          mesh_step=inst.mesh_step)
         if tune and precision == M.FP32:
             lo = M.mesh_sdd_autotune(h, st)
-            say("autotuned: block %d waves/SIMD %d chunk %d" % (lo.block, lo.waves_per_simd, lo.chunk_paths))
+            say("autotuned: %s" % lo.as_dict())
         M.mesh_sdd_solve_interfaces(h, st, res)
         return M.result_dict(arrs, res, m)
     finally:

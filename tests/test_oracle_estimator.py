@@ -359,40 +359,33 @@ def test_fd_single_domain_reference_sharp_bump(oracle_lib):
     assert np.mean(z ** 2) < 1.6, np.mean(z ** 2)
 
 
-def test_rounding_probe_is_a_rounding_sized_perturbation(oracle_lib):
-    """The sensitivity probe used by the GPU audits (each substep's position
-    rounded to binary32) must perturb a path by rounding and nothing else:
-    with a constant monitor there is no drift to amplify it, so every path
-    keeps its exit decisions (bar one whose exit test sits within rounding
-    of the side) and its end moves by at most K half-ulps of positions
-    below 1 (2^-25 each) times the mesh's slope (a uniform mesh on
-    [0, 2] x [0, 3] here), and at K = 500 on 33^2 to 513^2 by less than
-    1.5e-6; on the sharp 257^2 front the same probe moves a path crossing
-    the front by orders of magnitude more."""
-    inst = W.constant_problem(33, 2, 0, 0, tau=0.05, K=200, n_paths=512, Lx=2.0, Ly=3.0)
-    P = oracle_lib.Problem(**inst.problem_kwargs())
-    args = (P, inst.rho, inst.x, inst.y, inst.bnd_t0, inst.bnd_t1)
-    worst, flips = 0.0, 0
-    for node in (0, 17, 40):
-        o = oracle_lib.paths(*args, node, 0, inst.n_paths)
-        q = oracle_lib.paths(*args, node, 0, inst.n_paths, round_f32=True)
-        same = (o["side"] == q["side"]) & (o["steps"] == q["steps"])
-        flips += int(np.sum(~same))
-        worst = max(worst, float(np.max(np.maximum(np.abs(o["vx"] - q["vx"]), np.abs(o["vy"] - q["vy"]))[same])))
-    assert flips <= 1 and 0.0 < worst <= inst.K * 2.0 ** -25 * 3.0, (flips, worst)
-    # the GPU audits call a path sensitive when the probe moves it by 2e-6: without drift, at the
-    # workloads' K = 500 and grid sizes, no path comes near that
-    for n in (33, 257, 513):
-        flat = W.constant_problem(n, 2, 1, 0, tau=0.01, K=500, n_paths=1024)
-        P = oracle_lib.Problem(**flat.problem_kwargs())
-        args = (P, flat.rho, flat.x, flat.y, flat.bnd_t0, flat.bnd_t1, 3, 0, 1024)
-        o, q = oracle_lib.paths(*args), oracle_lib.paths(*args, round_f32=True)
-        same = o["steps"] == q["steps"]
-        moved = np.maximum(np.abs(o["vx"] - q["vx"]), np.abs(o["vy"] - q["vy"]))[same]
-        assert float(np.max(moved)) < 1.5e-6, (n, float(np.max(moved)))
-    front = W.config3(n_paths=1024)
-    P = oracle_lib.Problem(**front.problem_kwargs())
-    args = (P, front.rho, front.x, front.y, front.bnd_t0, front.bnd_t1, 2208, 0, 1024)
-    o, q = oracle_lib.paths(*args), oracle_lib.paths(*args, round_f32=True)
-    moved = np.maximum(np.abs(o["vx"] - q["vx"]), np.abs(o["vy"] - q["vy"]))
-    assert float(np.max(moved)) > 1e-2 and float(np.median(moved)) < 1e-6
+def test_path_amplification_closed_forms(oracle_lib):
+    """The rounding amplification used by the GPU audits (linearised: the
+    end point's standard deviation per unit per-substep perturbation).
+    Without drift every substep's Jacobian is I, so a path of s substeps has
+    exactly sqrt(s).  With rho = exp(a (xi - 1/2)^2 / 2) the drift is
+    b = (a (xi - 1/2), 0), every Jacobian diag(1 + dt a, 1), and
+    amp^2 = (sum_{m<s} (1 + dt a)^{2m} + s) / 2 -- up to the finite
+    differences and the bilinear interpolant of rho and rho_xi (first order
+    in h for the derivative, 257^2 here): growth for a > 0, contraction for
+    a < 0, so a wrong sign or a dropped or misplaced term fails."""
+    flat = W.constant_problem(33, 2, 1, 0, tau=0.01, K=500, n_paths=256)
+    P = oracle_lib.Problem(**flat.problem_kwargs())
+    args = (P, flat.rho, flat.x, flat.y, flat.bnd_t0, flat.bnd_t1, 3, 0, 256)
+    amp, o = oracle_lib.path_amplification(*args), oracle_lib.paths(*args)
+    assert np.allclose(amp, np.sqrt(o["steps"]), rtol=0, atol=1e-12)
+    n, tau, K = 257, 0.05, 500
+    dt = tau / K
+    xi = np.linspace(0.0, 1.0, n)
+    for a in (20.0, -20.0):
+        rho = np.tile(np.exp(a * (xi - 0.5) ** 2 / 2.0), (n, 1))
+        inst = W.constant_problem(n, 2, 0, 0, tau=tau, K=K, n_paths=256)
+        P = oracle_lib.Problem(**inst.problem_kwargs())
+        args = (P, rho, inst.x, inst.y, inst.bnd_t0, inst.bnd_t1, 100, 0, 256)
+        amp, o = oracle_lib.path_amplification(*args), oracle_lib.paths(*args)
+        g = (1.0 + dt * a) ** 2
+        want = np.sqrt(0.5 * ((g ** o["steps"] - 1.0) / (g - 1.0) + o["steps"]))
+        assert np.allclose(amp, want, rtol=2e-3), (a, float(np.max(np.abs(amp / want - 1.0))))
+        long = o["steps"] == K
+        assert np.any(long)
+        assert (np.all(amp[long] > np.sqrt(K) * 1.3) if a > 0 else np.all(amp[long] < np.sqrt(K) * 0.95))
