@@ -54,8 +54,8 @@ def w_slots(per_xi: int, per_eta: int) -> float:
 # scaled by what the counter reads for a 1 GiB device copy in the same run.
 # Valid only for the kernel code it was measured on (kernels_sha1: SHA-1 of
 # csrc/kernels.hip without comments) and the workload named; null otherwise.
-TRAFFIC_RECORD = {"workload": None, "kernels_sha1": None, "fetch_kib": 0.0, "write_kib": 0.0,
-                  "fetch_scale": 1.0, "write_scale": 1.0}
+TRAFFIC_RECORD = {"workload": "front257_8x8_perx", "kernels_sha1": "e5521e028646bb1b32d8c28fb230627fcfb586bf",
+                  "fetch_kib": 152920.0, "write_kib": 4290150.0, "fetch_scale": 2.0, "write_scale": 1.0}
 
 
 def kernels_code_sha1():
@@ -167,6 +167,10 @@ def parse():
                     help="comma-separated grid sizes: keep only the mix's instances of these sizes (batch mode)")
     ap.add_argument("--requests", type=int, default=40, help="measured requests of the serve mode")
     ap.add_argument("--serve-warmup", type=int, default=4, help="requests before the measured ones (serve mode)")
+    ap.add_argument("--fp64-requests", type=int, default=0,
+                    help="serve mode, FP64 leg: measured requests (0: as --requests)")
+    ap.add_argument("--fp64-warmup", type=int, default=-1,
+                    help="serve mode, FP64 leg: warm-up requests (-1: as --serve-warmup)")
     ap.add_argument("--rate", type=float, default=0.0,
                     help="arrival rate in req/s for serve mode (0: 0.7 x the measured capacity)")
     ap.add_argument("--capacity", type=float, default=0.0,
@@ -578,22 +582,51 @@ def serve_measure(requests: int, warmup: int, precision: str, sizes, max_paths: 
             "budget_mb": budget_mb or None}
 
 
+def fp64_capacity(count: int = 8, scale: float = 0.02) -> float:
+    """Nominal path-steps/s of the FP64 plain path (one launch per instance)
+    on the mix's first `count` instances at `scale` of their path counts,
+    solved one after the other as the serving scheduler runs FP64 work."""
+    from paper_1504_00084_amd import mesh_sdd as M
+    from paper_1504_00084_amd import workloads as W
+
+    M.load()
+    insts = W.config4(count=64)[:count]
+    ctx = new_ctx(M, 0)
+    nominal = 0
+    t = time.perf_counter()
+    for it in insts:
+        n = max(64, int(it.n_paths * scale) // 64 * 64)
+        r = M.solve_instance(ctx, it, M.FP64, n_paths=n)
+        nominal += len(r["mean_x"]) * n * it.K
+    wall = time.perf_counter() - t
+    M.mesh_sdd_ctx_destroy(ctx)
+    log("fp64 capacity probe: %d instances at %.2f of their paths, %.3e nominal path-steps/s"
+        % (len(insts), scale, nominal / wall))
+    return nominal / wall
+
+
 def run_serve(args):
     sizes = [int(v) for v in args.serve_sizes.split(",")]
-    cap = args.capacity
-    if args.rate <= 0.0 and cap <= 0.0:
-        m = batch_measure(0.05, 64, "", label="capacity probe (mix at 1/20 of its paths)")
-        cap = m["nominal_path_steps"] / m["wall_s"]
     precs = ["fp32", "fp64"] if args.serve_precision == "both" else [args.serve_precision]
+    caps = {}
+    for p in precs:   # measured capacities behind the 0.7 x rates (unless given)
+        if args.rate > 0.0 or args.capacity > 0.0:
+            caps[p] = args.capacity
+        elif p == "fp32":
+            m = batch_measure(0.05, 64, "", label="capacity probe (mix at 1/20 of its paths)")
+            caps[p] = m["nominal_path_steps"] / m["wall_s"]
+        else:
+            caps[p] = fp64_capacity()
     line = {"metric": "serving p50/p99 latency and throughput (Poisson stream of the batched mix)"}
     for p in precs:
-        c = cap if p == "fp32" else cap / 6.0 if args.capacity <= 0.0 else cap
-        line[p] = serve_measure(args.requests, args.serve_warmup, p, sizes, args.serve_max_paths, args.rate,
-                                args.budget_mb, capacity=c, launch=args.launch, jsonl=args.jsonl)
+        n_req = args.requests if p == "fp32" or args.fp64_requests <= 0 else args.fp64_requests
+        n_warm = args.serve_warmup if p == "fp32" or args.fp64_warmup < 0 else args.fp64_warmup
+        line[p] = serve_measure(n_req, n_warm, p, sizes, args.serve_max_paths, args.rate,
+                                args.budget_mb, capacity=caps[p], launch=args.launch, jsonl=args.jsonl)
         s = line[p]
+        line[p]["capacity_nominal_path_steps_s"] = caps[p]
         log("serving %s: %d requests at %.3f req/s: p50 %.1f ms, p99 %.1f ms, %.3e path-steps/s"
             % (p, s["requests"], s["rate_req_s"], s["p50_ms"], s["p99_ms"], s["throughput_path_steps_s"]))
-    line["capacity_nominal_path_steps_s"] = cap
     line["data"] = "synthetic"
     print(json.dumps(line), flush=True)
 
