@@ -167,8 +167,6 @@ __device__ __forceinline__ float side_distance(const ConstF &C, float x, float y
     return m;
 }
 
-// One EM substep of the FP32 path (a3-a6).  Returns the exit side (0: xi=0,
-// 1: xi=1, 2: eta=0, 3: eta=1) with the position moved onto it, or -1.
 // Bilinear interpolant from the four corner values of a cell.
 __device__ __forceinline__ float bilerp(float tx, float ty, float f00, float f10, float f01, float f11)
 {
@@ -185,6 +183,10 @@ struct Win {
     int i0, j0, tw, w1, h1, coff, tw8;   // tw8 = 8 tw: bytes per window row
 };
 
+// One EM substep of the FP32 path (a3-a6).  Returns the exit side (0: xi=0,
+// 1: xi=1, 2: eta=0, 3: eta=1), or -1; an exited path keeps the end of the
+// substep as its position (path_value_f32 moves it onto the side).
+//
 // TAB: where the corner values of rho and dt rho_xi come from.  0: the cell
 // record; 2: the LDS node table (rho, dt rho_xi interleaved); 3: the LDS
 // window when the cell lies inside it, else the cell record; 4: as 3, with
@@ -203,13 +205,19 @@ __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t w
     const float cs = __builtin_amdgcn_cosf(u1);
     const float sn = __builtin_amdgcn_sinf(u1);
 
-    // a4: bilinear interpolation of (rho, dt rho_xi, dt rho_eta) on the cell
-    // (x, y lie in [0, 1], so the truncation is the floor).
-    float tx, ty;
-    const int cx = min((int)(P.x * C.fnx1), C.nx1 - 1);
-    const int cy = min((int)(P.y * C.fny1), C.ny1 - 1);
-    tx = P.x * C.fnx1 - (float)cx;
-    ty = P.y * C.fny1 - (float)cy;
+    // a4: bilinear interpolation of (rho, dt rho_xi, dt rho_eta) on the cell.
+    // A coordinate lies in [0, 1) on a periodic axis (after the wrap) and in
+    // [0, 1] on a Dirichlet one; below 1 its product with the cell count c
+    // stays below c (the largest float below 1 times c rounds down, or is
+    // exact for a power of two), so the truncation is the cell and v_fract
+    // the local coordinate.  Exactly 1 on a Dirichlet side (a path that ends
+    // a substep there survives only if its bridge test, whose crossing
+    // probability is then 1, rounds below its uniform, or when the bridge is
+    // off) takes the last cell at local coordinate 0.
+    const float sx = P.x * C.fnx1, sy = P.y * C.fny1;
+    const int cx = C.per_xi ? (int)sx : min((int)sx, C.nx1 - 1);
+    const int cy = C.per_eta ? (int)sy : min((int)sy, C.ny1 - 1);
+    const float tx = __builtin_amdgcn_fractf(sx), ty = __builtin_amdgcn_fractf(sy);
     // 32-bit indices and byte offsets (a grid has at most 8193^2 nodes, 2^26
     // cells): each gather adds one lane offset to the scalar base of the cell
     // data, and the LDS address is one 24-bit multiply-add.  The record
@@ -297,25 +305,10 @@ __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t w
     const float m = side_distance(C, nx, ny);
     int side = -1;
     if (m < 0.0f) {
-        // endpoint outside; several sides out -> corner, first side crossed
-        if (!C.per_xi) {
-            if (nx < 0.0f) {
-                side = 0;
-                nx = 0.0f;
-            } else if (nx > 1.0f) {
-                side = 1;
-                nx = 1.0f;
-            }
-        }
-        if (!C.per_eta) {
-            if (ny < 0.0f) {
-                side = side < 0 ? 2 : side;
-                ny = 0.0f;
-            } else if (ny > 1.0f) {
-                side = side < 0 ? 3 : side;
-                ny = 1.0f;
-            }
-        }
+        // endpoint outside; several sides out -> corner, first side crossed.
+        // The position stays where it is: the value of an exit reads only the
+        // coordinate along its side, clamped onto the side there.
+        side = !C.per_xi && nx < 0.0f ? 0 : (!C.per_xi && nx > 1.0f ? 1 : (!C.per_eta && ny < 0.0f ? 2 : 3));
     } else if (C.bridge && min(__float_as_int(P.m), __float_as_int(m)) < __float_as_int(C.delta)) {
         // (the minimum of the two distances below delta; on the signed-integer
         // bit patterns, which order non-NaN floats as their values for a
@@ -347,10 +340,6 @@ __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t w
                 if (a2 < am) { s = 2; am = a2; }
                 if (a3 < am) { s = 3; am = a3; }
                 side = s;
-                if (s == 0) nx = 0.0f;
-                if (s == 1) nx = 1.0f;
-                if (s == 2) ny = 0.0f;
-                if (s == 3) ny = 1.0f;
             }
         }
     }
@@ -402,8 +391,10 @@ __device__ __forceinline__ void path_value_f32(const InstView &I, const ConstF &
                                                float &vx, float &vy)
 {
     if (side >= 0) {
+        // the exit point: the end of the substep moved onto the side, i.e. its
+        // coordinate along the side, clamped to [0, 1] (a corner exit)
         const float w_tn = (float)P.k * C.dt * C.inv_tau;
-        const float tang = side < 2 ? P.y : P.x;
+        const float tang = __builtin_amdgcn_fmed3f(side < 2 ? P.y : P.x, 0.0f, 1.0f);
         vx = boundary_f32(gptr(I.bnd0_f), gptr(I.bnd1_f), C.n_xi, C.n_eta, side, 0, tang, w_tn);
         vy = boundary_f32(gptr(I.bnd0_f), gptr(I.bnd1_f), C.n_xi, C.n_eta, side, 1, tang, w_tn);
     } else {
