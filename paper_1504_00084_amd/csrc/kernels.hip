@@ -104,9 +104,9 @@ struct ConstF {
     float sq2dt;   // sqrt(2 dt) (diagnostics only)
     float delta;   // sqrt(18.5 dt): farther from every side, no bridge crossing can matter
     // The instance's cell data, one allocation: first the compact plane of
-    // the dt rho_eta coefficients (16 B per cell), then from byte `rec0` the
+    // the dt rho_eta corner values (16 B per cell), then from byte `rec0` the
     // 48-B cell records ((rho, dt rho_xi) at corners 00, 10, 01, 11; the dt
-    // rho_eta coefficients again).  Every gather is this scalar base plus a
+    // rho_eta corners again).  Every gather is this scalar base plus a
     // 32-bit lane offset (the two parts together stay below 2^32 bytes).
     const GLOBAL char *cdata;
     uint32_t rec0;
@@ -177,10 +177,10 @@ __device__ __forceinline__ float bilerp(float tx, float ty, float f00, float f10
 // Window of the node tables held in LDS by the windowed kernel: nodes
 // [i0, i0 + tw) x [j0, j0 + th), (rho, dt rho_xi) interleaved, row stride tw;
 // w1 = tw - 1 and h1 = th - 1 cells.  Three-field windows (TAB 4) also hold
-// the dt rho_eta coefficients of their w1 x h1 cells, row stride w1, from
-// byte `coff` of the LDS on.
+// dt rho_eta of the same nodes, row stride tw, from byte `coff` of the LDS
+// on.
 struct Win {
-    int i0, j0, tw, w1, h1, coff, tw8;   // tw8 = 8 tw: bytes per window row
+    int i0, j0, tw, w1, h1, coff, tw8, tw4;   // tw8, tw4: bytes per window row (pairs, dt rho_eta)
 };
 
 // One EM substep of the FP32 path (a3-a6).  Returns the exit side (0: xi=0,
@@ -190,8 +190,8 @@ struct Win {
 // TAB: where the corner values of rho and dt rho_xi come from.  0: the cell
 // record; 2: the LDS node table (rho, dt rho_xi interleaved); 3: the LDS
 // window when the cell lies inside it, else the cell record; 4: as 3, with
-// the dt rho_eta coefficients of the cells inside the window from LDS too.  The
-// values are the same in every case, so the results are identical.
+// dt rho_eta at the corners of the cells inside the window from LDS too.
+// The values are the same in every case, so the results are identical.
 template <int TAB>
 __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t wa, uint32_t wb, uint32_t wc,
                                            float *trace4, const float *tab, const Win &win)
@@ -228,7 +228,7 @@ __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t w
     const GLOBAL f32x4 *cell = (const GLOBAL f32x4 *)(C.cdata + rec);
     const GLOBAL f32x4 *coef = (const GLOBAL f32x4 *)(C.cdata + (ci << 4));
     float r00, r10, r01, r11, g00, g10, g01, g11;
-    f32x4 G;   // dt rho_eta coefficients
+    f32x4 G;   // dt rho_eta at corners 00, 10, 01, 11
     if (TAB == 2) {
         const uint32_t off = __umul24((uint32_t)cy, (uint32_t)C.n_xi << 3) + ((uint32_t)cx << 3);
         const float2 *t2 = (const float2 *)((const char *)tab + off);
@@ -241,11 +241,11 @@ __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t w
         // both branches load into the same registers, so neither waits for its
         // loads before the join.  The LDS branch comes first, so a record load
         // waits only for LDS reads before it overwrites their registers, never a
-        // gather for an LDS read.  The two-field window's coefficients come from
-        // the plane or the record through one gather issued ahead of both.
+        // gather for an LDS read.  The two-field window's dt rho_eta corners come
+        // from the plane or the record through one gather issued ahead of both.
         const int rx = cx - win.i0, ry = cy - win.j0;
         const bool outside = ((uint32_t)rx >= (uint32_t)win.w1) | ((uint32_t)ry >= (uint32_t)win.h1);
-        // one base, a selected 32-bit offset: the record's coefficients or the plane's
+        // one base, a selected 32-bit offset: the record's corners or the plane's
         if (TAB == 3) G = *(const GLOBAL f32x4 *)(C.cdata + (outside ? rec + 32u : ci << 4));
         if (outside) {
             const f32x4 A = cell[0], B = cell[1];
@@ -260,9 +260,13 @@ __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t w
             r00 = c00.x, r10 = c10.x, r01 = c01.x, r11 = c11.x;
             g00 = c00.y, g10 = c10.y, g01 = c01.y, g11 = c11.y;
             if (TAB == 4) {
-                const uint32_t co = (uint32_t)win.coff + __umul24((uint32_t)ry, (uint32_t)win.w1 << 4) +
-                                    ((uint32_t)rx << 4);
-                G = *(const f32x4 *)((const char *)tab + co);
+                const uint32_t co = (uint32_t)win.coff + __umul24((uint32_t)ry, (uint32_t)win.tw4) + ((uint32_t)rx << 2);
+                const float *e0 = (const float *)((const char *)tab + co);
+                const float *e1 = (const float *)((const char *)tab + co + (uint32_t)win.tw4);
+                G.x = e0[0];
+                G.y = e0[1];
+                G.z = e1[0];
+                G.w = e1[1];
             }
         }
     } else {
@@ -270,13 +274,13 @@ __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t w
         r00 = A.x, g00 = A.y, r10 = A.z, g10 = A.w;
         r01 = B.x, g01 = B.y, r11 = B.z, g11 = B.w;
     }
-    // the two-field table kernel reads the coefficients from the compact
-    // plane (its only gather: better L1 reuse), the window kernel too inside
-    // its window; the others from the record
+    // the two-field table kernel reads the dt rho_eta corners from the
+    // compact plane (its only gather: better L1 reuse), the window kernel too
+    // inside a two-field window; the others from the record
     if (TAB < 3) G = TAB == 2 ? *coef : cell[2];
     const float rho = bilerp(tx, ty, r00, r10, r01, r11);
     const float gx = bilerp(tx, ty, g00, g10, g01, g11);
-    const float gy = fmaf(ty, fmaf(G.w, tx, G.z), fmaf(G.y, tx, G.x));
+    const float gy = bilerp(tx, ty, G.x, G.y, G.z, G.w);
     const float inv_rho = __builtin_amdgcn_rcpf(rho);
 
     // a5: Euler-Maruyama, x + (grad rho / rho) dt + sqrt(2 dt) N.
@@ -833,7 +837,7 @@ __global__ __launch_bounds__(BLOCK) void paths_fp32(const InstView *__restrict__
     }
 
     QueueSrc src{head, gptr(ranges), n_ranges};
-    const Win none{0, 0, 0, 0, 0, 0, 0};
+    const Win none{0, 0, 0, 0, 0, 0, 0, 0};
     item_loop<TAB, PER>(src, n_items, insts, buf, cap, tab, none, lane, rf);
 }
 
@@ -860,8 +864,8 @@ __global__ __launch_bounds__(kTableBlock) void paths_fp32_win(const InstView *__
 {
     constexpr int BLOCK = kTableBlock;
     // The only LDS of this kernel is the dynamic block (base 0): the job and
-    // item counters in its first 16 bytes, then the window, 16-byte aligned
-    // for the float4 cell coefficients of three-field windows.
+    // item counters in its first 16 bytes, then the window: (rho, dt rho_xi)
+    // per node, and in three-field windows dt rho_eta per node after them.
     extern __shared__ float lds[];
     uint32_t *ctl = (uint32_t *)lds;   // [0]: current job, [1]: next item of the job
     float *wtab = lds + 4;
@@ -892,7 +896,7 @@ __global__ __launch_bounds__(kTableBlock) void paths_fp32_win(const InstView *__
         const WorkRange R = ranges[J.range];
         const InstView &I = insts[R.inst];
         const bool ok = PER < 0 || (I.per_xi == (PER & 1) && I.per_eta == (PER >> 1));
-        const int coff = (J.tw * J.th * 8 + 15) & ~15;   // three-field windows: cell coefficients from here
+        const int coff = J.tw * J.th * 8;   // three-field windows: dt rho_eta from here
         {
             const GLOBAL float *src = gptr(I.rho_f);
             const GLOBAL float *srx = gptr(I.rhox_f);
@@ -904,18 +908,17 @@ __global__ __launch_bounds__(kTableBlock) void paths_fp32_win(const InstView *__
                 t2[q] = make_float2(src[g], srx[g]);
             }
             if (J.kind == 1) {
-                const GLOBAL f32x4 *cy = (const GLOBAL f32x4 *)I.coef_y;
-                f32x4 *t4 = (f32x4 *)((char *)wtab + coff);
-                const int w1 = J.tw - 1, nc = w1 * (J.th - 1);
-                for (int q = threadIdx.x; q < nc; q += BLOCK) {
-                    const int r = q / w1, c = q - r * w1;
-                    t4[q] = cy[(uint32_t)((J.j0 + r) * (I.n_xi - 1) + J.i0 + c)];
+                const GLOBAL float *sry = gptr(I.rhoy_f);
+                float *t1 = (float *)((char *)wtab + coff);
+                for (int q = threadIdx.x; q < n; q += BLOCK) {
+                    const int r = q / J.tw, c = q - r * J.tw;
+                    t1[q] = sry[(uint32_t)((J.j0 + r) * I.n_xi + J.i0 + c)];
                 }
             }
         }
         __syncthreads();
         JobSrc js{ctl + 1, R, J.q0};
-        const Win win{J.i0, J.j0, J.tw, J.tw - 1, J.th - 1, coff, J.tw * 8};
+        const Win win{J.i0, J.j0, J.tw, J.tw - 1, J.th - 1, coff, J.tw * 8, J.tw * 4};
         const uint32_t count = ok ? J.count : 0u;
         if (PER >= 0) {
             if (J.kind == 1)
@@ -1252,11 +1255,9 @@ __global__ void prep_cells_kernel(const double *__restrict__ rho, const double *
                                          (float)(grad_scale * rx[a + 1]));
     cells[3 * (size_t)idx + 1] = make_float4((float)rho[b], (float)(grad_scale * rx[b]), (float)rho[b + 1],
                                              (float)(grad_scale * rx[b + 1]));
-    {   // dt rho_eta in coefficient form a + b tx + c ty + d tx ty
-        const double f00 = grad_scale * f[2][a], f10 = grad_scale * f[2][a + 1];
-        const double f01 = grad_scale * f[2][b], f11 = grad_scale * f[2][b + 1];
-        const float4 g = make_float4((float)f00, (float)(f10 - f00), (float)(f01 - f00),
-                                     (float)(f11 - f10 - f01 + f00));
+    {   // dt rho_eta at the four corners, the FP32 node table's values
+        const float4 g = make_float4((float)(grad_scale * f[2][a]), (float)(grad_scale * f[2][a + 1]),
+                                     (float)(grad_scale * f[2][b]), (float)(grad_scale * f[2][b + 1]));
         cells[3 * (size_t)idx + 2] = g;
         coef_y[idx] = g;
     }
@@ -1476,7 +1477,7 @@ __global__ void debug_paths_kernel(const InstView *__restrict__ inst, int fp64, 
     int side = -1;
     bool ended = false;
     while (!ended) {
-        const Win none{0, 0, 0, 0, 0, 0, 0};
+        const Win none{0, 0, 0, 0, 0, 0, 0, 0};
         side = tr ? group_f32<true, 0>(P, C, path, I.node_r[node], I.ctr3, I.key0, I.key1, ended, tr, nullptr, none,
                                        Refill{64u, 1u})
                   : group_f32<false, 0>(P, C, path, I.node_r[node], I.ctr3, I.key0, I.key1, ended, nullptr, nullptr,

@@ -29,9 +29,8 @@ struct WorkRange {
 // of range `range`, whose nodes all lie in one block of the grid, and the
 // window of the node tables that the workgroup stages in LDS for them:
 // nodes [i0, i0 + tw) x [j0, j0 + th), inside the grid.  kind 0: the window
-// holds (rho, dt rho_xi) per node (8 B); kind 1: also the dt rho_eta
-// coefficients of its (tw - 1)(th - 1) cells (16 B each, after the nodes,
-// 16-byte aligned).
+// holds (rho, dt rho_xi) per node (8 B); kind 1: also dt rho_eta per node
+// (4 B each, after the pairs).
 struct WinJob {
     uint32_t range;
     uint32_t q0;
@@ -83,17 +82,17 @@ struct InstView {
 
     // FP32 path: per-cell records of three float4, (n_xi-1)(n_eta-1) cells:
     // (rho, dt rho_xi) at the corners 00, 10, then 01, 11, then dt rho_eta
-    // in coefficient form a + b tx + c ty + d tx ty; the same coefficients
-    // again as a compact plane (coef_y, read by the kernels that take rho and
-    // dt rho_xi from LDS), in the same allocation ahead of the records
-    // (cells = coef_y + rec0 bytes); the FP32 node tables of rho and dt rho_xi
-    // [n_eta][n_xi] (the same corner values, staged in LDS whole by launches
-    // that hold this instance alone when they fit, else in windows); padded
+    // at 00, 10, 01, 11; the last four again as a compact plane (coef_y,
+    // read by the kernels that take rho and dt rho_xi from LDS), in the same
+    // allocation ahead of the records (cells = coef_y + rec0 bytes); the FP32
+    // node tables of rho, dt rho_xi and dt rho_eta [n_eta][n_xi] (the same
+    // corner values, staged in LDS whole by launches that hold this instance
+    // alone when they fit, else in windows); padded
     // mesh [n_eta+2][n_xi+2] with ghost /
     // wrapped values, origin at node (-1, -1); boundary arrays in the C-ABI
     // layout.
     const float4 *cells, *coef_y;
-    const float *rho_f, *rhox_f;
+    const float *rho_f, *rhox_f, *rhoy_f;
     const float *xpad_f, *ypad_f;
     const float *bnd0_f, *bnd1_f;
 

@@ -15,7 +15,7 @@ hipError_t launch_prep_gradient(const double *rho_in, int n_xi, int n_eta, int p
                                 double *rho, double *rho_xi, double *rho_eta, hipStream_t s);
 
 // a0 (FP32 path): per-cell records of three float4: (rho, s rho_xi) at the
-// corners 00, 10, then 01, 11, then s rho_eta in bilinear coefficient form, with s =
+// corners 00, 10, then 01, 11, then s rho_eta at 00, 10, 01, 11, with s =
 // grad_scale (the substep dt); coef_y gets the last float4 of every record
 // again, as a compact plane.
 hipError_t launch_prep_cells(const double *rho, const double *rho_xi, const double *rho_eta, int n_xi,
@@ -66,8 +66,8 @@ int paths_fp32_table_blocks_per_cu(int level, int n_nodes);
 // around that block), cut into kJobQueues queues; each 1024-thread workgroup
 // pops jobs from its queue and then the others (`head`: kJobQueues counters,
 // zeroed here), stages the job's window in LDS -- (rho, dt rho_xi) per node,
-// 8 bytes, and for kind-1 jobs the dt rho_eta coefficients of the window's
-// cells too, 16 bytes each -- and runs its items; lanes outside the window
+// 8 bytes, and for kind-1 jobs dt rho_eta per node too, 4 bytes -- and runs
+// its items; lanes outside the window
 // read the cell records.  `lds` = the largest window of the launch in bytes
 // (at most kWinBytes).  `periodic` = per_xi + 2 per_eta shared by every
 // instance of the launch (compiled in), or -1 (read per instance).  `ends`,

@@ -88,6 +88,8 @@ int install_monitor(mesh_sdd *inst, hipStream_t st)
     HIP_TRY(msdd::launch_to_f32(inst->rho.as<double>(), inst->rho_f.as<float>(), (size_t)d.n_xi * d.n_eta, st));
     HIP_TRY(msdd::launch_scaled_to_f32(inst->rho_xi.as<double>(), d.tau / (double)d.K, inst->rhox_f.as<float>(),
                                        (size_t)d.n_xi * d.n_eta, st));
+    HIP_TRY(msdd::launch_scaled_to_f32(inst->rho_eta.as<double>(), d.tau / (double)d.K, inst->rhoy_f.as<float>(),
+                                       (size_t)d.n_xi * d.n_eta, st));
     HIP_TRY(hipStreamSynchronize(st));
     inst->monitor_set = true;
     return MESH_SDD_OK;
@@ -171,9 +173,9 @@ size_t instance_bytes(const mesh_sdd_desc &d, int M)
 {
     const size_t n = (size_t)d.n_xi * d.n_eta;
     const size_t cells = (size_t)(d.n_xi - 1) * (d.n_eta - 1);
-    // monitor tables, FP32 rho and dt rho_xi, cell records, node-rank map, interface nodes in rank order,
-    // stride-1 node lists (block order)
-    return 4 * n * sizeof(double) + 2 * n * sizeof(float) + 4 * cells * sizeof(float4) + n * sizeof(int32_t) +
+    // monitor tables, FP32 rho, dt rho_xi and dt rho_eta, cell records, node-rank map, interface nodes in
+    // rank order, stride-1 node lists (block order)
+    return 4 * n * sizeof(double) + 3 * n * sizeof(float) + 4 * cells * sizeof(float4) + n * sizeof(int32_t) +
            2 * (size_t)M * sizeof(int32_t) + 3 * (size_t)M * sizeof(int32_t);
 }
 
@@ -385,9 +387,9 @@ std::shared_ptr<Request> make_request(mesh_sdd *inst, const mesh_sdd_step &s, in
 }
 
 // Windows of the windowed kernel.  Kind 0 holds (rho, dt rho_xi) per node (8
-// bytes, at most kWinNodes nodes); kind 1 also the dt rho_eta coefficients of
-// its cells (16 bytes each), so a lane inside it gathers nothing from memory,
-// at the price of a smaller window.  Chosen per grid, by measurement: kind 1
+// bytes, at most kWinNodes nodes); kind 1 also dt rho_eta per node (4 bytes
+// more), so a lane inside it gathers nothing from memory, at the price of a
+// smaller window.  Chosen per grid, by measurement: kind 1
 // where it holds the whole grid (no gather at all); kind 0 where the two
 // fields of the whole grid fit (one well-cached gather per path-step beats
 // many small blocks and window refills); kind 1 below kWin1MaxN nodes per
@@ -399,8 +401,7 @@ constexpr int kWin1MaxN = 400;
 // LDS bytes of a window of tw x th nodes.
 size_t window_bytes(int kind, int tw, int th)
 {
-    const size_t nodes = (size_t)tw * th * 8;
-    return kind ? ((nodes + 15) & ~(size_t)15) + (size_t)(tw - 1) * (th - 1) * 16 : nodes;
+    return (size_t)tw * th * (kind ? 12 : 8);
 }
 
 // want: 0 automatic, 1 two-field (kind 0), 2 three-field (kind 1); a
@@ -418,7 +419,7 @@ int window_kind(const mesh_sdd_desc &d, int want = 0)
 // whole axis where it fits.
 void window_dims(int kind, int n_xi, int n_eta, int *wx, int *wy)
 {
-    const int side = kind ? 81 : 140;   // the largest square of each kind within kWinBytes
+    const int side = kind ? 114 : 140;   // the largest square of each kind within kWinBytes
     int y = std::min(n_eta, side);
     int x = n_xi;
     while (window_bytes(kind, x, y) > msdd::kWinBytes) --x;
@@ -649,6 +650,7 @@ int stage_request(Request &r, const mesh_sdd_step *dev_step, Arena *arena = null
     v.rec0 = (uint32_t)((size_t)(d.n_xi - 1) * (d.n_eta - 1) * sizeof(float4));
     v.rho_f = inst.rho_f.as<float>();
     v.rhox_f = inst.rhox_f.as<float>();
+    v.rhoy_f = inst.rhoy_f.as<float>();
     v.xpad_f = r.xpad_f.as<float>();
     v.ypad_f = r.ypad_f.as<float>();
     v.bnd0_f = r.b0f.as<float>();
@@ -1527,6 +1529,7 @@ try {
     HIP_TRY(hipSetDevice(ctx->device));
     if (inst->rho_in.alloc(n * 8) || inst->rho.alloc(n * 8) || inst->rho_xi.alloc(n * 8) ||
         inst->rho_eta.alloc(n * 8) || inst->rho_f.alloc(n * 4) || inst->rhox_f.alloc(n * 4) ||
+        inst->rhoy_f.alloc(n * 4) ||
         inst->cells.alloc(cells * 4 * sizeof(float4)) ||
         inst->node_rank.alloc(n * 4) || inst->node_ij.alloc(std::max<size_t>(1, 2 * (size_t)inst->M) * 4))
         return fail(MESH_SDD_E_NOMEM, "device allocation for the instance tables failed");

@@ -255,11 +255,11 @@ struct mesh_sdd {
     // keeps a pointer to its set, so a set is never rebuilt in place
     std::map<std::tuple<int, int, int>, std::unique_ptr<SampleSet>> samples;
     DevBuf rho_in, rho, rho_xi, rho_eta;    // FP64 monitor staging and node tables
-    DevBuf rho_f, rhox_f;                   // FP32 node tables of rho and dt rho_xi (staged in LDS whole
-                                            // or in windows)
-    DevBuf cells;                           // FP32 cell data: the dt rho_eta coefficients alone (one float4 per
+    DevBuf rho_f, rhox_f, rhoy_f;           // FP32 node tables of rho, dt rho_xi, dt rho_eta (staged in LDS
+                                            // whole or in windows)
+    DevBuf cells;                           // FP32 cell data: the dt rho_eta corners alone (one float4 per
                                             // cell), then the 48-B records (rho and dt rho_xi corners, the
-                                            // coefficients again); one allocation, below 2^32 bytes
+                                            // dt rho_eta corners again); one allocation, below 2^32 bytes
     DevBuf node_rank;                       // [n_eta][n_xi] interface rank or -1
     DevBuf node_ij;                         // interface nodes in rank order: i[M], then j[M]
     bool monitor_set = false;

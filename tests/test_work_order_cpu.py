@@ -5,7 +5,7 @@ permutation of the sampled interface ranks (section 3.6 sampling for a
 stride), the blocks must cover it in order, in Z (Morton) order of their
 grid position, with ranks ascending inside each block, and every window
 must lie in the grid, fit the LDS budget of its kind
-(kind 0: 8 B per node; kind 1: 8 B per node plus 16 B per cell; kind 1 where
+(kind 0: 8 B per node; kind 1: 12 B per node; kind 1 where
 it holds the whole grid, else kind 0 where that does, else kind 1 below 400
 nodes per axis), and hold each of its nodes with the kind's margin on every
 side (45 or 30 nodes; less only where the grid ends; the whole axis where it
@@ -16,12 +16,11 @@ import pytest
 from paper_1504_00084_amd import mesh_sdd as M
 
 LDS = 156800
-MARGIN, CORE, SIDE = {0: 45, 1: 30}, {0: 50, 1: 21}, {0: 140, 1: 81}
+MARGIN, CORE, SIDE = {0: 45, 1: 30}, {0: 50, 1: 54}, {0: 140, 1: 114}
 
 
 def window_bytes(kind, tw, th):
-    nodes = tw * th * 8
-    return ((nodes + 15) & ~15) + (tw - 1) * (th - 1) * 16 if kind else nodes
+    return tw * th * (12 if kind else 8)
 
 
 CASES = [
@@ -114,9 +113,9 @@ def test_non_square_windows_use_the_whole_short_axis():
     d = M.make_desc(65, 449, 2, 8, 0, 0)
     _, blocks = M.mesh_sdd_desc_work_order(d)
     assert set(map(tuple, blocks[:, 4:7])) == {(65, 301, 0)}
-    d = M.make_desc(385, 65, 8, 2, 1, 0)   # kind 1: 1544 w - 1024 <= 156800 along xi
+    d = M.make_desc(385, 65, 8, 2, 1, 0)   # kind 1: 12 B x 65 w <= 156800 along xi
     _, blocks = M.mesh_sdd_desc_work_order(d)
-    assert set(map(tuple, blocks[:, 4:7])) == {(102, 65, 1)}
+    assert set(map(tuple, blocks[:, 4:7])) == {(201, 65, 1)}
     d = M.make_desc(385, 49, 8, 2, 1, 0)   # the whole grid in a two-field window (150 920 B)
     _, blocks = M.mesh_sdd_desc_work_order(d)
     assert set(map(tuple, blocks[:, 4:7])) == {(385, 49, 0)}
