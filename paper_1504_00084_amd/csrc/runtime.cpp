@@ -536,8 +536,12 @@ int sample_set(mesh_sdd &inst, int stride, const Layout &lay, const SampleSet **
 
 // Work items of one FP32 launch (and of one request) are numbered in 32 bits,
 // and the queue counters pass the last item by one pop per wave: 2^20 of
-// headroom below 2^32.
-constexpr uint32_t kMaxLaunchItems = 0xFFF00000u;
+// headroom below 2^32.  A host test build lowers the limit to exercise the
+// split of a batch into several launches.
+#ifndef MESH_SDD_MAX_LAUNCH_ITEMS
+#define MESH_SDD_MAX_LAUNCH_ITEMS 0xFFF00000u
+#endif
+constexpr uint32_t kMaxLaunchItems = MESH_SDD_MAX_LAUNCH_ITEMS;
 
 // Allocate the request's device buffers, stage its inputs and run the prep
 // kernels; builds the work items.  With an arena the buffers are carved from

@@ -8,6 +8,9 @@
 //            no exception across the ABI)
 //   threads  concurrent clients submitting, polling, waiting and cancelling
 //            on one context while another thread reads its statistics
+//   split    (a build with MESH_SDD_MAX_LAUNCH_ITEMS lowered to 3000) a
+//            batch whose FP32 items exceed one launch runs in several, every
+//            request in exactly one; a request above the limit is refused
 // Exit status 0 when every check holds; a message names the first failure.
 #include <atomic>
 #include <cstdio>
@@ -21,6 +24,10 @@
 #include <hip/hip_runtime.h>
 
 #include "mesh_sdd.h"
+
+namespace msdd {
+extern std::atomic<int> g_fp32_launches;   // stub launchers: FP32 path launches so far
+}
 
 // ---- host-allocation failure injection: operator new counts down ---------
 static std::atomic<long> g_new_countdown{-1};   // < 0: never fail
@@ -375,6 +382,42 @@ static void scenario_threads()
     CHECK(done + cancelled == 150, "every request ended (%d)", done + cancelled);
 }
 
+// ---------------------------------------------------------------------------
+static void scenario_split()
+{
+    mesh_sdd_ctx *ctx = nullptr;
+    CHECK(mesh_sdd_ctx_create(0, 0, nullptr, &ctx) == MESH_SDD_OK, "ctx_create");
+    if (!ctx) return;
+    Problem p = make_problem(17);
+    // 29 nodes x 40 chunks of 128 paths = 1160 items per request: two fit
+    // under the limit of 3000, the third starts a second launch, the fourth
+    // joins it; then a lone request of 29 x 104 = 3016 items is refused
+    std::vector<mesh_sdd *> hs(4, nullptr);
+    for (int q = 0; q < 4; ++q) {
+        mesh_sdd_desc d = make_desc(17, 2, MESH_SDD_FP32, (uint32_t)q);
+        CHECK(mesh_sdd_create(ctx, &d, &hs[q]) == MESH_SDD_OK, "create %d", q);
+        if (hs[q]) CHECK(mesh_sdd_set_monitor(hs[q], p.rho.data(), 0) == MESH_SDD_OK, "set_monitor %d", q);
+    }
+    for (mesh_sdd *h : hs)
+        if (!h) return;
+    const int m = mesh_sdd_num_interface_nodes(hs[0]);
+    std::vector<mesh_sdd_step> steps(4, make_step(p, 128 * 40, 0));
+    std::vector<Out> outs;
+    for (int q = 0; q < 4; ++q) outs.emplace_back(m);
+    std::vector<mesh_sdd_result> res;
+    for (auto &o : outs) res.push_back(o.r);
+    int32_t status[4] = {9, 9, 9, 9};
+    const int before = msdd::g_fp32_launches.load();
+    CHECK(mesh_sdd_solve_batch(hs.data(), steps.data(), res.data(), 4, status) == MESH_SDD_OK, "split batch");
+    for (int q = 0; q < 4; ++q) CHECK(status[q] == MESH_SDD_OK, "status %d = %d", q, status[q]);
+    CHECK(msdd::g_fp32_launches.load() - before == 2, "launches %d, want 2", msdd::g_fp32_launches.load() - before);
+    mesh_sdd_step big = make_step(p, 128 * 104, 0);
+    Out ob(m);
+    CHECK(mesh_sdd_solve_interfaces(hs[0], &big, &ob.r) == MESH_SDD_E_INVAL, "a request above the launch limit");
+    for (mesh_sdd *h : hs) mesh_sdd_destroy(h);
+    mesh_sdd_ctx_destroy(ctx);
+}
+
 int main(int argc, char **argv)
 {
     const std::string what = argc > 1 ? argv[1] : "abi";
@@ -385,6 +428,8 @@ int main(int argc, char **argv)
         scenario_nomem();
     else if (what == "threads")
         scenario_threads();
+    else if (what == "split")
+        scenario_split();
     else {
         std::fprintf(stderr, "unknown scenario %s\n", what.c_str());
         return 2;

@@ -4,6 +4,7 @@
 // compute nothing of the method; they write the outputs the host code reads
 // back (zeros, a monitor of ones, a quality ratio of one) so that every host
 // code path runs to its end.
+#include <atomic>
 #include <cstdlib>
 #include <mutex>
 
@@ -56,10 +57,14 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t)
     for (size_t k = 0; k < n; ++k) p[k] = v;
     return hipSuccess;
 }
+// FP32 path launches made so far (any form), read by the harness
+std::atomic<int> g_fp32_launches{0};
+
 hipError_t launch_paths_fp32(const InstView *, const WorkRange *, uint32_t, uint32_t, uint32_t *head, uint32_t, int,
                              int, hipStream_t)
 {
     *head = 0;
+    ++g_fp32_launches;
     return hipSuccess;
 }
 size_t paths_fp32_lds_bytes(int block, uint32_t cap) { return (size_t)(block / 64) * 6u * cap * sizeof(float); }
@@ -69,6 +74,7 @@ hipError_t launch_paths_fp32_table(const InstView *, const WorkRange *, uint32_t
 {
     if (lanes < 1 || lanes > 64 || quarters < 1 || quarters > 64) return hipErrorInvalidValue;
     *head = 0;
+    ++g_fp32_launches;
     return hipSuccess;
 }
 int paths_fp32_table_blocks_per_cu(int level, int n_nodes)
@@ -84,6 +90,7 @@ hipError_t launch_paths_fp32_window(const InstView *, const WorkRange *, const W
     if (periodic < -1 || periodic > 3 || lds > kWinBytes || lanes < 1 || lanes > 64 || quarters < 1 || quarters > 64)
         return hipErrorInvalidValue;
     for (int q = 0; q < kJobQueues; ++q) head[q] = 0;
+    ++g_fp32_launches;
     return hipSuccess;
 }
 int paths_fp32_window_blocks_per_cu(size_t) { return 1; }

@@ -26,10 +26,10 @@ INCLUDES = ["-I" + HARNESS, "-I" + os.path.join(ROOT, "include"),
             "-I" + os.path.join(ROOT, "paper_1504_00084_amd", "csrc")]
 
 
-def build(tmp, name, sanitize):
+def build(tmp, name, sanitize, defines=()):
     exe = os.path.join(tmp, name)
     cmd = ["g++", "-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=" + sanitize] + INCLUDES + \
-        SOURCES + ["-o", exe, "-lpthread"]
+        ["-D" + d for d in defines] + SOURCES + ["-o", exe, "-lpthread"]
     res = subprocess.run(cmd, capture_output=True, text=True)
     assert res.returncode == 0, res.stderr[-3000:]
     return exe
@@ -56,6 +56,17 @@ def asan(tmp_path_factory):
 @pytest.mark.parametrize("scenario", ["abi", "nomem", "threads"])
 def test_host_runtime_under_asan_ubsan(asan, scenario, tmp_path):
     out = run(asan, scenario, tmp_path)
+    assert "all checks passed" in out
+
+
+def test_batch_split_into_launches_under_asan(tmp_path):
+    """A build whose launch item limit is 3000 instead of 2^32 - 2^20: a
+    batch of four requests of 1160 items each runs in two FP32 launches
+    (every request OK), and a request of 3016 items is refused."""
+    if not shutil.which("g++"):
+        pytest.skip("g++ not available")
+    exe = build(str(tmp_path), "harness_split", "address,undefined", ["MESH_SDD_MAX_LAUNCH_ITEMS=3000u"])
+    out = run(exe, "split", tmp_path)
     assert "all checks passed" in out
 
 
