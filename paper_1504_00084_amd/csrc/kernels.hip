@@ -260,7 +260,8 @@ __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t w
             r00 = c00.x, r10 = c10.x, r01 = c01.x, r11 = c11.x;
             g00 = c00.y, g10 = c10.y, g01 = c01.y, g11 = c11.y;
             if (TAB == 4) {
-                const uint32_t co = (uint32_t)win.coff + __umul24((uint32_t)ry, (uint32_t)win.tw4) + ((uint32_t)rx << 2);
+                // dt rho_eta of node k sits at coff + 4 k, its pair at 8 k: half the pair's offset
+                const uint32_t co = (uint32_t)win.coff + (off >> 1);
                 const float *e0 = (const float *)((const char *)tab + co);
                 const float *e1 = (const float *)((const char *)tab + co + (uint32_t)win.tw4);
                 G.x = e0[0];
