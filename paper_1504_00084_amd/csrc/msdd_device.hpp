@@ -82,8 +82,9 @@ struct InstView {
 
     // FP32 path: per-cell records of three float4, (n_xi-1)(n_eta-1) cells:
     // (rho, dt rho_xi) at the corners 00, 10, then 01, 11, then dt rho_eta
-    // at 00, 10, 01, 11; the last four again as a compact plane (coef_y,
-    // read by the kernels that take rho and dt rho_xi from LDS), in the same
+    // at 00, 10, 01, 11; dt rho_eta again as a compact plane in difference
+    // form, e00, e10 - e00, e01, e11 - e01 (coef_y, read by the kernels that
+    // take rho and dt rho_xi alone from LDS), in the same
     // allocation ahead of the records (cells = coef_y + rec0 bytes); the FP32
     // node tables of rho, dt rho_xi and dt rho_eta [n_eta][n_xi] (the same
     // corner values, staged in LDS whole by launches that hold this instance

@@ -16,8 +16,8 @@ hipError_t launch_prep_gradient(const double *rho_in, int n_xi, int n_eta, int p
 
 // a0 (FP32 path): per-cell records of three float4: (rho, s rho_xi) at the
 // corners 00, 10, then 01, 11, then s rho_eta at 00, 10, 01, 11, with s =
-// grad_scale (the substep dt); coef_y gets the last float4 of every record
-// again, as a compact plane.
+// grad_scale (the substep dt); coef_y gets s rho_eta of every cell again, as
+// a compact plane, in difference form: e00, e10 - e00, e01, e11 - e01.
 hipError_t launch_prep_cells(const double *rho, const double *rho_xi, const double *rho_eta, int n_xi,
                              int n_eta, double grad_scale, float4 *cells, float4 *coef_y, hipStream_t s);
 

@@ -68,7 +68,7 @@ int abi_exception() noexcept
     }
 }
 
-// The 48-B cell records, behind the coefficient plane in inst.cells.
+// The 48-B cell records, behind the dt rho_eta plane in inst.cells.
 float4 *cell_records(const mesh_sdd &inst)
 {
     return inst.cells.as<float4>() + (size_t)(inst.d.n_xi - 1) * (inst.d.n_eta - 1);
