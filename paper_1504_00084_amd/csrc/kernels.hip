@@ -99,6 +99,7 @@ __device__ __forceinline__ double uniform_f64(uint32_t r)
 struct ConstF {
     int n_xi, n_eta, nx1, ny1;
     int per_xi, per_eta, bridge, K;
+    int four;      // 1: the bridge test takes all four sides, 0: the nearer side per Dirichlet axis
     float fnx1, fny1, dt, inv_dt, inv_tau, Lx, Ly;
     float c_rad;   // -4 ln2 dt, so that sqrt(c_rad log2 u) = sqrt(2 dt) sqrt(-2 ln u)
     float sq2dt;   // sqrt(2 dt) (diagnostics only)
@@ -112,9 +113,11 @@ struct ConstF {
     uint32_t rec0;
 };
 
-// PER >= 0: the periodic flags are the compile-time constants PER & 1 (xi)
-// and PER >> 1 (eta) -- the launch holds one instance of that kind -- so the
-// tests and selects they guard vanish from the code; PER < 0: from I.
+// PER >= 0: the instance's path kind (path_kind) as a compile-time constant:
+// the periodic flags PER & 1 (xi) and (PER >> 1) & 1 (eta), and PER >> 2 for
+// the four-side bridge test -- the launch (or the job) holds instances of
+// that kind -- so the tests and selects they guard vanish from the code;
+// PER < 0: from I.
 template <int PER>
 __device__ __forceinline__ ConstF load_const_f(const InstView &I)
 {
@@ -124,8 +127,9 @@ __device__ __forceinline__ ConstF load_const_f(const InstView &I)
     c.nx1 = I.n_xi - 1;
     c.ny1 = I.n_eta - 1;
     c.per_xi = PER < 0 ? I.per_xi : (PER & 1);
-    c.per_eta = PER < 0 ? I.per_eta : (PER >> 1);
+    c.per_eta = PER < 0 ? I.per_eta : ((PER >> 1) & 1);
     c.bridge = I.bridge;
+    c.four = PER < 0 ? (path_kind(I) >> 2) : (PER >> 2);
     c.K = I.K;
     c.fnx1 = (float)(I.n_xi - 1);
     c.fny1 = (float)(I.n_eta - 1);
@@ -330,32 +334,62 @@ __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t w
         // Brownian bridge between the two inside points: crossing probability
         // exp(-d0 d1 / dt) per side; d0 d1 / dt > 18.5 gives < 2^-26.6, below
         // the smallest uniform even summed over four sides.
-        // Per Dirichlet axis only the side with the smaller d0 d1 / dt is
-        // evaluated: the two values sum to ((s - 1)^2 + 1 - e^2) / (2 dt),
-        // with s the sum and e the difference of the two coordinates, so the
-        // other side's is at least (1 - e^2) / (4 dt) and its probability
-        // below 2^-86 for dt <= 4e-3, and 0 in FP32 for dt <= 2.4e-3, where
-        // q and the side are those of all four sides (ties: lower index).
         const float big = 1.0e30f;
-        float ax = big, ay = big;
-        int sx = 0, sy = 2;
-        if (!C.per_xi) {
-            const float a0 = P.x * nx * C.inv_dt, a1 = (1.0f - P.x) * (1.0f - nx) * C.inv_dt;
-            sx = a1 < a0;
-            ax = fminf(a0, a1);
-        }
-        if (!C.per_eta) {
-            const float a2 = P.y * ny * C.inv_dt, a3 = (1.0f - P.y) * (1.0f - ny) * C.inv_dt;
-            sy = 2 + (a3 < a2);
-            ay = fminf(a2, a3);
-        }
-        if (fminf(ax, ay) < 18.5f) {
-            const float L2E = 1.4426950408889634f;
-            const float px = __builtin_amdgcn_exp2f(-ax * L2E);
-            const float py = __builtin_amdgcn_exp2f(-ay * L2E);
-            // q = 1 - (1 - px)(1 - py), without cancellation
-            const float q = fmaf(-px, py, px + py);
-            if (uniform_f32(wc) < q) side = ay < ax ? sy : sx;
+        const float L2E = 1.4426950408889634f;
+        if (!C.four) {
+            // Substeps up to 4e-3: per Dirichlet axis only the side with the
+            // smaller d0 d1 / dt is evaluated.  The two values of an axis sum
+            // to ((s - 1)^2 + 1 - e^2) / (2 dt), s the sum and e the
+            // difference of the two coordinates, so the other's is at least
+            // 62.5 (1 - e^2): unless the substep moved more than half the
+            // domain, its probability is below 1e-20, and the decision is that
+            // of all four sides but when the uniform falls that close to q
+            // (bit for bit that of the four-side form, where the probability
+            // underflows to 0 in FP32).
+            float ax = big, ay = big;
+            int sx = 0, sy = 2;
+            if (!C.per_xi) {
+                const float a0 = P.x * nx * C.inv_dt, a1 = (1.0f - P.x) * (1.0f - nx) * C.inv_dt;
+                sx = a1 < a0;
+                ax = fminf(a0, a1);
+            }
+            if (!C.per_eta) {
+                const float a2 = P.y * ny * C.inv_dt, a3 = (1.0f - P.y) * (1.0f - ny) * C.inv_dt;
+                sy = 2 + (a3 < a2);
+                ay = fminf(a2, a3);
+            }
+            if (fminf(ax, ay) < 18.5f) {
+                const float px = __builtin_amdgcn_exp2f(-ax * L2E);
+                const float py = __builtin_amdgcn_exp2f(-ay * L2E);
+                // q = 1 - (1 - px)(1 - py), without cancellation
+                const float q = fmaf(-px, py, px + py);
+                // the side with the smaller value, the lower index on ties
+                if (uniform_f32(wc) < q) side = ay < ax ? sy : sx;
+            }
+        } else {
+            const float a0 = C.per_xi ? big : P.x * nx * C.inv_dt;
+            const float a1 = C.per_xi ? big : (1.0f - P.x) * (1.0f - nx) * C.inv_dt;
+            const float a2 = C.per_eta ? big : P.y * ny * C.inv_dt;
+            const float a3 = C.per_eta ? big : (1.0f - P.y) * (1.0f - ny) * C.inv_dt;
+            if (fminf(fminf(a0, a1), fminf(a2, a3)) < 18.5f) {
+                const float p0 = __builtin_amdgcn_exp2f(-a0 * L2E);
+                const float p1 = __builtin_amdgcn_exp2f(-a1 * L2E);
+                const float p2 = __builtin_amdgcn_exp2f(-a2 * L2E);
+                const float p3 = __builtin_amdgcn_exp2f(-a3 * L2E);
+                // q = 1 - prod(1 - p_s), accumulated without cancellation
+                float q = p0;
+                q = fmaf(-q, p1, q + p1);
+                q = fmaf(-q, p2, q + p2);
+                q = fmaf(-q, p3, q + p3);
+                if (uniform_f32(wc) < q) {
+                    int s = 0;
+                    float am = a0;
+                    if (a1 < am) { s = 1; am = a1; }
+                    if (a2 < am) { s = 2; am = a2; }
+                    if (a3 < am) { s = 3; am = a3; }
+                    side = s;
+                }
+            }
         }
     }
     P.x = nx;
@@ -797,16 +831,19 @@ __device__ __forceinline__ void item_loop(Src &src, uint32_t n_items, const Inst
     }
 }
 
-// The wave loop compiled for the periodicity `per` (per_xi + 2 per_eta).
+// The wave loop compiled for the path kind `kind` (path_kind).
 template <int TAB, class Src>
-__device__ __forceinline__ void item_loop_per(int per, Src &src, uint32_t n_items, const InstView *__restrict__ insts,
-                                              float *buf, uint32_t cap, const float *tab, const Win &win, int lane,
-                                              const Refill rf)
+__device__ __forceinline__ void item_loop_kind(int kind, Src &src, uint32_t n_items, const InstView *__restrict__ insts,
+                                               float *buf, uint32_t cap, const float *tab, const Win &win, int lane,
+                                               const Refill rf)
 {
-    switch (per) {
+    switch (kind) {
     case 0: item_loop<TAB, 0>(src, n_items, insts, buf, cap, tab, win, lane, rf); break;
     case 1: item_loop<TAB, 1>(src, n_items, insts, buf, cap, tab, win, lane, rf); break;
     case 2: item_loop<TAB, 2>(src, n_items, insts, buf, cap, tab, win, lane, rf); break;
+    case 4: item_loop<TAB, 4>(src, n_items, insts, buf, cap, tab, win, lane, rf); break;
+    case 5: item_loop<TAB, 5>(src, n_items, insts, buf, cap, tab, win, lane, rf); break;
+    case 6: item_loop<TAB, 6>(src, n_items, insts, buf, cap, tab, win, lane, rf); break;
     default: item_loop<TAB, 3>(src, n_items, insts, buf, cap, tab, win, lane, rf); break;
     }
 }
@@ -820,7 +857,7 @@ __device__ __forceinline__ void item_loop_per(int per, Src &src, uint32_t n_item
 // texture path.  The table fills the LDS, so the waves keep the
 // end states of their items in `ends` (global memory, 6 * cap words per
 // wave, room for `end_waves` waves; read back by the same wave only).
-// PER >= 0 (single-instance launches): the instance's periodic flags as
+// PER >= 0 (single-instance launches): the instance's path kind as
 // compile-time constants (see load_const_f); a mismatching instance ends the
 // launch at once, untouched.
 template <int BLOCK, int TAB, int PER>
@@ -830,7 +867,7 @@ __global__ __launch_bounds__(BLOCK) void paths_fp32(const InstView *__restrict__
                                                     float *__restrict__ ends, uint32_t end_waves, Refill rf)
 {
     extern __shared__ float lds[];
-    if (PER >= 0 && (insts[0].per_xi != (PER & 1) || insts[0].per_eta != (PER >> 1))) return;
+    if (PER >= 0 && path_kind(insts[0]) != PER) return;
     const int lane = threadIdx.x & 63;
     const uint32_t wave = blockIdx.x * (uint32_t)(BLOCK / 64) + (threadIdx.x >> 6);
     if (TAB > 0 && (blockIdx.x + 1u) * (uint32_t)(BLOCK / 64) > end_waves) return;   // whole block: no room
@@ -864,8 +901,8 @@ __global__ __launch_bounds__(BLOCK) void paths_fp32(const InstView *__restrict__
 // cell record instead (TAB 3 and 4 in substep_f32), so the results are those
 // of every other kernel.  The waves
 // keep their items' end states in `ends` as the table kernel does.
-// PER >= 0: every instance of the launch has that periodicity (compiled
-// in); a job of another kind is skipped, untouched.
+// PER >= 0: every instance of the launch has that path kind (compiled in);
+// a job of another kind is skipped, untouched.
 template <int PER>
 __global__ __launch_bounds__(kTableBlock) void paths_fp32_win(const InstView *__restrict__ insts,
                                                             const WorkRange *__restrict__ ranges,
@@ -906,7 +943,7 @@ __global__ __launch_bounds__(kTableBlock) void paths_fp32_win(const InstView *__
         const WinJob J = jobs[job];
         const WorkRange R = ranges[J.range];
         const InstView &I = insts[R.inst];
-        const bool ok = PER < 0 || (I.per_xi == (PER & 1) && I.per_eta == (PER >> 1));
+        const bool ok = PER < 0 || path_kind(I) == PER;
         const int coff = J.tw * J.th * 8;   // three-field windows: dt rho_eta from here
         {
             const GLOBAL float *src = gptr(I.rho_f);
@@ -937,14 +974,14 @@ __global__ __launch_bounds__(kTableBlock) void paths_fp32_win(const InstView *__
             else
                 item_loop<3, PER>(js, count, insts, buf, cap, wtab, win, lane, rf);
         } else {
-            // a launch of mixed periodicity: a job holds one instance, so its
-            // periodic flags are uniform over the workgroup; each kind runs the
-            // wave loop compiled for it
-            const int per = I.per_xi + 2 * I.per_eta;
+            // a launch of mixed kinds: a job holds one instance, so its kind is
+            // uniform over the workgroup; each kind runs the wave loop
+            // compiled for it
+            const int kind = path_kind(I);
             if (J.kind == 1)
-                item_loop_per<4>(per, js, count, insts, buf, cap, wtab, win, lane, rf);
+                item_loop_kind<4>(kind, js, count, insts, buf, cap, wtab, win, lane, rf);
             else
-                item_loop_per<3>(per, js, count, insts, buf, cap, wtab, win, lane, rf);
+                item_loop_kind<3>(kind, js, count, insts, buf, cap, wtab, win, lane, rf);
         }
         __syncthreads();   // every wave is done with the window
     }
@@ -1600,21 +1637,24 @@ static void launch_table(int grid, size_t lds, hipStream_t s, const InstView *in
 }
 
 hipError_t launch_paths_fp32_table(const InstView *insts, const WorkRange *ranges, uint32_t n_items, uint32_t *head,
-                                   uint32_t cap, int level, int periodic, int n_nodes, int grid, float *ends,
+                                   uint32_t cap, int level, int kind, int n_nodes, int grid, float *ends,
                                    uint32_t end_waves, uint32_t refill_lanes, uint32_t max_quarters, hipStream_t s)
 {
     hipError_t e = launch_fill_u32(head, 0u, 1, s);
     if (e != hipSuccess) return e;
     if (n_items == 0) return hipSuccess;
-    if ((size_t)grid * (kTableBlock / 64) > end_waves || level != 2 || periodic < 0 || periodic > 3 ||
+    if ((size_t)grid * (kTableBlock / 64) > end_waves || level != 2 || kind < 0 || kind > 6 ||
         refill_lanes < 1 || refill_lanes > 64 || max_quarters < 1 || max_quarters > 64)
         return hipErrorInvalidValue;
     const size_t lds = paths_fp32_table_lds_bytes(level, n_nodes);
     const Refill rf{refill_lanes, max_quarters};
-    switch (periodic) {
+    switch (kind) {
     case 0: launch_table<2, 0>(grid, lds, s, insts, ranges, n_items, head, cap, ends, end_waves, rf); break;
     case 1: launch_table<2, 1>(grid, lds, s, insts, ranges, n_items, head, cap, ends, end_waves, rf); break;
     case 2: launch_table<2, 2>(grid, lds, s, insts, ranges, n_items, head, cap, ends, end_waves, rf); break;
+    case 4: launch_table<2, 4>(grid, lds, s, insts, ranges, n_items, head, cap, ends, end_waves, rf); break;
+    case 5: launch_table<2, 5>(grid, lds, s, insts, ranges, n_items, head, cap, ends, end_waves, rf); break;
+    case 6: launch_table<2, 6>(grid, lds, s, insts, ranges, n_items, head, cap, ends, end_waves, rf); break;
     default: launch_table<2, 3>(grid, lds, s, insts, ranges, n_items, head, cap, ends, end_waves, rf); break;
     }
     return hipGetLastError();
@@ -1641,7 +1681,7 @@ static void launch_win(int grid, size_t lds, hipStream_t s, const InstView *inst
 }
 
 hipError_t launch_paths_fp32_window(const InstView *insts, const WorkRange *ranges, const WinJob *jobs,
-                                    const JobQueues &qs, uint32_t *head, uint32_t cap, int periodic, size_t lds,
+                                    const JobQueues &qs, uint32_t *head, uint32_t cap, int kind, size_t lds,
                                     int grid, float *ends, uint32_t end_waves, uint32_t refill_lanes,
                                     uint32_t max_quarters, hipStream_t s)
 {
@@ -1650,16 +1690,19 @@ hipError_t launch_paths_fp32_window(const InstView *insts, const WorkRange *rang
     if (qs.b[kJobQueues] == 0) return hipSuccess;
     for (int q = 0; q < kJobQueues; ++q)
         if (qs.b[q] > qs.b[q + 1]) return hipErrorInvalidValue;
-    if ((size_t)grid * (kTableBlock / 64) > end_waves || periodic < -1 || periodic > 3 || lds < 32 ||
+    if ((size_t)grid * (kTableBlock / 64) > end_waves || kind < -1 || kind > 6 || lds < 32 ||
         lds > kWinBytes || refill_lanes < 1 || refill_lanes > 64 || max_quarters < 1 || max_quarters > 64)
         return hipErrorInvalidValue;
     lds += 16;   // the job and item counters ahead of the window
     const Refill rf{refill_lanes, max_quarters};
-    switch (periodic) {
+    switch (kind) {
     case 0: launch_win<0>(grid, lds, s, insts, ranges, jobs, qs, head, cap, ends, end_waves, rf); break;
     case 1: launch_win<1>(grid, lds, s, insts, ranges, jobs, qs, head, cap, ends, end_waves, rf); break;
     case 2: launch_win<2>(grid, lds, s, insts, ranges, jobs, qs, head, cap, ends, end_waves, rf); break;
     case 3: launch_win<3>(grid, lds, s, insts, ranges, jobs, qs, head, cap, ends, end_waves, rf); break;
+    case 4: launch_win<4>(grid, lds, s, insts, ranges, jobs, qs, head, cap, ends, end_waves, rf); break;
+    case 5: launch_win<5>(grid, lds, s, insts, ranges, jobs, qs, head, cap, ends, end_waves, rf); break;
+    case 6: launch_win<6>(grid, lds, s, insts, ranges, jobs, qs, head, cap, ends, end_waves, rf); break;
     default: launch_win<-1>(grid, lds, s, insts, ranges, jobs, qs, head, cap, ends, end_waves, rf); break;
     }
     return hipGetLastError();

@@ -62,7 +62,7 @@ struct InstView {
     int32_t n_xi, n_eta;          // nodes per axis
     int32_t per_xi, per_eta;      // periodic flags
     int32_t K;                    // substeps
-    int32_t bridge;               // Brownian-bridge test on/off
+    int32_t bridge;               // Brownian-bridge test: 0 off, 1 on, 2 on with substeps up to 4e-3
     int32_t M;                    // nodes that run paths (entries of node_i / node_j / node_r)
     int32_t pad0;
     uint32_t key0, key1;          // Philox key (seed low / high word)
@@ -108,6 +108,16 @@ struct InstView {
     // Partial sums of this request's work items.
     Partial *partials;
 };
+
+// The FP32 path kernels' compile-time kind of an instance: its periodicity
+// (per_xi + 2 per_eta) plus 4 where the bridge test must take all four sides
+// (bridge on with substeps above 4e-3 and some axis Dirichlet); the kernels
+// take the nearer side of each Dirichlet axis alone otherwise.
+__host__ __device__ inline int path_kind(int per_xi, int per_eta, int bridge)
+{
+    return per_xi + 2 * per_eta + (bridge == 1 && !(per_xi && per_eta) ? 4 : 0);
+}
+__host__ __device__ inline int path_kind(const InstView &v) { return path_kind(v.per_xi, v.per_eta, v.bridge); }
 
 // Per-node finalize descriptor: the partials of one node are
 // partials[first .. first + count) in chunk order.

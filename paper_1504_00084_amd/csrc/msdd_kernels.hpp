@@ -51,12 +51,12 @@ size_t paths_fp32_lds_bytes(int block, uint32_t cap);
 // Results are identical to launch_paths_fp32's.
 constexpr int kTableBlock = 1024;
 size_t paths_fp32_table_lds_bytes(int level, int n_nodes);
-// `periodic` = per_xi + 2 per_eta of the instance (compiled in).
+// `kind` = path_kind of the instance, 0..6 (compiled in).
 // refill_lanes, max_quarters (1..64): a wave leaves its stepping loop for the
 // refill once fewer than refill_lanes of its lanes have a path in flight, or
 // after max_quarters groups of four substeps (no result depends on them).
 hipError_t launch_paths_fp32_table(const InstView *insts, const WorkRange *ranges, uint32_t n_items, uint32_t *head,
-                                   uint32_t cap, int level, int periodic, int n_nodes, int grid, float *ends,
+                                   uint32_t cap, int level, int kind, int n_nodes, int grid, float *ends,
                                    uint32_t end_waves, uint32_t refill_lanes, uint32_t max_quarters, hipStream_t s);
 int paths_fp32_table_blocks_per_cu(int level, int n_nodes);
 
@@ -69,14 +69,14 @@ int paths_fp32_table_blocks_per_cu(int level, int n_nodes);
 // 8 bytes, and for kind-1 jobs dt rho_eta per node too, 4 bytes -- and runs
 // its items; lanes outside the window
 // read the cell records.  `lds` = the largest window of the launch in bytes
-// (at most kWinBytes).  `periodic` = per_xi + 2 per_eta shared by every
-// instance of the launch (compiled in), or -1 (read per instance).  `ends`,
+// (at most kWinBytes).  `kind` = path_kind shared by every instance of the
+// launch (compiled in), or -1 (each job runs the loop of its instance's).  `ends`,
 // refill_lanes and max_quarters as for the table kernel.  Results are
 // identical to launch_paths_fp32's.
 constexpr size_t kWinBytes = 156800;   // LDS of one window (of the 160 KB of a CU)
 constexpr int kWinNodes = 19600;       // two-field windows: at most 140 x 140 nodes
 hipError_t launch_paths_fp32_window(const InstView *insts, const WorkRange *ranges, const WinJob *jobs,
-                                    const JobQueues &qs, uint32_t *head, uint32_t cap, int periodic, size_t lds,
+                                    const JobQueues &qs, uint32_t *head, uint32_t cap, int kind, size_t lds,
                                     int grid, float *ends, uint32_t end_waves, uint32_t refill_lanes,
                                     uint32_t max_quarters, hipStream_t s);
 int paths_fp32_window_blocks_per_cu(size_t lds);

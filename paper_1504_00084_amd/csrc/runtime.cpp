@@ -629,7 +629,10 @@ int stage_request(Request &r, const mesh_sdd_step *dev_step, Arena *arena = null
     v.per_xi = d.periodic_xi;
     v.per_eta = d.periodic_eta;
     v.K = d.K;
-    v.bridge = d.bridge;
+    // 2: substeps up to 4e-3, where the FP32 kernels take the nearer side of
+    // each Dirichlet axis alone (the other's crossing probability is below
+    // 1e-20); 1: longer substeps, all four sides (see path_kind)
+    v.bridge = d.bridge ? (d.tau / (double)d.K <= 4e-3 ? 2 : 1) : 0;
     v.M = Ms;
     v.key0 = (uint32_t)(d.seed & 0xFFFFFFFFu);
     v.key1 = (uint32_t)(d.seed >> 32);
@@ -750,7 +753,7 @@ int run_fp32_launch(mesh_sdd_ctx *ctx, const std::vector<InstView> &views, const
     std::vector<msdd::WinJob> jobs;
     msdd::JobQueues qs{};
     size_t win_lds = 32;
-    int periodic = -2;
+    int kind = -2;
     if (level == 3) {
         const size_t share = ((size_t)ctx->cu_count * (size_t)per_cu);
         const size_t split = l.job_split > 0 ? (size_t)l.job_split : 32u;
@@ -760,8 +763,8 @@ int run_fp32_launch(mesh_sdd_ctx *ctx, const std::vector<InstView> &views, const
         for (size_t ri = 0; ri < ranges.size(); ++ri) {
             const WorkRange &w = ranges[ri];
             const InstView &v = views[w.inst];
-            const int p = v.per_xi + 2 * v.per_eta;
-            periodic = periodic == -2 || periodic == p ? p : -1;
+            const int p = msdd::path_kind(v);
+            kind = kind == -2 || kind == p ? p : -1;
             const size_t lo = w.first, hi = (size_t)w.first + w.count;
             for (const BlockRun &b : sets[w.inst]->blocks) {
                 const size_t qa = std::max(lo, (size_t)b.pos_begin * w.chunks);
@@ -796,12 +799,12 @@ int run_fp32_launch(mesh_sdd_ctx *ctx, const std::vector<InstView> &views, const
     hipError_t le =
         level == 3 ? msdd::launch_paths_fp32_window(views_b.as<InstView>(), ranges_b.as<WorkRange>(),
                                                     jobs_b.as<msdd::WinJob>(), qs, head_b.as<uint32_t>(),
-                                                    cap, periodic, win_lds, table_grid,
+                                                    cap, kind, win_lds, table_grid,
                                                     ends_b.as<float>(), end_waves, (uint32_t)l.refill_lanes,
                                                     (uint32_t)l.max_quarters, st)
         : level > 0 ? msdd::launch_paths_fp32_table(views_b.as<InstView>(), ranges_b.as<WorkRange>(),
                                                     (uint32_t)n_items, head_b.as<uint32_t>(), cap, level,
-                                                    views[0].per_xi + 2 * views[0].per_eta, n_nodes, table_grid,
+                                                    msdd::path_kind(views[0]), n_nodes, table_grid,
                                                     ends_b.as<float>(), end_waves, (uint32_t)l.refill_lanes,
                                                     (uint32_t)l.max_quarters, st)
                     : msdd::launch_paths_fp32(views_b.as<InstView>(), ranges_b.as<WorkRange>(),

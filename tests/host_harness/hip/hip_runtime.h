@@ -14,6 +14,15 @@
 #include <cstdlib>
 #include <cstring>
 
+// HIP's function-space attributes (host and device inline helpers in the
+// library's shared headers): no meaning on the CPU
+#ifndef __host__
+#define __host__
+#endif
+#ifndef __device__
+#define __device__
+#endif
+
 typedef enum hipError_t {
     hipSuccess = 0,
     hipErrorInvalidValue = 1,

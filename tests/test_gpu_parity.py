@@ -72,6 +72,12 @@ SMALL_CASES = {
     "front17_perxy_2x2": (17, 17, 2, 2, 1, 1, 37, 1000, 0.02, 1.0, 1.0, "front"),
     "ragged31x13_3x4": (31, 13, 3, 4, 0, 0, 33, 1111, 0.01, 1.5, 1.0, "bump"),
     "k1_bump9": (9, 9, 2, 2, 0, 0, 1, 777, 0.002, 1.0, 1.0, "bump"),
+    # coarse substeps: the FP32 kernels' bridge test takes all four sides
+    # above dt = 4e-3 (here 1e-2) and one side per Dirichlet axis at or below
+    # it (3.6e-3, where the other side's probability is below 1e-20)
+    "coarse_dt_bump17_dir": (17, 17, 2, 2, 0, 0, 4, 2000, 0.04, 1.0, 1.0, "bump"),
+    "coarse_dt_bump33_pery": (33, 33, 4, 2, 0, 1, 3, 1500, 0.03, 1.0, 1.0, "bump"),
+    "fine_dt_edge_bump17_dir": (17, 17, 2, 2, 0, 0, 5, 2000, 0.018, 1.0, 1.0, "bump"),
 }
 
 
@@ -164,12 +170,19 @@ def test_windowed_kernel_with_every_periodicity(M, ctx, oracle_lib, name):
     assert s["err"] <= 1e-5 * max(inst.Lx, inst.Ly)
 
 
+# a windowed grid with substeps of 1e-2, whose bridge test takes all four sides
+COARSE_WINDOW_CASES = {"win161_coarse_dt_dir_8x8": (161, 161, 8, 8, 0, 0, 5, 256, 0.05, 1.0, 1.0, "bump")}
+
+
 def test_batch_of_every_periodicity_equals_alone(M, ctx):
-    """The four windowed cases above and a Dirichlet one in one batch: the
-    launch mixes periodicities, so its windowed kernel reads them per
-    instance at run time instead of having them compiled in; every result
+    """The four windowed cases above, a Dirichlet one, and three with
+    substeps above 4e-3 (four-side bridge test) in one batch: the launch
+    mixes path kinds, so each job of its windowed kernel runs the wave loop
+    compiled for its instance's kind instead of the launch's; every result
     must equal the instance's solve alone bitwise."""
     insts = [small_instance(n, WINDOW_CASES) for n in sorted(WINDOW_CASES)] + [small_instance("bump17_dir_2x2")]
+    insts += [small_instance(n, COARSE_WINDOW_CASES) for n in sorted(COARSE_WINDOW_CASES)]
+    insts += [small_instance("coarse_dt_bump17_dir"), small_instance("coarse_dt_bump33_pery")]
     for q, it in enumerate(insts):
         it.instance_id = 40 + q
     hs = [M.mesh_sdd_create(ctx, M.desc_for(it, M.FP32)) for it in insts]
