@@ -149,7 +149,7 @@ __device__ __forceinline__ ConstF load_const_f(const InstView &I)
 struct PathF {
     float x, y;   // position in [0,1]^2 (periodic axes wrapped)
     float m;      // distance of (x, y) to the nearest Dirichlet side (1e30 without one)
-    int wx, wy;   // winding numbers
+    float wx, wy; // winding numbers (whole numbers, exact in FP32 below 2^24)
     int k;        // substeps done
 };
 
@@ -190,10 +190,10 @@ __device__ __forceinline__ float bilerp_d(float tx, float ty, float f00, float d
 // Window of the node tables held in LDS by the windowed kernel: nodes
 // [i0, i0 + tw) x [j0, j0 + th), (rho, dt rho_xi) interleaved, row stride tw;
 // w1 = tw - 1 and h1 = th - 1 cells.  Three-field windows (TAB 4) also hold
-// dt rho_eta of the same nodes, row stride tw, from byte `coff` of the LDS
-// on.
+// dt rho_eta of the same nodes, row stride tw, from byte `coff` of the
+// window on.
 struct Win {
-    int i0, j0, tw, w1, h1, coff, tw8, tw4;   // tw8, tw4: bytes per window row (pairs, dt rho_eta)
+    int i0, j0, tw, w1, h1, coff;
 };
 
 // One EM substep of the FP32 path (a3-a6).  Returns the exit side (0: xi=0,
@@ -265,17 +265,17 @@ __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t w
             r01 = B.x, g01 = B.y, r11 = B.z, g11 = B.w;
             if (TAB == 4) G = cell[2];
         } else {
-            const uint32_t off = __umul24((uint32_t)ry, (uint32_t)win.tw8) + ((uint32_t)rx << 3);
-            const float2 *t2 = (const float2 *)((const char *)tab + off);
-            const float2 *u2 = (const float2 *)((const char *)tab + off + (uint32_t)win.tw8);
+            // window node of corner 00 (row stride tw); the row above is tw on
+            const uint32_t node = __umul24((uint32_t)ry, (uint32_t)win.tw) + (uint32_t)rx;
+            const float2 *t2 = (const float2 *)tab + node;
+            const float2 *u2 = t2 + win.tw;
             const float2 c00 = t2[0], c10 = t2[1], c01 = u2[0], c11 = u2[1];
             r00 = c00.x, r10 = c10.x, r01 = c01.x, r11 = c11.x;
             g00 = c00.y, g10 = c10.y, g01 = c01.y, g11 = c11.y;
             if (TAB == 4) {
-                // dt rho_eta of node k sits at coff + 4 k, its pair at 8 k: half the pair's offset
-                const uint32_t co = (uint32_t)win.coff + (off >> 1);
-                const float *e0 = (const float *)((const char *)tab + co);
-                const float *e1 = (const float *)((const char *)tab + co + (uint32_t)win.tw4);
+                // dt rho_eta of window node k sits at byte coff + 4 k
+                const float *e0 = (const float *)((const char *)tab + win.coff) + node;
+                const float *e1 = e0 + win.tw;
                 G.x = e0[0];
                 G.y = e0[1];
                 G.z = e1[0];
@@ -302,13 +302,14 @@ __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t w
     float ny = fmaf(rad, sn, fmaf(gy, inv_rho, P.y));
 
     // a6: periodic wrap with winding: x - floor(x) by v_fract, which also
-    // keeps the rare tiny negative x (where x + 1 rounds to 1) below 1.
+    // keeps the rare tiny negative x (where x + 1 rounds to 1) below 1; the
+    // winding is summed as a float (no conversion per substep).
     if (C.per_xi) {
-        P.wx += (int)floorf(nx);
+        P.wx += floorf(nx);
         nx = __builtin_amdgcn_fractf(nx);
     }
     if (C.per_eta) {
-        P.wy += (int)floorf(ny);
+        P.wy += floorf(ny);
         ny = __builtin_amdgcn_fractf(ny);
     }
     if (trace4) {   // diagnostics: position after the wrap, before any exit projection
@@ -450,8 +451,8 @@ __device__ __forceinline__ void path_value_f32(const InstView &I, const ConstF &
         vx = keys_f32(gptr(I.xpad_f), C.n_xi, C.nx1, C.ny1, C.fnx1, C.fny1, P.x, P.y);
         vy = keys_f32(gptr(I.ypad_f), C.n_xi, C.nx1, C.ny1, C.fnx1, C.fny1, P.x, P.y);
     }
-    if (C.per_xi) vx = fmaf((float)P.wx, C.Lx, vx);
-    if (C.per_eta) vy = fmaf((float)P.wy, C.Ly, vy);
+    if (C.per_xi) vx = fmaf(P.wx, C.Lx, vx);
+    if (C.per_eta) vy = fmaf(P.wy, C.Ly, vy);
 }
 
 // When a wave leaves its stepping loop for the refill and item bookkeeping
@@ -577,8 +578,9 @@ __device__ __forceinline__ void store_end(float *b, uint32_t cap, uint32_t slot,
                                           const PathF &P, int side)
 {
     uint32_t w0, w1, w2;
-    if (P.wx >= -8192 && P.wx < 8192 && P.wy >= -8192 && P.wy < 8192) {
-        w2 = ((uint32_t)P.wx & 0x3FFFu) | (((uint32_t)P.wy & 0x3FFFu) << 14) | ((uint32_t)(side + 1) << 28);
+    if (P.wx >= -8192.0f && P.wx < 8192.0f && P.wy >= -8192.0f && P.wy < 8192.0f) {
+        w2 = ((uint32_t)(int)P.wx & 0x3FFFu) | (((uint32_t)(int)P.wy & 0x3FFFu) << 14) |
+             ((uint32_t)(side + 1) << 28);
         if (side >= 0) {
             w0 = (uint32_t)P.k;
             w1 = __float_as_uint(side < 2 ? P.y : P.x);
@@ -610,8 +612,8 @@ __device__ __forceinline__ void stored_value(const float *b, uint32_t cap, uint3
     }
     const int side = (int)(w2 >> 28) - 1;
     PathF P;
-    P.wx = (int)(w2 << 18) >> 18;   // sign-extend the 14-bit fields
-    P.wy = (int)(w2 << 4) >> 18;
+    P.wx = (float)((int)(w2 << 18) >> 18);   // sign-extend the 14-bit fields
+    P.wy = (float)((int)(w2 << 4) >> 18);
     P.m = 0.0f;
     if (side < 0) {
         P.x = __uint_as_float(w0);
@@ -723,7 +725,7 @@ __device__ __forceinline__ void item_loop(Src &src, uint32_t n_items, const Inst
     // lane state
     bool has = false;
     uint32_t which = 0, slot = 0, path = 0, node = 0;
-    PathF P{0.f, 0.f, 0.f, 0, 0, 0};
+    PathF P{0.f, 0.f, 0.f, 0.f, 0.f, 0};
     uint32_t ex0 = 0, ex1 = 0;
     unsigned long long st0 = 0, st1 = 0;
 
@@ -782,8 +784,8 @@ __device__ __forceinline__ void item_loop(Src &src, uint32_t n_items, const Inst
                 P.x = cur ? x01 : x00;
                 P.y = cur ? y01 : y00;
                 P.m = cur ? m01 : m00;
-                P.wx = 0;
-                P.wy = 0;
+                P.wx = 0.0f;
+                P.wy = 0.0f;
                 P.k = 0;
             }
             issued = min(count, issued + (uint32_t)__popcll(need));
@@ -885,7 +887,7 @@ __global__ __launch_bounds__(BLOCK) void paths_fp32(const InstView *__restrict__
     }
 
     QueueSrc src{head, gptr(ranges), n_ranges};
-    const Win none{0, 0, 0, 0, 0, 0, 0, 0};
+    const Win none{0, 0, 0, 0, 0, 0};
     item_loop<TAB, PER>(src, n_items, insts, buf, cap, tab, none, lane, rf);
 }
 
@@ -911,10 +913,12 @@ __global__ __launch_bounds__(kTableBlock) void paths_fp32_win(const InstView *__
                                                             float *__restrict__ ends, uint32_t end_waves, Refill rf)
 {
     constexpr int BLOCK = kTableBlock;
-    // The only LDS of this kernel is the dynamic block (base 0): the job and
-    // item counters in its first 16 bytes, then the window: (rho, dt rho_xi)
-    // per node, and in three-field windows dt rho_eta per node after them.
-    extern __shared__ float lds[];
+    // The only LDS of this kernel, a static block (so that its address is a
+    // compile-time constant, folded into the LDS instructions' offsets): the
+    // job and item counters in its first 16 bytes, then the window: (rho,
+    // dt rho_xi) per node, and in three-field windows dt rho_eta per node
+    // after them.
+    __shared__ float lds[(kWinBytes + 16) / sizeof(float)];
     uint32_t *ctl = (uint32_t *)lds;   // [0]: current job, [1]: next item of the job
     float *wtab = lds + 4;
     const int lane = threadIdx.x & 63;
@@ -966,7 +970,7 @@ __global__ __launch_bounds__(kTableBlock) void paths_fp32_win(const InstView *__
         }
         __syncthreads();
         JobSrc js{ctl + 1, R, J.q0};
-        const Win win{J.i0, J.j0, J.tw, J.tw - 1, J.th - 1, coff, J.tw * 8, J.tw * 4};
+        const Win win{J.i0, J.j0, J.tw, J.tw - 1, J.th - 1, coff};
         const uint32_t count = ok ? J.count : 0u;
         if (PER >= 0) {
             if (J.kind == 1)
@@ -1523,12 +1527,12 @@ __global__ void debug_paths_kernel(const InstView *__restrict__ inst, int fp64, 
     }
     const ConstF C = load_const_f<-1>(I);
     const int i0 = I.node_i[node], j0 = I.node_j[node];
-    PathF P{(float)((double)i0 / (double)C.nx1), (float)((double)j0 / (double)C.ny1), 0.0f, 0, 0, 0};
+    PathF P{(float)((double)i0 / (double)C.nx1), (float)((double)j0 / (double)C.ny1), 0.0f, 0.0f, 0.0f, 0};
     P.m = side_distance(C, P.x, P.y);
     int side = -1;
     bool ended = false;
     while (!ended) {
-        const Win none{0, 0, 0, 0, 0, 0, 0, 0};
+        const Win none{0, 0, 0, 0, 0, 0};
         side = tr ? group_f32<true, 0>(P, C, path, I.node_r[node], I.ctr3, I.key0, I.key1, ended, tr, nullptr, none,
                                        Refill{64u, 1u})
                   : group_f32<false, 0>(P, C, path, I.node_r[node], I.ctr3, I.key0, I.key1, ended, nullptr, nullptr,
@@ -1693,7 +1697,7 @@ hipError_t launch_paths_fp32_window(const InstView *insts, const WorkRange *rang
     if ((size_t)grid * (kTableBlock / 64) > end_waves || kind < -1 || kind > 6 || lds < 32 ||
         lds > kWinBytes || refill_lanes < 1 || refill_lanes > 64 || max_quarters < 1 || max_quarters > 64)
         return hipErrorInvalidValue;
-    lds += 16;   // the job and item counters ahead of the window
+    lds = 0;   // the kernel's LDS is its static block (counters and the largest window)
     const Refill rf{refill_lanes, max_quarters};
     switch (kind) {
     case 0: launch_win<0>(grid, lds, s, insts, ranges, jobs, qs, head, cap, ends, end_waves, rf); break;
@@ -1711,8 +1715,8 @@ hipError_t launch_paths_fp32_window(const InstView *insts, const WorkRange *rang
 int paths_fp32_window_blocks_per_cu(size_t lds)
 {
     int n = 0;
-    lds += 16;   // the job and item counters ahead of the window
-    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32_win<-1>, kTableBlock, lds);
+    if (lds > kWinBytes) return 0;   // the static block holds windows up to kWinBytes
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, paths_fp32_win<-1>, kTableBlock, 0);
     return e == hipSuccess ? n : 0;
 }
 
