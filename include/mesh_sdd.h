@@ -174,7 +174,7 @@ typedef struct {
                                         them whole; any other launch (several
                                         instances, or a larger grid) stages
                                         windows of them (and, on most grids, of
-                                        the dt rho_eta cell coefficients) around
+                                        dt rho_eta per node too) around
                                         blocks of interface nodes, and paths that
                                         leave a window read the cell records
                                         (1024-thread workgroups, item end states in
@@ -194,8 +194,8 @@ typedef struct {
     int32_t window_kind;             /* windowed kernel, grids whose tables the LDS
                                         cannot hold whole: 1 two-field windows (rho,
                                         dt rho_xi per node, up to 140 x 140 nodes),
-                                        2 three-field windows (also the dt rho_eta
-                                        coefficients of their cells, up to 81 x 81);
+                                        2 three-field windows (also dt rho_eta per
+                                        node, 12 B per node, up to 114 x 114);
                                         default: three-field below 400 nodes per
                                         axis, two-field above.  A window that holds
                                         the whole grid is always used.               */
@@ -289,8 +289,8 @@ int mesh_sdd_desc_interface_nodes(const mesh_sdd_desc *desc, int32_t *i, int32_t
  * windowed kernel stages in LDS around it, clamped to the grid, the whole
  * axis where it fits.  Kind 0: windows of (rho, dt rho_xi) per node, at
  * most 140 x 140 nodes, blocks of 50 nodes, 45 nodes of margin; kind 1:
- * windows that also hold the dt rho_eta coefficients of their cells, 81 x 81
- * nodes when square, blocks of 21 nodes, 30 nodes of margin.  Kind 1 where
+ * windows that also hold dt rho_eta per node, 114 x 114 nodes when square,
+ * blocks of 54 nodes, 30 nodes of margin.  Kind 1 where
  * its window holds the whole grid, else kind 0 where that one does, else
  * kind 1 for grids under 400 nodes per axis and kind 0 above.  The order changes no result.  Returns the
  * number of nodes Ms >= 0 or a negative error.  When `ranks` is not NULL,

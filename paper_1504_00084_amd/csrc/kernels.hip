@@ -897,8 +897,8 @@ __global__ __launch_bounds__(BLOCK) void paths_fp32(const InstView *__restrict__
 // with a window of the monitor tables around that block (the block plus a
 // margin, clamped to the grid), blocks in Z order, cut into per-XCD queues
 // (JobQueues).  A workgroup (1024 threads, one per CU) pops a job and copies
-// its window into LDS: (rho, dt rho_xi) per node (kind 0), and also the dt
-// rho_eta coefficients of its cells (kind 1).  Its waves run the job's items
+// its window into LDS: (rho, dt rho_xi) per node (kind 0), and also dt
+// rho_eta per node (kind 1).  Its waves run the job's items
 // with the wave loop above; a lane whose path has left the window reads the
 // cell record instead (TAB 3 and 4 in substep_f32), so the results are those
 // of every other kernel.  The waves

@@ -224,7 +224,7 @@ struct Request;
 struct BlockRun {
     int32_t pos_begin, pos_end;
     int32_t i0, j0, tw, th;
-    int32_t kind;   // 0: (rho, dt rho_xi) per node; 1: also the cells' dt rho_eta coefficients
+    int32_t kind;   // 0: (rho, dt rho_xi) per node; 1: also dt rho_eta per node
 };
 
 // The nodes that run paths for one interface stride.  They are stored in
