@@ -103,7 +103,8 @@ def new_ctx(M, budget_bytes=0, stream=None, tune_cache=None):
 def host_threads():
     """Host cores this process may use for the oracle: the CPU affinity, cut
     to the cgroup's CPU quota and to OMP_NUM_THREADS where those are set (a
-    GPU machine exposes its share of the host that way).  Returns (threads, info)."""
+    container can expose its share of the host that way).  Returns (threads,
+    info)."""
     info = {"nproc": os.cpu_count()}
     try:
         info["affinity"] = len(os.sched_getaffinity(0))
