@@ -256,9 +256,13 @@ int mesh_sdd_autotune(mesh_sdd *inst, const mesh_sdd_step *step, mesh_sdd_launch
  * mesh_sdd_autotune, on the first instance of the bucket), then the
  * launch-wide knobs of a multi-instance launch (job_split, refill_lanes,
  * max_quarters) by timing the whole batch at 1/scale_down of every step's
- * path count (at least 64 paths).  The launch-wide winner is kept for every
+ * path count (at least 64 paths), then, timed the same way, each bucket's
+ * chunk_paths {64, 128, 256} and, for grids no window holds whole, its
+ * window_margin {default, 30, 38, 45} (a bucket tuned alone can prefer a
+ * shape that the batch does not).  The launch-wide winner is kept for every
  * later launch of several instances (mesh_sdd_solve_batch, serving ticks)
- * and written to *out if non-NULL.  All FP32. */
+ * and written to *out if non-NULL; the bucket knobs replace the buckets'.
+ * All FP32. */
 int mesh_sdd_autotune_batch(mesh_sdd *const *insts, const mesh_sdd_step *steps, int32_t count, int32_t scale_down,
                             mesh_sdd_launch *out);
 
