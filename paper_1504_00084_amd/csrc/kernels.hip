@@ -203,7 +203,8 @@ struct Win {
 // TAB: where the corner values of rho and dt rho_xi come from.  0: the cell
 // record; 2: the LDS node table (rho, dt rho_xi interleaved); 3: the LDS
 // window when the cell lies inside it, else the cell record; 4: as 3, with
-// dt rho_eta at the corners of the cells inside the window from LDS too.
+// dt rho_eta at the corners of the cells inside the window from LDS too; 5:
+// as 4, for a square window of kWin3Side nodes.
 // The values are the same in every case, so the results are identical.
 template <int TAB>
 __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t wa, uint32_t wb, uint32_t wc,
@@ -248,7 +249,7 @@ __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t w
         const float2 c00 = t2[0], c10 = t2[1], c01 = t2[C.n_xi], c11 = t2[C.n_xi + 1];
         r00 = c00.x, r10 = c10.x, r01 = c01.x, r11 = c11.x;
         g00 = c00.y, g10 = c10.y, g01 = c01.y, g11 = c11.y;
-    } else if (TAB == 3 || TAB == 4) {
+    } else if (TAB >= 3) {
         // Lanes outside the window read the cell record, which keeps its corner
         // values in the window's order (rho, dt rho_xi per node, row by row):
         // both branches load into the same registers, so neither waits for its
@@ -256,26 +257,35 @@ __device__ __forceinline__ int substep_f32(PathF &P, const ConstF &C, uint32_t w
         // waits only for LDS reads before it overwrites their registers, never a
         // gather for an LDS read.  The two-field window's dt rho_eta comes from
         // the plane for every lane, through one gather issued ahead of both.
+        // TAB 5: a square three-field window of kWin3Side nodes, whose row
+        // stride and dt rho_eta offset are then compile-time constants (the
+        // row above becomes an immediate offset of the same LDS address)
+        const uint32_t tw = TAB == 5 ? (uint32_t)kWin3Side : (uint32_t)win.tw;
+        const uint32_t w1 = TAB == 5 ? (uint32_t)kWin3Side - 1u : (uint32_t)win.w1;
+        const uint32_t h1 = TAB == 5 ? (uint32_t)kWin3Side - 1u : (uint32_t)win.h1;
         const int rx = cx - win.i0, ry = cy - win.j0;
-        const bool outside = ((uint32_t)rx >= (uint32_t)win.w1) | ((uint32_t)ry >= (uint32_t)win.h1);
+        const bool outside = ((uint32_t)rx >= w1) | ((uint32_t)ry >= h1);
         if (TAB == 3) G = *coef;
         if (outside) {
             const f32x4 A = cell[0], B = cell[1];
             r00 = A.x, g00 = A.y, r10 = A.z, g10 = A.w;
             r01 = B.x, g01 = B.y, r11 = B.z, g11 = B.w;
-            if (TAB == 4) G = cell[2];
+            if (TAB >= 4) G = cell[2];
         } else {
             // window node of corner 00 (row stride tw); the row above is tw on
+            // (the multiply takes the job's width, equal to kWin3Side for TAB 5,
+            // as a scalar operand of one 24-bit multiply-add)
             const uint32_t node = __umul24((uint32_t)ry, (uint32_t)win.tw) + (uint32_t)rx;
             const float2 *t2 = (const float2 *)tab + node;
-            const float2 *u2 = t2 + win.tw;
+            const float2 *u2 = t2 + tw;
             const float2 c00 = t2[0], c10 = t2[1], c01 = u2[0], c11 = u2[1];
             r00 = c00.x, r10 = c10.x, r01 = c01.x, r11 = c11.x;
             g00 = c00.y, g10 = c10.y, g01 = c01.y, g11 = c11.y;
-            if (TAB == 4) {
+            if (TAB >= 4) {
                 // dt rho_eta of window node k sits at byte coff + 4 k
-                const float *e0 = (const float *)((const char *)tab + win.coff) + node;
-                const float *e1 = e0 + win.tw;
+                const uint32_t coff = TAB == 5 ? (uint32_t)(kWin3Side * kWin3Side * 8) : (uint32_t)win.coff;
+                const float *e0 = (const float *)((const char *)tab + coff) + node;
+                const float *e1 = e0 + tw;
                 G.x = e0[0];
                 G.y = e0[1];
                 G.z = e1[0];
@@ -972,8 +982,11 @@ __global__ __launch_bounds__(kTableBlock) void paths_fp32_win(const InstView *__
         JobSrc js{ctl + 1, R, J.q0};
         const Win win{J.i0, J.j0, J.tw, J.tw - 1, J.th - 1, coff};
         const uint32_t count = ok ? J.count : 0u;
+        const bool square = J.kind == 1 && J.tw == kWin3Side && J.th == kWin3Side;
         if (PER >= 0) {
-            if (J.kind == 1)
+            if (square)
+                item_loop<5, PER>(js, count, insts, buf, cap, wtab, win, lane, rf);
+            else if (J.kind == 1)
                 item_loop<4, PER>(js, count, insts, buf, cap, wtab, win, lane, rf);
             else
                 item_loop<3, PER>(js, count, insts, buf, cap, wtab, win, lane, rf);
@@ -982,7 +995,9 @@ __global__ __launch_bounds__(kTableBlock) void paths_fp32_win(const InstView *__
             // uniform over the workgroup; each kind runs the wave loop
             // compiled for it
             const int kind = path_kind(I);
-            if (J.kind == 1)
+            if (square)
+                item_loop_kind<5>(kind, js, count, insts, buf, cap, wtab, win, lane, rf);
+            else if (J.kind == 1)
                 item_loop_kind<4>(kind, js, count, insts, buf, cap, wtab, win, lane, rf);
             else
                 item_loop_kind<3>(kind, js, count, insts, buf, cap, wtab, win, lane, rf);

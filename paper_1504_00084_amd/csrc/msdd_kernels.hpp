@@ -75,6 +75,7 @@ int paths_fp32_table_blocks_per_cu(int level, int n_nodes);
 // identical to launch_paths_fp32's.
 constexpr size_t kWinBytes = 156800;   // LDS of one window (of the 160 KB of a CU)
 constexpr int kWinNodes = 19600;       // two-field windows: at most 140 x 140 nodes
+constexpr int kWin3Side = 114;         // three-field windows: at most 114 x 114 nodes when square
 hipError_t launch_paths_fp32_window(const InstView *insts, const WorkRange *ranges, const WinJob *jobs,
                                     const JobQueues &qs, uint32_t *head, uint32_t cap, int kind, size_t lds,
                                     int grid, float *ends, uint32_t end_waves, uint32_t refill_lanes,

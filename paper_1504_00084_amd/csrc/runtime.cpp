@@ -419,7 +419,7 @@ int window_kind(const mesh_sdd_desc &d, int want = 0)
 // whole axis where it fits.
 void window_dims(int kind, int n_xi, int n_eta, int *wx, int *wy)
 {
-    const int side = kind ? 114 : 140;   // the largest square of each kind within kWinBytes
+    const int side = kind ? msdd::kWin3Side : 140;   // the largest square of each kind within kWinBytes
     int y = std::min(n_eta, side);
     int x = n_xi;
     while (window_bytes(kind, x, y) > msdd::kWinBytes) --x;
